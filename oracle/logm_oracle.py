@@ -1,0 +1,527 @@
+"""Oracle: plain fp64 NumPy implementation of the paper's matrix logarithm.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).  Not to be used by the
+product path; it shares no code with the HIP library.
+
+Paper: E. Jarlebring, J. Sastre, J. Ibanez, "Polynomial approximations for the
+matrix logarithm with computation graphs", arXiv 2401.10089.
+
+What is computed (Algorithm 1, Section 6):
+
+* inverse scaling: take square roots X <- X^{1/2} with the scaled Denman-Beavers
+  iteration (eq. ScalDB) until the backward-error test of Section 5 passes for the
+  largest scheme available, using the saved-product form (A-I)^2 = A_2 - 2A + I
+  (eq. AI2) and the norm-estimate savings (eqs. normAm9, alpha2term1,
+  normAm9plus1);
+* degree selection (the enumerated procedure after Algorithm 1: eqs. min_in,
+  min_inp, roughmin_in, alpharoughbound_even, roughmax_even);
+* polynomial: log(I+B) ~ -S(-B) (eqs. Taylor_log, logipASTM) evaluated in the
+  degree-optimal computation-graph form (eq. five_mult_degopt);
+* squaring phase: L <- 2^s L.
+
+Every step is written plainly: matrix products with ``@``, inverses and
+log-determinants with ``numpy.linalg`` (LAPACK LU with partial pivoting), norms as
+explicit column sums, and the 1-norm estimator as a Python loop.
+
+Readings of points where the paper is silent or garbled (each is restated in
+the design doc):
+
+R1  Schemes shipped: k in {1, 2, 3, 5}.  The paper prints coefficients only for
+    k = 5 (Table 1); k = 1, 2 are the Taylor polynomials T_2, T_4 written in the
+    degree-optimal form; k = 3 is the three-product scheme eq. eqP8pol solved for
+    T_8 (Section 2.2).  k = 4 and k = 6..9 are not printed, so "m_9" in
+    Algorithm 1 is read as m_{k_max} = m_5 = 14 with Theta_5.
+R2  k = 3: eq. eqP8pol has two distinct real solutions with c_4 > 0; the one with
+    the smaller coefficients (e_0 ~ 0.729) is used (its stability indicator,
+    eq. stability_error, is the smaller of the two).
+R3  At s = 0 the product B2 = B*B is formed once before the scaling loop (the
+    paper forms it after the loop when s = 0; forming it first lets the loop use
+    the same saved-product shortcuts and does not change any result).
+R4  Denman-Beavers stopping rule (the paper gives none): stop when
+    rel = ||X_{k+1}-X_k||_1/||X_{k+1}||_1 <= sqrt(n) u, or when scaling is off,
+    rel < 1e-6 and rel > rel_prev/2 (stagnation at the rounding floor).  Scaling
+    is switched off once rel < 1e-2.  At most ``db_max_iter`` iterations; after
+    the last one the root is accepted if rel <= 1e-6.
+R5  1-norm estimator: the deterministic Hager-Higham estimator with one column
+    (start vector e/n, at most 5 iterations, sign vectors with sign(0) = +1,
+    smallest index on argmax ties, final alternating-sign vector).
+R6  Degree selection: min_in is the *smallest* index whose Theta passes (the
+    text says "maximum", eq. roughmin_in says min); tabmin_im is applied only
+    in the no-estimate branch and mapped to the largest shipped k not above it;
+    max_in uses the even-m bound (all shipped m_k are even); when testing
+    candidate j the term estimates are skipped whenever the bound already decides
+    against the threshold being tested (Theta_j, or Theta_next for the "j+1"
+    shortcut).
+R7  Balancing (steps 1 and 14) is off: log(T^{-1} A T) = T^{-1} log(A) T exactly.
+"""
+
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+__all__ = [
+    "TABLE2",
+    "SHIPPED_K",
+    "TABMIN_IM",
+    "UNIT_ROUNDOFF",
+    "OracleError",
+    "scheme_coefficients",
+    "eval_scheme",
+    "norm1",
+    "normest_power",
+    "db_sqrt",
+    "select_degree",
+    "logm",
+]
+
+UNIT_ROUNDOFF = 2.0 ** -53
+
+# Table 2 (Section 5): k -> (m_k, Theta_{m_k}).  m_k for k = 4..9 carries a "+"
+# in the paper (Taylor-like order); only the integer part matters here.
+TABLE2 = {
+    1: (2, 1.83e-8),
+    2: (4, 1.53e-4),
+    3: (8, 1.33e-2),
+    4: (14, 9.31e-2),
+    5: (14, 2.46e-1),
+    6: (20, 3.72e-1),
+    7: (24, 5.86e-1),
+    8: (27, 6.69e-1),
+    9: (28, 7.28e-1),
+}
+
+# Schemes with coefficients available (reading R1).
+SHIPPED_K = (1, 2, 3, 5)
+
+# tabmin_im from the degree-selection procedure after Algorithm 1 (1-based in k).
+TABMIN_IM = (1, 2, 3, 4, 4, 5, 5, 6, 6)
+
+# Table 1 (Section 3): k = 5 degree-optimal coefficients, rows j = 2..5 acting on
+# P_2..P_{j+1}; y_1..y_7 acting on P_1..P_7.
+_TABLE1_H = {
+    2: (7.363757032799957e-02, -1.050281301619960e+00),
+    3: (8.897468955192446e-02, -1.599651928992725e-01, 9.577281350989334e-01),
+    4: (5.394999133948797e-01, 6.700731102561937e-02, -5.158769100223212e-02,
+        1.094308587350110e+00),
+    5: (1.027072285939197e-01, -8.964023050065877e-03, -2.100705663612491e-01,
+        1.949655359168707e-01, 1.117368056772713e+00),
+}
+_TABLE1_G = {
+    2: (-9.666134174379001e-01, -4.395519034717933e-01),
+    3: (1.048664069004776e-01, 1.585606124033259e-01, 1.668066506920988e-01),
+    4: (-8.025600931705978e-02, -1.159854366397558e-01, 1.066554944706011e-01,
+        1.127094008297975e+00),
+    5: (2.702180425508705e-01, 4.137541209720699e-02, 4.857347452405025e-01,
+        -6.000256005636980e-01, 1.063393233943084e+00),
+}
+_TABLE1_Y = (0.0, 1.0, 5.065546620208965e-01, 3.832512052972577e-01,
+             1.088307723749078e+00, 2.787461897212877e-01, 8.157421998489228e-01)
+
+
+class OracleError(RuntimeError):
+    """Raised when the method cannot proceed (singular input, no convergence)."""
+
+    def __init__(self, code: str, msg: str):
+        super().__init__(f"{code}: {msg}")
+        self.code = code
+
+
+# ---------------------------------------------------------------------------
+# Coefficients of the degree-optimal schemes (eq. five_mult_degopt)
+# ---------------------------------------------------------------------------
+
+def _k3_coefficients():
+    """Solve the three-product scheme eq. eqP8pol for T_8 (Section 2.2).
+
+    With x the argument, the scheme is y02 = x^2 (c4 x^2 + c3 x) and
+    z = (y02 + d2 x^2 + d1 x)(y02 + e2 x^2) + e0 y02 + x^2/2 + x, whose monomial
+    coefficients of x^8..x^3 must equal 1/8..1/3 (eq. Taylor_log).  Matching x^8
+    gives c4^2 = 1/8, x^7 gives c3 = 1/(14 c4), x^6 fixes d2 + e2, x^5 fixes d1,
+    and x^4, x^3 give a quadratic in e2 (reading R2 picks its root).
+    """
+    c4 = 1.0 / math.sqrt(8.0)
+    c3 = 1.0 / (14.0 * c4)
+    s_de = (1.0 / 6.0 - c3 * c3) / c4          # d2 + e2
+    d1 = (1.0 / 5.0 - c3 * s_de) / c4
+    # x^4: d1 c3 + d2 e2 + e0 c4 = 1/4 ; x^3: d1 e2 + e0 c3 = 1/3
+    p = s_de - c4 * d1 / c3
+    q = d1 * c3 + c4 / (3.0 * c3) - 0.25
+    e2 = 0.5 * (p + math.sqrt(p * p + 4.0 * q))
+    d2 = s_de - e2
+    e0 = (1.0 / 3.0 - d1 * e2) / c3
+    # Degree-optimal layout: P4 = (P3)(c3 P2 + c4 P3); P5 = (d1 P2 + d2 P3 + P4)(e2 P3 + P4)
+    h = {2: (0.0, 1.0), 3: (d1, d2, 1.0)}
+    g = {2: (c3, c4), 3: (0.0, e2, 1.0)}
+    y = (0.0, 1.0, 0.5, e0, 1.0)
+    return h, g, y
+
+
+def scheme_coefficients(k: int):
+    """Return (h, g, y) for the k-product scheme, k in SHIPPED_K.
+
+    h[j], g[j] (j = 2..k) hold the coefficients on P_2..P_{j+1} of the two factors
+    whose product is P_{j+2}; y holds the output weights on P_1..P_{k+2}.  P_1 = I,
+    P_2 = x, P_3 = x^2 (normalisation theorem and conjecture of Section 3).
+    """
+    if k == 1:    # T_2 = x + x^2/2
+        return {}, {}, (0.0, 1.0, 0.5)
+    if k == 2:    # T_4 = x + x^2/2 + x^2 (x/3 + x^2/4)
+        return {2: (0.0, 1.0)}, {2: (1.0 / 3.0, 0.25)}, (0.0, 1.0, 0.5, 1.0)
+    if k == 3:
+        return _k3_coefficients()
+    if k == 5:
+        return dict(_TABLE1_H), dict(_TABLE1_G), tuple(_TABLE1_Y)
+    raise ValueError(f"no coefficients for k={k}")
+
+
+def eval_scheme(k: int, x: np.ndarray, x2: np.ndarray) -> np.ndarray:
+    """Evaluate z(x) = sum_q y_q P_q of eq. five_mult_degopt.
+
+    ``x2`` must hold x @ x (P_3); it is passed in so that the caller can use the
+    saved product of eq. AI2.  Uses k - 1 matrix products.
+    """
+    h, g, y = scheme_coefficients(k)
+    n = x.shape[0]
+    P = [None, np.eye(n, dtype=x.dtype), x, x2]          # 1-based P_1..P_3
+    for j in range(2, k + 1):
+        left = sum(h[j][i - 2] * P[i] for i in range(2, j + 2))
+        right = sum(g[j][i - 2] * P[i] for i in range(2, j + 2))
+        P.append(left @ right)                              # P_{j+2}
+    return sum(y[q - 1] * P[q] for q in range(1, k + 3))
+
+
+# ---------------------------------------------------------------------------
+# Norms
+# ---------------------------------------------------------------------------
+
+def norm1(M: np.ndarray) -> float:
+    """Exact matrix 1-norm: the largest column sum of absolute values."""
+    return float(np.abs(M).sum(axis=0).max())
+
+
+def _sign(v: np.ndarray) -> np.ndarray:
+    if np.iscomplexobj(v):
+        a = np.abs(v)
+        out = np.ones_like(v)
+        nz = a > 0
+        out[nz] = v[nz] / a[nz]
+        return out
+    return np.where(v >= 0, 1.0, -1.0)
+
+
+def normest_power(B2: np.ndarray, B: np.ndarray, q: int, r: int):
+    """Estimate ||B2^q B^r||_1 (r in {0, 1}) without forming the power.
+
+    Hager's method with Higham's refinements (reading R5): returns
+    (estimate, number of matrix-vector products).  Every value it can return is
+    ||M v||_1 for some v with ||v||_1 = 1, so the estimate never exceeds the true
+    norm.
+    """
+    n = B2.shape[0]
+    nmv = 0
+
+    def apply(v):
+        nonlocal nmv
+        for _ in range(r):
+            v = B @ v
+        for _ in range(q):
+            v = B2 @ v
+        nmv += q + r
+        return v
+
+    def apply_adj(v):
+        nonlocal nmv
+        for _ in range(q):
+            v = B2.conj().T @ v
+        for _ in range(r):
+            v = B.conj().T @ v
+        nmv += q + r
+        return v
+
+    dtype = np.result_type(B2.dtype, B.dtype)
+    if n == 1:
+        return float(abs(apply(np.ones(1, dtype=dtype))[0])), nmv
+
+    x = np.full(n, 1.0 / n, dtype=dtype)
+    est = -1.0
+    xi_prev = None
+    for it in range(1, 6):
+        y = apply(x)
+        est_y = float(np.abs(y).sum())
+        if it > 1 and est_y <= est:
+            break
+        est = est_y
+        xi = _sign(y)
+        if xi_prev is not None and np.array_equal(xi, xi_prev):
+            break
+        z = apply_adj(xi)
+        za = np.abs(z)
+        j = int(np.argmax(za))                  # first index of the maximum
+        if it > 1 and za[j] <= float(np.real(np.vdot(x, z))):
+            break
+        x = np.zeros(n, dtype=dtype)
+        x[j] = 1.0
+        xi_prev = xi
+    i = np.arange(n, dtype=np.float64)
+    alt = ((-1.0) ** i) * (1.0 + i / (n - 1))
+    est_alt = 2.0 * float(np.abs(apply(alt.astype(dtype))).sum()) / (3.0 * n)
+    return max(est, est_alt), nmv
+
+
+# ---------------------------------------------------------------------------
+# Square root: scaled Denman-Beavers iteration (eq. ScalDB)
+# ---------------------------------------------------------------------------
+
+def _inv_logdet(M: np.ndarray):
+    sign, logabs = np.linalg.slogdet(M)
+    if sign == 0 or not np.isfinite(logabs):
+        raise OracleError("ESINGULAR", "singular matrix in square-root iteration")
+    return np.linalg.inv(M), float(logabs)
+
+
+def db_sqrt(A: np.ndarray, max_iter: int = 30, force_iters: int | None = None):
+    """Principal square root by the scaled Denman-Beavers iteration, eq. ScalDB.
+
+    X_0 = A, Y_0 = I, mu_k = |det X_k det Y_k|^{-1/(2n)},
+    X_{k+1} = (mu X_k + Y_k^{-1}/mu)/2, Y_{k+1} = (mu Y_k + X_k^{-1}/mu)/2.
+    Stopping and scaling switch-off follow reading R4.  With ``force_iters`` the
+    iteration runs exactly that many steps (used to replay another
+    implementation's decisions).  Returns (X, iterations, rel history,
+    number of inverses).
+    """
+    n = A.shape[0]
+    X = np.array(A, copy=True)
+    Y = np.eye(n, dtype=A.dtype)
+    scaled = True
+    rel_prev = math.inf
+    hist = []
+    n_inv = 0
+    tol = math.sqrt(n) * UNIT_ROUNDOFF
+    limit = force_iters if force_iters is not None else max_iter
+    for it in range(1, limit + 1):
+        Xi, ldx = _inv_logdet(X)
+        n_inv += 1
+        if it == 1:                 # Y_0 = I: inverse I, log|det| 0
+            Yi, ldy = np.eye(n, dtype=A.dtype), 0.0
+        else:
+            Yi, ldy = _inv_logdet(Y)
+            n_inv += 1
+        mu = math.exp(-(ldx + ldy) / (2.0 * n)) if scaled else 1.0
+        Xn = 0.5 * (mu * X + Yi / mu)
+        Yn = 0.5 * (mu * Y + Xi / mu)
+        rel = norm1(Xn - X) / norm1(Xn)
+        X, Y = Xn, Yn
+        hist.append(rel)
+        if not np.isfinite(rel):
+            raise OracleError("ENONFINITE", "non-finite square-root iterate")
+        if force_iters is not None:
+            if rel < 1e-2:
+                scaled = False
+            rel_prev = rel
+            continue
+        if rel < 1e-2:
+            scaled = False
+        if rel <= tol or (not scaled and rel < 1e-6 and rel > rel_prev / 2.0):
+            return X, it, hist, n_inv
+        rel_prev = rel
+    if force_iters is None and hist[-1] > 1e-6:
+        raise OracleError("ENOCONV", "square-root iteration did not converge")
+    return X, limit, hist, n_inv
+
+
+# ---------------------------------------------------------------------------
+# Degree selection (procedure after Algorithm 1)
+# ---------------------------------------------------------------------------
+
+def _theta(k, theta_table):
+    return theta_table[k][1]
+
+
+def _m(k, theta_table):
+    return theta_table[k][0]
+
+
+def select_degree(n1, n2, e_top, e_top1, estimate, kset, theta_table=TABLE2):
+    """Choose k from kset (sorted).  Reading R6.
+
+    n1 = ||B||_1, n2 = ||B^2||_1; e_top / e_top1 are the estimates of
+    ||B^{m_top}||, ||B^{m_top+1}|| from the last scaling-loop pass (or None);
+    ``estimate(q, r)`` returns an estimate of ||B2^q B^r||_1.
+    """
+    kset = sorted(kset)
+    ktop = kset[-1]
+    mtop = _m(ktop, theta_table)
+    sq2 = math.sqrt(n2)
+
+    def first_pass(value):
+        for j in kset:
+            if value <= _theta(j, theta_table):
+                return j
+        return ktop
+
+    # min_in (eqs. min_in, min_inp, roughmin_in)
+    if e_top is not None:
+        min_in = first_pass(e_top ** (1.0 / mtop))
+        if e_top1 is not None:
+            min_in = max(min_in, first_pass(e_top1 ** (1.0 / (mtop + 1))))
+    else:
+        r = first_pass(sq2)
+        t = TABMIN_IM[r - 1]
+        min_in = max(j for j in kset if j <= t)
+        if sq2 > _theta(1, theta_table):
+            min_in = max(min_in, 2 if 2 in kset else min_in)
+        else:
+            min_in = kset[0]
+
+    # max_in (eqs. alpharoughbound_even, roughmax_even)
+    max_in = ktop
+    for j in kset:
+        m = _m(j, theta_table)
+        if (n2 ** (m / 2) * n1) ** (1.0 / (m + 1)) <= _theta(j, theta_table):
+            max_in = j
+            break
+
+    if min_in >= max_in:
+        return max_in
+
+    idx = kset.index(min_in)
+    while kset[idx] < max_in:
+        j = kset[idx]
+        nxt = kset[idx + 1]
+        th_j = _theta(j, theta_table)
+        th_n = _theta(nxt, theta_table)
+        m = _m(j, theta_table)
+        h = m // 2
+        # term 1: ||B^m||^{1/m}
+        if h == 1:
+            e1 = n2
+            t1 = sq2
+        elif sq2 <= th_j:
+            e1 = n2 ** h
+            t1 = sq2
+        else:
+            e1 = estimate(h, 0)
+            t1 = e1 ** (1.0 / m)
+        if t1 > th_n:
+            alpha = t1
+        else:
+            tau = th_j if t1 <= th_j else th_n
+            bound = (e1 * n1) ** (1.0 / (m + 1))
+            if bound <= tau:
+                t2 = bound
+            else:
+                t2 = estimate(h, 1) ** (1.0 / (m + 1))
+            alpha = max(t1, t2)
+        if alpha <= th_j:
+            return j
+        if alpha <= th_n:
+            return nxt
+        idx += 1
+    return max_in
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 1
+# ---------------------------------------------------------------------------
+
+def logm(A, k_max: int = 5, max_sqrt: int = 50, db_max_iter: int = 30,
+         theta_table=TABLE2, force: dict | None = None):
+    """Principal matrix logarithm by Algorithm 1 (Section 6).
+
+    Returns (L, info).  ``force`` = {"s": int, "k": int, "db_iters": [..]}
+    replays a given sequence of decisions (number of roots, iterations per root,
+    scheme) instead of taking them, so that two implementations can be compared
+    without decision flips.
+    """
+    A = np.asarray(A)
+    if A.ndim != 2 or A.shape[0] != A.shape[1] or A.shape[0] < 1:
+        raise ValueError("A must be a non-empty square matrix")
+    if not np.all(np.isfinite(A)):
+        raise OracleError("ENONFINITE", "input has non-finite entries")
+    dtype = np.complex128 if np.iscomplexobj(A) else np.float64
+    X = np.array(A, dtype=dtype, copy=True)
+    n = X.shape[0]
+    eye = np.eye(n, dtype=dtype)
+    kset = tuple(k for k in SHIPPED_K if k <= k_max)
+    ktop = kset[-1]
+    mtop = _m(ktop, theta_table)
+    th_top = _theta(ktop, theta_table)
+    h_top = mtop // 2
+
+    info = {"s": 0, "k": None, "m": None, "db_iters": [], "db_rel": [],
+            "n_inv": 0, "n_gemm": 0, "n_matvec": 0, "n_est": 0}
+
+    def estimate(q, r):
+        est, nmv = normest_power(B2, B, q, r)
+        info["n_matvec"] += nmv
+        info["n_est"] += 1
+        return est
+
+    s = 0
+    B = X - eye
+    n1 = norm1(B)
+    B2 = B @ B                                   # reading R3
+    info["n_gemm"] += 1
+    e_top = e_top1 = None
+    if force is None:
+        finished = n1 <= th_top
+        while not finished and s < max_sqrt:
+            e_top = e_top1 = None
+            n2 = norm1(B2)
+            # first term of eq. alphaapprox, with the shortcut of eq. alpha2term1
+            if math.sqrt(n2) <= th_top:
+                t1 = True
+                base = n2 ** h_top
+            else:
+                e_top = estimate(h_top, 0)       # ||(B^2)^{m/2}||, eq. AI2 note 2
+                t1 = e_top ** (1.0 / mtop) <= th_top
+                base = e_top
+            t2 = False
+            if t1:                               # second term, eq. normAm9plus1
+                if (base * n1) ** (1.0 / (mtop + 1)) <= th_top:
+                    t2 = True
+                else:
+                    e_top1 = estimate(h_top, 1)
+                    t2 = e_top1 ** (1.0 / (mtop + 1)) <= th_top
+            finished = t1 and t2
+            if not finished:
+                A2 = X
+                X, it, hist, ninv = db_sqrt(X, db_max_iter)
+                s += 1
+                info["db_iters"].append(it)
+                info["db_rel"].append(hist)
+                info["n_inv"] += ninv
+                B = X - eye
+                B2 = A2 - 2.0 * X + eye           # eq. AI2
+                n1 = norm1(B)
+        if not finished:
+            raise OracleError("ENOCONV", "no convergence within max_sqrt roots")
+        n2 = norm1(B2)
+        k = select_degree(n1, n2, e_top, e_top1, estimate, kset, theta_table)
+    else:
+        for r in range(force["s"]):
+            A2 = X
+            X, it, hist, ninv = db_sqrt(X, db_max_iter, force_iters=force["db_iters"][r])
+            s += 1
+            info["db_iters"].append(it)
+            info["db_rel"].append(hist)
+            info["n_inv"] += ninv
+            B = X - eye
+            B2 = A2 - 2.0 * X + eye
+        k = force["k"]
+
+    # Step 12: L = -S(-B) with P_2 = -B, P_3 = B^2 (eqs. logipASTM, five_mult_degopt)
+    Z = eval_scheme(k, -B, B2)
+    info["n_gemm"] += k - 1
+    L = -(2.0 ** s) * Z                         # step 13 (squaring phase) and sign
+    info["s"] = s
+    info["k"] = k
+    info["m"] = _m(k, theta_table)
+    cplx = 4.0 if dtype == np.complex128 else 1.0
+    info["flops"] = cplx * (2.0 * n ** 3 * (info["n_inv"] + info["n_gemm"])
+                            + 2.0 * n ** 2 * info["n_matvec"])
+    if not np.all(np.isfinite(L)):
+        raise OracleError("ENONFINITE", "non-finite result")
+    return L, info

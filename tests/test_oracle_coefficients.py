@@ -1,0 +1,260 @@
+"""Pins for the oracle's scheme coefficients and Theta constants.
+
+Independent checks: exact rational expansion of each scheme against the Taylor
+coefficients of -log(1-x) (eq. Taylor_log), recomputation of Theta from the
+backward-error series (eqs. backwarderror, Eb, theta_Eb), a Paterson-Stockmeyer
+evaluation of T_8, the degrees-of-freedom count of Section 3, and the stability
+indicator of eq. stability_error.
+"""
+
+from fractions import Fraction
+
+import mpmath
+import numpy as np
+import pytest
+
+import oracle
+from oracle import scheme_coefficients
+
+U = 2.0 ** -53
+
+
+# ---------------------------------------------------------------- helpers ---
+def poly_mul(a, b):
+    out = [Fraction(0)] * (len(a) + len(b) - 1)
+    for i, x in enumerate(a):
+        if x == 0:
+            continue
+        for j, z in enumerate(b):
+            out[i + j] += x * z
+    return out
+
+
+def poly_add(a, b):
+    n = max(len(a), len(b))
+    a = list(a) + [Fraction(0)] * (n - len(a))
+    b = list(b) + [Fraction(0)] * (n - len(b))
+    return [x + z for x, z in zip(a, b)]
+
+
+def expand_exact(k):
+    """Monomial coefficients b_0..b_{2^k} of the scheme, exact in the doubles."""
+    h, g, y = scheme_coefficients(k)
+    P = [None, [Fraction(1)], [Fraction(0), Fraction(1)], [Fraction(0), Fraction(0), Fraction(1)]]
+    for j in range(2, k + 1):
+        left = [Fraction(0)]
+        right = [Fraction(0)]
+        for i in range(2, j + 2):
+            left = poly_add(left, [Fraction(h[j][i - 2]) * c for c in P[i]])
+            right = poly_add(right, [Fraction(g[j][i - 2]) * c for c in P[i]])
+        P.append(poly_mul(left, right))
+    z = [Fraction(0)]
+    for q in range(1, k + 3):
+        z = poly_add(z, [Fraction(y[q - 1]) * c for c in P[q]])
+    return z
+
+
+def expand_float(k, coeffs=None):
+    """Same expansion with every operation rounded to double (b-tilde of eq. stability_error)."""
+    h, g, y = coeffs if coeffs is not None else scheme_coefficients(k)
+    P = [None, np.array([1.0]), np.array([0.0, 1.0]), np.array([0.0, 0.0, 1.0])]
+
+    def add(a, b):
+        n = max(len(a), len(b))
+        return np.pad(a, (0, n - len(a))) + np.pad(b, (0, n - len(b)))
+
+    for j in range(2, k + 1):
+        left = np.zeros(1)
+        right = np.zeros(1)
+        for i in range(2, j + 2):
+            left = add(left, h[j][i - 2] * P[i])
+            right = add(right, g[j][i - 2] * P[i])
+        P.append(np.convolve(left, right))
+    z = np.zeros(1)
+    for q in range(1, k + 3):
+        z = add(z, y[q - 1] * P[q])
+    return z
+
+
+def backward_series(b, nterms):
+    """c_k of Delta(x) = exp(-S(-x)) - 1 - x for S(x) = sum b_i x^i (mpmath)."""
+    # f(x) = -S(-x) = sum_i -b_i (-1)^i x^i
+    f = [mpmath.mpf(0)] * nterms
+    for i, bi in enumerate(b):
+        if 0 < i < nterms:
+            f[i] = -mpmath.mpf(bi.numerator) / bi.denominator * (-1) ** i
+    # E = exp(f):  E' = f' E  ->  E_k = (1/k) sum_{j=1}^{k} j f_j E_{k-j}
+    E = [mpmath.mpf(0)] * nterms
+    E[0] = mpmath.mpf(1)
+    for kk in range(1, nterms):
+        acc = mpmath.mpf(0)
+        for j in range(1, kk + 1):
+            if f[j] != 0:
+                acc += j * f[j] * E[kk - j]
+        E[kk] = acc / kk
+    c = list(E)
+    c[0] -= 1
+    c[1] -= 1
+    return c
+
+
+def theta_from_series(c, m):
+    """Theta_m = max{theta : sum_{k>=m+1} |c_k| theta^(k-1) <= u}, eq. theta_Eb."""
+    coeffs = [(k, abs(c[k])) for k in range(m + 1, len(c))]
+
+    def hbar(t):
+        t = mpmath.mpf(t)
+        return sum(ck * t ** (k - 1) for k, ck in coeffs)
+
+    lo, hi = mpmath.mpf(0), mpmath.mpf(1)
+    for _ in range(200):
+        mid = (lo + hi) / 2
+        if hbar(mid) <= U:
+            lo = mid
+        else:
+            hi = mid
+    return float(lo)
+
+
+# ------------------------------------------------------------------ tests ---
+def test_table1_transcription(golden):
+    """The oracle's k=5 constants equal the printed Table 1."""
+    t = golden("table1_k5.txt")
+    h, g, y = scheme_coefficients(5)
+    for j in range(2, 6):
+        for i in range(2, j + 2):
+            assert h[j][i - 2] == float(t[f"h_{j}_{i}"][0])
+            assert g[j][i - 2] == float(t[f"g_{j}_{i}"][0])
+    for q in range(1, 8):
+        assert y[q - 1] == float(t[f"y_{q}"][0])
+
+
+def test_table2_transcription(golden):
+    t = golden("table2_theta.txt")
+    for k in range(1, 10):
+        m, deg, th = t[str(k)]
+        assert oracle.TABLE2[k] == (int(m), float(th))
+        assert int(deg) == 2 ** k
+    assert tuple(int(v) for v in t["tabmin"]) == oracle.TABMIN_IM
+
+
+@pytest.mark.parametrize("k,m", [(1, 2), (2, 4), (3, 8)])
+def test_taylor_schemes_match_taylor(k, m):
+    """k = 1, 2, 3 reproduce T_{m_k} (eq. Taylor_log) up to coefficient rounding."""
+    b = expand_exact(k)
+    assert b[0] == 0
+    assert len(b) - 1 == 2 ** k
+    for i in range(1, m + 1):
+        rel = abs((b[i] - Fraction(1, i)) * i)
+        assert rel <= 4 * U, (k, i, float(rel / U))
+    for i in range(m + 1, len(b)):
+        assert b[i] == 0 or k == 3
+
+
+def test_k5_table1_taylor_match():
+    """Table 1 expands to b_i = 1/i within a few u for i <= 12 (Section 3's claim),
+    and |(1/i - b_i) i| <= 1 for every i > m_5 (eq. after stabcompgraph)."""
+    b = expand_exact(5)
+    assert len(b) - 1 == 32
+    assert b[0] == 0
+    assert b[1] == 1
+    for i in range(2, 13):
+        assert abs((b[i] - Fraction(1, i)) * i) <= 8 * U, i
+    # i = 13, 14 are printed-coefficient limited (about 1.4e2 u and 7.2e3 u)
+    assert abs(float((b[14] - Fraction(1, 14)) * 14)) < 1e-11
+    for i in range(15, 33):
+        assert abs(float((Fraction(1, i) - b[i]) * i)) <= 1.0, i
+
+
+@pytest.mark.parametrize("k,m,printed", [(1, 2, 1.83e-8), (2, 4, 1.53e-4), (3, 8, 1.33e-2)])
+def test_theta_recomputed_taylor(k, m, printed):
+    """Theta_{m_k} of Table 2 from the backward-error series of the exact T_m."""
+    mpmath.mp.dps = 40
+    b = [Fraction(0)] + [Fraction(1, i) for i in range(1, m + 1)]
+    c = backward_series(b, 60)
+    assert c[0] == 0 and abs(c[1]) < 1e-35
+    th = theta_from_series(c, m)
+    assert abs(th - printed) / printed < 5e-3, th
+    # the leading term alone gives the closed form ((m+1) u)^(1/m)
+    assert abs(th / ((m + 1) * U) ** (1.0 / m) - 1) < 0.05
+
+
+def test_theta5_recomputed_from_table1():
+    """Theta_5 from the printed Table 1: 0.2448, vs 0.246 printed in Table 2."""
+    mpmath.mp.dps = 40
+    b = expand_exact(5)
+    c = backward_series(b, 160)
+    th = theta_from_series(c, 14)
+    assert 0.244 < th < 0.2455, th
+    assert abs(th - oracle.TABLE2[5][1]) / oracle.TABLE2[5][1] < 0.01
+
+
+def test_k3_equals_paterson_stockmeyer():
+    """The three-product k = 3 scheme equals a four-product PS evaluation of T_8."""
+    rng = np.random.default_rng(7)
+    for trial in range(3):
+        n = 12
+        x = rng.standard_normal((n, n))
+        x *= 0.3 / np.linalg.norm(x, 1)
+        x2 = x @ x
+        x3 = x2 @ x
+        x4 = x2 @ x2
+        I = np.eye(n)
+        ps = x + x2 / 2 + x3 / 3 + x4 @ (I / 4 + x / 5 + x2 / 6 + x3 / 7 + x4 / 8)
+        z = oracle.eval_scheme(3, x, x2)
+        assert np.linalg.norm(z - ps) / np.linalg.norm(ps) < 1e-14
+
+
+def test_degrees_of_freedom_layout():
+    """Section 3: k^2+4k+2 coefficients in the full form, k^2+2k-2 free ones after the
+    normalisation theorem, the conjecture and y_1 = 0, y_2 = 1."""
+    for k in (2, 3, 5):
+        h, g, y = scheme_coefficients(k)
+        stored = sum(len(v) for v in h.values()) + sum(len(v) for v in g.values()) + len(y)
+        assert stored == k * k + 2 * k       # rows j=2..k on P_2..P_{j+1}, plus y
+        assert stored - 2 == k * k + 2 * k - 2
+        full = sum(2 * (j + 1) for j in range(1, k + 1)) + (k + 2)
+        assert full == k * k + 4 * k + 2
+        assert y[0] == 0.0 and y[1] == 1.0
+    assert 6 * 6 + 4 * 6 - 2 == 58 and 6 * 6 + 2 * 6 - 2 == 46   # numbers quoted for k = 6
+
+
+def test_k3_root_choice_by_stability_indicator():
+    """Reading R2: of the two real T_8 solutions of eq. eqP8pol the shipped one has the
+    smaller stability indicator (eq. stability_error)."""
+    import math
+    h, g, y = scheme_coefficients(3)
+    # rebuild the other root from the same equations
+    c4 = 1 / math.sqrt(8)
+    c3 = 1 / (14 * c4)
+    s_de = (1 / 6 - c3 * c3) / c4
+    d1 = (1 / 5 - c3 * s_de) / c4
+    p = s_de - c4 * d1 / c3
+    q = d1 * c3 + c4 / (3 * c3) - 0.25
+    e2 = 0.5 * (p - math.sqrt(p * p + 4 * q))
+    other = ({2: (0.0, 1.0), 3: (d1, s_de - e2, 1.0)},
+             {2: (c3, c4), 3: (0.0, e2, 1.0)},
+             (0.0, 1.0, 0.5, (1 / 3 - d1 * e2) / c3, 1.0))
+    assert expand_exact(3)[8] != 0
+
+    def indicator(coeffs):
+        bt = expand_float(3, coeffs)
+        return max(abs(bt[i] - 1.0 / i) * i for i in range(1, 9))
+
+    assert indicator((h, g, y)) <= indicator(other)
+    assert abs(y[3] - 0.7290085258759623) < 1e-12
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 5])
+def test_scalar_backward_error_at_theta(k):
+    """eq. Des_Eb on the scalar case: |exp(-S(-x)) - 1 - x| / |x| <= ~u at |x| = Theta."""
+    mpmath.mp.dps = 50
+    b = expand_exact(k)
+    th = oracle.TABLE2[k][1]
+    worst = 0.0
+    for ang in np.linspace(0, 2 * np.pi, 17):
+        x = mpmath.mpc(th * np.cos(ang), th * np.sin(ang))
+        S = sum(mpmath.mpf(bi.numerator) / bi.denominator * (-x) ** i for i, bi in enumerate(b))
+        delta = mpmath.exp(-S) - 1 - x
+        worst = max(worst, float(abs(delta) / abs(x)))
+    assert worst <= 1.2 * U, worst / U
