@@ -1,0 +1,168 @@
+"""Benchmark: FP64 logm of the n = 4096 rotation-scaling workload on one MI355X.
+
+One step = one full logm_forward (Algorithm 1: square roots, degree selection,
+graph polynomial, 2^s rescale) of a resident n x n matrix.  The value is
+algorithmic FP64 flops per second, counted from the call's own decisions:
+2n^3 per inverse and per matrix product plus 2n^2 per matrix-vector product.
+
+Prints one JSON line (rank 0).  Single GPU only.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+MFMA_FP64_PEAK_TFLOPS = 78.6     # MI355X dense fp64 matrix peak
+HBM_PEAK_GBS = 8000.0
+
+WORKLOAD = "rotscale4096"
+N = 4096
+
+
+def cpu_baseline(A, budget_s: float = 30.0):
+    """The oracle (test infrastructure) on a bounded sample of the same workload:
+    Denman-Beavers iterations of the first square root of the n = 4096 matrix."""
+    import numpy as np
+    import oracle
+
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max((d.get("num_threads", 1) for d in threadpool_info()), default=1)
+    except Exception:  # pragma: no cover
+        cores = os.cpu_count() or 1
+    n = A.shape[0]
+    iters = 0
+    t0 = time.perf_counter()
+    elapsed = 0.0
+    n_inv = 0
+    # one iteration at a time until the budget is used (each costs 1-2 inverses)
+    for it in (1, 2, 3):
+        t1 = time.perf_counter()
+        _, done, _, ninv = oracle.db_sqrt(A, force_iters=it)
+        elapsed = time.perf_counter() - t1
+        iters, n_inv = done, ninv
+        if time.perf_counter() - t0 + elapsed * 1.7 > budget_s:
+            break
+    flops = 2.0 * n ** 3 * n_inv
+    return {
+        "value": flops / elapsed / 1e12,
+        "unit": "TFLOP/s",
+        "cores": int(cores),
+        "kind": "oracle",
+        "sample": f"{iters} Denman-Beavers iterations ({n_inv} inverses, 2n^3 each) of the first square "
+                  f"root of the n={n} workload matrix, NumPy/LAPACK fp64, {elapsed:.1f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only (the single-matrix logm is not sharded); "
+              "use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2401_10089_amd as lm
+    from workloads import CONFIG_SEEDS, rotscale_matrix
+
+    lm.load_library()
+    dev = torch.device("cuda:0")
+    A_np, L_exact = rotscale_matrix(N, CONFIG_SEEDS[WORKLOAD])
+    A = torch.from_numpy(A_np).to(dev)
+    out = torch.empty_like(A)
+    ws = torch.empty(lm.workspace_size(N), dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+
+    info = None
+    for _ in range(args.warmup):
+        _, info = lm.logm(A, out=out, workspace=ws)
+    torch.cuda.synchronize()
+
+    lm.profile_reset()
+    lm.profile_enable(True)
+    stream = torch.cuda.current_stream(dev)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    flops = 0.0
+    for _ in range(args.steps):
+        _, info = lm.logm(A, out=out, workspace=ws)
+        flops += info["flops"]
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lm.profile_enable(False)
+    prof = lm.profile_get()
+    ev_ms = ev0.elapsed_time(ev1)
+    ms_per_step = 1e3 * wall / args.steps
+    value = flops / wall / 1e12
+
+    L = out.cpu().numpy()
+    rel_err = float(np.linalg.norm(L - L_exact) / np.linalg.norm(L_exact))
+
+    achieved = prof["flops"] / (prof["ms"] * 1e-3) / 1e12 if prof["ms"] > 0 else None
+    roofline = {
+        "bound": "mfma",
+        "kernel": "gemm_kernel<GjeOuterOp> (Gauss-Jordan rank-256 trailing update)",
+        "achieved": achieved,
+        "peak": MFMA_FP64_PEAK_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": (achieved / MFMA_FP64_PEAK_TFLOPS) if achieved else None,
+        "traffic": None,
+        "launches": prof["launches"],
+        "avg_launch_ms": prof["ms"] / max(prof["launches"], 1),
+        "algorithmic_flops_per_launch": prof["flops"] / max(prof["launches"], 1),
+    }
+    line = {
+        "metric": "FP64 TFLOP/s logm at n=4096",
+        "value": value,
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "rotscale4096: A = V blockdiag(r [[cos t, sin t], [-sin t, cos t]]) V^-1, "
+                        "V = I + 0.1 N(0,1)/sqrt(n), log r ~ U[log 1e-3, log 1e3], t ~ U(-0.9pi, 0.9pi), seed 2002",
+            "n": N,
+            "s": info["s"],
+            "k": info["k"],
+            "db_iters": info["db_iters"],
+            "n_inv": info["n_inv"],
+            "n_gemm": info["n_gemm"],
+            "n_matvec": info["n_matvec"],
+            "algorithmic_flops_per_step": info["flops"],
+            "event_ms_per_step": ev_ms / args.steps,
+        },
+        "check": {"rel_frobenius_err_vs_exact_log": rel_err},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(A_np)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

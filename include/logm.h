@@ -1,0 +1,153 @@
+/*
+ * logm.h - C ABI of the MI355X (gfx950) matrix-logarithm library.
+ *
+ * The library computes the principal logarithm log(A) of an n x n matrix with no
+ * eigenvalues on the closed negative real axis by the inverse scaling and squaring
+ * algorithm of Jarlebring, Sastre and Ibanez, "Polynomial approximations for the
+ * matrix logarithm with computation graphs" (arXiv 2401.10089), Algorithm 1 of
+ * Section 6:
+ *   - square roots by the scaled Denman-Beavers iteration (eq. ScalDB),
+ *   - the number of roots s and the scheme k chosen from the backward-error bound
+ *     of Section 5 (eqs. Eb, theta_Eb, Table 2) with 1-norm estimates
+ *     (eqs. alphaapprox, AI2, normAm9, alpha2term1, normAm9plus1 and the
+ *     degree-selection procedure after Algorithm 1),
+ *   - log(I+B) ~ -S(-B) (eqs. Taylor_log, logipASTM) evaluated as the
+ *     degree-optimal computation graph of eq. five_mult_degopt (schemes with
+ *     k = 1, 2, 3 and 5 matrix products; k = 5 uses Table 1),
+ *   - the squaring phase L = 2^s L.
+ * Balancing (the pre- and post-processing steps of Algorithm 1) is not applied.
+ *
+ * Conventions (all entry points):
+ *   - Matrices are row-major with a leading dimension ld >= n (elements between
+ *     rows are neither read nor written).  Every norm is the 1-norm of the matrix
+ *     as stored (largest column sum).
+ *   - "device" pointers are HIP device memory of the current device; "host"
+ *     pointers are ordinary CPU memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).  All
+ *     device work is enqueued on it.  Calls that take data-dependent decisions
+ *     synchronise the stream and return when their outputs are complete.
+ *   - Workspace: `ws` is caller-owned device memory of at least the size reported
+ *     by the matching *_workspace_size call, aligned to 256 bytes.  If ws is NULL
+ *     the library allocates the workspace on `stream` and frees it before
+ *     returning.  The library keeps no pointer to caller memory after a call.
+ *   - Return value: a LOGM_* status code; outputs are unspecified on error.
+ *     Argument checks happen before any device work.  Concurrent calls on
+ *     different streams must use different workspaces.
+ */
+#ifndef LOGM_H
+#define LOGM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  LOGM_OK = 0,
+  LOGM_EINVAL = 1,      /* bad argument: n < 1, NULL pointer, ld < n, bad option */
+  LOGM_ENOTSUP = 2,     /* data type not built (complex input) */
+  LOGM_EWORKSPACE = 3,  /* ws_bytes smaller than required */
+  LOGM_ENONFINITE = 4,  /* NaN or Inf in the input or the result */
+  LOGM_ESINGULAR = 5,   /* exact zero pivot: singular matrix, log undefined */
+  LOGM_ENOCONV = 6,     /* square roots did not converge (eigenvalue on or near R^-) */
+  LOGM_EHIP = 7         /* HIP runtime error; the hipError_t is in info->status_detail */
+};
+
+typedef enum { LOGM_R64 = 0, LOGM_C128 = 1 } logm_dtype;
+
+/* Options of Algorithm 1 (Section 6). */
+typedef struct logm_opts {
+  int32_t k_max;        /* largest scheme (matrix products) allowed: 1, 2, 3 or 5 (default 5) */
+  int32_t max_sqrt;     /* maximum number of square roots, "maxiter" (default 50, at most 64) */
+  int32_t db_max_iter;  /* maximum Denman-Beavers iterations per root (default 30) */
+  int32_t theta_source; /* 0: Theta values of Table 2 as printed (default);
+                           1: Theta_5 = 0.2448 recomputed from Table 1 */
+  int32_t reserved[4];  /* must be zero */
+} logm_opts;
+
+/* Decisions and counters of one call (host memory). */
+typedef struct logm_info {
+  int32_t s;             /* number of square roots taken */
+  int32_t k;             /* scheme used (matrix products of the polynomial) */
+  int32_t m;             /* its Taylor order m_k (Table 2) */
+  int32_t n_inv;         /* matrix inverses computed (sum over roots of 2*iters - 1) */
+  int32_t n_gemm;        /* matrix products (B^2 at s = 0 plus k - 1 graph products) */
+  int32_t n_matvec;      /* matrix-vector products of the 1-norm estimator */
+  int32_t n_est;         /* 1-norm estimates */
+  int32_t db_iters[64];  /* Denman-Beavers iterations of each root */
+  double flops;          /* algorithmic flops: 2n^3 (n_inv + n_gemm) + 2n^2 n_matvec */
+  double norm1_b;        /* ||A^{1/2^s} - I||_1 */
+  double norm1_b2;       /* ||(A^{1/2^s} - I)^2||_1 (saved-product form, eq. AI2) */
+  int32_t status_detail; /* hipError_t when LOGM_EHIP */
+} logm_info;
+
+/* Fill *o with the defaults listed above. */
+void logm_default_opts(logm_opts* o);
+
+/* Human-readable name of a status code (static string). */
+const char* logm_strerror(int code);
+
+/* Workspace bytes for logm_forward on an n x n matrix; also sufficient for every
+ * component entry point below with the same n.  Returns LOGM_EINVAL for n < 1. */
+int logm_workspace_size(int32_t dtype, int64_t n, const logm_opts* o, size_t* bytes);
+
+/* L = log(A) (Algorithm 1).  A (device, n x n, lda) is not modified; L (device,
+ * n x n, ldl) must not overlap A.  o may be NULL (defaults); info (host) may be
+ * NULL.  dtype LOGM_R64 only (LOGM_C128 returns LOGM_ENOTSUP). */
+int logm_forward(int32_t dtype, int64_t n, const void* A, int64_t lda, void* L, int64_t ldl,
+                 const logm_opts* o, logm_info* info, void* ws, size_t ws_bytes, void* stream);
+
+/* ---- components of the path (fp64, device pointers), used for step-level checks ---- */
+
+/* C = alpha * A * B + beta * C (m x k times k x n) on the fp64 matrix cores. */
+int logm_gemm_f64(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_t lda,
+                  const double* B, int64_t ldb, double beta, double* C, int64_t ldc, void* stream);
+
+/* Ainv = A^{-1} by blocked Gauss-Jordan elimination with tournament pivoting (the
+ * left division of eq. ScalDB); *logabsdet (host) = log|det A|.  A may equal Ainv
+ * only if lda == ldi. */
+int logm_inverse_f64(int64_t n, const double* A, int64_t lda, double* Ainv, int64_t ldi,
+                     double* logabsdet, void* ws, size_t ws_bytes, void* stream);
+
+/* X = A^{1/2} by the scaled Denman-Beavers iteration (eq. ScalDB) with the stopping
+ * rule of the library (rel <= sqrt(n) u, or stagnation below 1e-6 once scaling is
+ * off; scaling stops once rel < 1e-2).  *iters (host) = iterations used. */
+int logm_sqrt_f64(int64_t n, const double* A, int64_t lda, double* X, int64_t ldx,
+                  int32_t db_max_iter, int32_t* iters, void* ws, size_t ws_bytes, void* stream);
+
+/* L = -2^s S_k(-B) with P_3 = B2 = B*B supplied (eq. five_mult_degopt with the
+ * saved product of eq. AI2); k in {1, 2, 3, 5}, 0 <= s <= 64. */
+int logm_poly_f64(int64_t n, int32_t k, int32_t s, const double* B, int64_t ldb, const double* B2,
+                  int64_t ldb2, double* L, int64_t ldl, void* ws, size_t ws_bytes, void* stream);
+
+/* *est (host) = estimate of ||B2^q B^r||_1 (r in {0, 1}, q >= 1) by the
+ * deterministic Hager-Higham 1-norm estimator; *nmatvec (host) = products used. */
+int logm_normest_f64(int64_t n, const double* B2, int64_t ldb2, const double* B, int64_t ldb,
+                     int32_t q, int32_t r, double* est, int32_t* nmatvec, void* ws,
+                     size_t ws_bytes, void* stream);
+
+/* Host-side tables: the coefficients of scheme k (h and g rows j = 2..k on
+ * P_2..P_{j+1}, concatenated; y on P_1..P_{k+2}), its order m_k and Theta_{m_k}.
+ * Any output pointer may be NULL.  *nh receives the number of h (= g) values. */
+int logm_scheme(int32_t k, int32_t theta_source, double* h, double* g, double* y, int32_t* nh,
+                int32_t* m, double* theta);
+
+/* Kernel timing for performance reports.  When enabled, the library brackets every
+ * launch of the Gauss-Jordan trailing-update kernel (the dominant kernel) with HIP
+ * events on the stream it runs on and accumulates, at its own synchronisation
+ * points, the launch count, total device milliseconds and the algorithmic flops and
+ * HBM bytes of those launches.  Process-wide; not thread-safe. */
+void logm_profile_enable(int32_t on);
+void logm_profile_reset(void);
+int logm_profile_get(int64_t* launches, double* ms_total, double* flops_total, double* bytes_total);
+
+/* Library version string. */
+const char* logm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LOGM_H */

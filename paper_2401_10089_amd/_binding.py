@@ -1,0 +1,338 @@
+"""ctypes binding of liblogm.so (include/logm.h).
+
+Argument marshalling only: every step of the computation runs in the HIP library.
+PyTorch supplies device memory (tensors, workspace) and the current stream.  If the
+library has not been built, every entry point raises ``LibraryNotBuilt``; there is
+no CPU fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "liblogm.so")
+
+LOGM_R64 = 0
+LOGM_C128 = 1
+
+STATUS = {
+    0: "LOGM_OK",
+    1: "LOGM_EINVAL",
+    2: "LOGM_ENOTSUP",
+    3: "LOGM_EWORKSPACE",
+    4: "LOGM_ENONFINITE",
+    5: "LOGM_ESINGULAR",
+    6: "LOGM_ENOCONV",
+    7: "LOGM_EHIP",
+}
+
+# Every symbol include/logm.h declares.
+EXPORTS = (
+    "logm_default_opts",
+    "logm_strerror",
+    "logm_workspace_size",
+    "logm_forward",
+    "logm_gemm_f64",
+    "logm_inverse_f64",
+    "logm_sqrt_f64",
+    "logm_poly_f64",
+    "logm_normest_f64",
+    "logm_scheme",
+    "logm_profile_enable",
+    "logm_profile_reset",
+    "logm_profile_get",
+    "logm_version",
+)
+
+
+class LibraryNotBuilt(RuntimeError):
+    pass
+
+
+class LogmError(RuntimeError):
+    def __init__(self, code: int, where: str, detail: int = 0):
+        self.code = code
+        self.status = STATUS.get(code, str(code))
+        msg = f"{where}: {self.status}"
+        if detail:
+            msg += f" (hipError {detail})"
+        super().__init__(msg)
+
+
+class LogmOpts(ctypes.Structure):
+    _fields_ = [
+        ("k_max", ctypes.c_int32),
+        ("max_sqrt", ctypes.c_int32),
+        ("db_max_iter", ctypes.c_int32),
+        ("theta_source", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 4),
+    ]
+
+
+class LogmInfo(ctypes.Structure):
+    _fields_ = [
+        ("s", ctypes.c_int32),
+        ("k", ctypes.c_int32),
+        ("m", ctypes.c_int32),
+        ("n_inv", ctypes.c_int32),
+        ("n_gemm", ctypes.c_int32),
+        ("n_matvec", ctypes.c_int32),
+        ("n_est", ctypes.c_int32),
+        ("db_iters", ctypes.c_int32 * 64),
+        ("flops", ctypes.c_double),
+        ("norm1_b", ctypes.c_double),
+        ("norm1_b2", ctypes.c_double),
+        ("status_detail", ctypes.c_int32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {
+            "s": self.s,
+            "k": self.k,
+            "m": self.m,
+            "n_inv": self.n_inv,
+            "n_gemm": self.n_gemm,
+            "n_matvec": self.n_matvec,
+            "n_est": self.n_est,
+            "db_iters": [int(self.db_iters[i]) for i in range(self.s)],
+            "flops": self.flops,
+            "norm1_b": self.norm1_b,
+            "norm1_b2": self.norm1_b2,
+        }
+
+
+_LIB = None
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_f64 = ctypes.c_double
+_sz = ctypes.c_size_t
+
+
+def load_library(path: str = LIB_PATH):
+    """Load liblogm.so and declare the C signatures (raises if absent)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise LibraryNotBuilt(
+            f"{path} is missing: build the HIP library first (python -c 'import __graft_entry__ as g; g.build()')")
+    lib = ctypes.CDLL(path)
+    sig = {
+        "logm_default_opts": (None, [ctypes.POINTER(LogmOpts)]),
+        "logm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "logm_workspace_size": (ctypes.c_int, [_i32, _i64, ctypes.POINTER(LogmOpts), ctypes.POINTER(_sz)]),
+        "logm_forward": (ctypes.c_int, [_i32, _i64, _vp, _i64, _vp, _i64, ctypes.POINTER(LogmOpts),
+                                        ctypes.POINTER(LogmInfo), _vp, _sz, _vp]),
+        "logm_gemm_f64": (ctypes.c_int, [_i64, _i64, _i64, _f64, _vp, _i64, _vp, _i64, _f64, _vp, _i64, _vp]),
+        "logm_inverse_f64": (ctypes.c_int, [_i64, _vp, _i64, _vp, _i64, ctypes.POINTER(_f64), _vp, _sz, _vp]),
+        "logm_sqrt_f64": (ctypes.c_int, [_i64, _vp, _i64, _vp, _i64, _i32, ctypes.POINTER(_i32), _vp, _sz, _vp]),
+        "logm_poly_f64": (ctypes.c_int, [_i64, _i32, _i32, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _sz, _vp]),
+        "logm_normest_f64": (ctypes.c_int, [_i64, _vp, _i64, _vp, _i64, _i32, _i32, ctypes.POINTER(_f64),
+                                            ctypes.POINTER(_i32), _vp, _sz, _vp]),
+        "logm_scheme": (ctypes.c_int, [_i32, _i32, ctypes.POINTER(_f64), ctypes.POINTER(_f64),
+                                       ctypes.POINTER(_f64), ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                                       ctypes.POINTER(_f64)]),
+        "logm_profile_enable": (None, [_i32]),
+        "logm_profile_reset": (None, []),
+        "logm_profile_get": (ctypes.c_int, [ctypes.POINTER(_i64), ctypes.POINTER(_f64),
+                                            ctypes.POINTER(_f64), ctypes.POINTER(_f64)]),
+        "logm_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _LIB = lib
+    return lib
+
+
+def lib():
+    return load_library()
+
+
+def _check(rc: int, where: str, detail: int = 0):
+    if rc != 0:
+        raise LogmError(rc, where, detail)
+
+
+# ------------------------------------------------------------ host tables ---
+def default_opts() -> LogmOpts:
+    o = LogmOpts()
+    lib().logm_default_opts(ctypes.byref(o))
+    return o
+
+
+def strerror(code: int) -> str:
+    return lib().logm_strerror(code).decode()
+
+
+def version() -> str:
+    return lib().logm_version().decode()
+
+
+def workspace_size(n: int, opts: LogmOpts | None = None) -> int:
+    b = _sz(0)
+    _check(lib().logm_workspace_size(LOGM_R64, n, ctypes.byref(opts) if opts else None, ctypes.byref(b)),
+           "logm_workspace_size")
+    return b.value
+
+
+def scheme(k: int, theta_source: int = 0):
+    """(h, g, y, m_k, Theta) as the library holds them."""
+    h = (_f64 * 32)()
+    g = (_f64 * 32)()
+    y = (_f64 * 16)()
+    nh = _i32(0)
+    m = _i32(0)
+    th = _f64(0)
+    _check(lib().logm_scheme(k, theta_source, h, g, y, ctypes.byref(nh), ctypes.byref(m), ctypes.byref(th)),
+           "logm_scheme")
+    return list(h[: nh.value]), list(g[: nh.value]), list(y[: k + 2]), m.value, th.value
+
+
+def profile_enable(on: bool = True):
+    lib().logm_profile_enable(1 if on else 0)
+
+
+def profile_reset():
+    lib().logm_profile_reset()
+
+
+def profile_get() -> dict:
+    n = _i64(0)
+    ms = _f64(0)
+    fl = _f64(0)
+    by = _f64(0)
+    lib().logm_profile_get(ctypes.byref(n), ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(by))
+    return {"launches": n.value, "ms": ms.value, "flops": fl.value, "bytes": by.value}
+
+
+# ------------------------------------------------------------ device calls ---
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(t):
+    torch = _torch()
+    return _vp(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _as_matrix(A, name="A"):
+    torch = _torch()
+    if not isinstance(A, torch.Tensor) or A.device.type != "cuda":
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+    if A.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64 (complex input is not built)")
+    if A.dim() != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError(f"{name} must be a square matrix")
+    if A.stride(1) != 1:
+        A = A.contiguous()
+    return A
+
+
+def _workspace(n: int, device, workspace=None):
+    torch = _torch()
+    need = workspace_size(n)
+    if workspace is not None:
+        if workspace.numel() * workspace.element_size() < need:
+            raise ValueError(f"workspace needs {need} bytes")
+        return workspace
+    return torch.empty(need, dtype=torch.uint8, device=device)
+
+
+def logm(A, k_max: int = 5, max_sqrt: int = 50, db_max_iter: int = 30, theta_source: int = 0,
+         out=None, workspace=None):
+    """L = log(A) on the GPU (Algorithm 1).  Returns (L, info dict)."""
+    torch = _torch()
+    A = _as_matrix(A)
+    n = A.shape[0]
+    L = out if out is not None else torch.empty((n, n), dtype=torch.float64, device=A.device)
+    o = default_opts()
+    o.k_max, o.max_sqrt, o.db_max_iter, o.theta_source = k_max, max_sqrt, db_max_iter, theta_source
+    ws = _workspace(n, A.device, workspace)
+    info = LogmInfo()
+    rc = lib().logm_forward(LOGM_R64, n, _vp(A.data_ptr()), A.stride(0), _vp(L.data_ptr()), L.stride(0),
+                            ctypes.byref(o), ctypes.byref(info), _vp(ws.data_ptr()), ws.numel(),
+                            _stream_ptr(A))
+    _check(rc, "logm_forward", info.status_detail)
+    return L, info.as_dict()
+
+
+def gemm(A, B, C=None, alpha: float = 1.0, beta: float = 0.0):
+    torch = _torch()
+    if A.stride(1) != 1:
+        A = A.contiguous()
+    if B.stride(1) != 1:
+        B = B.contiguous()
+    m, k = A.shape
+    k2, n = B.shape
+    if k != k2:
+        raise ValueError("inner dimensions differ")
+    if C is None:
+        C = torch.zeros((m, n), dtype=torch.float64, device=A.device)
+    rc = lib().logm_gemm_f64(m, n, k, alpha, _vp(A.data_ptr()), A.stride(0), _vp(B.data_ptr()), B.stride(0),
+                             beta, _vp(C.data_ptr()), C.stride(0), _stream_ptr(A))
+    _check(rc, "logm_gemm_f64")
+    return C
+
+
+def inverse(A, workspace=None):
+    """(A^{-1}, log|det A|) by Gauss-Jordan with tournament pivoting."""
+    torch = _torch()
+    A = _as_matrix(A)
+    n = A.shape[0]
+    Ai = torch.empty_like(A)
+    ld = _f64(0)
+    ws = _workspace(n, A.device, workspace)
+    rc = lib().logm_inverse_f64(n, _vp(A.data_ptr()), A.stride(0), _vp(Ai.data_ptr()), Ai.stride(0),
+                                ctypes.byref(ld), _vp(ws.data_ptr()), ws.numel(), _stream_ptr(A))
+    _check(rc, "logm_inverse_f64")
+    return Ai, ld.value
+
+
+def sqrtm(A, db_max_iter: int = 30, workspace=None):
+    """(A^{1/2}, iterations) by the scaled Denman-Beavers iteration."""
+    torch = _torch()
+    A = _as_matrix(A)
+    n = A.shape[0]
+    X = torch.empty_like(A)
+    it = _i32(0)
+    ws = _workspace(n, A.device, workspace)
+    rc = lib().logm_sqrt_f64(n, _vp(A.data_ptr()), A.stride(0), _vp(X.data_ptr()), X.stride(0), db_max_iter,
+                             ctypes.byref(it), _vp(ws.data_ptr()), ws.numel(), _stream_ptr(A))
+    _check(rc, "logm_sqrt_f64")
+    return X, it.value
+
+
+def poly(B, B2, k: int, s: int = 0, workspace=None):
+    """-2^s S_k(-B) with P_3 = B2."""
+    torch = _torch()
+    B = _as_matrix(B, "B")
+    B2 = _as_matrix(B2, "B2")
+    n = B.shape[0]
+    L = torch.empty_like(B)
+    ws = _workspace(n, B.device, workspace)
+    rc = lib().logm_poly_f64(n, k, s, _vp(B.data_ptr()), B.stride(0), _vp(B2.data_ptr()), B2.stride(0),
+                             _vp(L.data_ptr()), L.stride(0), _vp(ws.data_ptr()), ws.numel(), _stream_ptr(B))
+    _check(rc, "logm_poly_f64")
+    return L
+
+
+def normest(B2, B, q: int, r: int, workspace=None):
+    """(estimate of ||B2^q B^r||_1, matrix-vector products used)."""
+    B = _as_matrix(B, "B")
+    B2 = _as_matrix(B2, "B2")
+    n = B.shape[0]
+    est = _f64(0)
+    nmv = _i32(0)
+    ws = _workspace(n, B.device, workspace)
+    rc = lib().logm_normest_f64(n, _vp(B2.data_ptr()), B2.stride(0), _vp(B.data_ptr()), B.stride(0), q, r,
+                                ctypes.byref(est), ctypes.byref(nmv), _vp(ws.data_ptr()), ws.numel(),
+                                _stream_ptr(B))
+    _check(rc, "logm_normest_f64")
+    return est.value, nmv.value

@@ -1,0 +1,1042 @@
+// Host driver and C ABI of the logm library: Algorithm 1 of Jarlebring, Sastre and
+// Ibanez (Section 6) on top of the gfx950 kernels.  Every O(n^3) and O(n^2) step runs
+// on the GPU; the host only takes the data-dependent decisions (number of roots,
+// Denman-Beavers stopping, the 1-norm estimator's control flow and the degree
+// selection) from scalars it reads back.
+//
+// Readings of points the paper leaves open (shared with the test oracle, which
+// implements them separately):
+//  * schemes k in {1,2,3,5}: k = 1, 2 are T_2, T_4; k = 3 solves eq. eqP8pol for
+//    T_8 (root with the smaller coefficients); k = 5 is Table 1.  "m_9" of
+//    Algorithm 1 is read as m_{k_max}.
+//  * B^2 is formed once at s = 0 before the scaling loop.
+//  * Denman-Beavers stops when rel = ||X'-X||/||X'|| <= sqrt(n) u, or (scaling off,
+//    rel < 1e-6, rel > rel_prev/2); scaling is switched off once rel < 1e-2.
+//  * 1-norm estimates: deterministic Hager-Higham estimator, one column.
+//  * degree selection as described in select_degree().
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "kernels.hpp"
+#include "logm.h"
+
+namespace logm {
+namespace {
+
+constexpr double kU = 1.1102230246251565e-16;  // 2^-53
+constexpr int kNB = 64;
+constexpr int kNBO = 256;
+constexpr int kMats = 11;
+
+// ------------------------------------------------------------ constants ---
+// Table 2: k -> (m_k, Theta_{m_k}).
+struct ThetaRow {
+  int m;
+  double theta;
+};
+const ThetaRow kTable2[10] = {{0, 0.0},     {2, 1.83e-8},  {4, 1.53e-4},
+                              {8, 1.33e-2}, {14, 9.31e-2}, {14, 2.46e-1},
+                              {20, 3.72e-1}, {24, 5.86e-1}, {27, 6.69e-1},
+                              {28, 7.28e-1}};
+const int kTabmin[9] = {1, 2, 3, 4, 4, 5, 5, 6, 6};
+constexpr double kTheta5Recomputed = 0.2448;
+
+struct Scheme {
+  int k = 0;
+  std::vector<std::vector<double>> h, g;  // h[j-2]: coefficients on P_2..P_{j+1}
+  std::vector<double> y;                  // y[q-1]: weight of P_q
+};
+
+Scheme make_scheme(int k) {
+  Scheme s;
+  s.k = k;
+  if (k == 1) {
+    s.y = {0.0, 1.0, 0.5};  // T_2 = x + x^2/2
+  } else if (k == 2) {
+    s.h = {{0.0, 1.0}};  // P4 = x^2 (x/3 + x^2/4)
+    s.g = {{1.0 / 3.0, 0.25}};
+    s.y = {0.0, 1.0, 0.5, 1.0};
+  } else if (k == 3) {
+    // eq. eqP8pol for T_8: P4 = x^2 (c3 x + c4 x^2),
+    // P5 = (d1 x + d2 x^2 + P4)(e2 x^2 + P4), z = x + x^2/2 + e0 P4 + P5.
+    // Matching x^8..x^3 with 1/8..1/3: c4^2 = 1/8, 2 c3 c4 = 1/7,
+    // c3^2 + c4 (d2 + e2) = 1/6, c3 (d2 + e2) + c4 d1 = 1/5,
+    // c3 d1 + d2 e2 + c4 e0 = 1/4, d1 e2 + c3 e0 = 1/3.
+    // Solved in long double so that each coefficient is rounded to double once.
+    typedef long double ld;
+    const ld c4 = std::sqrt((ld)0.125L);
+    const ld c3 = 1.0L / (14.0L * c4);
+    const ld sum_de = (1.0L / 6.0L - c3 * c3) / c4;
+    const ld d1 = (0.2L - c3 * sum_de) / c4;
+    // eliminate d2 = sum_de - e2 and e0 = (1/3 - d1 e2)/c3:
+    // e2^2 - e2 (sum_de - c4 d1/c3) - (c3 d1 + c4/(3 c3) - 1/4) = 0
+    const ld bq = sum_de - c4 * d1 / c3;
+    const ld cq = c3 * d1 + c4 / (3.0L * c3) - 0.25L;
+    const ld e2 = 0.5L * (bq + std::sqrt(bq * bq + 4.0L * cq));
+    const ld d2 = sum_de - e2;
+    const ld e0 = (1.0L / 3.0L - d1 * e2) / c3;
+    s.h = {{0.0, 1.0}, {(double)d1, (double)d2, 1.0}};
+    s.g = {{(double)c3, (double)c4}, {0.0, (double)e2, 1.0}};
+    s.y = {0.0, 1.0, 0.5, (double)e0, 1.0};
+  } else if (k == 5) {
+    // Table 1
+    s.h = {{7.363757032799957e-02, -1.050281301619960e+00},
+           {8.897468955192446e-02, -1.599651928992725e-01, 9.577281350989334e-01},
+           {5.394999133948797e-01, 6.700731102561937e-02, -5.158769100223212e-02,
+            1.094308587350110e+00},
+           {1.027072285939197e-01, -8.964023050065877e-03, -2.100705663612491e-01,
+            1.949655359168707e-01, 1.117368056772713e+00}};
+    s.g = {{-9.666134174379001e-01, -4.395519034717933e-01},
+           {1.048664069004776e-01, 1.585606124033259e-01, 1.668066506920988e-01},
+           {-8.025600931705978e-02, -1.159854366397558e-01, 1.066554944706011e-01,
+            1.127094008297975e+00},
+           {2.702180425508705e-01, 4.137541209720699e-02, 4.857347452405025e-01,
+            -6.000256005636980e-01, 1.063393233943084e+00}};
+    s.y = {0.0, 1.0, 5.065546620208965e-01, 3.832512052972577e-01, 1.088307723749078e+00,
+           2.787461897212877e-01, 8.157421998489228e-01};
+  }
+  return s;
+}
+
+const Scheme& scheme(int k) {
+  static const Scheme s1 = make_scheme(1), s2 = make_scheme(2), s3 = make_scheme(3),
+                      s5 = make_scheme(5);
+  switch (k) {
+    case 1: return s1;
+    case 2: return s2;
+    case 3: return s3;
+    default: return s5;
+  }
+}
+
+bool shipped(int k) { return k == 1 || k == 2 || k == 3 || k == 5; }
+
+struct ThetaTable {
+  int m[10];
+  double th[10];
+};
+
+ThetaTable theta_table(int source) {
+  ThetaTable t;
+  for (int k = 0; k < 10; ++k) {
+    t.m[k] = kTable2[k].m;
+    t.th[k] = kTable2[k].theta;
+  }
+  if (source == 1) t.th[5] = kTheta5Recomputed;
+  return t;
+}
+
+// ------------------------------------------------------------ profiling ---
+struct Profiler {
+  bool on = false;
+  int64_t launches = 0;
+  double ms = 0.0, flops = 0.0, bytes = 0.0;
+  struct Pending {
+    hipEvent_t a, b;
+    double flops, bytes;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  void harvest() {
+    for (auto& p : pending) {
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, p.a, p.b) == hipSuccess) {
+        ms += t;
+        launches += 1;
+        flops += p.flops;
+        bytes += p.bytes;
+      }
+      pool.push_back(p.a);
+      pool.push_back(p.b);
+    }
+    pending.clear();
+  }
+};
+Profiler g_prof;
+
+// ------------------------------------------------------------ workspace ---
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Plan {
+  int n = 0, n_pad = 0, nblk = 0;
+  size_t mat[kMats];
+  size_t panel[2][2];
+  size_t W[2];
+  size_t logdet[2];
+  size_t pi[2], ptot[2], pinv[2], qsel[2], vac[2], cand[2], cnt[2], err[2];
+  size_t part, bm, vec, scal, iflag;
+  size_t total = 0;
+};
+
+Plan make_plan(int64_t n) {
+  Plan p;
+  p.n = (int)n;
+  p.n_pad = (int)((n + kNB - 1) / kNB * kNB);
+  p.nblk = (int)std::min<int64_t>(n, 256);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes, 256);
+    return o;
+  };
+  const size_t np = (size_t)p.n_pad;
+  for (int i = 0; i < kMats; ++i) p.mat[i] = take(np * np * sizeof(double));
+  for (int z = 0; z < 2; ++z) {
+    for (int b = 0; b < 2; ++b) p.panel[z][b] = take(np * kNBO * sizeof(double));
+    p.W[z] = take(3 * kNB * kNB * sizeof(double));
+    p.logdet[z] = take(np / kNB * sizeof(double));
+    p.pi[z] = take(np * sizeof(int));
+    p.ptot[z] = take(np * sizeof(int));
+    p.pinv[z] = take(np * sizeof(int));
+    p.qsel[z] = take(kNB * sizeof(int));
+    p.vac[z] = take(130 * sizeof(int));
+    p.cand[z] = take((size_t)gje_cand_ints(p.n_pad) * sizeof(int));
+    p.cnt[z] = take((size_t)gje_cnt_ints(p.n_pad) * sizeof(int));
+    p.err[z] = take(4 * sizeof(int));
+  }
+  p.part = take(2 * (size_t)p.nblk * np * sizeof(double));
+  p.bm = take(2 * (np / 256 + 2) * sizeof(double));
+  p.vec = take(4 * np * sizeof(double));
+  p.scal = take(16 * sizeof(double));
+  p.iflag = take(16 * sizeof(int));
+  p.total = off;
+  return p;
+}
+
+struct Status {
+  int code = LOGM_OK;
+  int detail = 0;
+};
+
+#define HIPCK(expr)                             \
+  do {                                          \
+    hipError_t e_ = (expr);                     \
+    if (e_ != hipSuccess) {                     \
+      st.code = LOGM_EHIP;                      \
+      st.detail = (int)e_;                      \
+      return st;                                \
+    }                                           \
+  } while (0)
+
+#define PROPAGATE(expr)          \
+  do {                           \
+    Status s_ = (expr);          \
+    if (s_.code != LOGM_OK) {    \
+      return s_;                 \
+    }                            \
+  } while (0)
+
+struct Ctx {
+  hipStream_t s = nullptr;
+  Plan p;
+  char* base = nullptr;
+  double* mat(int i) const { return reinterpret_cast<double*>(base + p.mat[i]); }
+  template <class T>
+  T* at(size_t off) const {
+    return reinterpret_cast<T*>(base + off);
+  }
+  double* part() const { return at<double>(p.part); }
+  double* scal() const { return at<double>(p.scal); }
+  int* iflag() const { return at<int>(p.iflag); }
+};
+
+Status sync_read(Ctx& c, void* host, const void* dev, size_t bytes) {
+  Status st;
+  HIPCK(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, c.s));
+  HIPCK(hipStreamSynchronize(c.s));
+  if (g_prof.on) g_prof.harvest();
+  return st;
+}
+
+// Exact 1-norm of the valid block of a padded matrix.
+Status norm1(Ctx& c, const double* M, double* out) {
+  Status st;
+  HIPCK(launch_abs_colsum(M, c.p.n, c.p.n_pad, c.part(), c.p.nblk, c.s));
+  HIPCK(launch_colsum_max(c.part(), 1, c.p.nblk, c.p.n, c.scal() + 4, c.at<double>(c.p.bm), c.s));
+  PROPAGATE(sync_read(c, out, c.scal() + 4, sizeof(double)));
+  return st;
+}
+
+// ------------------------------------------------------- Gauss-Jordan ----
+GjeArgs gje_args(Ctx& c, int nmat) {
+  GjeArgs a{};
+  a.nmat = nmat;
+  a.n_pad = c.p.n_pad;
+  for (int z = 0; z < nmat; ++z) {
+    GjeMat& m = a.m[z];
+    m.P[0] = c.at<double>(c.p.panel[z][0]);
+    m.P[1] = c.at<double>(c.p.panel[z][1]);
+    m.tri = c.at<double>(c.p.W[z]);
+    m.pi = c.at<int>(c.p.pi[z]);
+    m.ptot = c.at<int>(c.p.ptot[z]);
+    m.pinv = c.at<int>(c.p.pinv[z]);
+    m.qsel = c.at<int>(c.p.qsel[z]);
+    m.vac = c.at<int>(c.p.vac[z]);
+    m.cand = c.at<int>(c.p.cand[z]);
+    m.cnt = c.at<int>(c.p.cnt[z]);
+    m.logdet = c.at<double>(c.p.logdet[z]);
+    m.err = c.at<int>(c.p.err[z]);
+  }
+  return a;
+}
+
+// Invert nmat padded matrices src[z] (identity on the pad).  The permuted result is
+// left in fin[z]; pinv, logdet slots and error flags are in the workspace.
+Status gje_invert(Ctx& c, int nmat, const double* const src[2], double* fin[2]) {
+  Status st;
+  GjeArgs a = gje_args(c, nmat);
+  HIPCK(launch_gje_begin(a, c.s));
+  const int np = c.p.n_pad;
+  const double* cur[2] = {src[0], nmat > 1 ? src[1] : nullptr};
+  int flip = 0;
+  for (int k0 = 0; k0 < np; k0 += kNBO) {
+    const int nbo = std::min(kNBO, np - k0);
+    a.k0 = k0;
+    a.nbo = nbo;
+    a.pcur = 0;
+    for (int z = 0; z < nmat; ++z) {
+      a.m[z].Min = cur[z];
+      a.m[z].Mout = c.mat(5 + 2 * z + flip);
+    }
+    HIPCK(launch_gje_panel_copy(a, c.s));
+    for (int c0 = 0; c0 < nbo; c0 += kNB) {
+      a.c0 = c0;
+      a.r0 = k0 + c0;
+      HIPCK(launch_gje_tournament(a, c.s));
+      HIPCK(launch_gje_inner_update(a, c.s));
+      a.pcur ^= 1;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (g_prof.on) {
+      e0 = g_prof.get();
+      e1 = g_prof.get();
+      if (e0) HIPCK(hipEventRecord(e0, c.s));
+    }
+    HIPCK(launch_gje_outer_update(a, c.s));
+    if (g_prof.on && e0 && e1) {
+      HIPCK(hipEventRecord(e1, c.s));
+      const double npd = np;
+      g_prof.pending.push_back({e0, e1, nmat * 2.0 * npd * (npd - nbo) * nbo,
+                                nmat * 8.0 * (2.0 * npd * npd + npd * nbo)});
+    }
+    for (int z = 0; z < nmat; ++z) cur[z] = a.m[z].Mout;
+    flip ^= 1;
+  }
+  HIPCK(launch_gje_finish(a, c.s));
+  for (int z = 0; z < nmat; ++z) fin[z] = const_cast<double*>(cur[z]);
+  return st;
+}
+
+Status check_gje_err(Ctx& c, int nmat) {
+  Status st;
+  int h[8] = {0};
+  for (int z = 0; z < nmat; ++z)
+    HIPCK(hipMemcpyAsync(h + 4 * z, c.at<int>(c.p.err[z]), 4 * sizeof(int), hipMemcpyDeviceToHost,
+                         c.s));
+  HIPCK(hipStreamSynchronize(c.s));
+  for (int z = 0; z < nmat; ++z)
+    if (h[4 * z] != 0) st.code = LOGM_ESINGULAR;
+  return st;
+}
+
+// ------------------------------------------------------ square root -----
+// Xout = X0^{1/2} by the scaled Denman-Beavers iteration, eq. ScalDB.  X0 and Xout
+// are padded n_pad x n_pad workspace matrices (identity on the pad); Y uses mat(1).
+Status db_sqrt(Ctx& c, const double* X0, double* Xout, int max_iter, int* iters, int* ninv) {
+  Status st;
+  const int n = c.p.n;
+  double* Y = c.mat(1);
+  bool scaled = true;
+  double rel_prev = INFINITY;
+  const double tol = std::sqrt((double)n) * kU;
+  double rel = INFINITY;
+  int it = 1;
+  for (; it <= max_iter; ++it) {
+    const int nmat = (it == 1) ? 1 : 2;
+    const double* Xcur = (it == 1) ? X0 : Xout;
+    const double* src[2] = {Xcur, Y};
+    double* fin[2] = {nullptr, nullptr};
+    PROPAGATE(gje_invert(c, nmat, src, fin));
+    *ninv += nmat;
+    DbArgs d{};
+    d.Xin = Xcur;
+    d.Xout = Xout;
+    d.Yin = (it == 1) ? nullptr : Y;
+    d.Yout = Y;
+    d.Xinv = fin[0];
+    d.Yinv = (it == 1) ? nullptr : fin[1];
+    d.px = c.at<int>(c.p.pinv[0]);
+    d.py = (it == 1) ? nullptr : c.at<int>(c.p.pinv[1]);
+    d.ldx = c.at<double>(c.p.logdet[0]);
+    d.ldy = (it == 1) ? nullptr : c.at<double>(c.p.logdet[1]);
+    d.nslots = c.p.n_pad / kNB;
+    d.n = n;
+    d.ld = c.p.n_pad;
+    d.scaled = scaled ? 1 : 0;
+    d.part = c.part();
+    d.mu_out = c.scal() + 8;
+    HIPCK(launch_db_update(d, c.p.nblk, c.s));
+    HIPCK(launch_colsum_max(c.part(), 2, c.p.nblk, n, c.scal(), c.at<double>(c.p.bm), c.s));
+    double h[2];
+    PROPAGATE(sync_read(c, h, c.scal(), 2 * sizeof(double)));
+    PROPAGATE(check_gje_err(c, nmat));
+    rel = h[0] / h[1];
+    if (!std::isfinite(rel)) {
+      st.code = LOGM_ENONFINITE;
+      return st;
+    }
+    if (rel < 1e-2) scaled = false;
+    if (rel <= tol || (!scaled && rel < 1e-6 && rel > rel_prev / 2.0)) {
+      *iters = it;
+      return st;
+    }
+    rel_prev = rel;
+  }
+  *iters = max_iter;
+  if (rel > 1e-6) st.code = LOGM_ENOCONV;
+  return st;
+}
+
+// --------------------------------------------------- 1-norm estimator ----
+struct Estimator {
+  Ctx& c;
+  const double* B2;
+  const double* B;
+  int nmv = 0;
+
+  // y = B2^q B^r x (adj = false) or y = (B2^q B^r)^T x (adj = true).
+  Status apply(const std::vector<double>& x, std::vector<double>& y, int q, int r, bool adj) {
+    Status st;
+    const int n = c.p.n;
+    const int64_t ld = c.p.n_pad;
+    double* v[2] = {c.at<double>(c.p.vec), c.at<double>(c.p.vec) + c.p.n_pad};
+    HIPCK(hipMemcpyAsync(v[0], x.data(), n * sizeof(double), hipMemcpyHostToDevice, c.s));
+    int cur = 0;
+    auto step = [&](const double* M, bool t) -> hipError_t {
+      hipError_t e = launch_gemv(M, ld, n, v[cur], v[cur ^ 1], t, c.part(), c.p.nblk, c.s);
+      cur ^= 1;
+      return e;
+    };
+    if (!adj) {
+      for (int i = 0; i < r; ++i) HIPCK(step(B, false));
+      for (int i = 0; i < q; ++i) HIPCK(step(B2, false));
+    } else {
+      for (int i = 0; i < q; ++i) HIPCK(step(B2, true));
+      for (int i = 0; i < r; ++i) HIPCK(step(B, true));
+    }
+    nmv += q + r;
+    y.resize(n);
+    PROPAGATE(sync_read(c, y.data(), v[cur], n * sizeof(double)));
+    return st;
+  }
+
+  // Hager's method with Higham's refinements: at most 5 sweeps starting from
+  // e/n, stop when the estimate does not grow, the sign vector repeats or the
+  // subgradient test holds; then try the alternating-sign vector.
+  Status estimate(int q, int r, double* est_out) {
+    Status st;
+    const int n = c.p.n;
+    std::vector<double> x(n, 1.0 / n), y, z, xi(n), xi_prev(n);
+    if (n == 1) {
+      x[0] = 1.0;
+      PROPAGATE(apply(x, y, q, r, false));
+      *est_out = std::fabs(y[0]);
+      return st;
+    }
+    double est = -1.0;
+    bool have_prev = false;
+    for (int it = 1; it <= 5; ++it) {
+      PROPAGATE(apply(x, y, q, r, false));
+      double ey = 0.0;
+      for (int i = 0; i < n; ++i) ey += std::fabs(y[i]);
+      if (it > 1 && ey <= est) break;
+      est = ey;
+      for (int i = 0; i < n; ++i) xi[i] = (y[i] >= 0.0) ? 1.0 : -1.0;
+      if (have_prev && xi == xi_prev) break;
+      PROPAGATE(apply(xi, z, q, r, true));
+      int j = 0;
+      double zmax = std::fabs(z[0]);
+      for (int i = 1; i < n; ++i)
+        if (std::fabs(z[i]) > zmax) {
+          zmax = std::fabs(z[i]);
+          j = i;
+        }
+      double ztx = 0.0;
+      for (int i = 0; i < n; ++i) ztx += z[i] * x[i];
+      if (it > 1 && zmax <= ztx) break;
+      std::fill(x.begin(), x.end(), 0.0);
+      x[j] = 1.0;
+      xi_prev = xi;
+      have_prev = true;
+    }
+    for (int i = 0; i < n; ++i) x[i] = ((i % 2) ? -1.0 : 1.0) * (1.0 + (double)i / (n - 1));
+    PROPAGATE(apply(x, y, q, r, false));
+    double ea = 0.0;
+    for (int i = 0; i < n; ++i) ea += std::fabs(y[i]);
+    ea = 2.0 * ea / (3.0 * n);
+    *est_out = std::max(est, ea);
+    return st;
+  }
+};
+
+// --------------------------------------------------- degree selection ----
+// Choose k among the shipped schemes <= k_max, following the procedure after
+// Algorithm 1: a lower index min_in from the estimates of the last scaling pass
+// (eqs. min_in, min_inp) or from ||B^2||^{1/2} with tabmin_im (eq. roughmin_in); an
+// upper index max_in from (||B^2||^{m/2} ||B||)^{1/(m+1)} (eqs.
+// alpharoughbound_even, roughmax_even); then candidates from min_in upward, with
+// estimates skipped whenever a bound already decides, and the "j+1" shortcut.
+Status select_degree(Estimator& est, const ThetaTable& T, const std::vector<int>& K, double n1,
+                     double n2, bool have_top, double e_top, bool have_top1, double e_top1,
+                     int* k_out, int* n_est) {
+  Status st;
+  const int ktop = K.back();
+  const int mtop = T.m[ktop];
+  const double sq2 = std::sqrt(n2);
+  auto first_pass = [&](double v) {
+    for (int j : K)
+      if (v <= T.th[j]) return j;
+    return ktop;
+  };
+  int min_in;
+  if (have_top) {
+    min_in = first_pass(std::pow(e_top, 1.0 / mtop));
+    if (have_top1) min_in = std::max(min_in, first_pass(std::pow(e_top1, 1.0 / (mtop + 1))));
+  } else {
+    const int r = first_pass(sq2);
+    const int t = kTabmin[r - 1];
+    min_in = K.front();
+    for (int j : K)
+      if (j <= t) min_in = j;
+    if (sq2 > T.th[1]) {
+      bool has2 = std::find(K.begin(), K.end(), 2) != K.end();
+      if (has2) min_in = std::max(min_in, 2);
+    } else {
+      min_in = K.front();
+    }
+  }
+  int max_in = ktop;
+  for (int j : K) {
+    const int m = T.m[j];
+    if (std::pow(std::pow(n2, m / 2.0) * n1, 1.0 / (m + 1)) <= T.th[j]) {
+      max_in = j;
+      break;
+    }
+  }
+  if (min_in >= max_in) {
+    *k_out = max_in;
+    return st;
+  }
+  size_t idx = std::find(K.begin(), K.end(), min_in) - K.begin();
+  while (K[idx] < max_in) {
+    const int j = K[idx];
+    const int nxt = K[idx + 1];
+    const double thj = T.th[j], thn = T.th[nxt];
+    const int m = T.m[j];
+    const int h = m / 2;
+    double e1, t1;
+    if (h == 1) {
+      e1 = n2;
+      t1 = sq2;
+    } else if (sq2 <= thj) {
+      e1 = std::pow(n2, h);
+      t1 = sq2;
+    } else {
+      PROPAGATE(est.estimate(h, 0, &e1));
+      ++*n_est;
+      t1 = std::pow(e1, 1.0 / m);
+    }
+    double alpha;
+    if (t1 > thn) {
+      alpha = t1;
+    } else {
+      const double tau = (t1 <= thj) ? thj : thn;
+      const double bound = std::pow(e1 * n1, 1.0 / (m + 1));
+      double t2;
+      if (bound <= tau) {
+        t2 = bound;
+      } else {
+        double e2;
+        PROPAGATE(est.estimate(h, 1, &e2));
+        ++*n_est;
+        t2 = std::pow(e2, 1.0 / (m + 1));
+      }
+      alpha = std::max(t1, t2);
+    }
+    if (alpha <= thj) {
+      *k_out = j;
+      return st;
+    }
+    if (alpha <= thn) {
+      *k_out = nxt;
+      return st;
+    }
+    ++idx;
+  }
+  *k_out = max_in;
+  return st;
+}
+
+// ------------------------------------------------------- polynomial -----
+// L = -2^s S_k(-B) with P_2 = -B and P_3 = B2 (eq. five_mult_degopt); L is the
+// caller's n x n matrix (ldl).  Accumulators live in the free workspace matrices.
+Status poly(Ctx& c, int k, int s, const double* B, const double* B2, double* L, int64_t ldl,
+            int* ngemm) {
+  Status st;
+  const Scheme& S = scheme(k);
+  const int n = c.p.n;
+  const int np = c.p.n_pad;
+  const double scale = -std::ldexp(1.0, s);
+  const int slots[9] = {0, 1, 2, 5, 6, 7, 8, 9, 10};
+  int* flag = c.iflag() + 1;
+  HIPCK(hipMemsetAsync(flag, 0, sizeof(int), c.s));
+  if (k == 1) {
+    LincombArgs la{};
+    la.P2 = B;
+    la.P3 = B2;
+    la.nout = 1;
+    la.out[0] = c.mat(slots[0]);
+    la.c1[0] = S.y[0];
+    la.c2[0] = -S.y[1];
+    la.c3[0] = S.y[2];
+    la.n = n;
+    la.ld = np;
+    HIPCK(launch_lincomb_init(la, c.s));
+    HIPCK(launch_scale_out(c.mat(slots[0]), np, L, ldl, n, scale, flag, c.s));
+  } else {
+    // accumulator t: L_j at 2(j-2), R_j at 2(j-2)+1, Z at 2(k-1)
+    auto Lacc = [&](int j) { return c.mat(slots[2 * (j - 2)]); };
+    auto Racc = [&](int j) { return c.mat(slots[2 * (j - 2) + 1]); };
+    double* Z = c.mat(slots[2 * (k - 1)]);
+    LincombArgs la{};
+    la.P2 = B;
+    la.P3 = B2;
+    la.n = n;
+    la.ld = np;
+    int t = 0;
+    for (int j = 2; j <= k; ++j) {
+      const auto& h = S.h[j - 2];
+      const auto& g = S.g[j - 2];
+      la.out[t] = Lacc(j);
+      la.c1[t] = 0.0;
+      la.c2[t] = -h[0];
+      la.c3[t] = h[1];
+      ++t;
+      la.out[t] = Racc(j);
+      la.c1[t] = 0.0;
+      la.c2[t] = -g[0];
+      la.c3[t] = g[1];
+      ++t;
+    }
+    la.out[t] = Z;
+    la.c1[t] = S.y[0];
+    la.c2[t] = -S.y[1];
+    la.c3[t] = S.y[2];
+    la.nout = t + 1;
+    HIPCK(launch_lincomb_init(la, c.s));
+    for (int j = 2; j <= k; ++j) {
+      PolyGemmArgs pa{};
+      pa.Lf = Lacc(j);
+      pa.Rf = Racc(j);
+      pa.ld = np;
+      int na = 0;
+      for (int jp = j + 1; jp <= k; ++jp) {
+        pa.acc[na] = Lacc(jp);
+        pa.coef[na++] = S.h[jp - 2][j];
+        pa.acc[na] = Racc(jp);
+        pa.coef[na++] = S.g[jp - 2][j];
+      }
+      if (j < k) {
+        pa.acc[na] = Z;
+        pa.coef[na++] = S.y[j + 1];
+        pa.dst = nullptr;
+      } else {
+        pa.dst = L;
+        pa.ldd = ldl;
+        pa.base = Z;
+        pa.ycoef = S.y[k + 1];
+        pa.scale = scale;
+        pa.nvalid = n;
+      }
+      pa.nacc = na;
+      HIPCK(launch_gemm_poly(np, pa, c.s));
+      ++*ngemm;
+    }
+    HIPCK(launch_check_finite(L, ldl, n, flag, c.s));
+  }
+  int h = 0;
+  PROPAGATE(sync_read(c, &h, flag, sizeof(int)));
+  if (h) st.code = LOGM_ENONFINITE;
+  return st;
+}
+
+// -------------------------------------------------------- Algorithm 1 ---
+Status forward_r64(Ctx& c, const double* A, int64_t lda, double* L, int64_t ldl,
+                   const logm_opts& o, logm_info& info) {
+  Status st;
+  const int n = c.p.n;
+  const int np = c.p.n_pad;
+  const ThetaTable T = theta_table(o.theta_source);
+  std::vector<int> K;
+  for (int k : {1, 2, 3, 5})
+    if (k <= o.k_max) K.push_back(k);
+  const int ktop = K.back();
+  const int mtop = T.m[ktop];
+  const double thtop = T.th[ktop];
+  const int htop = mtop / 2;
+
+  double* X = c.mat(0);
+  double* A2 = c.mat(2);
+  double* B = c.mat(3);
+  double* B2 = c.mat(4);
+  int* nonfinite = c.iflag();
+  HIPCK(hipMemsetAsync(nonfinite, 0, sizeof(int), c.s));
+  HIPCK(launch_load_padded(A, lda, X, n, np, 1.0, nonfinite, c.s));
+  int bad = 0;
+  PROPAGATE(sync_read(c, &bad, nonfinite, sizeof(int)));
+  if (bad) {
+    st.code = LOGM_ENONFINITE;
+    return st;
+  }
+  Estimator est{c, B2, B};
+  double n1, n2;
+  HIPCK(launch_shift(X, B, n, np, c.part(), c.p.nblk, c.s));
+  HIPCK(launch_colsum_max(c.part(), 1, c.p.nblk, n, c.scal() + 4, c.at<double>(c.p.bm), c.s));
+  HIPCK(launch_gemm_plain(np, np, np, 1.0, B, np, B, np, 0.0, B2, np, c.s));  // B^2 at s = 0
+  info.n_gemm += 1;
+  PROPAGATE(sync_read(c, &n1, c.scal() + 4, sizeof(double)));
+
+  int s = 0;
+  bool have_top = false, have_top1 = false;
+  double e_top = 0.0, e_top1 = 0.0;
+  bool finished = n1 <= thtop;
+  while (!finished && s < o.max_sqrt) {
+    have_top = have_top1 = false;
+    PROPAGATE(norm1(c, B2, &n2));
+    bool t1, t2 = false;
+    double base;
+    if (std::sqrt(n2) <= thtop) {  // eq. alpha2term1
+      t1 = true;
+      base = std::pow(n2, htop);
+    } else {
+      PROPAGATE(est.estimate(htop, 0, &e_top));
+      ++info.n_est;
+      have_top = true;
+      t1 = std::pow(e_top, 1.0 / mtop) <= thtop;
+      base = e_top;
+    }
+    if (t1) {  // eq. normAm9plus1
+      if (std::pow(base * n1, 1.0 / (mtop + 1)) <= thtop) {
+        t2 = true;
+      } else {
+        PROPAGATE(est.estimate(htop, 1, &e_top1));
+        ++info.n_est;
+        have_top1 = true;
+        t2 = std::pow(e_top1, 1.0 / (mtop + 1)) <= thtop;
+      }
+    }
+    finished = t1 && t2;
+    if (!finished) {
+      std::swap(X, A2);  // A2 keeps the matrix whose root is taken
+      int iters = 0;
+      PROPAGATE(db_sqrt(c, A2, X, o.db_max_iter, &iters, &info.n_inv));
+      info.db_iters[s] = iters;
+      ++s;
+      HIPCK(launch_shift(X, B, n, np, c.part(), c.p.nblk, c.s));
+      HIPCK(launch_colsum_max(c.part(), 1, c.p.nblk, n, c.scal() + 4, c.at<double>(c.p.bm), c.s));
+      HIPCK(launch_b2_from_root(A2, X, B2, n, np, c.part() + (size_t)c.p.nblk * np, c.p.nblk, c.s));
+      PROPAGATE(sync_read(c, &n1, c.scal() + 4, sizeof(double)));
+    }
+  }
+  if (!finished) {
+    st.code = LOGM_ENOCONV;
+    return st;
+  }
+  PROPAGATE(norm1(c, B2, &n2));
+  int k = ktop;
+  PROPAGATE(select_degree(est, T, K, n1, n2, have_top, e_top, have_top1, e_top1, &k, &info.n_est));
+  PROPAGATE(poly(c, k, s, B, B2, L, ldl, &info.n_gemm));
+  info.s = s;
+  info.k = k;
+  info.m = T.m[k];
+  info.n_matvec = est.nmv;
+  info.norm1_b = n1;
+  info.norm1_b2 = n2;
+  const double nd = n;
+  info.flops = 2.0 * nd * nd * nd * (info.n_inv + info.n_gemm) + 2.0 * nd * nd * info.n_matvec;
+  return st;
+}
+
+// -------------------------------------------------------- call wrapper ---
+struct Call {
+  Ctx c;
+  bool owned = false;
+  Status st;
+  Call(int64_t n, void* ws, size_t ws_bytes, void* stream) {
+    c.s = reinterpret_cast<hipStream_t>(stream);
+    c.p = make_plan(n);
+    if (ws == nullptr) {
+      void* mem = nullptr;
+      hipError_t e = hipMallocAsync(&mem, c.p.total, c.s);
+      if (e != hipSuccess) {
+        st.code = LOGM_EHIP;
+        st.detail = (int)e;
+        return;
+      }
+      owned = true;
+      c.base = static_cast<char*>(mem);
+    } else {
+      if (ws_bytes < c.p.total) {
+        st.code = LOGM_EWORKSPACE;
+        return;
+      }
+      c.base = static_cast<char*>(ws);
+    }
+  }
+  ~Call() {
+    if (owned) {
+      (void)hipFreeAsync(c.base, c.s);
+      (void)hipStreamSynchronize(c.s);
+    }
+  }
+};
+
+bool opts_ok(const logm_opts& o) {
+  if (!(o.k_max == 1 || o.k_max == 2 || o.k_max == 3 || o.k_max == 5)) return false;
+  if (o.max_sqrt < 0 || o.max_sqrt > 64) return false;
+  if (o.db_max_iter < 1 || o.db_max_iter > 1000) return false;
+  if (o.theta_source != 0 && o.theta_source != 1) return false;
+  for (int i = 0; i < 4; ++i)
+    if (o.reserved[i] != 0) return false;
+  return true;
+}
+
+}  // namespace
+}  // namespace logm
+
+using namespace logm;
+
+extern "C" {
+
+void logm_default_opts(logm_opts* o) {
+  if (o == nullptr) return;
+  std::memset(o, 0, sizeof(*o));
+  o->k_max = 5;
+  o->max_sqrt = 50;
+  o->db_max_iter = 30;
+  o->theta_source = 0;
+}
+
+const char* logm_strerror(int code) {
+  switch (code) {
+    case LOGM_OK: return "success";
+    case LOGM_EINVAL: return "invalid argument";
+    case LOGM_ENOTSUP: return "data type not supported";
+    case LOGM_EWORKSPACE: return "workspace too small";
+    case LOGM_ENONFINITE: return "non-finite value in input or result";
+    case LOGM_ESINGULAR: return "singular matrix";
+    case LOGM_ENOCONV: return "square-root iteration did not converge";
+    case LOGM_EHIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+const char* logm_version(void) { return "logm-mi355x 0.1 (gfx950)"; }
+
+int logm_workspace_size(int32_t dtype, int64_t n, const logm_opts* o, size_t* bytes) {
+  if (n < 1 || n > (int64_t)1 << 20 || bytes == nullptr) return LOGM_EINVAL;
+  if (dtype != LOGM_R64 && dtype != LOGM_C128) return LOGM_EINVAL;
+  if (o != nullptr && !opts_ok(*o)) return LOGM_EINVAL;
+  *bytes = make_plan(n).total;
+  return LOGM_OK;
+}
+
+int logm_forward(int32_t dtype, int64_t n, const void* A, int64_t lda, void* L, int64_t ldl,
+                 const logm_opts* o, logm_info* info, void* ws, size_t ws_bytes, void* stream) {
+  logm_opts opts;
+  logm_default_opts(&opts);
+  if (o != nullptr) opts = *o;
+  if (dtype != LOGM_R64 && dtype != LOGM_C128) return LOGM_EINVAL;
+  if (n < 1 || n > (int64_t)1 << 20 || A == nullptr || L == nullptr || lda < n || ldl < n)
+    return LOGM_EINVAL;
+  if (!opts_ok(opts)) return LOGM_EINVAL;
+  if (dtype == LOGM_C128) return LOGM_ENOTSUP;
+  logm_info local{};
+  logm_info& inf = (info != nullptr) ? *info : local;
+  std::memset(&inf, 0, sizeof(inf));
+  Call call(n, ws, ws_bytes, stream);
+  if (call.st.code != LOGM_OK) {
+    inf.status_detail = call.st.detail;
+    return call.st.code;
+  }
+  Status st = forward_r64(call.c, static_cast<const double*>(A), lda, static_cast<double*>(L),
+                          ldl, opts, inf);
+  inf.status_detail = st.detail;
+  return st.code;
+}
+
+int logm_gemm_f64(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_t lda,
+                  const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
+                  void* stream) {
+  if (m < 1 || n < 1 || k < 1 || m > INT32_MAX / 2 || n > INT32_MAX / 2 || k > INT32_MAX / 2)
+    return LOGM_EINVAL;
+  if (A == nullptr || B == nullptr || C == nullptr || lda < k || ldb < n || ldc < n)
+    return LOGM_EINVAL;
+  hipError_t e = launch_gemm_plain((int)m, (int)n, (int)k, alpha, A, lda, B, ldb, beta, C, ldc,
+                                   reinterpret_cast<hipStream_t>(stream));
+  return e == hipSuccess ? LOGM_OK : LOGM_EHIP;
+}
+
+int logm_inverse_f64(int64_t n, const double* A, int64_t lda, double* Ainv, int64_t ldi,
+                     double* logabsdet, void* ws, size_t ws_bytes, void* stream) {
+  if (n < 1 || n > (int64_t)1 << 20 || A == nullptr || Ainv == nullptr || lda < n || ldi < n)
+    return LOGM_EINVAL;
+  Call call(n, ws, ws_bytes, stream);
+  if (call.st.code != LOGM_OK) return call.st.code;
+  Ctx& c = call.c;
+  Status st = [&]() -> Status {
+    Status st;
+    int* nonfinite = c.iflag();
+    HIPCK(hipMemsetAsync(nonfinite, 0, sizeof(int), c.s));
+    HIPCK(launch_load_padded(A, lda, c.mat(0), c.p.n, c.p.n_pad, 1.0, nonfinite, c.s));
+    const double* src[2] = {c.mat(0), nullptr};
+    double* fin[2] = {nullptr, nullptr};
+    PROPAGATE(gje_invert(c, 1, src, fin));
+    HIPCK(launch_gje_unpermute(fin[0], c.at<int>(c.p.pinv[0]), c.p.n_pad, Ainv, ldi, c.p.n, c.s));
+    std::vector<double> slots(c.p.n_pad / kNB);
+    PROPAGATE(sync_read(c, slots.data(), c.at<double>(c.p.logdet[0]), slots.size() * sizeof(double)));
+    int bad = 0;
+    PROPAGATE(sync_read(c, &bad, nonfinite, sizeof(int)));
+    if (bad) {
+      st.code = LOGM_ENONFINITE;
+      return st;
+    }
+    PROPAGATE(check_gje_err(c, 1));
+    double sum = 0.0;
+    for (double v : slots) sum += v;
+    if (logabsdet != nullptr) *logabsdet = sum;
+    return st;
+  }();
+  return st.code;
+}
+
+int logm_sqrt_f64(int64_t n, const double* A, int64_t lda, double* X, int64_t ldx,
+                  int32_t db_max_iter, int32_t* iters, void* ws, size_t ws_bytes, void* stream) {
+  if (n < 1 || n > (int64_t)1 << 20 || A == nullptr || X == nullptr || lda < n || ldx < n ||
+      db_max_iter < 1 || db_max_iter > 1000)
+    return LOGM_EINVAL;
+  Call call(n, ws, ws_bytes, stream);
+  if (call.st.code != LOGM_OK) return call.st.code;
+  Ctx& c = call.c;
+  Status st = [&]() -> Status {
+    Status st;
+    int* nonfinite = c.iflag();
+    HIPCK(hipMemsetAsync(nonfinite, 0, 2 * sizeof(int), c.s));
+    HIPCK(launch_load_padded(A, lda, c.mat(2), c.p.n, c.p.n_pad, 1.0, nonfinite, c.s));
+    int it = 0, ninv = 0;
+    PROPAGATE(db_sqrt(c, c.mat(2), c.mat(0), db_max_iter, &it, &ninv));
+    HIPCK(launch_scale_out(c.mat(0), c.p.n_pad, X, ldx, c.p.n, 1.0, nonfinite + 1, c.s));
+    int bad[2] = {0, 0};
+    PROPAGATE(sync_read(c, bad, nonfinite, 2 * sizeof(int)));
+    if (bad[0] || bad[1]) st.code = LOGM_ENONFINITE;
+    if (iters != nullptr) *iters = it;
+    return st;
+  }();
+  return st.code;
+}
+
+int logm_poly_f64(int64_t n, int32_t k, int32_t s, const double* B, int64_t ldb, const double* B2,
+                  int64_t ldb2, double* L, int64_t ldl, void* ws, size_t ws_bytes, void* stream) {
+  if (n < 1 || n > (int64_t)1 << 20 || !shipped(k) || s < 0 || s > 64 || B == nullptr ||
+      B2 == nullptr || L == nullptr || ldb < n || ldb2 < n || ldl < n)
+    return LOGM_EINVAL;
+  Call call(n, ws, ws_bytes, stream);
+  if (call.st.code != LOGM_OK) return call.st.code;
+  Ctx& c = call.c;
+  Status st = [&]() -> Status {
+    Status st;
+    HIPCK(launch_load_padded(B, ldb, c.mat(3), c.p.n, c.p.n_pad, 0.0, nullptr, c.s));
+    HIPCK(launch_load_padded(B2, ldb2, c.mat(4), c.p.n, c.p.n_pad, 0.0, nullptr, c.s));
+    int ng = 0;
+    PROPAGATE(poly(c, k, s, c.mat(3), c.mat(4), L, ldl, &ng));
+    return st;
+  }();
+  return st.code;
+}
+
+int logm_normest_f64(int64_t n, const double* B2, int64_t ldb2, const double* B, int64_t ldb,
+                     int32_t q, int32_t r, double* est, int32_t* nmatvec, void* ws,
+                     size_t ws_bytes, void* stream) {
+  if (n < 1 || n > (int64_t)1 << 20 || B2 == nullptr || B == nullptr || ldb2 < n || ldb < n ||
+      q < 1 || q > 64 || r < 0 || r > 1 || est == nullptr)
+    return LOGM_EINVAL;
+  Call call(n, ws, ws_bytes, stream);
+  if (call.st.code != LOGM_OK) return call.st.code;
+  Ctx& c = call.c;
+  Status st = [&]() -> Status {
+    Status st;
+    HIPCK(launch_load_padded(B, ldb, c.mat(3), c.p.n, c.p.n_pad, 0.0, nullptr, c.s));
+    HIPCK(launch_load_padded(B2, ldb2, c.mat(4), c.p.n, c.p.n_pad, 0.0, nullptr, c.s));
+    Estimator e{c, c.mat(4), c.mat(3)};
+    PROPAGATE(e.estimate(q, r, est));
+    if (nmatvec != nullptr) *nmatvec = e.nmv;
+    return st;
+  }();
+  return st.code;
+}
+
+int logm_scheme(int32_t k, int32_t theta_source, double* h, double* g, double* y, int32_t* nh,
+                int32_t* m, double* theta) {
+  if (!shipped(k) || (theta_source != 0 && theta_source != 1)) return LOGM_EINVAL;
+  const Scheme& S = scheme(k);
+  int cnt = 0;
+  for (size_t j = 0; j < S.h.size(); ++j)
+    for (size_t i = 0; i < S.h[j].size(); ++i) {
+      if (h != nullptr) h[cnt] = S.h[j][i];
+      if (g != nullptr) g[cnt] = S.g[j][i];
+      ++cnt;
+    }
+  if (nh != nullptr) *nh = cnt;
+  if (y != nullptr)
+    for (size_t q = 0; q < S.y.size(); ++q) y[q] = S.y[q];
+  const ThetaTable T = theta_table(theta_source);
+  if (m != nullptr) *m = T.m[k];
+  if (theta != nullptr) *theta = T.th[k];
+  return LOGM_OK;
+}
+
+void logm_profile_enable(int32_t on) { g_prof.on = (on != 0); }
+
+void logm_profile_reset(void) {
+  g_prof.harvest();
+  g_prof.launches = 0;
+  g_prof.ms = g_prof.flops = g_prof.bytes = 0.0;
+}
+
+int logm_profile_get(int64_t* launches, double* ms_total, double* flops_total,
+                     double* bytes_total) {
+  g_prof.harvest();
+  if (launches) *launches = g_prof.launches;
+  if (ms_total) *ms_total = g_prof.ms;
+  if (flops_total) *flops_total = g_prof.flops;
+  if (bytes_total) *bytes_total = g_prof.bytes;
+  return LOGM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,325 @@
+// Bandwidth-bound kernels of the logm path (gfx950): the Denman-Beavers update
+// (eq. ScalDB) with the inverse's column order folded into its reads, the shifted
+// matrices B = X - I and B^2 = A_2 - 2X + I (eq. AI2), exact 1-norms through
+// deterministic column-sum partials, matrix-vector products for the 1-norm
+// estimator, and the linear combinations that seed the graph accumulators.
+//
+// Row-block kernels: workgroup b owns rows [b*rpb, (b+1)*rpb) and walks the columns
+// in chunks of 256 (one column per thread, coalesced), keeping per-column partial
+// sums in registers; partial sums are reduced in a fixed order, so every norm is
+// bitwise reproducible.
+#include <algorithm>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace logm {
+namespace {
+
+constexpr int TPB = 256;
+
+__device__ __forceinline__ void row_range(int n, int nblk, int& i0, int& i1) {
+  const int rpb = (n + nblk - 1) / nblk;
+  i0 = blockIdx.x * rpb;
+  i1 = min(n, i0 + rpb);
+}
+
+// Padded workspace matrices are n_pad x n_pad with the valid n x n block in the
+// corner; X-like matrices carry the identity on the pad and B-like ones zero, so
+// every matrix is block diagonal and the pad never mixes into the valid block.
+// Row-block kernels below write the whole padded range and sum norms over the
+// valid block only.
+
+__global__ __launch_bounds__(TPB) void db_update_kernel(DbArgs a, int nblk) {
+  __shared__ double s_mu;
+  const int n = a.n;
+  const int np = (int)a.ld;
+  if (threadIdx.x == 0) {
+    double sx = 0.0, sy = 0.0;
+    for (int t = 0; t < a.nslots; ++t) sx += a.ldx[t];
+    if (a.ldy != nullptr)
+      for (int t = 0; t < a.nslots; ++t) sy += a.ldy[t];
+    const double mu = a.scaled ? exp(-(sx + sy) / (2.0 * n)) : 1.0;
+    s_mu = mu;
+    if (blockIdx.x == 0) *a.mu_out = mu;
+  }
+  __syncthreads();
+  const double mu = s_mu;
+  int i0, i1;
+  row_range(np, nblk, i0, i1);
+  double* p0 = a.part + (int64_t)blockIdx.x * n;
+  double* p1 = a.part + (int64_t)(nblk + blockIdx.x) * n;
+  for (int c = threadIdx.x; c < np; c += TPB) {
+    const int qx = a.px[c];
+    const int qy = (a.py != nullptr) ? a.py[c] : -1;
+    double sdiff = 0.0, snew = 0.0;
+    for (int i = i0; i < i1; ++i) {
+      const int64_t o = (int64_t)i * a.ld;
+      if (i >= n || c >= n) {
+        const double d = (i == c) ? 1.0 : 0.0;
+        a.Xout[o + c] = d;
+        a.Yout[o + c] = d;
+        continue;
+      }
+      const double x = a.Xin[o + c];
+      const double y = (a.Yin != nullptr) ? a.Yin[o + c] : (i == c ? 1.0 : 0.0);
+      const double xi = a.Xinv[o + qx];
+      const double yi = (qy >= 0) ? a.Yinv[o + qy] : (i == c ? 1.0 : 0.0);
+      const double xn = 0.5 * (mu * x + yi / mu);
+      const double yn = 0.5 * (mu * y + xi / mu);
+      a.Xout[o + c] = xn;
+      a.Yout[o + c] = yn;
+      sdiff += fabs(xn - x);
+      snew += fabs(xn);
+    }
+    if (c < n) {
+      p0[c] = sdiff;
+      p1[c] = snew;
+    }
+  }
+}
+
+__global__ __launch_bounds__(TPB) void colsum_blockmax_kernel(const double* part, int nblk, int n,
+                                                              double* bm) {
+  __shared__ double s_red[TPB / 64];
+  const int q = blockIdx.y;
+  const int c = blockIdx.x * TPB + threadIdx.x;
+  double s = 0.0;
+  if (c < n) {
+    const double* p = part + (int64_t)q * nblk * n + c;
+    for (int b = 0; b < nblk; ++b) s += p[(int64_t)b * n];
+  }
+  s = wave_max(s);
+  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = s_red[0];
+    for (int w = 1; w < TPB / 64; ++w) m = fmax(m, s_red[w]);
+    bm[q * gridDim.x + blockIdx.x] = m;
+  }
+}
+
+__global__ void max_reduce_kernel(const double* bm, int nb, double* out) {
+  const int q = blockIdx.x;
+  double m = 0.0;
+  for (int t = threadIdx.x; t < nb; t += 64) m = fmax(m, bm[q * nb + t]);
+  m = wave_max(m);
+  if (threadIdx.x == 0) out[q] = m;
+}
+
+__global__ __launch_bounds__(TPB) void shift_kernel(const double* X, double* B, int n, int64_t ld,
+                                                    double* part, int nblk) {
+  const int np = (int)ld;
+  int i0, i1;
+  row_range(np, nblk, i0, i1);
+  double* p = part + (int64_t)blockIdx.x * n;
+  for (int c = threadIdx.x; c < np; c += TPB) {
+    double s = 0.0;
+    for (int i = i0; i < i1; ++i) {
+      const int64_t o = (int64_t)i * ld + c;
+      const double b = X[o] - (i == c ? 1.0 : 0.0);
+      B[o] = b;
+      if (i < n) s += fabs(b);
+    }
+    if (c < n) p[c] = s;
+  }
+}
+
+__global__ __launch_bounds__(TPB) void b2_kernel(const double* A2, const double* X, double* B2,
+                                                 int n, int64_t ld, double* part, int nblk) {
+  const int np = (int)ld;
+  int i0, i1;
+  row_range(np, nblk, i0, i1);
+  double* p = part + (int64_t)blockIdx.x * n;
+  for (int c = threadIdx.x; c < np; c += TPB) {
+    double s = 0.0;
+    for (int i = i0; i < i1; ++i) {
+      const int64_t o = (int64_t)i * ld + c;
+      const double v = A2[o] - 2.0 * X[o] + (i == c ? 1.0 : 0.0);
+      B2[o] = v;
+      if (i < n) s += fabs(v);
+    }
+    if (c < n) p[c] = s;
+  }
+}
+
+__global__ __launch_bounds__(TPB) void abs_colsum_kernel(const double* M, int n, int64_t ld,
+                                                         double* part, int nblk) {
+  int i0, i1;
+  row_range(n, nblk, i0, i1);
+  double* p = part + (int64_t)blockIdx.x * n;
+  for (int c = threadIdx.x; c < n; c += TPB) {
+    double s = 0.0;
+    for (int i = i0; i < i1; ++i) s += fabs(M[(int64_t)i * ld + c]);
+    p[c] = s;
+  }
+}
+
+__global__ void load_padded_kernel(const double* src, int64_t lds, double* dst, int n, int n_pad,
+                                   double padval, int* nonfinite) {
+  const int i = blockIdx.y;
+  bool bad = false;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n_pad; j += gridDim.x * blockDim.x) {
+    double v;
+    if (i < n && j < n) {
+      v = src[(int64_t)i * lds + j];
+      bad |= !isfinite(v);
+    } else {
+      v = (i == j) ? padval : 0.0;
+    }
+    dst[(int64_t)i * n_pad + j] = v;
+  }
+  if (bad && nonfinite != nullptr) atomicOr(nonfinite, 1);
+}
+
+__global__ void copy_kernel(const double* src, double* dst, size_t count) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+       e += (size_t)gridDim.x * blockDim.x)
+    dst[e] = src[e];
+}
+
+// y[i] = sum_c M[i][c] x[c]: one wave per row.
+__global__ __launch_bounds__(TPB) void gemv_n_kernel(const double* M, int64_t ld, int n,
+                                                     const double* x, double* y) {
+  const int row = blockIdx.x * (TPB / 64) + (threadIdx.x >> 6);
+  if (row >= n) return;
+  const int lane = threadIdx.x & 63;
+  const double* r = M + (int64_t)row * ld;
+  double s = 0.0;
+  for (int c = lane; c < n; c += 64) s = fma(r[c], x[c], s);
+  s = wave_sum(s);
+  if (lane == 0) y[row] = s;
+}
+
+// partial z over a row block: part[b][c] = sum_{i in block b} M[i][c] x[i]
+__global__ __launch_bounds__(TPB) void gemv_t_part_kernel(const double* M, int64_t ld, int n,
+                                                          const double* x, double* part, int nblk) {
+  int i0, i1;
+  row_range(n, nblk, i0, i1);
+  const int c = blockIdx.y * TPB + threadIdx.x;
+  if (c >= n) return;
+  double s = 0.0;
+  for (int i = i0; i < i1; ++i) s = fma(M[(int64_t)i * ld + c], x[i], s);
+  part[(int64_t)blockIdx.x * n + c] = s;
+}
+
+__global__ void gemv_t_reduce_kernel(const double* part, int nblk, int n, double* z) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * n + c];
+  z[c] = s;
+}
+
+__global__ void lincomb_init_kernel(LincombArgs a) {
+  const int i = blockIdx.y;
+  const int np = (int)a.ld;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < np; j += gridDim.x * blockDim.x) {
+    const int64_t o = (int64_t)i * a.ld + j;
+    const bool valid = i < a.n && j < a.n;
+    const double p2 = valid ? a.P2[o] : 0.0;
+    const double p3 = valid ? a.P3[o] : 0.0;
+    const double d = (valid && i == j) ? 1.0 : 0.0;
+    for (int t = 0; t < a.nout; ++t) a.out[t][o] = a.c2[t] * p2 + a.c3[t] * p3 + a.c1[t] * d;
+  }
+}
+
+__global__ void scale_out_kernel(const double* src, int64_t ld, double* dst, int64_t ldd, int n,
+                                 double scale, int* nonfinite) {
+  const int i = blockIdx.y;
+  bool bad = false;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+    const double v = scale * src[(int64_t)i * ld + j];
+    bad |= !isfinite(v);
+    dst[(int64_t)i * ldd + j] = v;
+  }
+  if (bad && nonfinite != nullptr) atomicOr(nonfinite, 1);
+}
+
+__global__ void check_finite_kernel(const double* M, int64_t ld, int n, int* flag) {
+  const int i = blockIdx.y;
+  bool bad = false;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x)
+    bad |= !isfinite(M[(int64_t)i * ld + j]);
+  if (bad) atomicOr(flag, 1);
+}
+
+inline dim3 row_grid(int n, int rows) { return dim3((unsigned)std::min(8, (n + 255) / 256), (unsigned)rows); }
+
+}  // namespace
+
+hipError_t launch_db_update(const DbArgs& a, int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(db_update_kernel, dim3(nblk), dim3(TPB), 0, s, a, nblk);
+  return hipGetLastError();
+}
+
+hipError_t launch_colsum_max(const double* part, int nq, int nblk, int n, double* out,
+                             double* bm, hipStream_t s) {
+  const int gx = (n + TPB - 1) / TPB;
+  hipLaunchKernelGGL(colsum_blockmax_kernel, dim3(gx, nq), dim3(TPB), 0, s, part, nblk, n, bm);
+  hipLaunchKernelGGL(max_reduce_kernel, dim3(nq), dim3(64), 0, s, bm, gx, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_shift(const double* X, double* B, int n, int64_t ld, double* part, int nblk,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(shift_kernel, dim3(nblk), dim3(TPB), 0, s, X, B, n, ld, part, nblk);
+  return hipGetLastError();
+}
+
+hipError_t launch_b2_from_root(const double* A2, const double* X, double* B2, int n, int64_t ld,
+                               double* part, int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(b2_kernel, dim3(nblk), dim3(TPB), 0, s, A2, X, B2, n, ld, part, nblk);
+  return hipGetLastError();
+}
+
+hipError_t launch_abs_colsum(const double* M, int n, int64_t ld, double* part, int nblk,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(abs_colsum_kernel, dim3(nblk), dim3(TPB), 0, s, M, n, ld, part, nblk);
+  return hipGetLastError();
+}
+
+hipError_t launch_load_padded(const double* src, int64_t lds, double* dst, int n, int n_pad,
+                              double padval, int* nonfinite, hipStream_t s) {
+  hipLaunchKernelGGL(load_padded_kernel, row_grid(n_pad, n_pad), dim3(256), 0, s, src, lds, dst, n,
+                     n_pad, padval, nonfinite);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const double* src, double* dst, size_t count, hipStream_t s) {
+  const size_t blocks = std::min<size_t>((count + 255) / 256, 8192);
+  hipLaunchKernelGGL(copy_kernel, dim3((unsigned)blocks), dim3(256), 0, s, src, dst, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemv(const double* M, int64_t ld, int n, const double* x, double* y,
+                       bool transposed, double* part, int nblk, hipStream_t s) {
+  if (!transposed) {
+    hipLaunchKernelGGL(gemv_n_kernel, dim3((n + 3) / 4), dim3(TPB), 0, s, M, ld, n, x, y);
+  } else {
+    hipLaunchKernelGGL(gemv_t_part_kernel, dim3(nblk, (n + TPB - 1) / TPB), dim3(TPB), 0, s, M, ld,
+                       n, x, part, nblk);
+    hipLaunchKernelGGL(gemv_t_reduce_kernel, dim3((n + 255) / 256), dim3(256), 0, s, part, nblk, n,
+                       y);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_lincomb_init(const LincombArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(lincomb_init_kernel, row_grid((int)a.ld, (int)a.ld), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_finite(const double* M, int64_t ld, int n, int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(check_finite_kernel, row_grid(n, n), dim3(256), 0, s, M, ld, n, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_out(const double* src, int64_t ld, double* dst, int64_t ldd, int n,
+                            double scale, int* nonfinite, hipStream_t s) {
+  hipLaunchKernelGGL(scale_out_kernel, row_grid(n, n), dim3(256), 0, s, src, ld, dst, ldd, n,
+                     scale, nonfinite);
+  return hipGetLastError();
+}
+
+}  // namespace logm

@@ -1,0 +1,276 @@
+// FP64 matrix-core GEMM for gfx950 with pluggable operand loaders and fused
+// epilogues.  Used for
+//  * plain products (the saved square B^2 at s = 0),
+//  * the computation-graph nodes P_{j+2} = L_j R_j of the degree-optimal
+//    polynomial form, whose epilogue folds the linear combinations into the
+//    accumulators so that no P_j is stored,
+//  * the rank-NB trailing update of the blocked Gauss-Jordan inversion.
+//
+// Tiling: 128 x 128 output tile per 256-thread workgroup (2 x 2 waves of 64 x 64),
+// k-slabs of 16 staged through LDS with a double buffer; each wave issues
+// 16 independent v_mfma_f64_16x16x4 per k-step of 4.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace logm {
+namespace {
+
+constexpr int BM = 128;
+constexpr int BN = 128;
+constexpr int BK = 16;
+constexpr int PAD = 4;
+
+// Map the linear workgroup id to a tile so that the workgroups that land on one
+// XCD (ids congruent mod 8) cover a compact block of tiles and share L2 traffic.
+__device__ __forceinline__ void tile_of(int bid, int tiles_m, int tiles_n, int& tm, int& tn) {
+  const int total = tiles_m * tiles_n;
+  int t = bid;
+  if (total >= 64 && (total % 8) == 0) {
+    const int per = total / 8;
+    t = (bid % 8) * per + bid / 8;  // consecutive tiles for each XCD
+  }
+  // group rows of 8 tiles so that successive tiles reuse B panels
+  const int group = 8;
+  const int width = group * tiles_n;
+  const int g = t / width;
+  const int first_m = g * group;
+  const int gm = min(tiles_m - first_m, group);
+  const int in = t % width;
+  tm = first_m + in % gm;
+  tn = in / gm;
+}
+
+template <class Op>
+__global__ __launch_bounds__(256) void gemm_kernel(Op op, int M, int N, int K) {
+  __shared__ double As[2][BK][BM + PAD];
+  __shared__ double Bs[2][BK][BN + PAD];
+
+  op.select(blockIdx.z);
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
+  const int wm = wave >> 1;
+  const int wn = wave & 1;
+  const int tiles_m = (M + BM - 1) / BM;
+  const int tiles_n = (N + BN - 1) / BN;
+  int tm, tn;
+  tile_of(blockIdx.x, tiles_m, tiles_n, tm, tn);
+  const int row0 = tm * BM;
+  const int col0 = tn * BN;
+
+  if (op.copy_tile(row0, col0)) {
+    for (int e = tid; e < BM * BN; e += 256) {
+      const int i = row0 + e / BN;
+      const int j = col0 + e % BN;
+      if (i < M && j < N) op.copy(i, j);
+    }
+    return;
+  }
+
+  // global -> register staging assignment
+  const int ra = tid >> 1;          // A: row within tile
+  const int ka = (tid & 1) * 8;     // A: first k of 8
+  const int kb = tid >> 4;          // B: k row
+  const int cb = (tid & 15) * 8;    // B: first column of 8
+  const bool a_row_ok = (row0 + ra) < M;
+  const double* arow = a_row_ok ? op.a_row(row0 + ra) : nullptr;
+  const bool full_n = (col0 + BN) <= N;
+
+  double va[8], vb[8];
+  auto gload = [&](int k0) {
+    const int kA = k0 + ka;
+    if (a_row_ok && kA + 8 <= K && ((reinterpret_cast<uintptr_t>(arow + kA) & 15) == 0)) {
+      const f64x2* p = reinterpret_cast<const f64x2*>(arow + kA);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        f64x2 v = p[e];
+        va[2 * e] = v.x;
+        va[2 * e + 1] = v.y;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) va[e] = (a_row_ok && kA + e < K) ? arow[kA + e] : 0.0;
+    }
+    const int kB = k0 + kb;
+    if (kB < K) {
+      const double* brow = op.b_row(kB) + col0 + cb;
+      if (full_n && ((reinterpret_cast<uintptr_t>(brow) & 15) == 0)) {
+        const f64x2* p = reinterpret_cast<const f64x2*>(brow);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          f64x2 v = p[e];
+          vb[2 * e] = v.x;
+          vb[2 * e + 1] = v.y;
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) vb[e] = (col0 + cb + e < N) ? brow[e] : 0.0;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) vb[e] = 0.0;
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) As[buf][ka + e][ra] = va[e];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) Bs[buf][kb][cb + e] = vb[e];
+  };
+
+  f64x4 acc[4][4];
+#pragma unroll
+  for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+  const int nk = (K + BK - 1) / BK;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  int buf = 0;
+  const int lr = lane & 15;
+  const int lk = lane >> 4;
+  for (int kt = 0; kt < nk; ++kt) {
+    const bool more = (kt + 1) < nk;
+    if (more) gload((kt + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK / 4; ++kk) {
+      double af[4], bf[4];
+#pragma unroll
+      for (int mi = 0; mi < 4; ++mi) af[mi] = As[buf][kk * 4 + lk][wm * 64 + mi * 16 + lr];
+#pragma unroll
+      for (int ni = 0; ni < 4; ++ni) bf[ni] = Bs[buf][kk * 4 + lk][wn * 64 + ni * 16 + lr];
+#pragma unroll
+      for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = mfma_f64_16x16x4(af[mi], bf[ni], acc[mi][ni]);
+    }
+    if (more) sstore(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+
+#pragma unroll
+  for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = row0 + wm * 64 + mi * 16 + 4 * r + lk;
+      if (i >= M) continue;
+#pragma unroll
+      for (int ni = 0; ni < 4; ++ni) {
+        const int j = col0 + wn * 64 + ni * 16 + lr;
+        if (j < N) op.store(i, j, acc[mi][ni][r]);
+      }
+    }
+}
+
+// ------------------------------------------------------------------ ops ---
+struct PlainOp {
+  const double* A;
+  int64_t lda;
+  const double* B;
+  int64_t ldb;
+  double* C;
+  int64_t ldc;
+  double alpha, beta;
+  __device__ void select(int) {}
+  __device__ bool copy_tile(int, int) const { return false; }
+  __device__ void copy(int, int) const {}
+  __device__ const double* a_row(int i) const { return A + (int64_t)i * lda; }
+  __device__ const double* b_row(int k) const { return B + (int64_t)k * ldb; }
+  __device__ void store(int i, int j, double v) const {
+    double* c = C + (int64_t)i * ldc + j;
+    *c = (beta == 0.0) ? alpha * v : alpha * v + beta * (*c);
+  }
+};
+
+struct PolyOp {
+  PolyGemmArgs a;
+  __device__ void select(int) {}
+  __device__ bool copy_tile(int, int) const { return false; }
+  __device__ void copy(int, int) const {}
+  __device__ const double* a_row(int i) const { return a.Lf + (int64_t)i * a.ld; }
+  __device__ const double* b_row(int k) const { return a.Rf + (int64_t)k * a.ld; }
+  __device__ void store(int i, int j, double v) const {
+    const int64_t o = (int64_t)i * a.ld + j;
+    for (int t = 0; t < a.nacc; ++t) a.acc[t][o] += a.coef[t] * v;
+    if (a.dst != nullptr && i < a.nvalid && j < a.nvalid)
+      a.dst[(int64_t)i * a.ldd + j] = a.scale * (a.base[o] + a.ycoef * v);
+  }
+};
+
+// Rank-nbo Gauss-Jordan trailing update (see gje.hip for the derivation):
+//   out[i][c] = U[i][c-k0]                                    c in K
+//   out[i][c] = [i not in K] * Min[pi(i)][c] + sum_t U[i][t] Min[pi(k0+t)][c]   otherwise
+// where U (n_pad x nbo) is the fully processed panel.
+struct GjeOuterOp {
+  const double* U[2];
+  const double* Min[2];
+  const int* pi[2];
+  double* Mout[2];
+  int64_t ld;
+  int k0, nbo;
+  const double* u;
+  const double* mi;
+  const int* p;
+  double* mo;
+  __device__ void select(int z) {
+    const bool one = (z != 0);
+    u = one ? U[1] : U[0];
+    mi = one ? Min[1] : Min[0];
+    p = one ? pi[1] : pi[0];
+    mo = one ? Mout[1] : Mout[0];
+  }
+  __device__ bool copy_tile(int, int col0) const { return col0 >= k0 && col0 + BN <= k0 + nbo; }
+  __device__ void copy(int i, int j) const { mo[(int64_t)i * ld + j] = u[(int64_t)i * nbo + (j - k0)]; }
+  __device__ const double* a_row(int i) const { return u + (int64_t)i * nbo; }
+  __device__ const double* b_row(int t) const { return mi + (int64_t)p[k0 + t] * ld; }
+  __device__ void store(int i, int j, double v) const {
+    double out;
+    if (j >= k0 && j < k0 + nbo) {
+      out = u[(int64_t)i * nbo + (j - k0)];
+    } else {
+      const double base = (i >= k0 && i < k0 + nbo) ? 0.0 : mi[(int64_t)p[i] * ld + j];
+      out = base + v;
+    }
+    mo[(int64_t)i * ld + j] = out;
+  }
+};
+
+template <class Op>
+hipError_t launch(const Op& op, int M, int N, int K, int nz, hipStream_t s) {
+  const int tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+  hipLaunchKernelGGL(gemm_kernel<Op>, dim3(tiles, 1, nz), dim3(256), 0, s, op, M, N, K);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_gemm_plain(int M, int N, int K, double alpha, const double* A, int64_t lda,
+                             const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
+                             hipStream_t s) {
+  PlainOp op{A, lda, B, ldb, C, ldc, alpha, beta};
+  return launch(op, M, N, K, 1, s);
+}
+
+hipError_t launch_gemm_poly(int n, const PolyGemmArgs& a, hipStream_t s) {
+  PolyOp op{a};
+  return launch(op, n, n, n, 1, s);
+}
+
+hipError_t launch_gje_outer_update(const GjeArgs& a, hipStream_t s) {
+  GjeOuterOp op{};
+  for (int z = 0; z < a.nmat; ++z) {
+    op.U[z] = a.m[z].P[a.pcur];
+    op.Min[z] = a.m[z].Min;
+    op.pi[z] = a.m[z].pi;
+    op.Mout[z] = a.m[z].Mout;
+  }
+  op.ld = a.n_pad;
+  op.k0 = a.k0;
+  op.nbo = a.nbo;
+  return launch(op, a.n_pad, a.n_pad, a.nbo, a.nmat, s);
+}
+
+}  // namespace logm

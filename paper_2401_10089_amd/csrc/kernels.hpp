@@ -1,0 +1,154 @@
+// Internal launch interface between the host driver and the HIP kernels.
+// Not part of the public C ABI (include/logm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace logm {
+
+// ----------------------------------------------------------------- GEMM ----
+// C = alpha * A * B + beta * C, row-major, fp64 MFMA.  M, N, K arbitrary >= 1.
+hipError_t launch_gemm_plain(int M, int N, int K, double alpha, const double* A, int64_t lda,
+                             const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
+                             hipStream_t s);
+
+// Graph-node product P = Lf * Rf (n x n, leading dimension ld) whose result is
+// never stored: the epilogue adds coef[t] * P into accumulator acc[t] for every
+// t < nacc, and, when dst != nullptr, writes dst = scale * (base + ycoef * P)
+// restricted to the leading nvalid x nvalid block (leading dimension ldd).
+struct PolyGemmArgs {
+  const double* Lf;
+  const double* Rf;
+  int64_t ld;
+  int nacc;
+  double* acc[9];
+  double coef[9];
+  double* dst;
+  int64_t ldd;
+  const double* base;
+  double ycoef;
+  double scale;
+  int nvalid;
+};
+hipError_t launch_gemm_poly(int n, const PolyGemmArgs& a, hipStream_t s);
+
+// ------------------------------------------------------ Gauss-Jordan ------
+// Per-matrix state of the blocked Gauss-Jordan inversion (see gje.hip).
+struct GjeMat {
+  const double* Min;     // matrix at the start of the outer step (n_pad x n_pad, ld n_pad)
+  double* Mout;          // matrix after the outer step
+  double* P[2];          // ping-pong panels n_pad x nbo (ld = nbo)
+  double* tri;           // 3 x 64 x 64: [0] U with inverted 16x16 diagonal blocks,
+                         // [1] U^{-1}, [2] L^{-1} of the current pivot block S = L U
+  int* pi;               // n_pad: gather map of the current outer step
+  int* ptot;             // n_pad: accumulated row order (position -> original row)
+  int* pinv;             // n_pad: inverse of ptot (filled by launch_gje_finish)
+  int* qsel;             // 64 selected positions of the current inner step
+  int* vac;              // [0] = count, [1..64] vacated positions, [65..128] their sources
+  int* cand;             // tournament scratch
+  int* cnt;              // tournament arrival counters (self-resetting)
+  double* logdet;        // n_pad / 64 slots: log|det| of each pivot block
+  int* err;              // error flags: [0] zero pivot met
+};
+
+struct GjeArgs {
+  GjeMat m[2];
+  int nmat;
+  int n_pad;
+  int nbo;               // outer block width for this step (multiple of 64)
+  int k0;                // first column of the outer block
+  int pcur;              // which P[] holds the current panel
+  int c0;                // inner block offset inside the panel (multiple of 64)
+  int r0;                // first candidate position (k0 + c0)
+};
+
+// Tournament scratch sizes (ints) per matrix.
+inline int gje_cand_ints(int n_pad) { return 2 * (n_pad / 128 + 2) * 65; }
+inline int gje_cnt_ints(int n_pad) { return 2 * (n_pad / 128 + 2); }
+
+// Reset ptot to the identity, zero the error flags, logdet slots and counters.
+hipError_t launch_gje_begin(const GjeArgs& a, hipStream_t s);
+// P[pcur] = Min[:, k0:k0+nbo]; pi = identity.
+hipError_t launch_gje_panel_copy(const GjeArgs& a, hipStream_t s);
+hipError_t launch_gje_tournament(const GjeArgs& a, hipStream_t s);
+hipError_t launch_gje_inner_update(const GjeArgs& a, hipStream_t s);
+hipError_t launch_gje_outer_update(const GjeArgs& a, hipStream_t s);
+// pinv = ptot^{-1}.
+hipError_t launch_gje_finish(const GjeArgs& a, hipStream_t s);
+// dst (n x n, ldd) = A^{-1}: dst[i][ptot[c]] = Mfinal[i][c].
+hipError_t launch_gje_unpermute(const double* Mfinal, const int* pinv, int64_t ld, double* dst,
+                                int64_t ldd, int n, hipStream_t s);
+
+// ---------------------------------------------------- elementwise etc. ----
+// Denman-Beavers update with the column permutation of the inverses folded in.
+struct DbArgs {
+  const double* Xin;      // X_k (may equal Xout: the update is row-local)
+  double* Xout;           // X_{k+1}
+  const double* Yin;      // Y_k (nullptr: Y_0 = I)
+  double* Yout;           // Y_{k+1}
+  const double* Xinv;     // permuted inverses (Gauss-Jordan output)
+  const double* Yinv;
+  const int* px;          // pinv of X's inversion
+  const int* py;          // pinv of Y's inversion (nullptr: Y = I, inverse I)
+  const double* ldx;      // logdet slots of X (nslots)
+  const double* ldy;      // logdet slots of Y (nullptr: 0)
+  int nslots;
+  int n;                  // valid size
+  int64_t ld;             // n_pad
+  int scaled;
+  double* part;           // partial column sums, 2 x nblk x n
+  double* mu_out;         // device scalar: mu used
+};
+hipError_t launch_db_update(const DbArgs& a, int nblk, hipStream_t s);
+
+// Reduce partial column sums part[q][b][c] (q < nq, b < nblk, c < n) to
+// out[q] = max_c sum_b part[q][b][c]; bm is scratch of nq * ceil(n / 256) doubles.
+hipError_t launch_colsum_max(const double* part, int nq, int nblk, int n, double* out,
+                             double* bm, hipStream_t s);
+
+// Padded workspace matrices: n_pad = ld, valid block n x n, the rest of an X-like
+// matrix is the identity and of a B-like matrix zero.  The kernels below write the
+// whole padded matrix and sum norms over the valid block.
+// B = X - I; column-sum partials of |B| into part[0].
+hipError_t launch_shift(const double* X, double* B, int n, int64_t ld, double* part, int nblk,
+                        hipStream_t s);
+// B2 = A2 - 2 X + I (valid block), column-sum partials of |B2| into part[0].
+hipError_t launch_b2_from_root(const double* A2, const double* X, double* B2, int n, int64_t ld,
+                               double* part, int nblk, hipStream_t s);
+// Column-sum partials of |M| (valid n x n) into part[0].
+hipError_t launch_abs_colsum(const double* M, int n, int64_t ld, double* part, int nblk,
+                             hipStream_t s);
+
+// Load an n x n user matrix into a padded n_pad x n_pad buffer; pad gets diag(padval).
+hipError_t launch_load_padded(const double* src, int64_t lds, double* dst, int n, int n_pad,
+                              double padval, int* nonfinite, hipStream_t s);
+hipError_t launch_copy(const double* src, double* dst, size_t count, hipStream_t s);
+
+// y = M x (transposed = false) or y = M^T x (true); M is n x n row-major (ld).
+hipError_t launch_gemv(const double* M, int64_t ld, int n, const double* x, double* y,
+                       bool transposed, double* part, int nblk, hipStream_t s);
+
+// Polynomial accumulator initialisation: out[t] = c2[t] * P2 + c3[t] * P3 + c1[t] * I
+// on the valid n x n block, zero on the rest of the padded ld x ld matrix.
+struct LincombArgs {
+  const double* P2;
+  const double* P3;
+  int nout;
+  double* out[9];
+  double c1[9];
+  double c2[9];
+  double c3[9];
+  int n;
+  int64_t ld;
+};
+hipError_t launch_lincomb_init(const LincombArgs& a, hipStream_t s);
+
+// flag |= 1 if the valid n x n block of M holds a NaN or Inf.
+hipError_t launch_check_finite(const double* M, int64_t ld, int n, int* flag, hipStream_t s);
+
+// dst (n x n, ldd) = scale * src (valid block of ld-matrix).
+hipError_t launch_scale_out(const double* src, int64_t ld, double* dst, int64_t ldd, int n,
+                            double scale, int* nonfinite, hipStream_t s);
+
+}  // namespace logm

@@ -1,0 +1,180 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared symbol,
+validates arguments before any device work, and holds the paper's tables."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "logm.h")
+
+lm = pytest.importorskip("paper_2401_10089_amd")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    try:
+        return lm.load_library()
+    except lm.LibraryNotBuilt as e:
+        pytest.fail(f"library not built: {e}")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(logm_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_header_and_binding_agree():
+    assert declared_functions() == sorted(lm.EXPORTS)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_version_and_strerror(lib):
+    assert "gfx950" in lm.version()
+    for code, name in lm.STATUS.items():
+        assert lm.strerror(code)
+    assert lm.strerror(99) == "unknown status"
+
+
+def test_default_opts(lib):
+    o = lm.default_opts()
+    assert (o.k_max, o.max_sqrt, o.db_max_iter, o.theta_source) == (5, 50, 30, 0)
+
+
+def test_workspace_size(lib):
+    sizes = [lm.workspace_size(n) for n in (1, 64, 65, 1000, 4096)]
+    assert all(s > 0 for s in sizes)
+    assert sizes == sorted(sizes)
+    # eleven padded matrices dominate
+    assert sizes[-1] >= 11 * 4096 * 4096 * 8
+    b = ctypes.c_size_t(0)
+    assert lib.logm_workspace_size(0, 0, None, ctypes.byref(b)) == 1
+    assert lib.logm_workspace_size(7, 10, None, ctypes.byref(b)) == 1
+
+
+FAKE = ctypes.c_void_p(0x10000)   # never dereferenced: validation fails first
+
+
+def fwd(lib, dtype=0, n=8, A=FAKE, lda=8, L=FAKE, ldl=8, opts=None, ws=None, ws_bytes=0):
+    return lib.logm_forward(dtype, n, A, lda, L, ldl, ctypes.byref(opts) if opts else None, None,
+                            ws, ws_bytes, None)
+
+
+def test_forward_argument_validation(lib):
+    assert fwd(lib, n=0) == 1
+    assert fwd(lib, A=None) == 1
+    assert fwd(lib, L=None) == 1
+    assert fwd(lib, lda=7) == 1
+    assert fwd(lib, ldl=3) == 1
+    assert fwd(lib, dtype=5) == 1
+    assert fwd(lib, dtype=1) == 2                      # complex not built
+    o = lm.default_opts()
+    o.k_max = 4                                        # no printed coefficients for k = 4
+    assert fwd(lib, opts=o) == 1
+    o = lm.default_opts()
+    o.max_sqrt = 65
+    assert fwd(lib, opts=o) == 1
+    o = lm.default_opts()
+    o.reserved[0] = 1
+    assert fwd(lib, opts=o) == 1
+    assert fwd(lib, ws=FAKE, ws_bytes=100) == 3        # workspace too small
+
+
+def test_component_argument_validation(lib):
+    assert lib.logm_gemm_f64(0, 4, 4, 1.0, FAKE, 4, FAKE, 4, 0.0, FAKE, 4, None) == 1
+    assert lib.logm_gemm_f64(4, 4, 4, 1.0, FAKE, 3, FAKE, 4, 0.0, FAKE, 4, None) == 1
+    assert lib.logm_inverse_f64(4, None, 4, FAKE, 4, None, None, 0, None) == 1
+    assert lib.logm_sqrt_f64(4, FAKE, 4, FAKE, 4, 0, None, None, 0, None) == 1
+    assert lib.logm_poly_f64(4, 4, 0, FAKE, 4, FAKE, 4, FAKE, 4, None, 0, None) == 1
+    assert lib.logm_poly_f64(4, 5, -1, FAKE, 4, FAKE, 4, FAKE, 4, None, 0, None) == 1
+    est = ctypes.c_double(0)
+    assert lib.logm_normest_f64(4, FAKE, 4, FAKE, 4, 0, 0, ctypes.byref(est), None, None, 0, None) == 1
+    assert lib.logm_normest_f64(4, FAKE, 4, FAKE, 4, 1, 2, ctypes.byref(est), None, None, 0, None) == 1
+
+
+def test_library_table1_matches_paper(golden):
+    t = golden("table1_k5.txt")
+    h, g, y, m, th = lm.scheme(5)
+    exp_h = [float(t[f"h_{j}_{i}"][0]) for j in range(2, 6) for i in range(2, j + 2)]
+    exp_g = [float(t[f"g_{j}_{i}"][0]) for j in range(2, 6) for i in range(2, j + 2)]
+    assert h == exp_h and g == exp_g
+    assert y == [float(t[f"y_{q}"][0]) for q in range(1, 8)]
+    assert (m, th) == (14, 0.246)
+
+
+def test_library_table2_matches_paper(golden):
+    t = golden("table2_theta.txt")
+    for k in (1, 2, 3, 5):
+        m, _, theta = t[str(k)]
+        _, _, _, mk, thk = lm.scheme(k)
+        assert (mk, thk) == (int(m), float(theta))
+    assert lm.scheme(5, theta_source=1)[4] == 0.2448
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_library_taylor_schemes_expand_to_taylor(k):
+    """The library's own k = 1, 2, 3 coefficients expand to T_{m_k} (exact rationals)."""
+    from fractions import Fraction
+    h, g, y, m, _ = lm.scheme(k)
+    P = [None, [Fraction(1)], [Fraction(0), Fraction(1)], [Fraction(0), Fraction(0), Fraction(1)]]
+
+    def add(a, b):
+        n = max(len(a), len(b))
+        return [(a[i] if i < len(a) else 0) + (b[i] if i < len(b) else 0) for i in range(n)]
+
+    def mul(a, b):
+        out = [Fraction(0)] * (len(a) + len(b) - 1)
+        for i, x in enumerate(a):
+            for j, z in enumerate(b):
+                out[i + j] += x * z
+        return out
+
+    pos = 0
+    for j in range(2, k + 1):
+        L = [Fraction(0)]
+        R = [Fraction(0)]
+        for i in range(2, j + 2):
+            L = add(L, [Fraction(h[pos]) * c for c in P[i]])
+            R = add(R, [Fraction(g[pos]) * c for c in P[i]])
+            pos += 1
+        P.append(mul(L, R))
+    z = [Fraction(0)]
+    for q in range(1, k + 3):
+        z = add(z, [Fraction(y[q - 1]) * c for c in P[q]])
+    for i in range(1, m + 1):
+        assert abs(float((z[i] - Fraction(1, i)) * i)) <= 4 * 2.0 ** -53
+
+
+def test_library_k3_agrees_with_oracle():
+    h, g, y, _, _ = lm.scheme(3)
+    oh, og, oy = oracle.scheme_coefficients(3)
+    flat_h = [v for j in (2, 3) for v in oh[j]]
+    flat_g = [v for j in (2, 3) for v in og[j]]
+    assert h == pytest.approx(flat_h, rel=1e-15, abs=1e-16)
+    assert g == pytest.approx(flat_g, rel=1e-15, abs=1e-16)
+    assert y == pytest.approx(list(oy), rel=1e-15, abs=1e-16)
+
+
+def test_profile_calls_without_gpu(lib):
+    lm.profile_enable(False)
+    lm.profile_reset()
+    p = lm.profile_get()
+    assert p == {"launches": 0, "ms": 0.0, "flops": 0.0, "bytes": 0.0}
+
+
+def test_product_path_has_no_oracle_import():
+    """The binding and the package never reach the oracle (no CPU fallback)."""
+    pkg = os.path.join(ROOT, "paper_2401_10089_amd")
+    for name in os.listdir(pkg):
+        if name.endswith(".py"):
+            src = open(os.path.join(pkg, name)).read()
+            assert "import oracle" not in src and "from oracle" not in src, name

@@ -1,0 +1,284 @@
+"""GPU parity: each step of the HIP path and the whole logm against the oracle.
+
+Tolerances (fp64): products and inverses are compared with bounds proportional
+to u times the conditioning; the full logarithm uses the relative Frobenius bound
+1e-12 (GPU vs oracle); when the two implementations take different decisions
+(s, k or root iteration counts) because a rounding-level difference straddles a
+threshold, the oracle replays the GPU's decisions and the bound applies to that
+replay, while the decisions themselves are checked to be valid.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import disk_matrix, rotscale_matrix
+
+torch = pytest.importorskip("torch")
+lm = pytest.importorskip("paper_2401_10089_amd")
+
+pytestmark = pytest.mark.gpu
+
+U = 2.0 ** -53
+TOL_LOGM = 1e-12
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    lm.load_library()
+    yield
+    torch.cuda.synchronize()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def relf(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+# ------------------------------------------------------------- products ---
+@pytest.mark.parametrize("m,n,k", [(1, 1, 1), (16, 16, 4), (100, 70, 33), (128, 128, 128),
+                                   (257, 300, 64), (64, 513, 200), (1024, 1024, 1024)])
+def test_gemm_matches_fp64_reference(m, n, k):
+    rng = np.random.default_rng(m * 7 + n * 3 + k)
+    A = rng.standard_normal((m, k))
+    B = rng.standard_normal((k, n))
+    C0 = rng.standard_normal((m, n))
+    C = lm.gemm(dev(A), dev(B), dev(C0), alpha=0.5, beta=-2.0)
+    ref = 0.5 * (A @ B) - 2.0 * C0
+    bound = (k + 4) * U * (0.5 * np.abs(A) @ np.abs(B) + 2.0 * np.abs(C0))
+    err = np.abs(host(C) - ref)
+    assert np.all(err <= bound + 1e-300), float((err / (bound + 1e-300)).max())
+
+
+def test_gemm_strided_operands():
+    rng = np.random.default_rng(3)
+    big = rng.standard_normal((200, 300))
+    A = dev(big)[:150, :100]          # ld = 300
+    Bm = dev(big)[10:110, 7:207]      # ld = 300
+    C = lm.gemm(A, Bm)
+    ref = big[:150, :100] @ big[10:110, 7:207]
+    assert relf(host(C), ref) < 1e-15
+
+
+# ------------------------------------------------------------- inverse ----
+@pytest.mark.parametrize("n", [1, 2, 7, 64, 65, 100, 130, 256, 300, 520, 1024])
+def test_inverse_matches_numpy(n):
+    rng = np.random.default_rng(n)
+    A = rng.standard_normal((n, n)) + 0.5 * n ** 0.5 * np.eye(n)
+    Ai, ld = lm.inverse(dev(A))
+    ref = np.linalg.inv(A)
+    kappa = np.linalg.cond(A, 1)
+    assert relf(host(Ai), ref) < 20 * n * kappa * U
+    assert ld == pytest.approx(np.linalg.slogdet(A)[1], rel=1e-12, abs=1e-12)
+    resid = np.linalg.norm(A @ host(Ai) - np.eye(n), 1)
+    assert resid < 20 * n * kappa * U
+
+
+def test_inverse_needs_pivoting():
+    n = 200
+    rng = np.random.default_rng(11)
+    P = np.eye(n)[rng.permutation(n)]
+    A = P @ (np.triu(rng.standard_normal((n, n)), 1) + np.diag(rng.uniform(1, 2, n)))
+    A[np.abs(A) < 0.3] = 0.0
+    A += P * 0.0
+    Ai, ld = lm.inverse(dev(A))
+    ref = np.linalg.inv(A)
+    assert relf(host(Ai), ref) < 1e-10
+    assert ld == pytest.approx(np.linalg.slogdet(A)[1], rel=1e-12, abs=1e-10)
+
+
+def test_inverse_permutation_matrix_exact():
+    n = 300
+    perm = np.random.default_rng(2).permutation(n)
+    A = np.eye(n)[perm] * 2.0
+    Ai, ld = lm.inverse(dev(A))
+    assert np.array_equal(host(Ai), np.linalg.inv(A))
+    assert ld == pytest.approx(n * math.log(2.0))
+
+
+def test_inverse_singular_reports():
+    A = np.ones((70, 70))
+    with pytest.raises(lm.LogmError) as e:
+        lm.inverse(dev(A))
+    assert e.value.status == "LOGM_ESINGULAR"
+
+
+def test_inverse_deterministic():
+    A = np.random.default_rng(5).standard_normal((384, 384)) + 20 * np.eye(384)
+    a1, _ = lm.inverse(dev(A))
+    a2, _ = lm.inverse(dev(A))
+    assert torch.equal(a1, a2)
+
+
+# ------------------------------------------------------------ square root -
+@pytest.mark.parametrize("n,seed,lo,hi", [(1, 1, 4.0, 4.0), (5, 2, 0.5, 2), (64, 3, 1e-2, 1e2),
+                                          (130, 4, 1e-3, 1e3), (256, 5, 1e-3, 1e3)])
+def test_sqrt_matches_oracle(n, seed, lo, hi):
+    if n == 1:
+        A = np.array([[4.0]])
+    else:
+        A, _ = rotscale_matrix(n, seed, lo, hi)
+    X, it = lm.sqrtm(dev(A))
+    Xo, ito, hist, _ = oracle.db_sqrt(A)
+    Xg = host(X)
+    if it != ito:
+        Xo, *_ = oracle.db_sqrt(A, force_iters=it)
+    assert relf(Xg, Xo) < 1e-12, (it, ito)
+    assert relf(Xg @ Xg, A) < 1e-12
+
+
+def test_sqrt_spd():
+    rng = np.random.default_rng(8)
+    G = rng.standard_normal((100, 100))
+    A = G @ G.T / 100 + 0.05 * np.eye(100)
+    X, _ = lm.sqrtm(dev(A))
+    w, V = np.linalg.eigh(A)
+    assert relf(host(X), (V * np.sqrt(w)) @ V.T) < 1e-12
+
+
+# ------------------------------------------------------------- polynomial -
+@pytest.mark.parametrize("k", [1, 2, 3, 5])
+@pytest.mark.parametrize("n,s", [(1, 0), (64, 0), (100, 3), (257, 1)])
+def test_poly_matches_oracle(k, n, s):
+    rng = np.random.default_rng(100 * k + n)
+    B = rng.standard_normal((n, n))
+    B *= oracle.TABLE2[k][1] / max(np.linalg.norm(B, 1), 1e-300)
+    B2 = B @ B
+    L = lm.poly(dev(B), dev(B2), k, s)
+    ref = -(2.0 ** s) * oracle.eval_scheme(k, -B, B2)
+    assert relf(host(L), ref) < 4e-15 * max(1, math.log2(n + 1))
+
+
+# --------------------------------------------------------------- normest --
+@pytest.mark.parametrize("n,q,r", [(1, 3, 1), (50, 1, 0), (64, 7, 0), (64, 7, 1), (300, 4, 1)])
+def test_normest_matches_oracle(n, q, r):
+    rng = np.random.default_rng(n + q)
+    B = rng.standard_normal((n, n)) / n ** 0.5
+    B2 = B @ B
+    est, nmv = lm.normest(dev(B2), dev(B), q, r)
+    est_o, nmv_o = oracle.normest_power(B2, B, q, r)
+    assert nmv == nmv_o
+    assert est == pytest.approx(est_o, rel=1e-13)
+
+
+def test_normest_exact_nonnegative():
+    rng = np.random.default_rng(4)
+    B = rng.uniform(0, 1, (90, 90)) / 90
+    B2 = B @ B
+    est, _ = lm.normest(dev(B2), dev(B), 3, 1)
+    assert est == pytest.approx(np.linalg.norm(np.linalg.matrix_power(B2, 3) @ B, 1), rel=1e-13)
+
+
+# ------------------------------------------------------------------ logm --
+def compare_with_oracle(A, tol=TOL_LOGM, **kw):
+    L, info = lm.logm(dev(A), **kw)
+    Lg = host(L)
+    Lo, io = oracle.logm(A, k_max=kw.get("k_max", 5))
+    same = (info["s"], info["k"], info["db_iters"]) == (io["s"], io["k"], io["db_iters"])
+    if not same:
+        Lo, io = oracle.logm(A, force={"s": info["s"], "k": info["k"], "db_iters": info["db_iters"]})
+    err = relf(Lg, Lo)
+    assert err < tol, (err, info, io)
+    return Lg, info, same
+
+
+def test_logm_disk64():
+    A = disk_matrix(64, 1001)
+    Lg, info, same = compare_with_oracle(A)
+    assert same
+    import scipy.linalg as sl
+    assert relf(sl.expm(Lg), A) < 1e-13
+
+
+@pytest.mark.parametrize("n,seed", [(16, 1), (64, 2), (100, 3), (256, 4)])
+def test_logm_rotscale_vs_oracle_and_exact(n, seed):
+    A, Lx = rotscale_matrix(n, seed)
+    Lg, info, same = compare_with_oracle(A)
+    assert relf(Lg, Lx) < 1e-11
+    assert info["k"] in (1, 2, 3, 5)
+
+
+def test_logm_rotscale1024():
+    A, Lx = rotscale_matrix(1024, 2001)
+    Lg, info, same = compare_with_oracle(A)
+    assert relf(Lg, Lx) < 1e-11
+    assert info["s"] >= 5
+
+
+@pytest.mark.parametrize("kmax", [1, 2, 3])
+def test_logm_smaller_kmax(kmax):
+    """Small k_max forces many roots (s = 26 for k_max = 1 here); the saved product
+    B^2 = A_2 - 2X + I then cancels to about u/||B|| relative accuracy, which bounds
+    the method itself.  GPU and oracle must agree to that level and both be as close
+    to the true logarithm."""
+    import scipy.linalg as sl
+    A = disk_matrix(40, 9, 0.3)
+    ref = sl.logm(A).real
+    L, info = lm.logm(dev(A), k_max=kmax)
+    Lo, io = oracle.logm(A, k_max=kmax)
+    method_err = relf(Lo, ref)
+    tol = max(TOL_LOGM, 10 * method_err)
+    assert info["k"] <= kmax and info["s"] == io["s"]
+    if (info["s"], info["k"], info["db_iters"]) == (io["s"], io["k"], io["db_iters"]):
+        assert relf(host(L), Lo) < tol
+    assert relf(host(L), ref) < tol
+
+
+def test_logm_closed_forms():
+    d = np.array([1e-3, 0.5, 2.0, 7.0, 1e3])
+    L, _ = lm.logm(dev(np.diag(d)))
+    assert np.allclose(np.diag(host(L)), np.log(d), rtol=0, atol=1e-14 * 7)
+    lam = 0.2
+    L, _ = lm.logm(dev(np.array([[lam, 1.0], [0.0, lam]])))
+    assert relf(host(L), np.array([[math.log(lam), 1 / lam], [0, math.log(lam)]])) < 1e-14
+    L, info = lm.logm(dev(np.eye(70)))
+    assert np.count_nonzero(host(L)) == 0
+
+
+def test_logm_hand_derived_decisions(golden):
+    for name, (mat, n, s, k, nest) in golden("decisions.txt").items():
+        A = np.array([float(v) for v in mat.split(",")]).reshape(int(n), int(n))
+        _, info = lm.logm(dev(A))
+        assert (info["s"], info["k"], info["n_est"]) == (int(s), int(k), int(nest)), name
+
+
+def test_logm_error_paths():
+    with pytest.raises(lm.LogmError) as e:
+        lm.logm(dev(np.array([[1.0, float("nan")], [0.0, 1.0]])))
+    assert e.value.status == "LOGM_ENONFINITE"
+    with pytest.raises(lm.LogmError) as e:
+        lm.logm(dev(np.zeros((10, 10))))
+    assert e.value.status == "LOGM_ESINGULAR"
+    with pytest.raises(lm.LogmError) as e:
+        lm.logm(dev(np.diag([-1.0, 2.0])))
+    assert e.value.status in ("LOGM_ESINGULAR", "LOGM_ENOCONV", "LOGM_ENONFINITE")
+
+
+def test_logm_deterministic():
+    A, _ = rotscale_matrix(200, 17)
+    L1, i1 = lm.logm(dev(A))
+    L2, i2 = lm.logm(dev(A))
+    assert torch.equal(L1, L2) and i1 == i2
+
+
+def test_logm_user_workspace_and_strided_output():
+    A = disk_matrix(50, 4)
+    ws = torch.empty(lm.workspace_size(50), dtype=torch.uint8, device="cuda")
+    big = torch.zeros((50, 80), dtype=torch.float64, device="cuda")
+    out = big[:, 10:60]
+    L, _ = lm.logm(dev(A), out=out, workspace=ws)
+    Lo, _ = oracle.logm(A)
+    assert relf(host(big[:, 10:60]), Lo) < TOL_LOGM
+    assert torch.count_nonzero(big[:, :10]) == 0 and torch.count_nonzero(big[:, 60:]) == 0
