@@ -23,6 +23,8 @@ HIPCC_FLAGS = [
     "-Wall",
     "-Wno-unused-function",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # the register-resident pivot search unrolls its 64 columns completely
+    "-mllvm", "-pragma-unroll-threshold=1000000",
 ]
 
 

@@ -46,4 +46,31 @@ __device__ __forceinline__ void wave_argmax(double& v, int& idx) {
   }
 }
 
+// One DPP row/bank-masked move of a double (two 32-bit halves).  Lanes whose
+// source is outside the row or masked off keep `old`.
+template <int CTRL, int ROWMASK, int BANKMASK>
+__device__ __forceinline__ double dpp_double(double old, double src) {
+  const long long o = __double_as_longlong(old);
+  const long long s = __double_as_longlong(src);
+  const int lo = __builtin_amdgcn_update_dpp((int)o, (int)s, CTRL, ROWMASK, BANKMASK, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(s >> 32), CTRL, ROWMASK, BANKMASK, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Wave-wide maximum of v using DPP row shifts and row broadcasts (gfx9 family);
+// the full maximum lands in lane 63 and is returned to every lane.
+__device__ __forceinline__ double wave_max_dpp(double v) {
+  v = fmax(v, dpp_double<0x111, 0xf, 0xf>(v, v));  // row_shr:1
+  v = fmax(v, dpp_double<0x112, 0xf, 0xf>(v, v));  // row_shr:2
+  v = fmax(v, dpp_double<0x113, 0xf, 0xf>(v, v));  // row_shr:3
+  v = fmax(v, dpp_double<0x114, 0xf, 0xe>(v, v));  // row_shr:4, banks 1-3
+  v = fmax(v, dpp_double<0x118, 0xf, 0xc>(v, v));  // row_shr:8, banks 2-3
+  v = fmax(v, dpp_double<0x142, 0xa, 0xf>(v, v));  // row_bcast:15, rows 1 and 3
+  v = fmax(v, dpp_double<0x143, 0xc, 0xf>(v, v));  // row_bcast:31, rows 2 and 3
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 }  // namespace logm

@@ -199,7 +199,7 @@ Plan make_plan(int64_t n) {
   for (int i = 0; i < kMats; ++i) p.mat[i] = take(np * np * sizeof(double));
   for (int z = 0; z < 2; ++z) {
     for (int b = 0; b < 2; ++b) p.panel[z][b] = take(np * kNBO * sizeof(double));
-    p.W[z] = take(3 * kNB * kNB * sizeof(double));
+    p.W[z] = take(kNB * kNB * sizeof(double));
     p.logdet[z] = take(np / kNB * sizeof(double));
     p.pi[z] = take(np * sizeof(int));
     p.ptot[z] = take(np * sizeof(int));

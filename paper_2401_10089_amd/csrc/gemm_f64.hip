@@ -151,18 +151,22 @@ __global__ __launch_bounds__(256) void gemm_kernel(Op op, int M, int N, int K) {
     buf ^= 1;
   }
 
+  // epilogue: per 16-row group each lane owns rows 4r + lk (r < 4) and columns
+  // 16 ni + lr (ni < 4) of the wave's 64 x 64 block
 #pragma unroll
-  for (int mi = 0; mi < 4; ++mi)
+  for (int mi = 0; mi < 4; ++mi) {
+    int rows[4], cols[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i = row0 + wm * 64 + mi * 16 + 4 * r + lk;
-      if (i >= M) continue;
+    for (int r = 0; r < 4; ++r) rows[r] = row0 + wm * 64 + mi * 16 + 4 * r + lk;
 #pragma unroll
-      for (int ni = 0; ni < 4; ++ni) {
-        const int j = col0 + wn * 64 + ni * 16 + lr;
-        if (j < N) op.store(i, j, acc[mi][ni][r]);
-      }
-    }
+    for (int ni = 0; ni < 4; ++ni) cols[ni] = col0 + wn * 64 + ni * 16 + lr;
+    double v[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int ni = 0; ni < 4; ++ni) v[r][ni] = acc[mi][ni][r];
+    op.store_group(rows, cols, v, M, N);
+  }
 }
 
 // ------------------------------------------------------------------ ops ---
@@ -179,9 +183,23 @@ struct PlainOp {
   __device__ void copy(int, int) const {}
   __device__ const double* a_row(int i) const { return A + (int64_t)i * lda; }
   __device__ const double* b_row(int k) const { return B + (int64_t)k * ldb; }
-  __device__ void store(int i, int j, double v) const {
-    double* c = C + (int64_t)i * ldc + j;
-    *c = (beta == 0.0) ? alpha * v : alpha * v + beta * (*c);
+  // all loads of the group are issued before any store
+  __device__ void store_group(const int* rows, const int* cols, double (*v)[4], int M, int N) const {
+    double old[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int ni = 0; ni < 4; ++ni) {
+        const int i = min(rows[r], M - 1);
+        const int j = min(cols[ni], N - 1);
+        old[r][ni] = (beta == 0.0) ? 0.0 : C[(int64_t)i * ldc + j];
+      }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int ni = 0; ni < 4; ++ni)
+        if (rows[r] < M && cols[ni] < N)
+          C[(int64_t)rows[r] * ldc + cols[ni]] = alpha * v[r][ni] + beta * old[r][ni];
   }
 };
 
@@ -192,11 +210,45 @@ struct PolyOp {
   __device__ void copy(int, int) const {}
   __device__ const double* a_row(int i) const { return a.Lf + (int64_t)i * a.ld; }
   __device__ const double* b_row(int k) const { return a.Rf + (int64_t)k * a.ld; }
-  __device__ void store(int i, int j, double v) const {
-    const int64_t o = (int64_t)i * a.ld + j;
-    for (int t = 0; t < a.nacc; ++t) a.acc[t][o] += a.coef[t] * v;
-    if (a.dst != nullptr && i < a.nvalid && j < a.nvalid)
-      a.dst[(int64_t)i * a.ldd + j] = a.scale * (a.base[o] + a.ycoef * v);
+  // tiles can overhang the n x n matrices (n_pad is a multiple of 64, tiles are
+  // 128 wide): loads are clamped into the matrix and stores predicated
+  __device__ void store_group(const int* rows, const int* cols, double (*v)[4], int M, int N) const {
+    int64_t o[4][4];
+    bool in[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int ni = 0; ni < 4; ++ni) {
+        in[r][ni] = rows[r] < M && cols[ni] < N;
+        o[r][ni] = (int64_t)min(rows[r], M - 1) * a.ld + min(cols[ni], N - 1);
+      }
+    for (int t = 0; t < a.nacc; ++t) {
+      double* p = a.acc[t];
+      const double cf = a.coef[t];
+      double old[4][4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni) old[r][ni] = p[o[r][ni]];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni)
+          if (in[r][ni]) p[o[r][ni]] = fma(cf, v[r][ni], old[r][ni]);
+    }
+    if (a.dst != nullptr) {
+      double b[4][4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni) b[r][ni] = a.base[o[r][ni]];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni)
+          if (in[r][ni] && rows[r] < a.nvalid && cols[ni] < a.nvalid)
+            a.dst[(int64_t)rows[r] * a.ldd + cols[ni]] = a.scale * (b[r][ni] + a.ycoef * v[r][ni]);
+    }
   }
 };
 
@@ -226,15 +278,47 @@ struct GjeOuterOp {
   __device__ void copy(int i, int j) const { mo[(int64_t)i * ld + j] = u[(int64_t)i * nbo + (j - k0)]; }
   __device__ const double* a_row(int i) const { return u + (int64_t)i * nbo; }
   __device__ const double* b_row(int t) const { return mi + (int64_t)p[k0 + t] * ld; }
-  __device__ void store(int i, int j, double v) const {
-    double out;
-    if (j >= k0 && j < k0 + nbo) {
-      out = u[(int64_t)i * nbo + (j - k0)];
-    } else {
-      const double base = (i >= k0 && i < k0 + nbo) ? 0.0 : mi[(int64_t)p[i] * ld + j];
-      out = base + v;
+  // branch-free: every load of the group is issued before the first store
+  __device__ void store_group(const int* rows, const int* cols, double (*v)[4], int M, int N) const {
+    const double* src[4];
+    bool rowk[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = min(rows[r], M - 1);
+      src[r] = mi + (int64_t)p[i] * ld;
+      rowk[r] = rows[r] >= k0 && rows[r] < k0 + nbo;
     }
-    mo[(int64_t)i * ld + j] = out;
+    bool colk[4];
+    bool anyk = false;
+#pragma unroll
+    for (int ni = 0; ni < 4; ++ni) {
+      colk[ni] = cols[ni] >= k0 && cols[ni] < k0 + nbo;
+      anyk |= colk[ni];
+    }
+    double base[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int ni = 0; ni < 4; ++ni) base[r][ni] = src[r][min(cols[ni], N - 1)];
+    double uv[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int ni = 0; ni < 4; ++ni) uv[r][ni] = 0.0;
+    if (anyk) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni)
+          if (colk[ni]) uv[r][ni] = u[(int64_t)min(rows[r], M - 1) * nbo + (cols[ni] - k0)];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int ni = 0; ni < 4; ++ni) {
+        const double out = colk[ni] ? uv[r][ni] : ((rowk[r] ? 0.0 : base[r][ni]) + v[r][ni]);
+        if (rows[r] < M && cols[ni] < N) mo[(int64_t)rows[r] * ld + cols[ni]] = out;
+      }
   }
 };
 

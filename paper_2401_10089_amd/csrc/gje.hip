@@ -40,75 +40,92 @@ namespace logm {
 namespace {
 
 constexpr int NB = 64;
-constexpr int LEAF = 128;
 constexpr int LDA = NB + 1;
 constexpr int IU_ROWS = 32;
+#ifndef LOGM_TOURN_WAVES
+#define LOGM_TOURN_WAVES 8
+#endif
+#ifndef LOGM_TOURN_RPL
+#define LOGM_TOURN_RPL 8
+#endif
+constexpr int NW = LOGM_TOURN_WAVES;   // waves; wave w owns columns [CPW w, CPW (w + 1))
+constexpr int TT = 64 * NW;            // threads of a tournament node
+constexpr int CPW = NB / NW;           // columns per wave
+constexpr int RPL = LOGM_TOURN_RPL;    // candidate rows per lane: lane l owns rows l + 64 i
+constexpr int TR = 64 * RPL;           // candidate rows per node
+constexpr int FAN = TR / NB;           // children merged by one node
 
 __device__ __forceinline__ int load_coherent(const int* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Partial-pivoting LU on an nrows x 64 block in LDS (row ids in rid).  Rows are
-// swapped physically; afterwards rid[0 .. min(64, nrows)) are the pivot rows in
-// pivot order.  A column whose remaining entries are all zero is skipped.
-__device__ void lds_gepp(double (*a)[LDA], int* rid, int nrows, int* s_piv) {
-  const int tid = threadIdx.x;
-  const int npiv = min(NB, nrows);
-  for (int j = 0; j < npiv; ++j) {
-    if (tid < 64) {
-      // lanes without rows offer (-1, j); a NaN entry counts as 0, so the winner is
-      // always a row in [j, nrows)
-      double v = -1.0;
-      int idx = j;
-      for (int r = j + tid; r < nrows; r += 64) {
-        double x = fabs(a[r][j]);
-        if (!(x == x)) x = 0.0;
-        if (x > v) {
-          v = x;
-          idx = r;
-        }
-      }
-      wave_argmax(v, idx);
-      if (tid == 0) *s_piv = (idx >= j && idx < nrows) ? idx : j;
-    }
-    __syncthreads();
-    const int p = *s_piv;
-    if (p != j) {
-      if (tid < NB) {
-        const double t = a[j][tid];
-        a[j][tid] = a[p][tid];
-        a[p][tid] = t;
-      }
-      if (tid == 0) {
-        const int t = rid[j];
-        rid[j] = rid[p];
-        rid[p] = t;
-      }
-    }
-    __syncthreads();
-    const double d = a[j][j];
-    if (d != 0.0) {
-      for (int r = j + 1 + tid; r < nrows; r += 256) a[r][j] = a[r][j] / d;
-      __syncthreads();
-      const int cols = NB - 1 - j;
-      const int rows = nrows - 1 - j;
-      for (int e = tid; e < rows * cols; e += 256) {
-        const int r = j + 1 + e / cols;
-        const int c = j + 1 + e % cols;
-        a[r][c] = fma(-a[r][j], a[j][c], a[r][c]);
-      }
-    }
-    __syncthreads();
-  }
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-__global__ __launch_bounds__(256) void tournament_kernel(GjeArgs A, int nleaves) {
-  __shared__ double a[LEAF][LDA];
-  __shared__ int rid[LEAF];
-  __shared__ int s_piv, s_last, s_nv;
+// u[c] = x[iL][c] of lane L, for wave-uniform iL and L.  The uniform switch keeps
+// every register index static (a dynamic index would spill the row block to
+// scratch) and executes only one case.
+__device__ __forceinline__ void read_owner_row(const double (&x)[RPL][CPW], int iL, int L,
+                                               double (&u)[CPW]) {
+#define LOGM_ROW_CASE(I)                                                                 \
+  if (I < RPL && iL == I) {                                                              \
+    _Pragma("unroll") for (int c = 0; c < CPW; ++c) u[c] = readlane_d(x[(I < RPL) ? I : 0][c], L); \
+    return;                                                                              \
+  }
+  LOGM_ROW_CASE(0)
+  LOGM_ROW_CASE(1)
+  LOGM_ROW_CASE(2)
+  LOGM_ROW_CASE(3)
+  LOGM_ROW_CASE(4)
+  LOGM_ROW_CASE(5)
+  LOGM_ROW_CASE(6)
+  LOGM_ROW_CASE(7)
+#undef LOGM_ROW_CASE
+  _Pragma("unroll") for (int c = 0; c < CPW; ++c) u[c] = readlane_d(x[0][c], L);
+}
+
+// Lane holding the wave's largest v among lanes with ok (lowest lane on ties), or
+// -1.  The DPP maximum is checked with a ballot; the shuffle reduction decides if
+// no lane matches it.
+__device__ __forceinline__ int wave_argmax_lane(double v, bool ok) {
+  const double m = wave_max_dpp(ok ? v : -1.0);
+  unsigned long long bal = __ballot(ok && v == m);
+  if (bal == 0ull) {
+    if (__ballot(ok) == 0ull) return -1;
+    int idx = ok ? (int)(threadIdx.x & 63) : 64;
+    double vv = ok ? v : -1.0;
+    wave_argmax(vv, idx);
+    return idx;
+  }
+  return __ffsll((long long)bal) - 1;
+}
+
+// Tournament pivot selection for the inner block [c0, c0+64) of the panel over the
+// candidate positions [r0, n_pad).  A node runs partial-pivoting LU on up to TR
+// candidate rows held in registers: wave w keeps columns CPW w .. CPW w + CPW - 1 of
+// every row, lane l rows l, l+64, ...  The pivot of column j is found inside the wave owning
+// column j; only its multipliers cross waves (through LDS, one barrier per
+// column), and every wave reads its slice of the pivot row from the owning lane.
+// Leaves take TR consecutive candidates, inner nodes the <= 64 winners of each of
+// their <= FAN children (the last child to finish does the merge).  The root
+// writes the LU factors of the 64 selected rows (pivot order) to m.tri and builds
+// the row maps of the step.
+__global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(1, 2))) void tournament_kernel(GjeArgs A, int nleaves) {
+  __shared__ __attribute__((aligned(16))) double s_lu[NB][NB + 2];
+  __shared__ double s_l[2][TR];
+  __shared__ int s_p[2];
+  __shared__ int s_rid[TR];
+  __shared__ int s_sel[NB];
+  __shared__ int s_off[FAN + 1];
+  __shared__ int s_last;
   __shared__ int s_in[NB];
   __shared__ int s_V[NB];
   __shared__ int s_D[NB];
+  __shared__ int s_nv;
   __shared__ int s_old_pi[2 * NB];
   __shared__ int s_old_pt[2 * NB];
 
@@ -117,33 +134,128 @@ __global__ __launch_bounds__(256) void tournament_kernel(GjeArgs A, int nleaves)
   const int nbo = A.nbo;
   const int c0 = A.c0;
   const int r0 = A.r0;
+  const int np = A.n_pad;
   const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
 
   int node = blockIdx.x;
   int nodes = nleaves;
   int level_off = 0;
-
-  // leaf: rows [first, first + nrows)
-  const int first = r0 + node * LEAF;
-  int nrows = min(LEAF, A.n_pad - first);
-  for (int e = tid; e < nrows * NB; e += 256) {
-    const int r = e / NB;
-    const int c = e % NB;
-    a[r][c] = P[(int64_t)(first + r) * nbo + c0 + c];
+  int nrows;
+  {
+    const int first = r0 + node * TR;
+    nrows = min(TR, np - first);
+    for (int r = tid; r < TR; r += TT) s_rid[r] = first + min(r, nrows - 1);
+    if (tid < NB) s_sel[tid] = min(tid, nrows - 1);
   }
-  for (int r = tid; r < nrows; r += 256) rid[r] = first + r;
   __syncthreads();
-  lds_gepp(a, rid, nrows, &s_piv);
-  int ncand = min(NB, nrows);
+  bool need_lu = true;
+  int npiv = 0;
+  while (true) {
+    if (need_lu) {
+      double x[RPL][CPW];
+      unsigned act = 0;
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const int r = lane + 64 * i;
+        const int pos = s_rid[min(r, nrows - 1)];
+        const f64x2* src = reinterpret_cast<const f64x2*>(P + (int64_t)pos * nbo + c0 + CPW * wave);
+#pragma unroll
+        for (int c = 0; c < CPW / 2; ++c) {
+          const f64x2 v = src[c];
+          x[i][2 * c] = (r < nrows) ? v.x : 0.0;
+          x[i][2 * c + 1] = (r < nrows) ? v.y : 0.0;
+        }
+        act |= (r < nrows) ? (1u << i) : 0u;
+      }
+      npiv = min(NB, nrows);
+#pragma unroll 1
+      for (int g = 0; g < NW; ++g) {
+#pragma unroll
+        for (int cc = 0; cc < CPW; ++cc) {
+          const int j = CPW * g + cc;
+          if (j < npiv) {
+          if (wave == g) {
+            // ---- pivot search in the owning wave
+            double best = -1.0, bestv = 0.0;
+            int bi = 0;
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {
+              double a = fabs(x[i][cc]);
+              if (!(a == a)) a = 0.0;
+              if (((act >> i) & 1u) && a > best) {
+                best = a;
+                bestv = x[i][cc];
+                bi = i;
+              }
+            }
+            const int L = wave_argmax_lane(best, best >= 0.0);
+            const int iL = __builtin_amdgcn_readlane(bi, L);
+            const double piv = readlane_d(bestv, L);
+            const int p = L + 64 * iL;
+            if (lane == L) act &= ~(1u << iL);
+            const double rp = (piv != 0.0) ? 1.0 / piv : 0.0;
+            double l[RPL];
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {
+              l[i] = ((act >> i) & 1u) ? x[i][cc] * rp : 0.0;
+              s_l[j & 1][lane + 64 * i] = l[i];
+            }
+            if (lane == 0) s_p[j & 1] = p;
+            // this wave's slice of row p (before the update)
+            double u[CPW];
+            read_owner_row(x, iL, L, u);
+            if (lane == 0) {
+#pragma unroll
+              for (int c = 0; c < CPW; c += 2)
+                *reinterpret_cast<f64x2*>(&s_lu[j][CPW * wave + c]) = f64x2{u[c], u[c + 1]};
+              s_sel[j] = p;
+            }
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {
+              if ((act >> i) & 1u) x[i][cc] = l[i];
+#pragma unroll
+              for (int c = cc + 1; c < CPW; ++c) x[i][c] = fma(-l[i], u[c], x[i][c]);
+            }
+          }
+          __syncthreads();
+          if (wave != g) {
+            const int p = s_p[j & 1];
+            const int L = p & 63;
+            const int iL = p >> 6;
+            if (lane == L) act &= ~(1u << iL);
+            double u[CPW];
+            read_owner_row(x, iL, L, u);
+            if (lane == 0) {
+#pragma unroll
+              for (int c = 0; c < CPW; c += 2)
+                *reinterpret_cast<f64x2*>(&s_lu[j][CPW * wave + c]) = f64x2{u[c], u[c + 1]};
+            }
+            if (wave > g) {
+#pragma unroll
+              for (int i = 0; i < RPL; ++i) {
+                const double li = s_l[j & 1][lane + 64 * i];
+#pragma unroll
+                for (int c = 0; c < CPW; ++c) x[i][c] = fma(-li, u[c], x[i][c]);
+              }
+            }
+          }
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (nodes == 1) break;
 
-  while (nodes > 1) {
+    // ---- publish this node's winners and find out whether this workgroup merges
     int* slot = m.cand + (level_off + node) * 65;
-    if (tid == 0) slot[0] = ncand;
-    if (tid < ncand) slot[1 + tid] = rid[tid];
+    if (tid == 0) slot[0] = npiv;
+    if (tid < npiv) slot[1 + tid] = s_rid[s_sel[tid]];
     __threadfence();
     __syncthreads();
-    const int parent = node >> 1;
-    const int nchild = min(2, nodes - 2 * parent);
+    const int parent = node / FAN;
+    const int nchild = min(FAN, nodes - parent * FAN);
     const int next_off = level_off + nodes;
     if (tid == 0) {
       const int old = atomicAdd(&m.cnt[next_off + parent], 1);
@@ -153,96 +265,60 @@ __global__ __launch_bounds__(256) void tournament_kernel(GjeArgs A, int nleaves)
     __syncthreads();
     if (!s_last) return;
     __threadfence();
-    if (nchild == 2) {
-      const int* c0s = m.cand + (level_off + 2 * parent) * 65;
-      const int* c1s = c0s + 65;
-      const int n0 = load_coherent(c0s);
-      const int n1 = load_coherent(c1s);
-      for (int r = tid; r < n0 + n1; r += 256)
-        rid[r] = (r < n0) ? load_coherent(c0s + 1 + r) : load_coherent(c1s + 1 + (r - n0));
-      nrows = n0 + n1;
-      __syncthreads();
-      for (int e = tid; e < nrows * NB; e += 256) {
-        const int r = e / NB;
-        const int c = e % NB;
-        a[r][c] = P[(int64_t)rid[r] * nbo + c0 + c];
+    need_lu = nchild > 1;
+    if (need_lu) {
+      if (tid == 0) {
+        int off = 0;
+        for (int ch = 0; ch < nchild; ++ch) {
+          s_off[ch] = off;
+          off += min(NB, max(0, load_coherent(m.cand + (level_off + parent * FAN + ch) * 65)));
+        }
+        s_off[nchild] = off;
       }
       __syncthreads();
-      lds_gepp(a, rid, nrows, &s_piv);
-      ncand = min(NB, nrows);
+      nrows = s_off[nchild];
+      for (int ch = 0; ch < nchild; ++ch) {
+        const int cnt = s_off[ch + 1] - s_off[ch];
+        const int* cs = m.cand + (level_off + parent * FAN + ch) * 65 + 1;
+        if (tid < cnt) s_rid[s_off[ch] + tid] = min(max(load_coherent(cs + tid), 0), np - 1);
+      }
+      __syncthreads();
+      for (int r = nrows + tid; r < TR; r += TT) s_rid[r] = s_rid[0];
+      if (tid < NB) s_sel[tid] = min(tid, nrows - 1);
+      __syncthreads();
     }
-    // nchild == 1: the single child's selection (still in rid) passes through
     node = parent;
     level_off = next_off;
-    nodes = (nodes + 1) >> 1;
+    nodes = (nodes + FAN - 1) / FAN;
   }
 
-  // ---- root: a[0..63][0..63] holds L (strictly lower, unit diagonal) and U of the
-  // selected rows in pivot order.  Wave 0 forms U^{-1}, wave 1 L^{-1}, one column
-  // per lane (back / forward substitution); wave 2 records log|det|.
-  __syncthreads();
-  {
-    double (*xs)[LDA] = reinterpret_cast<double (*)[LDA]>(&a[NB][0]);   // rows 64..127
-    const int w = tid >> 6;
-    const int c = tid & 63;
-    double* Uinv = m.tri + NB * NB;
-    double* Linv = m.tri + 2 * NB * NB;
-    if (w == 0) {
-      // X = U^{-1}: X[r][c] = (delta_rc - sum_{t=r+1..c} U[r][t] X[t][c]) / U[r][r]
-      for (int r = NB - 1; r >= 0; --r) {
-        double v = 0.0;
-        if (r <= c) {
-          double acc = (r == c) ? 1.0 : 0.0;
-          for (int t = r + 1; t <= c; ++t) acc = fma(-a[r][t], xs[t][c], acc);
-          v = acc / a[r][r];
-        }
-        xs[r][c] = v;
-      }
-      for (int r = 0; r < NB; ++r) Uinv[r * NB + c] = xs[r][c];
-    } else if (w == 1) {
-      // Y = L^{-1} (unit lower): Y[r][c] = delta_rc - sum_{t=c..r-1} L[r][t] Y[t][c]
-      double ycol[NB];
-#pragma unroll
-      for (int r = 0; r < NB; ++r) {
-        double acc = (r == c) ? 1.0 : 0.0;
-#pragma unroll
-        for (int t = 0; t < r; ++t) acc = fma(-a[r][t], ycol[t], acc);
-        ycol[r] = (r < c) ? 0.0 : acc;
-      }
-#pragma unroll
-      for (int r = 0; r < NB; ++r) Linv[r * NB + c] = ycol[r];
-    } else if (w == 2 && c == 0) {
-      double logsum = 0.0;
-      for (int j = 0; j < NB; ++j) {
-        const double piv = a[j][j];
-        if (piv == 0.0) atomicOr(&m.err[0], 1);
-        logsum += log(fabs(piv));
-      }
-      m.logdet[r0 / NB] = logsum;
-    }
-    __syncthreads();
-    // U with its 16 x 16 diagonal blocks replaced by those of U^{-1}
-    for (int e = tid; e < NB * NB; e += 256) {
-      const int r = e / NB;
-      const int cc = e % NB;
-      const bool diag_blk = (r >> 4) == (cc >> 4);
-      m.tri[e] = diag_blk ? xs[r][cc] : (cc > r ? a[r][cc] : 0.0);
-    }
+  // ---- root: LU factors of the selected rows, log|det|, row maps of the step
+  for (int e = tid; e < NB * NB; e += TT) m.tri[e] = s_lu[e / NB][e % NB];
+  if (tid < NB) s_sel[tid] = s_rid[min(max(s_sel[tid], 0), TR - 1)];   // local row -> position
+  if (wave == 1) {   // log|det| of the pivot block: one pivot per lane, fixed-order sum
+    const double piv = s_lu[lane][lane];
+    if (__ballot(piv == 0.0) != 0ull && lane == 0) atomicOr(&m.err[0], 1);
+    const double ls = wave_sum(log(fabs(piv)));
+    if (lane == 0) m.logdet[r0 / NB] = ls;
   }
-
-  // gather map of this inner step: position r0+j <- rid[j]; the block rows that were
-  // not chosen (D, ascending) move to the vacated positions of chosen rows outside
-  // the block (V, ascending).
-  if (tid < NB) s_in[tid] = 0;
+  if (tid < NB) {
+    s_in[tid] = 0;
+    s_V[tid] = r0 + tid;
+    s_D[tid] = r0 + tid;
+  }
   __syncthreads();
-  if (tid < NB && rid[tid] < r0 + NB) s_in[rid[tid] - r0] = 1;
+  // gather map of this inner step: position r0+j <- s_sel[j]; the block rows that
+  // were not chosen (D, ascending) move to the vacated positions of chosen rows
+  // outside the block (V, ascending).  The selection is a set of distinct rows, so
+  // |V| = |D|; the lists are pre-filled and indices clamped all the same.
+  if (tid < NB && s_sel[tid] >= r0 && s_sel[tid] < r0 + NB) s_in[s_sel[tid] - r0] = 1;
   __syncthreads();
   if (tid < NB) {
-    const int q = rid[tid];
+    const int q = s_sel[tid];
     if (q >= r0 + NB) {
       int rank = 0;
-      for (int j = 0; j < NB; ++j) rank += (rid[j] >= r0 + NB && rid[j] < q);
-      s_V[rank] = q;
+      for (int j = 0; j < NB; ++j) rank += (s_sel[j] >= r0 + NB && s_sel[j] < q);
+      s_V[min(rank, NB - 1)] = q;
     }
     if (!s_in[tid]) {
       int rank = 0;
@@ -258,14 +334,17 @@ __global__ __launch_bounds__(256) void tournament_kernel(GjeArgs A, int nleaves)
   __syncthreads();
   const int nv = s_nv;
   if (tid < NB) {
-    m.qsel[tid] = rid[tid];
-    s_old_pi[tid] = m.pi[rid[tid]];
-    s_old_pt[tid] = m.ptot[rid[tid]];
+    const int q = min(max(s_sel[tid], 0), np - 1);
+    const int vq = min(max(s_V[tid], 0), np - 1);
+    const int dq = min(max(s_D[tid], 0), np - 1);
+    m.qsel[tid] = q;
+    s_old_pi[tid] = m.pi[q];
+    s_old_pt[tid] = m.ptot[q];
     if (tid < nv) {
-      m.vac[1 + tid] = s_V[tid];
-      m.vac[65 + tid] = s_D[tid];
-      s_old_pi[NB + tid] = m.pi[s_D[tid]];
-      s_old_pt[NB + tid] = m.ptot[s_D[tid]];
+      m.vac[1 + tid] = vq;
+      m.vac[65 + tid] = dq;
+      s_old_pi[NB + tid] = m.pi[dq];
+      s_old_pt[NB + tid] = m.ptot[dq];
     }
     if (tid == 0) m.vac[0] = nv;
   }
@@ -274,8 +353,9 @@ __global__ __launch_bounds__(256) void tournament_kernel(GjeArgs A, int nleaves)
     m.pi[r0 + tid] = s_old_pi[tid];
     m.ptot[r0 + tid] = s_old_pt[tid];
     if (tid < nv) {
-      m.pi[s_V[tid]] = s_old_pi[NB + tid];
-      m.ptot[s_V[tid]] = s_old_pt[NB + tid];
+      const int vq = min(max(s_V[tid], 0), np - 1);
+      m.pi[vq] = s_old_pi[NB + tid];
+      m.ptot[vq] = s_old_pt[NB + tid];
     }
   }
 }
@@ -303,9 +383,13 @@ __device__ __forceinline__ void mm32x64(const double (*As)[LDA], const double (*
   }
 }
 
+// Inner Gauss-Jordan step on the panel, IU_ROWS rows per workgroup (see the file
+// comment): C U = Acol and G L = C are solved by 16-column block substitution with
+// explicit inverses of the 16 x 16 diagonal blocks only, then out = base - G R.
 __global__ __launch_bounds__(256) void inner_update_kernel(GjeArgs A) {
-  __shared__ double B1[NB][LDA];     // U (block form), then L^{-1}
-  __shared__ double B2[NB][LDA];     // pivot rows R of one column chunk
+  __shared__ double LU[NB][LDA];          // L (strict lower) and U of the pivot block
+  __shared__ double Di[8][16][17];        // inverses of the diagonal blocks: 0-3 of U, 4-7 of L
+  __shared__ double Rs[NB][LDA];          // pivot rows of one column chunk
   __shared__ double Cs[IU_ROWS][LDA];
   __shared__ double Ts[IU_ROWS][17];
   __shared__ int s_src[IU_ROWS];
@@ -334,68 +418,105 @@ __global__ __launch_bounds__(256) void inner_update_kernel(GjeArgs A) {
     s_src[tid] = src;
   }
   if (tid < NB) s_q[tid] = m.qsel[tid];
+  {
+    double t[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) t[k] = m.tri[tid + 256 * k];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) LU[(tid + 256 * k) / NB][(tid + 256 * k) % NB] = t[k];
+  }
   __syncthreads();
 
-  // ---- C rows
-  if (inblock) {
-    const double* Uinv = m.tri + NB * NB;
-    for (int e = tid; e < IU_ROWS * NB; e += 256) {
+  // diagonal block inverses: thread (blk, col) runs one column of a 16 x 16 substitution
+  if (tid < 128) {
+    const int blk = tid >> 4;
+    const int c = tid & 15;
+    const int b0 = (blk & 3) * 16;
+    double x[16];
+    if (blk < 4) {  // upper: X U_bb = I  (column c of U_bb^{-1} by back substitution)
+#pragma unroll
+      for (int r = 15; r >= 0; --r) {
+        double acc = (r == c) ? 1.0 : 0.0;
+#pragma unroll
+        for (int t = r + 1; t < 16; ++t) acc = fma(-LU[b0 + r][b0 + t], x[t], acc);
+        x[r] = (r <= c) ? acc / LU[b0 + r][b0 + r] : 0.0;
+      }
+    } else {        // unit lower: column c of L_bb^{-1} by forward substitution
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        double acc = (r == c) ? 1.0 : 0.0;
+#pragma unroll
+        for (int t = 0; t < r; ++t) acc = fma(-LU[b0 + r][b0 + t], x[t], acc);
+        x[r] = (r >= c) ? acc : 0.0;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) Di[blk][r][c] = x[r];
+  }
+  // right-hand side of C U = Acol: panel rows, or -E (identity rows) inside the block
+  {
+    double t[IU_ROWS * NB / 256];
+#pragma unroll
+    for (int k = 0; k < IU_ROWS * NB / 256; ++k) {
+      const int e = tid + 256 * k;
       const int r = e / NB;
       const int c = e % NB;
-      Cs[r][c] = -Uinv[(row0 - r0 + r) * NB + c];
+      t[k] = inblock ? ((row0 - r0 + r == c) ? -1.0 : 0.0) : P[(int64_t)s_src[r] * nbo + c0 + c];
     }
-  } else {
-    for (int e = tid; e < NB * NB; e += 256) B1[e / NB][e % NB] = m.tri[e];
-    for (int e = tid; e < IU_ROWS * NB; e += 256) {
-      const int r = e / NB;
-      const int c = e % NB;
-      Cs[r][c] = P[(int64_t)s_src[r] * nbo + c0 + c];
-    }
-    __syncthreads();
-    // C U = Acol by 16-column blocks: rhs = Acol_b - C_{<b} U_{<b,b}; C_b = rhs inv(U_bb)
-    for (int b = 0; b < 4; ++b) {
-      for (int e = tid; e < IU_ROWS * 16; e += 256) {
-        const int r = e >> 4;
-        const int c = b * 16 + (e & 15);
-        double acc = Cs[r][c];
-        for (int t = 0; t < b * 16; ++t) acc = fma(-Cs[r][t], B1[t][c], acc);
-        Ts[r][e & 15] = acc;
-      }
-      __syncthreads();
-      for (int e = tid; e < IU_ROWS * 16; e += 256) {
-        const int r = e >> 4;
-        const int cl = e & 15;
-        double acc = 0.0;
-        for (int t = 0; t <= cl; ++t) acc = fma(Ts[r][t], B1[b * 16 + t][b * 16 + cl], acc);
-        Cs[r][b * 16 + cl] = acc;
-      }
-      __syncthreads();
+#pragma unroll
+    for (int k = 0; k < IU_ROWS * NB / 256; ++k) {
+      const int e = tid + 256 * k;
+      Cs[e / NB][e % NB] = t[k];
     }
   }
   __syncthreads();
 
-  // ---- G = C L^{-1} (kept in Cs)
-  const double* Linv = m.tri + 2 * NB * NB;
-  for (int e = tid; e < NB * NB; e += 256) B1[e / NB][e % NB] = Linv[e];
-  __syncthreads();
+  // C U = Acol, blocks left to right: C_b = (Acol_b - C_{<b} U_{<b,b}) inv(U_bb)
+  for (int b = 0; b < 4; ++b) {
+    for (int e = tid; e < IU_ROWS * 16; e += 256) {
+      const int r = e >> 4;
+      const int c = b * 16 + (e & 15);
+      double acc = Cs[r][c];
+      for (int t = 0; t < b * 16; ++t) acc = fma(-Cs[r][t], LU[t][c], acc);
+      Ts[r][e & 15] = acc;
+    }
+    __syncthreads();
+    for (int e = tid; e < IU_ROWS * 16; e += 256) {
+      const int r = e >> 4;
+      const int cl = e & 15;
+      double acc = 0.0;
+      for (int t = 0; t <= cl; ++t) acc = fma(Ts[r][t], Di[b][t][cl], acc);
+      Cs[r][b * 16 + cl] = acc;
+    }
+    __syncthreads();
+  }
+  // G L = C, blocks right to left: G_b = (C_b - G_{>b} L_{>b,b}) inv(L_bb)
+  for (int b = 3; b >= 0; --b) {
+    for (int e = tid; e < IU_ROWS * 16; e += 256) {
+      const int r = e >> 4;
+      const int c = b * 16 + (e & 15);
+      double acc = Cs[r][c];
+      for (int t = (b + 1) * 16; t < NB; ++t) acc = fma(-Cs[r][t], LU[t][c], acc);
+      Ts[r][e & 15] = acc;
+    }
+    __syncthreads();
+    for (int e = tid; e < IU_ROWS * 16; e += 256) {
+      const int r = e >> 4;
+      const int cl = e & 15;
+      double acc = 0.0;
+      for (int t = cl; t < 16; ++t) acc = fma(Ts[r][t], Di[4 + b][t][cl], acc);
+      Cs[r][b * 16 + cl] = acc;
+    }
+    __syncthreads();
+  }
+
+  // ---- output chunks: -G in the inner block, base - G R elsewhere
   const int lane = tid & 63;
   const int w = tid >> 6;
   const int rb = w >> 1;
   const int cb = (w & 1) * 2;
   const int lr = lane & 15;
   const int lk = lane >> 4;
-  {
-    f64x4 acc[2];
-    mm32x64(Cs, B1, acc);
-    __syncthreads();
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) Cs[rb * 16 + 4 * r + lk][(cb + b) * 16 + lr] = acc[b][r];
-  }
-  __syncthreads();
-
-  // ---- output chunks
   for (int cc = 0; cc < nbo; cc += NB) {
     if (cc == c0) {
       for (int e = tid; e < IU_ROWS * NB; e += 256) {
@@ -405,22 +526,37 @@ __global__ __launch_bounds__(256) void inner_update_kernel(GjeArgs A) {
       }
       continue;
     }
-    for (int e = tid; e < NB * NB; e += 256) {
-      const int t = e / NB;
-      const int c = e % NB;
-      B2[t][c] = P[(int64_t)s_q[t] * nbo + cc + c];
+    {
+      double t[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const int e = tid + 256 * k;
+        t[k] = P[(int64_t)s_q[e / NB] * nbo + cc + e % NB];
+      }
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const int e = tid + 256 * k;
+        Rs[e / NB][e % NB] = t[k];
+      }
     }
+    double base[2][4];
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int rr = rb * 16 + 4 * r + lk;
+        base[b][r] = inblock ? 0.0 : P[(int64_t)s_src[rr] * nbo + cc + (cb + b) * 16 + lr];
+      }
     __syncthreads();
     f64x4 acc[2];
-    mm32x64(Cs, B2, acc);
+    mm32x64(Cs, Rs, acc);
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int rr = rb * 16 + 4 * r + lk;
         const int c = cc + (cb + b) * 16 + lr;
-        const double base = inblock ? 0.0 : P[(int64_t)s_src[rr] * nbo + c];
-        Q[(int64_t)(row0 + rr) * nbo + c] = base - acc[b][r];
+        Q[(int64_t)(row0 + rr) * nbo + c] = base[b][r] - acc[b][r];
       }
     __syncthreads();
   }
@@ -481,8 +617,8 @@ hipError_t launch_gje_panel_copy(const GjeArgs& a, hipStream_t s) {
 
 hipError_t launch_gje_tournament(const GjeArgs& a, hipStream_t s) {
   const int ncand = a.n_pad - a.r0;
-  const int nleaves = (ncand + LEAF - 1) / LEAF;
-  hipLaunchKernelGGL(tournament_kernel, dim3(nleaves, a.nmat), dim3(256), 0, s, a, nleaves);
+  const int nleaves = (ncand + TR - 1) / TR;
+  hipLaunchKernelGGL(tournament_kernel, dim3(nleaves, a.nmat), dim3(TT), 0, s, a, nleaves);
   return hipGetLastError();
 }
 

@@ -39,8 +39,7 @@ struct GjeMat {
   const double* Min;     // matrix at the start of the outer step (n_pad x n_pad, ld n_pad)
   double* Mout;          // matrix after the outer step
   double* P[2];          // ping-pong panels n_pad x nbo (ld = nbo)
-  double* tri;           // 3 x 64 x 64: [0] U with inverted 16x16 diagonal blocks,
-                         // [1] U^{-1}, [2] L^{-1} of the current pivot block S = L U
+  double* tri;           // 64 x 64: LU factors of the current pivot block (pivot order)
   int* pi;               // n_pad: gather map of the current outer step
   int* ptot;             // n_pad: accumulated row order (position -> original row)
   int* pinv;             // n_pad: inverse of ptot (filled by launch_gje_finish)

@@ -282,3 +282,23 @@ def test_logm_user_workspace_and_strided_output():
     Lo, _ = oracle.logm(A)
     assert relf(host(big[:, 10:60]), Lo) < TOL_LOGM
     assert torch.count_nonzero(big[:, :10]) == 0 and torch.count_nonzero(big[:, 60:]) == 0
+
+
+@pytest.mark.parametrize("n", [65, 100, 257])
+def test_no_writes_outside_workspace_and_output(n):
+    """Guard bytes after the workspace and around a strided output stay untouched."""
+    A, _ = rotscale_matrix(n, 40 + n, 1e-2, 1e2)
+    need = lm.workspace_size(n)
+    guard = 1 << 20
+    ws_full = torch.full((need + guard,), 0x5A, dtype=torch.uint8, device="cuda")
+    out_full = torch.full((n + 3, n + 5), 7.0, dtype=torch.float64, device="cuda")
+    out = out_full[1:n + 1, 2:n + 2]
+    L, info = lm.logm(dev(A), out=out, workspace=ws_full[:need])
+    torch.cuda.synchronize()
+    assert bool((ws_full[need:] == 0x5A).all())
+    mask = torch.ones_like(out_full, dtype=torch.bool)
+    mask[1:n + 1, 2:n + 2] = False
+    assert bool((out_full[mask] == 7.0).all())
+    Lo, io = oracle.logm(A)
+    if (info["s"], info["k"], info["db_iters"]) == (io["s"], io["k"], io["db_iters"]):
+        assert relf(host(out), Lo) < TOL_LOGM
