@@ -23,6 +23,23 @@ if ROOT not in sys.path:
 MFMA_FP64_PEAK_TFLOPS = 78.6     # MI355X dense fp64 matrix peak
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of the dominant kernel, from the rocprofv3 FETCH_SIZE and
+# WRITE_SIZE counter runs summarised in profiles/, each scaled by what the same
+# counter reads for a plain copy of known size (--copy-calibration).  Tied to the
+# kernel source it was measured on: any later edit of that file voids it.
+TRAFFIC = None   # {"bytes_per_launch": float, "source_sha256": str}
+TRAFFIC_SOURCE = os.path.join(ROOT, "paper_2401_10089_amd", "csrc", "gemm_f64.hip")
+COPY_CALIBRATION_DOUBLES = 1 << 27   # 1 GiB read + 1 GiB written
+
+
+def traffic_per_launch():
+    if TRAFFIC is None:
+        return None
+    import hashlib
+    with open(TRAFFIC_SOURCE, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    return TRAFFIC["bytes_per_launch"] if sha == TRAFFIC["source_sha256"] else None
+
 WORKLOAD = "rotscale4096"
 N = 4096
 
@@ -68,6 +85,9 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed steps, run one plain copy (torch.neg) of 1 GiB so that "
+                         "counter runs can scale FETCH_SIZE / WRITE_SIZE to bytes")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (the single-matrix logm is not sharded); "
@@ -114,6 +134,14 @@ def main():
     ms_per_step = 1e3 * wall / args.steps
     value = flops / wall / 1e12
 
+    if args.copy_calibration:
+        src = torch.ones(COPY_CALIBRATION_DOUBLES, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+
     L = out.cpu().numpy()
     rel_err = float(np.linalg.norm(L - L_exact) / np.linalg.norm(L_exact))
 
@@ -125,7 +153,7 @@ def main():
         "peak": MFMA_FP64_PEAK_TFLOPS,
         "unit": "TFLOP/s",
         "frac": (achieved / MFMA_FP64_PEAK_TFLOPS) if achieved else None,
-        "traffic": None,
+        "traffic": traffic_per_launch(),
         "launches": prof["launches"],
         "avg_launch_ms": prof["ms"] / max(prof["launches"], 1),
         "algorithmic_flops_per_launch": prof["flops"] / max(prof["launches"], 1),

@@ -176,10 +176,11 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct Plan {
   int n = 0, n_pad = 0, nblk = 0;
   size_t mat[kMats];
-  size_t panel[2][2];
+  size_t panel[2][2][2];   // [matrix][outer-step parity][ping-pong]
   size_t W[2];
   size_t logdet[2];
-  size_t pi[2], ptot[2], pinv[2], qsel[2], vac[2], cand[2], cnt[2], err[2];
+  size_t pi[2][2];         // [matrix][outer-step parity]
+  size_t ptot[2], pinv[2], qsel[2], vac[2], cand[2], cnt[2], err[2];
   size_t part, bm, vec, scal, iflag;
   size_t total = 0;
 };
@@ -198,10 +199,11 @@ Plan make_plan(int64_t n) {
   const size_t np = (size_t)p.n_pad;
   for (int i = 0; i < kMats; ++i) p.mat[i] = take(np * np * sizeof(double));
   for (int z = 0; z < 2; ++z) {
-    for (int b = 0; b < 2; ++b) p.panel[z][b] = take(np * kNBO * sizeof(double));
+    for (int q = 0; q < 2; ++q)
+      for (int b = 0; b < 2; ++b) p.panel[z][q][b] = take(np * kNBO * sizeof(double));
     p.W[z] = take(kNB * kNB * sizeof(double));
     p.logdet[z] = take(np / kNB * sizeof(double));
-    p.pi[z] = take(np * sizeof(int));
+    for (int q = 0; q < 2; ++q) p.pi[z][q] = take(np * sizeof(int));
     p.ptot[z] = take(np * sizeof(int));
     p.pinv[z] = take(np * sizeof(int));
     p.qsel[z] = take(kNB * sizeof(int));
@@ -244,6 +246,9 @@ struct Status {
 
 struct Ctx {
   hipStream_t s = nullptr;
+  hipStream_t side = nullptr;     // factors the next Gauss-Jordan panel (look-ahead)
+  hipEvent_t ev_upd = nullptr;    // next panel's columns updated (on s)
+  hipEvent_t ev_pan = nullptr;    // next panel factored (on side)
   Plan p;
   char* base = nullptr;
   double* mat(int i) const { return reinterpret_cast<double*>(base + p.mat[i]); }
@@ -274,16 +279,16 @@ Status norm1(Ctx& c, const double* M, double* out) {
 }
 
 // ------------------------------------------------------- Gauss-Jordan ----
-GjeArgs gje_args(Ctx& c, int nmat) {
+GjeArgs gje_args(Ctx& c, int nmat, int parity) {
   GjeArgs a{};
   a.nmat = nmat;
   a.n_pad = c.p.n_pad;
   for (int z = 0; z < nmat; ++z) {
     GjeMat& m = a.m[z];
-    m.P[0] = c.at<double>(c.p.panel[z][0]);
-    m.P[1] = c.at<double>(c.p.panel[z][1]);
+    m.P[0] = c.at<double>(c.p.panel[z][parity][0]);
+    m.P[1] = c.at<double>(c.p.panel[z][parity][1]);
     m.tri = c.at<double>(c.p.W[z]);
-    m.pi = c.at<int>(c.p.pi[z]);
+    m.pi = c.at<int>(c.p.pi[z][parity]);
     m.ptot = c.at<int>(c.p.ptot[z]);
     m.pinv = c.at<int>(c.p.pinv[z]);
     m.qsel = c.at<int>(c.p.qsel[z]);
@@ -296,49 +301,114 @@ GjeArgs gje_args(Ctx& c, int nmat) {
   return a;
 }
 
+// Outer-step geometry: step K covers the columns [k0, k0 + nbo).
+struct OuterStep {
+  int k0, nbo;
+};
+
+// Panel of one outer step: copy the block column, then the inner 64-wide steps
+// (tournament pivot selection + panel update).  pcur ends on the processed panel.
+Status factor_panel(GjeArgs& a, hipStream_t s) {
+  Status st;
+  a.pcur = 0;
+  HIPCK(launch_gje_panel_copy(a, s));
+  for (int c0 = 0; c0 < a.nbo; c0 += kNB) {
+    a.c0 = c0;
+    a.r0 = a.k0 + c0;
+    HIPCK(launch_gje_tournament(a, s));
+    HIPCK(launch_gje_inner_update(a, s));
+    a.pcur ^= 1;
+  }
+  return st;
+}
+
+Status outer_update(Ctx& c, const GjeArgs& a, int c_lo, int c_hi, bool inside) {
+  Status st;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (g_prof.on) {
+    e0 = g_prof.get();
+    e1 = g_prof.get();
+    if (e0) HIPCK(hipEventRecord(e0, c.s));
+  }
+  HIPCK(launch_gje_outer_update(a, c_lo, c_hi, inside, c.s));
+  if (g_prof.on && e0 && e1) {
+    HIPCK(hipEventRecord(e1, c.s));
+    // algorithmic work: the columns outside the step's block get a rank-nbo update
+    const double npd = a.n_pad;
+    const int tn = (a.n_pad + 127) / 128;
+    const int t_lo = std::min(std::max(c_lo / 128, 0), tn);
+    const int t_hi = std::min(std::max((c_hi + 127) / 128, t_lo), tn);
+    auto cols_in = [&](int lo, int hi) {   // columns of [lo, hi) outside the step's block
+      lo = std::min(lo, a.n_pad);
+      hi = std::min(hi, a.n_pad);
+      if (hi <= lo) return 0.0;
+      const int ov = std::max(0, std::min(hi, a.k0 + a.nbo) - std::max(lo, a.k0));
+      return (double)(hi - lo - ov);
+    };
+    const double ncols = inside ? cols_in(128 * t_lo, 128 * t_hi)
+                                : cols_in(0, 128 * t_lo) + cols_in(128 * t_hi, a.n_pad);
+    const double rows = npd;
+    g_prof.pending.push_back({e0, e1, a.nmat * 2.0 * rows * ncols * a.nbo,
+                              a.nmat * 8.0 * (2.0 * rows * ncols + rows * a.nbo)});
+  }
+  return st;
+}
+
 // Invert nmat padded matrices src[z] (identity on the pad).  The permuted result is
 // left in fin[z]; pinv, logdet slots and error flags are in the workspace.
+//
+// Look-ahead: the outer update of step K first updates the columns of step K+1's
+// panel; the side stream then factors that panel while the rest of step K's update
+// runs on the main stream.  Panels and gather maps alternate between two buffers
+// by step parity, so the side stream never touches what the running update reads.
 Status gje_invert(Ctx& c, int nmat, const double* const src[2], double* fin[2]) {
   Status st;
-  GjeArgs a = gje_args(c, nmat);
-  HIPCK(launch_gje_begin(a, c.s));
   const int np = c.p.n_pad;
+  std::vector<OuterStep> steps;
+  for (int k0 = 0; k0 < np; k0 += kNBO) steps.push_back({k0, std::min(kNBO, np - k0)});
+  const int nsteps = (int)steps.size();
+  GjeArgs a0 = gje_args(c, nmat, 0);
+  HIPCK(launch_gje_begin(a0, c.s));
   const double* cur[2] = {src[0], nmat > 1 ? src[1] : nullptr};
   int flip = 0;
-  for (int k0 = 0; k0 < np; k0 += kNBO) {
-    const int nbo = std::min(kNBO, np - k0);
-    a.k0 = k0;
-    a.nbo = nbo;
-    a.pcur = 0;
+  const bool ahead = nsteps > 1 && c.side != nullptr;
+  for (int K = 0; K < nsteps; ++K) {
+    GjeArgs a = gje_args(c, nmat, K & 1);
+    a.k0 = steps[K].k0;
+    a.nbo = steps[K].nbo;
     for (int z = 0; z < nmat; ++z) {
       a.m[z].Min = cur[z];
       a.m[z].Mout = c.mat(5 + 2 * z + flip);
     }
-    HIPCK(launch_gje_panel_copy(a, c.s));
-    for (int c0 = 0; c0 < nbo; c0 += kNB) {
-      a.c0 = c0;
-      a.r0 = k0 + c0;
-      HIPCK(launch_gje_tournament(a, c.s));
-      HIPCK(launch_gje_inner_update(a, c.s));
-      a.pcur ^= 1;
+    if (K == 0 || !ahead) {
+      PROPAGATE(factor_panel(a, c.s));
+    } else {
+      HIPCK(hipStreamWaitEvent(c.s, c.ev_pan, 0));
+      a.pcur = (a.nbo / kNB) & 1;   // where the side stream's panel ended
     }
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (g_prof.on) {
-      e0 = g_prof.get();
-      e1 = g_prof.get();
-      if (e0) HIPCK(hipEventRecord(e0, c.s));
-    }
-    HIPCK(launch_gje_outer_update(a, c.s));
-    if (g_prof.on && e0 && e1) {
-      HIPCK(hipEventRecord(e1, c.s));
-      const double npd = np;
-      g_prof.pending.push_back({e0, e1, nmat * 2.0 * npd * (npd - nbo) * nbo,
-                                nmat * 8.0 * (2.0 * npd * npd + npd * nbo)});
+    if (ahead && K + 1 < nsteps) {
+      const int n_lo = steps[K + 1].k0;
+      const int n_hi = n_lo + steps[K + 1].nbo;
+      PROPAGATE(outer_update(c, a, n_lo, n_hi, true));
+      HIPCK(hipEventRecord(c.ev_upd, c.s));
+      GjeArgs b = gje_args(c, nmat, (K + 1) & 1);
+      b.k0 = steps[K + 1].k0;
+      b.nbo = steps[K + 1].nbo;
+      for (int z = 0; z < nmat; ++z) {
+        b.m[z].Min = a.m[z].Mout;
+        b.m[z].Mout = nullptr;
+      }
+      HIPCK(hipStreamWaitEvent(c.side, c.ev_upd, 0));
+      PROPAGATE(factor_panel(b, c.side));
+      HIPCK(hipEventRecord(c.ev_pan, c.side));
+      PROPAGATE(outer_update(c, a, n_lo, n_hi, false));
+    } else {
+      PROPAGATE(outer_update(c, a, 0, np, true));
     }
     for (int z = 0; z < nmat; ++z) cur[z] = a.m[z].Mout;
     flip ^= 1;
   }
-  HIPCK(launch_gje_finish(a, c.s));
+  HIPCK(launch_gje_finish(a0, c.s));
   for (int z = 0; z < nmat; ++z) fin[z] = const_cast<double*>(cur[z]);
   return st;
 }
@@ -350,8 +420,14 @@ Status check_gje_err(Ctx& c, int nmat) {
     HIPCK(hipMemcpyAsync(h + 4 * z, c.at<int>(c.p.err[z]), 4 * sizeof(int), hipMemcpyDeviceToHost,
                          c.s));
   HIPCK(hipStreamSynchronize(c.s));
-  for (int z = 0; z < nmat; ++z)
-    if (h[4 * z] != 0) st.code = LOGM_ESINGULAR;
+  for (int z = 0; z < nmat; ++z) {
+    if (h[4 * z] & 2) {   // a bounded wait in the pivot search gave up
+      st.code = LOGM_EHIP;
+      st.detail = -1;
+      return st;
+    }
+    if (h[4 * z] & 1) st.code = LOGM_ESINGULAR;
+  }
   return st;
 }
 
@@ -808,8 +884,22 @@ struct Call {
       }
       c.base = static_cast<char*>(ws);
     }
+    // look-ahead resources; without them the inversion runs on the main stream only
+    if (hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking) != hipSuccess) c.side = nullptr;
+    if (c.side != nullptr &&
+        (hipEventCreateWithFlags(&c.ev_upd, hipEventDisableTiming) != hipSuccess ||
+         hipEventCreateWithFlags(&c.ev_pan, hipEventDisableTiming) != hipSuccess)) {
+      (void)hipStreamDestroy(c.side);
+      c.side = nullptr;
+    }
   }
   ~Call() {
+    if (c.side != nullptr) {
+      (void)hipStreamSynchronize(c.side);   // error paths can leave a panel in flight
+      (void)hipStreamDestroy(c.side);
+    }
+    if (c.ev_upd != nullptr) (void)hipEventDestroy(c.ev_upd);
+    if (c.ev_pan != nullptr) (void)hipEventDestroy(c.ev_pan);
     if (owned) {
       (void)hipFreeAsync(c.base, c.s);
       (void)hipStreamSynchronize(c.s);

@@ -9,6 +9,8 @@
 // Tiling: 128 x 128 output tile per 256-thread workgroup (2 x 2 waves of 64 x 64),
 // k-slabs of 16 staged through LDS with a double buffer; each wave issues
 // 16 independent v_mfma_f64_16x16x4 per k-step of 4.
+#include <algorithm>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -40,8 +42,13 @@ __device__ __forceinline__ void tile_of(int bid, int tiles_m, int tiles_n, int& 
   tn = in / gm;
 }
 
+// Column tiles a launch covers: [a0, a0 + na) followed by [b0, b0 + nb).
+struct TileCols {
+  int a0, na, b0, nb;
+};
+
 template <class Op>
-__global__ __launch_bounds__(256) void gemm_kernel(Op op, int M, int N, int K) {
+__global__ __launch_bounds__(256) void gemm_kernel(Op op, int M, int N, int K, TileCols tc) {
   __shared__ double As[2][BK][BM + PAD];
   __shared__ double Bs[2][BK][BN + PAD];
 
@@ -52,9 +59,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(Op op, int M, int N, int K) {
   const int wm = wave >> 1;
   const int wn = wave & 1;
   const int tiles_m = (M + BM - 1) / BM;
-  const int tiles_n = (N + BN - 1) / BN;
-  int tm, tn;
-  tile_of(blockIdx.x, tiles_m, tiles_n, tm, tn);
+  int tm, vn;
+  tile_of(blockIdx.x, tiles_m, tc.na + tc.nb, tm, vn);
+  const int tn = (vn < tc.na) ? tc.a0 + vn : tc.b0 + (vn - tc.na);
   const int row0 = tm * BM;
   const int col0 = tn * BN;
 
@@ -323,11 +330,14 @@ struct GjeOuterOp {
 };
 
 template <class Op>
-hipError_t launch(const Op& op, int M, int N, int K, int nz, hipStream_t s) {
-  const int tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
-  hipLaunchKernelGGL(gemm_kernel<Op>, dim3(tiles, 1, nz), dim3(256), 0, s, op, M, N, K);
+hipError_t launch(const Op& op, int M, int N, int K, int nz, TileCols tc, hipStream_t s) {
+  const int tiles = ((M + BM - 1) / BM) * (tc.na + tc.nb);
+  if (tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(gemm_kernel<Op>, dim3(tiles, 1, nz), dim3(256), 0, s, op, M, N, K, tc);
   return hipGetLastError();
 }
+
+TileCols all_cols(int N) { return TileCols{0, (N + BN - 1) / BN, 0, 0}; }
 
 }  // namespace
 
@@ -335,15 +345,16 @@ hipError_t launch_gemm_plain(int M, int N, int K, double alpha, const double* A,
                              const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
                              hipStream_t s) {
   PlainOp op{A, lda, B, ldb, C, ldc, alpha, beta};
-  return launch(op, M, N, K, 1, s);
+  return launch(op, M, N, K, 1, all_cols(N), s);
 }
 
 hipError_t launch_gemm_poly(int n, const PolyGemmArgs& a, hipStream_t s) {
   PolyOp op{a};
-  return launch(op, n, n, n, 1, s);
+  return launch(op, n, n, n, 1, all_cols(n), s);
 }
 
-hipError_t launch_gje_outer_update(const GjeArgs& a, hipStream_t s) {
+hipError_t launch_gje_outer_update(const GjeArgs& a, int c_lo, int c_hi, bool inside,
+                                   hipStream_t s) {
   GjeOuterOp op{};
   for (int z = 0; z < a.nmat; ++z) {
     op.U[z] = a.m[z].P[a.pcur];
@@ -354,7 +365,12 @@ hipError_t launch_gje_outer_update(const GjeArgs& a, hipStream_t s) {
   op.ld = a.n_pad;
   op.k0 = a.k0;
   op.nbo = a.nbo;
-  return launch(op, a.n_pad, a.n_pad, a.nbo, a.nmat, s);
+  const int tn = (a.n_pad + BN - 1) / BN;
+  const int t_lo = std::min(std::max(c_lo / BN, 0), tn);
+  const int t_hi = std::min(std::max((c_hi + BN - 1) / BN, t_lo), tn);
+  const TileCols tc = inside ? TileCols{t_lo, t_hi - t_lo, 0, 0}
+                             : TileCols{0, t_lo, t_hi, tn - t_hi};
+  return launch(op, a.n_pad, a.n_pad, a.nbo, a.nmat, tc, s);
 }
 
 }  // namespace logm

@@ -27,7 +27,7 @@
 //    of LAPACK's LU-based inverse.
 //
 // Pivot rows of each inner block are chosen by tournament pivoting: leaves run
-// partial-pivoting LU on 128-row chunks of the candidate rows and forward their 64
+// partial-pivoting LU on 512-row chunks of the candidate rows and forward their 64
 // pivot rows; the last workgroup to arrive at a tree node merges its children the
 // same way.  The root keeps the LU factors of the selected block, forms the
 // triangular inverses and records log|det| = sum log|u_jj|.  Row exchanges are
@@ -42,15 +42,12 @@ namespace {
 constexpr int NB = 64;
 constexpr int LDA = NB + 1;
 constexpr int IU_ROWS = 32;
-#ifndef LOGM_TOURN_WAVES
-#define LOGM_TOURN_WAVES 8
-#endif
 #ifndef LOGM_TOURN_RPL
 #define LOGM_TOURN_RPL 8
 #endif
-constexpr int NW = LOGM_TOURN_WAVES;   // waves; wave w owns columns [CPW w, CPW (w + 1))
+constexpr int NW = 8;                  // waves of a tournament node
 constexpr int TT = 64 * NW;            // threads of a tournament node
-constexpr int CPW = NB / NW;           // columns per wave
+constexpr int SL = NB / NW;            // column slots per wave: wave w owns columns w + NW t
 constexpr int RPL = LOGM_TOURN_RPL;    // candidate rows per lane: lane l owns rows l + 64 i
 constexpr int TR = 64 * RPL;           // candidate rows per node
 constexpr int FAN = TR / NB;           // children merged by one node
@@ -66,14 +63,15 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// u[c] = x[iL][c] of lane L, for wave-uniform iL and L.  The uniform switch keeps
-// every register index static (a dynamic index would spill the row block to
-// scratch) and executes only one case.
-__device__ __forceinline__ void read_owner_row(const double (&x)[RPL][CPW], int iL, int L,
-                                               double (&u)[CPW]) {
+// u[c] = x[iL][c] of lane L for slots c >= c_first (a compile-time value after
+// unrolling), for wave-uniform iL and L.  The uniform if-chain keeps every register
+// index static (a dynamic index would spill the row block to scratch) and runs
+// one case.
+__device__ __forceinline__ void read_owner_row(const double (&x)[RPL][SL], int c_first, int iL,
+                                               int L, double (&u)[SL]) {
 #define LOGM_ROW_CASE(I)                                                                 \
   if (I < RPL && iL == I) {                                                              \
-    _Pragma("unroll") for (int c = 0; c < CPW; ++c) u[c] = readlane_d(x[(I < RPL) ? I : 0][c], L); \
+    _Pragma("unroll") for (int c = c_first; c < SL; ++c) u[c] = readlane_d(x[(I < RPL) ? I : 0][c], L); \
     return;                                                                              \
   }
   LOGM_ROW_CASE(0)
@@ -85,40 +83,171 @@ __device__ __forceinline__ void read_owner_row(const double (&x)[RPL][CPW], int 
   LOGM_ROW_CASE(6)
   LOGM_ROW_CASE(7)
 #undef LOGM_ROW_CASE
-  _Pragma("unroll") for (int c = 0; c < CPW; ++c) u[c] = readlane_d(x[0][c], L);
+  _Pragma("unroll") for (int c = c_first; c < SL; ++c) u[c] = readlane_d(x[0][c], L);
 }
 
-// Lane holding the wave's largest v among lanes with ok (lowest lane on ties), or
-// -1.  The DPP maximum is checked with a ballot; the shuffle reduction decides if
-// no lane matches it.
-__device__ __forceinline__ int wave_argmax_lane(double v, bool ok) {
-  const double m = wave_max_dpp(ok ? v : -1.0);
-  unsigned long long bal = __ballot(ok && v == m);
-  if (bal == 0ull) {
-    if (__ballot(ok) == 0ull) return -1;
-    int idx = ok ? (int)(threadIdx.x & 63) : 64;
-    double vv = ok ? v : -1.0;
-    wave_argmax(vv, idx);
-    return idx;
+// u[c] = x[iL][c] of lane L for slots c >= c_first, through the wave's own LDS
+// row: the owning lane stores its slice, then every lane reads it back with
+// broadcast loads.  LDS requests of one wave complete in order, so the loads see
+// the store; no other wave touches srow.
+__device__ __forceinline__ void bcast_owner_row(const double (&x)[RPL][SL], int c_first, int iL,
+                                                int L, double* srow, double (&u)[SL]) {
+  if ((int)(threadIdx.x & 63) == L) {
+#define LOGM_ROW_STORE(I)                                                            \
+    if (I < RPL && iL == I) {                                                        \
+      _Pragma("unroll") for (int c = c_first; c < SL; ++c) srow[c] = x[(I < RPL) ? I : 0][c]; \
+    } else
+    LOGM_ROW_STORE(0)
+    LOGM_ROW_STORE(1)
+    LOGM_ROW_STORE(2)
+    LOGM_ROW_STORE(3)
+    LOGM_ROW_STORE(4)
+    LOGM_ROW_STORE(5)
+    LOGM_ROW_STORE(6)
+    LOGM_ROW_STORE(7) {}
+#undef LOGM_ROW_STORE
   }
-  return __ffsll((long long)bal) - 1;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+  for (int c = c_first; c < SL; ++c) u[c] = srow[c];
+}
+
+// x[iL][T] of lane L for wave-uniform iL and L (T a compile-time slot after unrolling).
+__device__ __forceinline__ double read_owner_slot(const double (&x)[RPL][SL], int T, int iL, int L) {
+#define LOGM_SLOT_CASE(I) \
+  if (I < RPL && iL == I) return readlane_d(x[(I < RPL) ? I : 0][T], L);
+  LOGM_SLOT_CASE(0)
+  LOGM_SLOT_CASE(1)
+  LOGM_SLOT_CASE(2)
+  LOGM_SLOT_CASE(3)
+  LOGM_SLOT_CASE(4)
+  LOGM_SLOT_CASE(5)
+  LOGM_SLOT_CASE(6)
+  LOGM_SLOT_CASE(7)
+#undef LOGM_SLOT_CASE
+  return readlane_d(x[0][T], L);
+}
+
+// Wave-wide maximum of an unsigned key (DPP row shifts and broadcasts, the full
+// maximum lands in lane 63), returned to every lane.
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false));  // row_shr:1
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false));  // row_shr:2
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x113, 0xf, 0xf, false));  // row_shr:3
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xe, false));  // row_shr:4
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xc, false));  // row_shr:8
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));  // row_bcast:15
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));  // row_bcast:31
+  return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// Reciprocal for the multipliers: hardware estimate and two Newton steps (within
+// an ulp or so of 1/a); 0 for a zero pivot, whose singularity the root reports.
+__device__ __forceinline__ double pivot_recip(double a) {
+  double r = __builtin_amdgcn_rcp(a);
+  double e = fma(-a, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-a, r, 1.0);
+  r = fma(r, e, r);
+  return (a != 0.0) ? r : 0.0;
+}
+
+// Packed pivot key of candidate slot i: bits 31..3 hold 1 + the high word of |a|
+// shifted right by 3 (exponent and 17 leading mantissa bits), bits 2..0 the slot;
+// rows that are no longer candidates get 0.  The chosen pivot is therefore within a
+// factor 1 + 2^-17 of the largest magnitude in the column (a threshold variant of
+// partial pivoting); an exact zero wins only when every candidate is below 2^-1019.
+__device__ __forceinline__ unsigned pivot_key(double a, int i, unsigned act) {
+  const unsigned hi = (unsigned)((unsigned long long)__double_as_longlong(a) >> 32) & 0x7fffffffu;
+  const unsigned k = ((((hi >> 3) + 1u) << 3) | (unsigned)i);
+  return ((act >> i) & 1u) ? k : 0u;
+}
+
+// Branch-free selects on the bit patterns: v if bit else +0, and a if bit else b.
+__device__ __forceinline__ double masked(double v, unsigned bit) {
+  const unsigned m = 0u - (bit & 1u);
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)b & m, hi = (unsigned)(b >> 32) & m;
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ double blend(double a, double b, unsigned bit) {
+  const unsigned m = 0u - (bit & 1u);
+  const unsigned long long ab = (unsigned long long)__double_as_longlong(a);
+  const unsigned long long bb = (unsigned long long)__double_as_longlong(b);
+  const unsigned lo = ((unsigned)ab & m) | ((unsigned)bb & ~m);
+  const unsigned hi = ((unsigned)(ab >> 32) & m) | ((unsigned)(bb >> 32) & ~m);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Step ring of the pipelined node factorization: LDS flags instead of barriers.
+// A step's record: stamp (step + 1 once published), pivot row, reciprocal pivot;
+// 16 bytes so that one LDS load returns all of it.
+struct __attribute__((aligned(16))) StepRec {
+  int stamp;
+  int p;
+  double rp;
+};
+typedef int v4i __attribute__((ext_vector_type(4)));
+constexpr int RING = 16;                      // steps in flight
+constexpr int SPIN_LIMIT = 1 << 22;           // bounded waits (about 0.3 s)
+
+// Wait until the LDS word *f reaches target; false if the bound is hit (the caller
+// records an error and carries on with whatever is there, all indices stay clamped).
+// Wait until the step record's stamp reaches target and return the record (one
+// 16-byte LDS load per poll).  Publishers issue s_wakeup, which ends the sleep of
+// the waiting waves early.
+__device__ __forceinline__ bool lds_wait_rec(const StepRec* r, int target, v4i& rec) {
+  for (int it = 0; it < SPIN_LIMIT; ++it) {
+    rec = *reinterpret_cast<const volatile v4i*>(r);
+    if (rec.x >= target) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      return true;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+  return false;
+}
+
+__device__ __forceinline__ bool lds_wait_ge(const int* f, int target) {
+  for (int it = 0; it < SPIN_LIMIT; ++it) {
+    if (__hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) >= target) return true;
+    __builtin_amdgcn_s_sleep(1);
+  }
+  return false;
 }
 
 // Tournament pivot selection for the inner block [c0, c0+64) of the panel over the
 // candidate positions [r0, n_pad).  A node runs partial-pivoting LU on up to TR
-// candidate rows held in registers: wave w keeps columns CPW w .. CPW w + CPW - 1 of
-// every row, lane l rows l, l+64, ...  The pivot of column j is found inside the wave owning
-// column j; only its multipliers cross waves (through LDS, one barrier per
-// column), and every wave reads its slice of the pivot row from the owning lane.
+// candidate rows held in registers: lane l of wave w keeps rows l, l+64, ... and
+// the columns w, w+NW, w+2NW, ... of each (slot t holds column w + NW t).  Column j
+// is owned by wave j % NW, so consecutive pivot searches run in different waves.
+// Step j: the owner of column j applies step j-1 to that column, publishes the
+// updated column and then, at raised wave priority, searches it and publishes pivot
+// row p_j and its value; every wave (the owner included) forms the multipliers of
+// step j-1 from the published column and applies step j-1 to its other columns.
+// Steps are handed over through a ring of RING LDS slots with flags rather than
+// barriers: the serial path is the chain of column updates and searches, and the
+// bulk updates of a wave may trail it by up to RING steps.
+// Rows arrive through LDS in 128-row chunks so that every global load is a
+// contiguous 512-byte row segment.
 // Leaves take TR consecutive candidates, inner nodes the <= 64 winners of each of
 // their <= FAN children (the last child to finish does the merge).  The root
 // writes the LU factors of the 64 selected rows (pivot order) to m.tri and builds
 // the row maps of the step.
+constexpr int STG_ROWS = 128;                 // staged rows per chunk
+constexpr int STG_LD = NB + 1;                // odd stride: conflict-free column reads
+constexpr int BUF_DOUBLES = (STG_ROWS * STG_LD > NB * (NB + 2)) ? STG_ROWS * STG_LD : NB * (NB + 2);
+
 __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(1, 2))) void tournament_kernel(GjeArgs A, int nleaves) {
-  __shared__ __attribute__((aligned(16))) double s_lu[NB][NB + 2];
-  __shared__ double s_l[2][TR];
-  __shared__ int s_p[2];
+  __shared__ __attribute__((aligned(16))) double s_buf[BUF_DOUBLES];   // row staging, then LU rows
+  __shared__ double s_raw[RING][TR];
+  __shared__ StepRec s_rec[RING];  // step j in slot j % RING, stamp j + 1 once published
+  __shared__ int s_cons[RING];     // waves done with the step held in the slot (cumulative)
+  __shared__ double s_urow[NW][SL];   // per-wave pivot-row slice
   __shared__ int s_rid[TR];
+  __shared__ int s_stepof[TR];
   __shared__ int s_sel[NB];
   __shared__ int s_off[FAN + 1];
   __shared__ int s_last;
@@ -128,6 +257,7 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(1, 2))) void
   __shared__ int s_nv;
   __shared__ int s_old_pi[2 * NB];
   __shared__ int s_old_pt[2 * NB];
+  double (*s_lu)[NB + 2] = reinterpret_cast<double (*)[NB + 2]>(s_buf);
 
   const GjeMat& m = A.m[blockIdx.y];
   const double* P = m.P[A.pcur];
@@ -154,94 +284,174 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(1, 2))) void
   int npiv = 0;
   while (true) {
     if (need_lu) {
-      double x[RPL][CPW];
+      double x[RPL][SL];
       unsigned act = 0;
+      // ---- rows into registers through LDS, 128 rows per chunk: a wave load
+      // instruction covers two contiguous 512-byte row segments
+      {
+        f64x2 st[STG_ROWS * NB / 2 / TT];
+        auto gload = [&](int ch) {
 #pragma unroll
-      for (int i = 0; i < RPL; ++i) {
-        const int r = lane + 64 * i;
-        const int pos = s_rid[min(r, nrows - 1)];
-        const f64x2* src = reinterpret_cast<const f64x2*>(P + (int64_t)pos * nbo + c0 + CPW * wave);
+          for (int e = 0; e < STG_ROWS * NB / 2 / TT; ++e) {
+            const int lr = ch * STG_ROWS + (wave * (STG_ROWS * NB / 2 / TT) + e) * 2 + (lane >> 5);
+            const int pos = s_rid[min(lr, TR - 1)];
+            st[e] = *reinterpret_cast<const f64x2*>(P + (int64_t)pos * nbo + c0 + 2 * (lane & 31));
+          }
+        };
+        gload(0);
 #pragma unroll
-        for (int c = 0; c < CPW / 2; ++c) {
-          const f64x2 v = src[c];
-          x[i][2 * c] = (r < nrows) ? v.x : 0.0;
-          x[i][2 * c + 1] = (r < nrows) ? v.y : 0.0;
-        }
-        act |= (r < nrows) ? (1u << i) : 0u;
-      }
-      npiv = min(NB, nrows);
-#pragma unroll 1
-      for (int g = 0; g < NW; ++g) {
+        for (int ch = 0; ch < RPL / 2; ++ch) {
 #pragma unroll
-        for (int cc = 0; cc < CPW; ++cc) {
-          const int j = CPW * g + cc;
-          if (j < npiv) {
-          if (wave == g) {
-            // ---- pivot search in the owning wave
-            double best = -1.0, bestv = 0.0;
-            int bi = 0;
-#pragma unroll
-            for (int i = 0; i < RPL; ++i) {
-              double a = fabs(x[i][cc]);
-              if (!(a == a)) a = 0.0;
-              if (((act >> i) & 1u) && a > best) {
-                best = a;
-                bestv = x[i][cc];
-                bi = i;
-              }
-            }
-            const int L = wave_argmax_lane(best, best >= 0.0);
-            const int iL = __builtin_amdgcn_readlane(bi, L);
-            const double piv = readlane_d(bestv, L);
-            const int p = L + 64 * iL;
-            if (lane == L) act &= ~(1u << iL);
-            const double rp = (piv != 0.0) ? 1.0 / piv : 0.0;
-            double l[RPL];
-#pragma unroll
-            for (int i = 0; i < RPL; ++i) {
-              l[i] = ((act >> i) & 1u) ? x[i][cc] * rp : 0.0;
-              s_l[j & 1][lane + 64 * i] = l[i];
-            }
-            if (lane == 0) s_p[j & 1] = p;
-            // this wave's slice of row p (before the update)
-            double u[CPW];
-            read_owner_row(x, iL, L, u);
-            if (lane == 0) {
-#pragma unroll
-              for (int c = 0; c < CPW; c += 2)
-                *reinterpret_cast<f64x2*>(&s_lu[j][CPW * wave + c]) = f64x2{u[c], u[c + 1]};
-              s_sel[j] = p;
-            }
-#pragma unroll
-            for (int i = 0; i < RPL; ++i) {
-              if ((act >> i) & 1u) x[i][cc] = l[i];
-#pragma unroll
-              for (int c = cc + 1; c < CPW; ++c) x[i][c] = fma(-l[i], u[c], x[i][c]);
-            }
+          for (int e = 0; e < STG_ROWS * NB / 2 / TT; ++e) {
+            const int rr = (wave * (STG_ROWS * NB / 2 / TT) + e) * 2 + (lane >> 5);
+            s_buf[rr * STG_LD + 2 * (lane & 31)] = st[e].x;
+            s_buf[rr * STG_LD + 2 * (lane & 31) + 1] = st[e].y;
           }
           __syncthreads();
-          if (wave != g) {
-            const int p = s_p[j & 1];
-            const int L = p & 63;
-            const int iL = p >> 6;
-            if (lane == L) act &= ~(1u << iL);
-            double u[CPW];
-            read_owner_row(x, iL, L, u);
-            if (lane == 0) {
+          if (ch + 1 < RPL / 2) gload(ch + 1);
 #pragma unroll
-              for (int c = 0; c < CPW; c += 2)
-                *reinterpret_cast<f64x2*>(&s_lu[j][CPW * wave + c]) = f64x2{u[c], u[c + 1]};
-            }
-            if (wave > g) {
+          for (int h = 0; h < 2; ++h) {
+            const int i = 2 * ch + h;
+            const bool ok = lane + 64 * i < nrows;
 #pragma unroll
-              for (int i = 0; i < RPL; ++i) {
-                const double li = s_l[j & 1][lane + 64 * i];
+            for (int t = 0; t < SL; ++t) x[i][t] = masked(s_buf[(lane + 64 * h) * STG_LD + wave + NW * t], ok);
+            act |= ok ? (1u << i) : 0u;
+          }
+          __syncthreads();
+        }
+      }
+      npiv = min(NB, nrows);
+      if (tid < RING) {
+        s_rec[tid].stamp = 0;
+        s_cons[tid] = 0;
+      }
+      __syncthreads();
+      bool stuck = false;
 #pragma unroll
-                for (int c = 0; c < CPW; ++c) x[i][c] = fma(-li, u[c], x[i][c]);
+      for (int T = 0; T < SL; ++T) {
+#pragma unroll 1
+        for (int g = 0; g < NW; ++g) {
+          const int j = NW * T + g;
+          if (j < npiv) {
+            double lp[RPL];
+            double rv[RPL];
+            double rp = 0.0;
+            int Lp = 0, iLp = 0;
+            const int q = (j - 1) & (RING - 1);
+            if (j > 0) {   // step j-1: pivot row, reciprocal and published column
+              int pp = 0;
+              if (!stuck) {
+                v4i rec;
+                stuck = !lds_wait_rec(&s_rec[q], j, rec);
+                pp = rec.y;
+                rp = __longlong_as_double(((long long)rec.w << 32) | (unsigned)rec.z);
+              }
+              // all loads first, then branch-free masking: a conditional load would be
+              // sunk into its own branch and serialize the LDS latency
+#pragma unroll
+              for (int i = 0; i < RPL; ++i) rv[i] = s_raw[q][lane + 64 * i];
+              Lp = pp & 63;
+              iLp = (pp >> 6) & (RPL - 1);
+              if (lane == Lp) act &= ~(1u << iLp);
+              if (wave != g) {
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) lp[i] = masked(rv[i] * rp, (act >> i) & 1u);
               }
             }
+            if (wave == g) {
+              __builtin_amdgcn_s_setprio(2);
+              if (j > 0) {   // step j-1 on the pivot column: x -= raw (rp u) on candidates
+                const double c = rp * read_owner_slot(x, T, iLp, Lp);
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) x[i][T] = fma(-masked(rv[i], (act >> i) & 1u), c, x[i][T]);
+              }
+              const int r = j & (RING - 1);
+              // the slot's previous step (j - RING) must be done with by every wave
+              if (j >= RING && !stuck) stuck = !lds_wait_ge(&s_cons[r], NW * (j / RING));
+#pragma unroll
+              for (int i = 0; i < RPL; ++i) s_raw[r][lane + 64 * i] = x[i][T];
+              unsigned k[RPL];
+#pragma unroll
+              for (int i = 0; i < RPL; ++i) k[i] = pivot_key(x[i][T], i, act);
+#pragma unroll
+              for (int w = 1; w < RPL; w *= 2)
+#pragma unroll
+                for (int i = 0; i + w < RPL; i += 2 * w) k[i] = max(k[i], k[i + w]);
+              const unsigned best = k[0];
+              // each lane's best value by a select tree (runs beside the wave maximum)
+              const int bi = (int)(best & 7u);
+              double v[RPL];
+#pragma unroll
+              for (int i = 0; i < RPL; ++i) v[i] = x[i][T];
+#pragma unroll
+              for (int w = 1; w < RPL; w *= 2)
+#pragma unroll
+                for (int i = 0; i + w < RPL; i += 2 * w) v[i] = ((bi & w) != 0) ? v[i + w] : v[i];
+              const unsigned kmax = wave_max_u32(best);
+              const unsigned long long bal = __ballot(best == kmax);
+              const int L = bal ? (__ffsll((long long)bal) - 1) : 0;
+              const int iL = (int)(kmax & 7u) & (RPL - 1);
+              const double rpj = pivot_recip(readlane_d(v[0], L));
+              const unsigned act_prev = act;   // candidates of step j - 1 (p_j among them)
+              if (lane == L) act &= ~(1u << iL);
+              if (lane == 0) {
+                s_rec[r].p = L + 64 * iL;
+                s_rec[r].rp = rpj;
+                s_sel[j] = L + 64 * iL;
+                __hip_atomic_store(&s_rec[r].stamp, j + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+              }
+              asm volatile("s_wakeup" ::: "memory");   // end the sleep of waiting waves
+              __builtin_amdgcn_s_setprio(0);
+#pragma unroll
+              for (int i = 0; i < RPL; ++i)   // this column's multipliers (L factor)
+                x[i][T] = blend(x[i][T] * rpj, x[i][T], (act >> i) & 1u);
+              if (j > 0) {
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) lp[i] = masked(rv[i] * rp, (act_prev >> i) & 1u);
+              }
+              if (j > 0 && T + 1 < SL) {
+                double u[SL];
+                bcast_owner_row(x, T + 1, iLp, Lp, s_urow[wave], u);
+#pragma unroll
+                for (int t = T + 1; t < SL; ++t) {
+#pragma unroll
+                  for (int i = 0; i < RPL; ++i) x[i][t] = fma(-lp[i], u[t], x[i][t]);
+                }
+              }
+            } else if (j > 0) {
+              double u[SL];
+              if (wave > g) {
+                bcast_owner_row(x, T, iLp, Lp, s_urow[wave], u);
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) x[i][T] = fma(-lp[i], u[T], x[i][T]);
+              } else if (T + 1 < SL) {
+                bcast_owner_row(x, T + 1, iLp, Lp, s_urow[wave], u);
+              }
+#pragma unroll
+              for (int t = T + 1; t < SL; ++t) {
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) x[i][t] = fma(-lp[i], u[t], x[i][t]);
+              }
+            }
+            if (j > 0 && lane == 0)
+              __hip_atomic_fetch_add(&s_cons[q], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
           }
-          }
+        }
+      }
+      if (stuck && lane == 0) atomicOr(&m.err[0], 2);
+      __syncthreads();
+      // A pivot row is left alone by every later step, so the LU factors of the
+      // node are its pivot rows as they stand now: each owning lane stores its slice.
+      for (int r = tid; r < TR; r += TT) s_stepof[r] = -1;
+      __syncthreads();
+      if (tid < npiv) s_stepof[min(max(s_sel[tid], 0), TR - 1)] = tid;
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const int st = s_stepof[lane + 64 * i];
+        if (st >= 0) {
+#pragma unroll
+          for (int t = 0; t < SL; ++t) s_lu[st][wave + NW * t] = x[i][t];
         }
       }
       __syncthreads();

@@ -48,7 +48,7 @@ struct GjeMat {
   int* cand;             // tournament scratch
   int* cnt;              // tournament arrival counters (self-resetting)
   double* logdet;        // n_pad / 64 slots: log|det| of each pivot block
-  int* err;              // error flags: [0] zero pivot met
+  int* err;              // error flags: [0] bit 0 zero pivot met, bit 1 a bounded wait gave up
 };
 
 struct GjeArgs {
@@ -72,7 +72,10 @@ hipError_t launch_gje_begin(const GjeArgs& a, hipStream_t s);
 hipError_t launch_gje_panel_copy(const GjeArgs& a, hipStream_t s);
 hipError_t launch_gje_tournament(const GjeArgs& a, hipStream_t s);
 hipError_t launch_gje_inner_update(const GjeArgs& a, hipStream_t s);
-hipError_t launch_gje_outer_update(const GjeArgs& a, hipStream_t s);
+// Outer update of the columns [c_lo, c_hi) (inside) or of all others (!inside);
+// c_lo is a multiple of 128, the ranges are rounded out to whole 128-column tiles.
+hipError_t launch_gje_outer_update(const GjeArgs& a, int c_lo, int c_hi, bool inside,
+                                   hipStream_t s);
 // pinv = ptot^{-1}.
 hipError_t launch_gje_finish(const GjeArgs& a, hipStream_t s);
 // dst (n x n, ldd) = A^{-1}: dst[i][ptot[c]] = Mfinal[i][c].
