@@ -86,34 +86,6 @@ __device__ __forceinline__ void read_owner_row(const double (&x)[RPL][SL], int c
   _Pragma("unroll") for (int c = c_first; c < SL; ++c) u[c] = readlane_d(x[0][c], L);
 }
 
-// u[c] = x[iL][c] of lane L for slots c >= c_first, through the wave's own LDS
-// row: the owning lane stores its slice, then every lane reads it back with
-// broadcast loads.  LDS requests of one wave complete in order, so the loads see
-// the store; no other wave touches srow.
-__device__ __forceinline__ void bcast_owner_row(const double (&x)[RPL][SL], int c_first, int iL,
-                                                int L, double* srow, double (&u)[SL]) {
-  if ((int)(threadIdx.x & 63) == L) {
-#define LOGM_ROW_STORE(I)                                                            \
-    if (I < RPL && iL == I) {                                                        \
-      _Pragma("unroll") for (int c = c_first; c < SL; ++c) srow[c] = x[(I < RPL) ? I : 0][c]; \
-    } else
-    LOGM_ROW_STORE(0)
-    LOGM_ROW_STORE(1)
-    LOGM_ROW_STORE(2)
-    LOGM_ROW_STORE(3)
-    LOGM_ROW_STORE(4)
-    LOGM_ROW_STORE(5)
-    LOGM_ROW_STORE(6)
-    LOGM_ROW_STORE(7) {}
-#undef LOGM_ROW_STORE
-  }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-  for (int c = c_first; c < SL; ++c) u[c] = srow[c];
-}
-
 // x[iL][T] of lane L for wave-uniform iL and L (T a compile-time slot after unrolling).
 __device__ __forceinline__ double read_owner_slot(const double (&x)[RPL][SL], int T, int iL, int L) {
 #define LOGM_SLOT_CASE(I) \
@@ -182,40 +154,40 @@ __device__ __forceinline__ double blend(double a, double b, unsigned bit) {
 }
 
 // Step ring of the pipelined node factorization: LDS flags instead of barriers.
-// A step's record: stamp (step + 1 once published), pivot row, reciprocal pivot;
-// 16 bytes so that one LDS load returns all of it.
+// A step's record: stamp (step + 1 once published), pivot row, reciprocal pivot.
 struct __attribute__((aligned(16))) StepRec {
   int stamp;
   int p;
   double rp;
 };
-typedef int v4i __attribute__((ext_vector_type(4)));
 constexpr int RING = 16;                      // steps in flight
 constexpr int SPIN_LIMIT = 1 << 22;           // bounded waits (about 0.3 s)
 
 // Wait until the LDS word *f reaches target; false if the bound is hit (the caller
 // records an error and carries on with whatever is there, all indices stay clamped).
-// Wait until the step record's stamp reaches target and return the record (one
-// 16-byte LDS load per poll).  Publishers issue s_wakeup, which ends the sleep of
-// the waiting waves early.
-__device__ __forceinline__ bool lds_wait_rec(const StepRec* r, int target, v4i& rec) {
+// Wait until the LDS word *f reaches target; false if the bound is hit (the caller
+// records an error and carries on with whatever is there, all indices stay clamped).
+// The polled value is made wave-uniform, so the loop is a scalar loop.
+__device__ __forceinline__ bool lds_wait_ge(const int* f, int target) {
   for (int it = 0; it < SPIN_LIMIT; ++it) {
-    rec = *reinterpret_cast<const volatile v4i*>(r);
-    if (rec.x >= target) {
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-      return true;
-    }
+    const int v = __builtin_amdgcn_readfirstlane(
+        __hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP));
+    if (v >= target) return true;
     __builtin_amdgcn_s_sleep(2);
   }
   return false;
 }
 
-__device__ __forceinline__ bool lds_wait_ge(const int* f, int target) {
-  for (int it = 0; it < SPIN_LIMIT; ++it) {
-    if (__hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) >= target) return true;
-    __builtin_amdgcn_s_sleep(1);
-  }
-  return false;
+// Wait for a step record and return its pivot row and reciprocal pivot (uniform).
+// Publishers issue s_wakeup, which ends the sleep of the waiting waves early.
+__device__ __forceinline__ bool lds_wait_rec(const StepRec* r, int target, int& p, double& rp) {
+  const bool ok = lds_wait_ge(&r->stamp, target);
+  p = __builtin_amdgcn_readfirstlane(r->p);
+  const long long b = __double_as_longlong(r->rp);
+  const int lo = __builtin_amdgcn_readfirstlane((int)b);
+  const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  rp = __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+  return ok;
 }
 
 // Tournament pivot selection for the inner block [c0, c0+64) of the panel over the
@@ -245,7 +217,6 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(1, 2))) void
   __shared__ double s_raw[RING][TR];
   __shared__ StepRec s_rec[RING];  // step j in slot j % RING, stamp j + 1 once published
   __shared__ int s_cons[RING];     // waves done with the step held in the slot (cumulative)
-  __shared__ double s_urow[NW][SL];   // per-wave pivot-row slice
   __shared__ int s_rid[TR];
   __shared__ int s_stepof[TR];
   __shared__ int s_sel[NB];
@@ -314,7 +285,7 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(1, 2))) void
             const int i = 2 * ch + h;
             const bool ok = lane + 64 * i < nrows;
 #pragma unroll
-            for (int t = 0; t < SL; ++t) x[i][t] = masked(s_buf[(lane + 64 * h) * STG_LD + wave + NW * t], ok);
+            for (int t = 0; t < SL; ++t) x[i][t] = masked(s_buf[(lane + 64 * h) * STG_LD + SL * wave + t], ok);
             act |= ok ? (1u << i) : 0u;
           }
           __syncthreads();
@@ -327,117 +298,97 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(1, 2))) void
       }
       __syncthreads();
       bool stuck = false;
-#pragma unroll
-      for (int T = 0; T < SL; ++T) {
+      const int jb = SL * wave;              // first column (step) of this wave's block
+      // ---- steps of the earlier blocks, as their owners publish them
 #pragma unroll 1
-        for (int g = 0; g < NW; ++g) {
-          const int j = NW * T + g;
-          if (j < npiv) {
-            double lp[RPL];
-            double rv[RPL];
-            double rp = 0.0;
-            int Lp = 0, iLp = 0;
-            const int q = (j - 1) & (RING - 1);
-            if (j > 0) {   // step j-1: pivot row, reciprocal and published column
-              int pp = 0;
-              if (!stuck) {
-                v4i rec;
-                stuck = !lds_wait_rec(&s_rec[q], j, rec);
-                pp = rec.y;
-                rp = __longlong_as_double(((long long)rec.w << 32) | (unsigned)rec.z);
-              }
-              // all loads first, then branch-free masking: a conditional load would be
-              // sunk into its own branch and serialize the LDS latency
+      for (int j = 0; j < min(jb, npiv); ++j) {
+        const int q = j & (RING - 1);
+        int pp = 0;
+        double rp = 0.0;
+        if (!stuck) stuck = !lds_wait_rec(&s_rec[q], j + 1, pp, rp);
+        // all loads first, then branch-free masking: a conditional load would be
+        // sunk into its own branch and serialize the LDS latency
+        double rv[RPL];
 #pragma unroll
-              for (int i = 0; i < RPL; ++i) rv[i] = s_raw[q][lane + 64 * i];
-              Lp = pp & 63;
-              iLp = (pp >> 6) & (RPL - 1);
-              if (lane == Lp) act &= ~(1u << iLp);
-              if (wave != g) {
+        for (int i = 0; i < RPL; ++i) rv[i] = s_raw[q][lane + 64 * i];
+        const int Lp = pp & 63;
+        const int iLp = (pp >> 6) & (RPL - 1);
+        if (lane == Lp) act &= ~(1u << iLp);
+        double lp[RPL];
 #pragma unroll
-                for (int i = 0; i < RPL; ++i) lp[i] = masked(rv[i] * rp, (act >> i) & 1u);
-              }
+        for (int i = 0; i < RPL; ++i) lp[i] = masked(rv[i] * rp, (act >> i) & 1u);
+        double u[SL];
+        read_owner_row(x, 0, iLp, Lp, u);
+#pragma unroll
+        for (int t = 0; t < SL; ++t) {
+#pragma unroll
+          for (int i = 0; i < RPL; ++i) x[i][t] = fma(-lp[i], u[t], x[i][t]);
+        }
+        if (lane == 0)
+          __hip_atomic_fetch_add(&s_cons[q], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+      // ---- this wave's block: eight pivot steps back to back, all in registers
+      __builtin_amdgcn_s_setprio(2);
+#pragma unroll
+      for (int t = 0; t < SL; ++t) {
+        const int j = jb + t;
+        if (j < npiv) {
+          const int r = j & (RING - 1);
+          if (j >= RING && !stuck) {   // every consumer of the slot's earlier steps is done
+            int need = 0;
+            for (int k = r; k < j; k += RING) need += NW - 1 - k / SL;
+            stuck = !lds_wait_ge(&s_cons[r], need);
+          }
+#pragma unroll
+          for (int i = 0; i < RPL; ++i) s_raw[r][lane + 64 * i] = x[i][t];
+          unsigned k[RPL];
+#pragma unroll
+          for (int i = 0; i < RPL; ++i) k[i] = pivot_key(x[i][t], i, act);
+#pragma unroll
+          for (int w = 1; w < RPL; w *= 2)
+#pragma unroll
+            for (int i = 0; i + w < RPL; i += 2 * w) k[i] = max(k[i], k[i + w]);
+          const unsigned best = k[0];
+          // each lane's best value by a select tree (runs beside the wave maximum)
+          const int bi = (int)(best & 7u);
+          double v[RPL];
+#pragma unroll
+          for (int i = 0; i < RPL; ++i) v[i] = x[i][t];
+#pragma unroll
+          for (int w = 1; w < RPL; w *= 2)
+#pragma unroll
+            for (int i = 0; i + w < RPL; i += 2 * w) v[i] = ((bi & w) != 0) ? v[i + w] : v[i];
+          const unsigned kmax = wave_max_u32(best);
+          const unsigned long long bal = __ballot(best == kmax);
+          const int L = bal ? (__ffsll((long long)bal) - 1) : 0;
+          const int iL = (int)(kmax & 7u) & (RPL - 1);
+          const double rpj = pivot_recip(readlane_d(v[0], L));
+          if (lane == L) act &= ~(1u << iL);
+          if (lane == 0) {
+            s_rec[r].p = L + 64 * iL;
+            s_rec[r].rp = rpj;
+            s_sel[j] = L + 64 * iL;
+            __hip_atomic_store(&s_rec[r].stamp, j + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+          }
+          asm volatile("s_wakeup" ::: "memory");   // end the sleep of waiting waves
+          double l[RPL];
+#pragma unroll
+          for (int i = 0; i < RPL; ++i) {   // this column's multipliers (L factor)
+            l[i] = masked(x[i][t] * rpj, (act >> i) & 1u);
+            x[i][t] = blend(l[i], x[i][t], (act >> i) & 1u);
+          }
+          if (t + 1 < SL) {   // step j on the rest of the block, the next column first
+            double u[SL];
+            read_owner_row(x, t + 1, iL, L, u);
+#pragma unroll
+            for (int c = t + 1; c < SL; ++c) {
+#pragma unroll
+              for (int i = 0; i < RPL; ++i) x[i][c] = fma(-l[i], u[c], x[i][c]);
             }
-            if (wave == g) {
-              __builtin_amdgcn_s_setprio(2);
-              if (j > 0) {   // step j-1 on the pivot column: x -= raw (rp u) on candidates
-                const double c = rp * read_owner_slot(x, T, iLp, Lp);
-#pragma unroll
-                for (int i = 0; i < RPL; ++i) x[i][T] = fma(-masked(rv[i], (act >> i) & 1u), c, x[i][T]);
-              }
-              const int r = j & (RING - 1);
-              // the slot's previous step (j - RING) must be done with by every wave
-              if (j >= RING && !stuck) stuck = !lds_wait_ge(&s_cons[r], NW * (j / RING));
-#pragma unroll
-              for (int i = 0; i < RPL; ++i) s_raw[r][lane + 64 * i] = x[i][T];
-              unsigned k[RPL];
-#pragma unroll
-              for (int i = 0; i < RPL; ++i) k[i] = pivot_key(x[i][T], i, act);
-#pragma unroll
-              for (int w = 1; w < RPL; w *= 2)
-#pragma unroll
-                for (int i = 0; i + w < RPL; i += 2 * w) k[i] = max(k[i], k[i + w]);
-              const unsigned best = k[0];
-              // each lane's best value by a select tree (runs beside the wave maximum)
-              const int bi = (int)(best & 7u);
-              double v[RPL];
-#pragma unroll
-              for (int i = 0; i < RPL; ++i) v[i] = x[i][T];
-#pragma unroll
-              for (int w = 1; w < RPL; w *= 2)
-#pragma unroll
-                for (int i = 0; i + w < RPL; i += 2 * w) v[i] = ((bi & w) != 0) ? v[i + w] : v[i];
-              const unsigned kmax = wave_max_u32(best);
-              const unsigned long long bal = __ballot(best == kmax);
-              const int L = bal ? (__ffsll((long long)bal) - 1) : 0;
-              const int iL = (int)(kmax & 7u) & (RPL - 1);
-              const double rpj = pivot_recip(readlane_d(v[0], L));
-              const unsigned act_prev = act;   // candidates of step j - 1 (p_j among them)
-              if (lane == L) act &= ~(1u << iL);
-              if (lane == 0) {
-                s_rec[r].p = L + 64 * iL;
-                s_rec[r].rp = rpj;
-                s_sel[j] = L + 64 * iL;
-                __hip_atomic_store(&s_rec[r].stamp, j + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-              }
-              asm volatile("s_wakeup" ::: "memory");   // end the sleep of waiting waves
-              __builtin_amdgcn_s_setprio(0);
-#pragma unroll
-              for (int i = 0; i < RPL; ++i)   // this column's multipliers (L factor)
-                x[i][T] = blend(x[i][T] * rpj, x[i][T], (act >> i) & 1u);
-              if (j > 0) {
-#pragma unroll
-                for (int i = 0; i < RPL; ++i) lp[i] = masked(rv[i] * rp, (act_prev >> i) & 1u);
-              }
-              if (j > 0 && T + 1 < SL) {
-                double u[SL];
-                bcast_owner_row(x, T + 1, iLp, Lp, s_urow[wave], u);
-#pragma unroll
-                for (int t = T + 1; t < SL; ++t) {
-#pragma unroll
-                  for (int i = 0; i < RPL; ++i) x[i][t] = fma(-lp[i], u[t], x[i][t]);
-                }
-              }
-            } else if (j > 0) {
-              double u[SL];
-              if (wave > g) {
-                bcast_owner_row(x, T, iLp, Lp, s_urow[wave], u);
-#pragma unroll
-                for (int i = 0; i < RPL; ++i) x[i][T] = fma(-lp[i], u[T], x[i][T]);
-              } else if (T + 1 < SL) {
-                bcast_owner_row(x, T + 1, iLp, Lp, s_urow[wave], u);
-              }
-#pragma unroll
-              for (int t = T + 1; t < SL; ++t) {
-#pragma unroll
-                for (int i = 0; i < RPL; ++i) x[i][t] = fma(-lp[i], u[t], x[i][t]);
-              }
-            }
-            if (j > 0 && lane == 0)
-              __hip_atomic_fetch_add(&s_cons[q], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
           }
         }
       }
+      __builtin_amdgcn_s_setprio(0);
       if (stuck && lane == 0) atomicOr(&m.err[0], 2);
       __syncthreads();
       // A pivot row is left alone by every later step, so the LU factors of the
@@ -451,7 +402,7 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(1, 2))) void
         const int st = s_stepof[lane + 64 * i];
         if (st >= 0) {
 #pragma unroll
-          for (int t = 0; t < SL; ++t) s_lu[st][wave + NW * t] = x[i][t];
+          for (int t = 0; t < SL; ++t) s_lu[st][SL * wave + t] = x[i][t];
         }
       }
       __syncthreads();
@@ -615,19 +566,17 @@ __global__ __launch_bounds__(256) void inner_update_kernel(GjeArgs A) {
   const int row0 = blockIdx.x * IU_ROWS;
   const bool inblock = row0 >= r0 && row0 < r0 + NB;
 
-  if (tid < IU_ROWS) {
-    const int p = row0 + tid;
-    int src = p;
-    if (p >= r0 && p < r0 + NB) {
-      src = m.qsel[p - r0];
-    } else {
-      const int nv = m.vac[0];
-      for (int i = 0; i < nv; ++i)
-        if (m.vac[1 + i] == p) src = m.vac[65 + i];
-    }
-    s_src[tid] = src;
-  }
+  // source row of each output row: the selected row inside the block, the displaced
+  // block row at a vacated position, the row itself elsewhere
+  if (tid < IU_ROWS) s_src[tid] = inblock ? m.qsel[row0 - r0 + tid] : row0 + tid;
   if (tid < NB) s_q[tid] = m.qsel[tid];
+  __syncthreads();
+  if (!inblock && tid < NB) {
+    const int nv = m.vac[0];
+    const int v = m.vac[1 + tid];
+    const int src = m.vac[65 + tid];
+    if (tid < nv && v >= row0 && v < row0 + IU_ROWS) s_src[v - row0] = src;
+  }
   {
     double t[16];
 #pragma unroll
@@ -644,12 +593,15 @@ __global__ __launch_bounds__(256) void inner_update_kernel(GjeArgs A) {
     const int b0 = (blk & 3) * 16;
     double x[16];
     if (blk < 4) {  // upper: X U_bb = I  (column c of U_bb^{-1} by back substitution)
+      double rd[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) rd[r] = 1.0 / LU[b0 + r][b0 + r];
 #pragma unroll
       for (int r = 15; r >= 0; --r) {
         double acc = (r == c) ? 1.0 : 0.0;
 #pragma unroll
         for (int t = r + 1; t < 16; ++t) acc = fma(-LU[b0 + r][b0 + t], x[t], acc);
-        x[r] = (r <= c) ? acc / LU[b0 + r][b0 + r] : 0.0;
+        x[r] = (r <= c) ? acc * rd[r] : 0.0;
       }
     } else {        // unit lower: column c of L_bb^{-1} by forward substitution
 #pragma unroll
