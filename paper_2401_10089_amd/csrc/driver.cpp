@@ -32,6 +32,10 @@ constexpr double kU = 1.1102230246251565e-16;  // 2^-53
 constexpr int kNB = 64;
 constexpr int kNBO = 256;
 constexpr int kMats = 11;
+#ifndef LOGM_LOOKAHEAD_WGS
+#define LOGM_LOOKAHEAD_WGS 192
+#endif
+constexpr int kLookaheadWgs = LOGM_LOOKAHEAD_WGS;   // trailing-update workgroups beside a panel
 
 // ------------------------------------------------------------ constants ---
 // Table 2: k -> (m_k, Theta_{m_k}).
@@ -322,7 +326,7 @@ Status factor_panel(GjeArgs& a, hipStream_t s) {
   return st;
 }
 
-Status outer_update(Ctx& c, const GjeArgs& a, int c_lo, int c_hi, bool inside) {
+Status outer_update(Ctx& c, const GjeArgs& a, int c_lo, int c_hi, bool inside, int max_wgs = 0) {
   Status st;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (g_prof.on) {
@@ -330,7 +334,7 @@ Status outer_update(Ctx& c, const GjeArgs& a, int c_lo, int c_hi, bool inside) {
     e1 = g_prof.get();
     if (e0) HIPCK(hipEventRecord(e0, c.s));
   }
-  HIPCK(launch_gje_outer_update(a, c_lo, c_hi, inside, c.s));
+  HIPCK(launch_gje_outer_update(a, c_lo, c_hi, inside, max_wgs, c.s));
   if (g_prof.on && e0 && e1) {
     HIPCK(hipEventRecord(e1, c.s));
     // algorithmic work: the columns outside the step's block get a rank-nbo update
@@ -401,7 +405,9 @@ Status gje_invert(Ctx& c, int nmat, const double* const src[2], double* fin[2]) 
       HIPCK(hipStreamWaitEvent(c.side, c.ev_upd, 0));
       PROPAGATE(factor_panel(b, c.side));
       HIPCK(hipEventRecord(c.ev_pan, c.side));
-      PROPAGATE(outer_update(c, a, n_lo, n_hi, false));
+      // the rest of the update runs beside the next panel's factorization, which is
+      // the critical path: cap its workgroups so that the panel kernels find free CUs
+      PROPAGATE(outer_update(c, a, n_lo, n_hi, false, kLookaheadWgs / a.nmat));
     } else {
       PROPAGATE(outer_update(c, a, 0, np, true));
     }

@@ -59,8 +59,12 @@ __global__ __launch_bounds__(256) void gemm_kernel(Op op, int M, int N, int K, T
   const int wm = wave >> 1;
   const int wn = wave & 1;
   const int tiles_m = (M + BM - 1) / BM;
+  const int ntiles = tiles_m * (tc.na + tc.nb);
+  // persistent: a workgroup walks tiles blockIdx.x, + gridDim.x, ...; with a grid that
+  // is a multiple of 8 every tile of one workgroup stays on the same XCD group
+  for (int bid = blockIdx.x; bid < ntiles; bid += gridDim.x) {
   int tm, vn;
-  tile_of(blockIdx.x, tiles_m, tc.na + tc.nb, tm, vn);
+  tile_of(bid, tiles_m, tc.na + tc.nb, tm, vn);
   const int tn = (vn < tc.na) ? tc.a0 + vn : tc.b0 + (vn - tc.na);
   const int row0 = tm * BM;
   const int col0 = tn * BN;
@@ -71,7 +75,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(Op op, int M, int N, int K, T
       const int j = col0 + e % BN;
       if (i < M && j < N) op.copy(i, j);
     }
-    return;
+    continue;
   }
 
   // global -> register staging assignment
@@ -173,6 +177,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(Op op, int M, int N, int K, T
 #pragma unroll
       for (int ni = 0; ni < 4; ++ni) v[r][ni] = acc[mi][ni][r];
     op.store_group(rows, cols, v, M, N);
+  }
   }
 }
 
@@ -329,11 +334,14 @@ struct GjeOuterOp {
   }
 };
 
+// max_wgs > 0 caps the workgroups per matrix (the kernel then loops over tiles).
 template <class Op>
-hipError_t launch(const Op& op, int M, int N, int K, int nz, TileCols tc, hipStream_t s) {
+hipError_t launch(const Op& op, int M, int N, int K, int nz, TileCols tc, hipStream_t s,
+                  int max_wgs = 0) {
   const int tiles = ((M + BM - 1) / BM) * (tc.na + tc.nb);
   if (tiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(gemm_kernel<Op>, dim3(tiles, 1, nz), dim3(256), 0, s, op, M, N, K, tc);
+  const int grid = (max_wgs > 0 && tiles > max_wgs) ? max_wgs : tiles;
+  hipLaunchKernelGGL(gemm_kernel<Op>, dim3(grid, 1, nz), dim3(256), 0, s, op, M, N, K, tc);
   return hipGetLastError();
 }
 
@@ -354,7 +362,7 @@ hipError_t launch_gemm_poly(int n, const PolyGemmArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_gje_outer_update(const GjeArgs& a, int c_lo, int c_hi, bool inside,
-                                   hipStream_t s) {
+                                   int max_wgs, hipStream_t s) {
   GjeOuterOp op{};
   for (int z = 0; z < a.nmat; ++z) {
     op.U[z] = a.m[z].P[a.pcur];
@@ -370,7 +378,7 @@ hipError_t launch_gje_outer_update(const GjeArgs& a, int c_lo, int c_hi, bool in
   const int t_hi = std::min(std::max((c_hi + BN - 1) / BN, t_lo), tn);
   const TileCols tc = inside ? TileCols{t_lo, t_hi - t_lo, 0, 0}
                              : TileCols{0, t_lo, t_hi, tn - t_hi};
-  return launch(op, a.n_pad, a.n_pad, a.nbo, a.nmat, tc, s);
+  return launch(op, a.n_pad, a.n_pad, a.nbo, a.nmat, tc, s, max_wgs);
 }
 
 }  // namespace logm

@@ -548,11 +548,15 @@ __device__ __forceinline__ void mm32x64(const double (*As)[LDA], const double (*
 // comment): C U = Acol and G L = C are solved by 16-column block substitution with
 // explicit inverses of the 16 x 16 diagonal blocks only, then out = base - G R.
 __global__ __launch_bounds__(256) void inner_update_kernel(GjeArgs A) {
-  __shared__ double LU[NB][LDA];          // L (strict lower) and U of the pivot block
-  __shared__ double Di[8][16][17];        // inverses of the diagonal blocks: 0-3 of U, 4-7 of L
-  __shared__ double Rs[NB][LDA];          // pivot rows of one column chunk
+  // LU and Di/Ts live during the solves, Rs during the output chunks: the regions
+  // alias so that two workgroups fit in one CU's LDS
+  __shared__ __attribute__((aligned(16))) double s_a[NB * LDA];
+  __shared__ __attribute__((aligned(16))) double s_b[8 * 16 * 17 + IU_ROWS * 17];
   __shared__ double Cs[IU_ROWS][LDA];
-  __shared__ double Ts[IU_ROWS][17];
+  double (*LU)[LDA] = reinterpret_cast<double (*)[LDA]>(s_a);          // L (strict lower) and U of the pivot block
+  double (*Rs)[LDA] = reinterpret_cast<double (*)[LDA]>(s_a);          // pivot rows of one column chunk
+  double (*Di)[16][17] = reinterpret_cast<double (*)[16][17]>(s_b);   // inverses of the diagonal blocks: 0-3 of U, 4-7 of L
+  double (*Ts)[17] = reinterpret_cast<double (*)[17]>(s_b + 8 * 16 * 17);
   __shared__ int s_src[IU_ROWS];
   __shared__ int s_q[NB];
 

@@ -74,8 +74,10 @@ hipError_t launch_gje_tournament(const GjeArgs& a, hipStream_t s);
 hipError_t launch_gje_inner_update(const GjeArgs& a, hipStream_t s);
 // Outer update of the columns [c_lo, c_hi) (inside) or of all others (!inside);
 // c_lo is a multiple of 128, the ranges are rounded out to whole 128-column tiles.
+// max_wgs > 0 caps the workgroups per matrix (persistent tiles), leaving CUs to
+// work that runs beside it.
 hipError_t launch_gje_outer_update(const GjeArgs& a, int c_lo, int c_hi, bool inside,
-                                   hipStream_t s);
+                                   int max_wgs, hipStream_t s);
 // pinv = ptot^{-1}.
 hipError_t launch_gje_finish(const GjeArgs& a, hipStream_t s);
 // dst (n x n, ldd) = A^{-1}: dst[i][ptot[c]] = Mfinal[i][c].
