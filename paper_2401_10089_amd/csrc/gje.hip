@@ -216,7 +216,8 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(1, 2))) void
   __shared__ __attribute__((aligned(16))) double s_buf[BUF_DOUBLES];   // row staging, then LU rows
   __shared__ double s_raw[RING][TR];
   __shared__ StepRec s_rec[RING];  // step j in slot j % RING, stamp j + 1 once published
-  __shared__ int s_cons[RING];     // waves done with the step held in the slot (cumulative)
+  __shared__ int s_bcons[NW];      // waves done with all steps of a block
+  __shared__ double s_prow[NW][SL];   // per-wave broadcast of the current pivot row
   __shared__ int s_rid[TR];
   __shared__ int s_stepof[TR];
   __shared__ int s_sel[NB];
@@ -292,10 +293,8 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(1, 2))) void
         }
       }
       npiv = min(NB, nrows);
-      if (tid < RING) {
-        s_rec[tid].stamp = 0;
-        s_cons[tid] = 0;
-      }
+      if (tid < RING) s_rec[tid].stamp = 0;
+      if (tid < NW) s_bcons[tid] = 0;
       __syncthreads();
       bool stuck = false;
       const int jb = SL * wave;              // first column (step) of this wave's block
@@ -324,9 +323,13 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(1, 2))) void
 #pragma unroll
           for (int i = 0; i < RPL; ++i) x[i][t] = fma(-lp[i], u[t], x[i][t]);
         }
-        if (lane == 0)
-          __hip_atomic_fetch_add(&s_cons[q], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if ((j & (SL - 1)) == SL - 1 && lane == 0)   // done with block j / SL
+          __hip_atomic_fetch_add(&s_bcons[j / SL], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
       }
+      // the ring slots of this block last held block wave - 2: wait until all of its
+      // consumers (the waves after it) are done with it
+      if (wave >= RING / SL && jb < npiv && !stuck)
+        stuck = !lds_wait_ge(&s_bcons[wave - RING / SL], NW - 1 - (wave - RING / SL));
       // ---- this wave's block: eight pivot steps back to back, all in registers
       __builtin_amdgcn_s_setprio(2);
 #pragma unroll
@@ -334,11 +337,6 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(1, 2))) void
         const int j = jb + t;
         if (j < npiv) {
           const int r = j & (RING - 1);
-          if (j >= RING && !stuck) {   // every consumer of the slot's earlier steps is done
-            int need = 0;
-            for (int k = r; k < j; k += RING) need += NW - 1 - k / SL;
-            stuck = !lds_wait_ge(&s_cons[r], need);
-          }
 #pragma unroll
           for (int i = 0; i < RPL; ++i) s_raw[r][lane + 64 * i] = x[i][t];
           unsigned k[RPL];
@@ -349,27 +347,36 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(1, 2))) void
 #pragma unroll
             for (int i = 0; i + w < RPL; i += 2 * w) k[i] = max(k[i], k[i + w]);
           const unsigned best = k[0];
-          // each lane's best value by a select tree (runs beside the wave maximum)
+          // each lane's best row, slots t.. (select trees that run beside the wave
+          // maximum); the winning lane's selection is the pivot row
           const int bi = (int)(best & 7u);
-          double v[RPL];
+          double sr[SL];
 #pragma unroll
-          for (int i = 0; i < RPL; ++i) v[i] = x[i][t];
+          for (int c = t; c < SL; ++c) {
+            double v[RPL];
 #pragma unroll
-          for (int w = 1; w < RPL; w *= 2)
+            for (int i = 0; i < RPL; ++i) v[i] = x[i][c];
 #pragma unroll
-            for (int i = 0; i + w < RPL; i += 2 * w) v[i] = ((bi & w) != 0) ? v[i + w] : v[i];
+            for (int w = 1; w < RPL; w *= 2)
+#pragma unroll
+              for (int i = 0; i + w < RPL; i += 2 * w) v[i] = ((bi & w) != 0) ? v[i + w] : v[i];
+            sr[c] = v[0];
+          }
           const unsigned kmax = wave_max_u32(best);
           const unsigned long long bal = __ballot(best == kmax);
           const int L = bal ? (__ffsll((long long)bal) - 1) : 0;
           const int iL = (int)(kmax & 7u) & (RPL - 1);
-          const double rpj = pivot_recip(readlane_d(v[0], L));
-          if (lane == L) act &= ~(1u << iL);
-          if (lane == 0) {
-            s_rec[r].p = L + 64 * iL;
-            s_rec[r].rp = rpj;
-            s_sel[j] = L + 64 * iL;
-            __hip_atomic_store(&s_rec[r].stamp, j + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+          if (lane == L) {
+#pragma unroll
+            for (int c = t + 1; c < SL; ++c) s_prow[wave][c] = sr[c];
           }
+          const double rpj = pivot_recip(readlane_d(sr[t], L));
+          if (lane == L) act &= ~(1u << iL);
+          // every lane stores the same uniform values: no divergent branch
+          s_rec[r].p = L + 64 * iL;
+          s_rec[r].rp = rpj;
+          s_sel[j] = L + 64 * iL;
+          __hip_atomic_store(&s_rec[r].stamp, j + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
           asm volatile("s_wakeup" ::: "memory");   // end the sleep of waiting waves
           double l[RPL];
 #pragma unroll
@@ -379,7 +386,12 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(1, 2))) void
           }
           if (t + 1 < SL) {   // step j on the rest of the block, the next column first
             double u[SL];
-            read_owner_row(x, t + 1, iL, L, u);
+            // lane L's stores above precede these loads in the wave's LDS order
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+            for (int c = t + 1; c < SL; ++c) u[c] = s_prow[wave][c];   // broadcast loads
 #pragma unroll
             for (int c = t + 1; c < SL; ++c) {
 #pragma unroll
