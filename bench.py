@@ -27,7 +27,8 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE counter runs summarised in profiles/, each scaled by what the same
 # counter reads for a plain copy of known size (--copy-calibration).  Tied to the
 # kernel source it was measured on: any later edit of that file voids it.
-TRAFFIC = None   # {"bytes_per_launch": float, "source_sha256": str}
+TRAFFIC = {"bytes_per_launch": 4.4207e+08,
+           "source_sha256": "0e96962fd8f76dbc16d6d6fcc420ad1b7aa3d42b20112ea392c4fe33c7680bd5"}
 TRAFFIC_SOURCE = os.path.join(ROOT, "paper_2401_10089_amd", "csrc", "gemm_f64.hip")
 COPY_CALIBRATION_DOUBLES = 1 << 27   # 1 GiB read + 1 GiB written
 
@@ -155,6 +156,7 @@ def main():
         "frac": (achieved / MFMA_FP64_PEAK_TFLOPS) if achieved else None,
         "traffic": traffic_per_launch(),
         "launches": prof["launches"],
+        "algorithmic_bytes_per_launch": prof["bytes"] / max(prof["launches"], 1),
         "avg_launch_ms": prof["ms"] / max(prof["launches"], 1),
         "algorithmic_flops_per_launch": prof["flops"] / max(prof["launches"], 1),
     }
