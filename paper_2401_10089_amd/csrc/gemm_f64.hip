@@ -17,7 +17,7 @@
 namespace logm {
 namespace {
 
-constexpr int BM = 128;
+constexpr int BM = 128;   // default tile
 constexpr int BN = 128;
 constexpr int BK = 16;
 constexpr int PAD = 4;
@@ -47,10 +47,16 @@ struct TileCols {
   int a0, na, b0, nb;
 };
 
-template <class Op>
+// Tile TM x TN per 256-thread workgroup: 2 x 2 waves of (TM/2) x (TN/2), each made
+// of MI x NI blocks of 16 x 16 (MI = TM/32, NI = TN/32).
+template <class Op, int TM = BM, int TN = BN>
 __global__ __launch_bounds__(256) void gemm_kernel(Op op, int M, int N, int K, TileCols tc) {
-  __shared__ double As[2][BK][BM + PAD];
-  __shared__ double Bs[2][BK][BN + PAD];
+  constexpr int MI = TM / 32;
+  constexpr int NI = TN / 32;
+  constexpr int APT = TM * BK / 256;   // A elements per thread per k-slab
+  constexpr int BPT = TN * BK / 256;   // B elements per thread per k-slab
+  __shared__ double As[2][BK][TM + PAD];
+  __shared__ double Bs[2][BK][TN + PAD];
 
   op.select(blockIdx.z);
   const int tid = threadIdx.x;
@@ -58,7 +64,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(Op op, int M, int N, int K, T
   const int lane = tid & 63;
   const int wm = wave >> 1;
   const int wn = wave & 1;
-  const int tiles_m = (M + BM - 1) / BM;
+  const int tiles_m = (M + TM - 1) / TM;
   const int ntiles = tiles_m * (tc.na + tc.nb);
   // persistent: a workgroup walks tiles blockIdx.x, + gridDim.x, ...; with a grid that
   // is a multiple of 8 every tile of one workgroup stays on the same XCD group
@@ -66,41 +72,41 @@ __global__ __launch_bounds__(256) void gemm_kernel(Op op, int M, int N, int K, T
   int tm, vn;
   tile_of(bid, tiles_m, tc.na + tc.nb, tm, vn);
   const int tn = (vn < tc.na) ? tc.a0 + vn : tc.b0 + (vn - tc.na);
-  const int row0 = tm * BM;
-  const int col0 = tn * BN;
+  const int row0 = tm * TM;
+  const int col0 = tn * TN;
 
-  if (op.copy_tile(row0, col0)) {
-    for (int e = tid; e < BM * BN; e += 256) {
-      const int i = row0 + e / BN;
-      const int j = col0 + e % BN;
+  if (op.copy_tile(row0, col0, TN)) {
+    for (int e = tid; e < TM * TN; e += 256) {
+      const int i = row0 + e / TN;
+      const int j = col0 + e % TN;
       if (i < M && j < N) op.copy(i, j);
     }
     continue;
   }
 
   // global -> register staging assignment
-  const int ra = tid >> 1;          // A: row within tile
-  const int ka = (tid & 1) * 8;     // A: first k of 8
-  const int kb = tid >> 4;          // B: k row
-  const int cb = (tid & 15) * 8;    // B: first column of 8
+  const int ra = tid / (BK / APT);          // A: row within tile
+  const int ka = (tid % (BK / APT)) * APT;  // A: first k of APT
+  const int kb = tid / (TN / BPT);          // B: k row
+  const int cb = (tid % (TN / BPT)) * BPT;  // B: first column of BPT
   const bool a_row_ok = (row0 + ra) < M;
   const double* arow = a_row_ok ? op.a_row(row0 + ra) : nullptr;
-  const bool full_n = (col0 + BN) <= N;
+  const bool full_n = (col0 + TN) <= N;
 
-  double va[8], vb[8];
+  double va[APT], vb[BPT];
   auto gload = [&](int k0) {
     const int kA = k0 + ka;
-    if (a_row_ok && kA + 8 <= K && ((reinterpret_cast<uintptr_t>(arow + kA) & 15) == 0)) {
+    if (a_row_ok && kA + APT <= K && ((reinterpret_cast<uintptr_t>(arow + kA) & 15) == 0)) {
       const f64x2* p = reinterpret_cast<const f64x2*>(arow + kA);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
+      for (int e = 0; e < APT / 2; ++e) {
         f64x2 v = p[e];
         va[2 * e] = v.x;
         va[2 * e + 1] = v.y;
       }
     } else {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) va[e] = (a_row_ok && kA + e < K) ? arow[kA + e] : 0.0;
+      for (int e = 0; e < APT; ++e) va[e] = (a_row_ok && kA + e < K) ? arow[kA + e] : 0.0;
     }
     const int kB = k0 + kb;
     if (kB < K) {
@@ -108,32 +114,32 @@ __global__ __launch_bounds__(256) void gemm_kernel(Op op, int M, int N, int K, T
       if (full_n && ((reinterpret_cast<uintptr_t>(brow) & 15) == 0)) {
         const f64x2* p = reinterpret_cast<const f64x2*>(brow);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < BPT / 2; ++e) {
           f64x2 v = p[e];
           vb[2 * e] = v.x;
           vb[2 * e + 1] = v.y;
         }
       } else {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) vb[e] = (col0 + cb + e < N) ? brow[e] : 0.0;
+        for (int e = 0; e < BPT; ++e) vb[e] = (col0 + cb + e < N) ? brow[e] : 0.0;
       }
     } else {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) vb[e] = 0.0;
+      for (int e = 0; e < BPT; ++e) vb[e] = 0.0;
     }
   };
   auto sstore = [&](int buf) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) As[buf][ka + e][ra] = va[e];
+    for (int e = 0; e < APT; ++e) As[buf][ka + e][ra] = va[e];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) Bs[buf][kb][cb + e] = vb[e];
+    for (int e = 0; e < BPT; ++e) Bs[buf][kb][cb + e] = vb[e];
   };
 
-  f64x4 acc[4][4];
+  f64x4 acc[MI][NI];
 #pragma unroll
-  for (int mi = 0; mi < 4; ++mi)
+  for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
-    for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int ni = 0; ni < NI; ++ni) acc[mi][ni] = f64x4{0.0, 0.0, 0.0, 0.0};
 
   const int nk = (K + BK - 1) / BK;
   gload(0);
@@ -147,15 +153,15 @@ __global__ __launch_bounds__(256) void gemm_kernel(Op op, int M, int N, int K, T
     if (more) gload((kt + 1) * BK);
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
-      double af[4], bf[4];
+      double af[MI], bf[NI];
 #pragma unroll
-      for (int mi = 0; mi < 4; ++mi) af[mi] = As[buf][kk * 4 + lk][wm * 64 + mi * 16 + lr];
+      for (int mi = 0; mi < MI; ++mi) af[mi] = As[buf][kk * 4 + lk][wm * (TM / 2) + mi * 16 + lr];
 #pragma unroll
-      for (int ni = 0; ni < 4; ++ni) bf[ni] = Bs[buf][kk * 4 + lk][wn * 64 + ni * 16 + lr];
+      for (int ni = 0; ni < NI; ++ni) bf[ni] = Bs[buf][kk * 4 + lk][wn * (TN / 2) + ni * 16 + lr];
 #pragma unroll
-      for (int mi = 0; mi < 4; ++mi)
+      for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
-        for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = mfma_f64_16x16x4(af[mi], bf[ni], acc[mi][ni]);
+        for (int ni = 0; ni < NI; ++ni) acc[mi][ni] = mfma_f64_16x16x4(af[mi], bf[ni], acc[mi][ni]);
     }
     if (more) sstore(buf ^ 1);
     __syncthreads();
@@ -163,20 +169,20 @@ __global__ __launch_bounds__(256) void gemm_kernel(Op op, int M, int N, int K, T
   }
 
   // epilogue: per 16-row group each lane owns rows 4r + lk (r < 4) and columns
-  // 16 ni + lr (ni < 4) of the wave's 64 x 64 block
+  // 16 ni + lr (ni < NI) of the wave's block
 #pragma unroll
-  for (int mi = 0; mi < 4; ++mi) {
-    int rows[4], cols[4];
+  for (int mi = 0; mi < MI; ++mi) {
+    int rows[4], cols[NI];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) rows[r] = row0 + wm * 64 + mi * 16 + 4 * r + lk;
+    for (int r = 0; r < 4; ++r) rows[r] = row0 + wm * (TM / 2) + mi * 16 + 4 * r + lk;
 #pragma unroll
-    for (int ni = 0; ni < 4; ++ni) cols[ni] = col0 + wn * 64 + ni * 16 + lr;
-    double v[4][4];
+    for (int ni = 0; ni < NI; ++ni) cols[ni] = col0 + wn * (TN / 2) + ni * 16 + lr;
+    double v[4][NI];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
-      for (int ni = 0; ni < 4; ++ni) v[r][ni] = acc[mi][ni][r];
-    op.store_group(rows, cols, v, M, N);
+      for (int ni = 0; ni < NI; ++ni) v[r][ni] = acc[mi][ni][r];
+    op.template store_group<NI>(rows, cols, v, M, N);
   }
   }
 }
@@ -191,17 +197,18 @@ struct PlainOp {
   int64_t ldc;
   double alpha, beta;
   __device__ void select(int) {}
-  __device__ bool copy_tile(int, int) const { return false; }
+  __device__ bool copy_tile(int, int, int) const { return false; }
   __device__ void copy(int, int) const {}
   __device__ const double* a_row(int i) const { return A + (int64_t)i * lda; }
   __device__ const double* b_row(int k) const { return B + (int64_t)k * ldb; }
   // all loads of the group are issued before any store
-  __device__ void store_group(const int* rows, const int* cols, double (*v)[4], int M, int N) const {
-    double old[4][4];
+  template <int NI>
+  __device__ void store_group(const int* rows, const int* cols, double (*v)[NI], int M, int N) const {
+    double old[4][NI];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
-      for (int ni = 0; ni < 4; ++ni) {
+      for (int ni = 0; ni < NI; ++ni) {
         const int i = min(rows[r], M - 1);
         const int j = min(cols[ni], N - 1);
         old[r][ni] = (beta == 0.0) ? 0.0 : C[(int64_t)i * ldc + j];
@@ -209,7 +216,7 @@ struct PlainOp {
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
-      for (int ni = 0; ni < 4; ++ni)
+      for (int ni = 0; ni < NI; ++ni)
         if (rows[r] < M && cols[ni] < N)
           C[(int64_t)rows[r] * ldc + cols[ni]] = alpha * v[r][ni] + beta * old[r][ni];
   }
@@ -218,46 +225,47 @@ struct PlainOp {
 struct PolyOp {
   PolyGemmArgs a;
   __device__ void select(int) {}
-  __device__ bool copy_tile(int, int) const { return false; }
+  __device__ bool copy_tile(int, int, int) const { return false; }
   __device__ void copy(int, int) const {}
   __device__ const double* a_row(int i) const { return a.Lf + (int64_t)i * a.ld; }
   __device__ const double* b_row(int k) const { return a.Rf + (int64_t)k * a.ld; }
   // tiles can overhang the n x n matrices (n_pad is a multiple of 64, tiles are
   // 128 wide): loads are clamped into the matrix and stores predicated
-  __device__ void store_group(const int* rows, const int* cols, double (*v)[4], int M, int N) const {
-    int64_t o[4][4];
-    bool in[4][4];
+  template <int NI>
+  __device__ void store_group(const int* rows, const int* cols, double (*v)[NI], int M, int N) const {
+    int64_t o[4][NI];
+    bool in[4][NI];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
-      for (int ni = 0; ni < 4; ++ni) {
+      for (int ni = 0; ni < NI; ++ni) {
         in[r][ni] = rows[r] < M && cols[ni] < N;
         o[r][ni] = (int64_t)min(rows[r], M - 1) * a.ld + min(cols[ni], N - 1);
       }
     for (int t = 0; t < a.nacc; ++t) {
       double* p = a.acc[t];
       const double cf = a.coef[t];
-      double old[4][4];
+      double old[4][NI];
 #pragma unroll
       for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int ni = 0; ni < 4; ++ni) old[r][ni] = p[o[r][ni]];
+        for (int ni = 0; ni < NI; ++ni) old[r][ni] = p[o[r][ni]];
 #pragma unroll
       for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int ni = 0; ni < 4; ++ni)
+        for (int ni = 0; ni < NI; ++ni)
           if (in[r][ni]) p[o[r][ni]] = fma(cf, v[r][ni], old[r][ni]);
     }
     if (a.dst != nullptr) {
-      double b[4][4];
+      double b[4][NI];
 #pragma unroll
       for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int ni = 0; ni < 4; ++ni) b[r][ni] = a.base[o[r][ni]];
+        for (int ni = 0; ni < NI; ++ni) b[r][ni] = a.base[o[r][ni]];
 #pragma unroll
       for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int ni = 0; ni < 4; ++ni)
+        for (int ni = 0; ni < NI; ++ni)
           if (in[r][ni] && rows[r] < a.nvalid && cols[ni] < a.nvalid)
             a.dst[(int64_t)rows[r] * a.ldd + cols[ni]] = a.scale * (b[r][ni] + a.ycoef * v[r][ni]);
     }
@@ -286,12 +294,13 @@ struct GjeOuterOp {
     p = one ? pi[1] : pi[0];
     mo = one ? Mout[1] : Mout[0];
   }
-  __device__ bool copy_tile(int, int col0) const { return col0 >= k0 && col0 + BN <= k0 + nbo; }
+  __device__ bool copy_tile(int, int col0, int tn) const { return col0 >= k0 && col0 + tn <= k0 + nbo; }
   __device__ void copy(int i, int j) const { mo[(int64_t)i * ld + j] = u[(int64_t)i * nbo + (j - k0)]; }
   __device__ const double* a_row(int i) const { return u + (int64_t)i * nbo; }
   __device__ const double* b_row(int t) const { return mi + (int64_t)p[k0 + t] * ld; }
   // branch-free: every load of the group is issued before the first store
-  __device__ void store_group(const int* rows, const int* cols, double (*v)[4], int M, int N) const {
+  template <int NI>
+  __device__ void store_group(const int* rows, const int* cols, double (*v)[NI], int M, int N) const {
     const double* src[4];
     bool rowk[4];
 #pragma unroll
@@ -300,34 +309,34 @@ struct GjeOuterOp {
       src[r] = mi + (int64_t)p[i] * ld;
       rowk[r] = rows[r] >= k0 && rows[r] < k0 + nbo;
     }
-    bool colk[4];
+    bool colk[NI];
     bool anyk = false;
 #pragma unroll
-    for (int ni = 0; ni < 4; ++ni) {
+    for (int ni = 0; ni < NI; ++ni) {
       colk[ni] = cols[ni] >= k0 && cols[ni] < k0 + nbo;
       anyk |= colk[ni];
     }
-    double base[4][4];
+    double base[4][NI];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
-      for (int ni = 0; ni < 4; ++ni) base[r][ni] = src[r][min(cols[ni], N - 1)];
-    double uv[4][4];
+      for (int ni = 0; ni < NI; ++ni) base[r][ni] = src[r][min(cols[ni], N - 1)];
+    double uv[4][NI];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
-      for (int ni = 0; ni < 4; ++ni) uv[r][ni] = 0.0;
+      for (int ni = 0; ni < NI; ++ni) uv[r][ni] = 0.0;
     if (anyk) {
 #pragma unroll
       for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int ni = 0; ni < 4; ++ni)
+        for (int ni = 0; ni < NI; ++ni)
           if (colk[ni]) uv[r][ni] = u[(int64_t)min(rows[r], M - 1) * nbo + (cols[ni] - k0)];
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
-      for (int ni = 0; ni < 4; ++ni) {
+      for (int ni = 0; ni < NI; ++ni) {
         const double out = colk[ni] ? uv[r][ni] : ((rowk[r] ? 0.0 : base[r][ni]) + v[r][ni]);
         if (rows[r] < M && cols[ni] < N) mo[(int64_t)rows[r] * ld + cols[ni]] = out;
       }
@@ -335,13 +344,13 @@ struct GjeOuterOp {
 };
 
 // max_wgs > 0 caps the workgroups per matrix (the kernel then loops over tiles).
-template <class Op>
+template <class Op, int TM = BM, int TN = BN>
 hipError_t launch(const Op& op, int M, int N, int K, int nz, TileCols tc, hipStream_t s,
                   int max_wgs = 0) {
-  const int tiles = ((M + BM - 1) / BM) * (tc.na + tc.nb);
+  const int tiles = ((M + TM - 1) / TM) * (tc.na + tc.nb);
   if (tiles == 0) return hipSuccess;
   const int grid = (max_wgs > 0 && tiles > max_wgs) ? max_wgs : tiles;
-  hipLaunchKernelGGL(gemm_kernel<Op>, dim3(grid, 1, nz), dim3(256), 0, s, op, M, N, K, tc);
+  hipLaunchKernelGGL((gemm_kernel<Op, TM, TN>), dim3(grid, 1, nz), dim3(256), 0, s, op, M, N, K, tc);
   return hipGetLastError();
 }
 
@@ -373,12 +382,21 @@ hipError_t launch_gje_outer_update(const GjeArgs& a, int c_lo, int c_hi, bool in
   op.ld = a.n_pad;
   op.k0 = a.k0;
   op.nbo = a.nbo;
+  if (inside) {
+    // the look-ahead columns are on the critical path: small tiles spread them over
+    // every CU (c_lo is a multiple of 128, so also of 64)
+    constexpr int ST = 64;
+    const int tn = (a.n_pad + ST - 1) / ST;
+    const int t_lo = std::min(std::max(c_lo / ST, 0), tn);
+    const int t_hi = std::min(std::max((c_hi + ST - 1) / ST, t_lo), tn);
+    return launch<GjeOuterOp, ST, ST>(op, a.n_pad, a.n_pad, a.nbo, a.nmat,
+                                      TileCols{t_lo, t_hi - t_lo, 0, 0}, s, max_wgs);
+  }
   const int tn = (a.n_pad + BN - 1) / BN;
   const int t_lo = std::min(std::max(c_lo / BN, 0), tn);
   const int t_hi = std::min(std::max((c_hi + BN - 1) / BN, t_lo), tn);
-  const TileCols tc = inside ? TileCols{t_lo, t_hi - t_lo, 0, 0}
-                             : TileCols{0, t_lo, t_hi, tn - t_hi};
-  return launch(op, a.n_pad, a.n_pad, a.nbo, a.nmat, tc, s, max_wgs);
+  return launch(op, a.n_pad, a.n_pad, a.nbo, a.nmat, TileCols{0, t_lo, t_hi, tn - t_hi}, s,
+                max_wgs);
 }
 
 }  // namespace logm

@@ -86,6 +86,26 @@ __device__ __forceinline__ void read_owner_row(const double (&x)[RPL][SL], int c
   _Pragma("unroll") for (int c = c_first; c < SL; ++c) u[c] = readlane_d(x[0][c], L);
 }
 
+// dst[c] = x[iL][c] for c >= c_first (compile-time after unrolling), iL wave-uniform:
+// a scalar if-chain keeps every register index static.
+__device__ __forceinline__ void store_row_tail(const double (&x)[RPL][SL], int c_first, int iL,
+                                               double* dst) {
+#define LOGM_TAIL_CASE(I)                                                                  \
+  if (I < RPL && iL == I) {                                                                \
+    _Pragma("unroll") for (int c = c_first; c < SL; ++c) dst[c] = x[(I < RPL) ? I : 0][c]; \
+    return;                                                                                \
+  }
+  LOGM_TAIL_CASE(0)
+  LOGM_TAIL_CASE(1)
+  LOGM_TAIL_CASE(2)
+  LOGM_TAIL_CASE(3)
+  LOGM_TAIL_CASE(4)
+  LOGM_TAIL_CASE(5)
+  LOGM_TAIL_CASE(6)
+  LOGM_TAIL_CASE(7)
+#undef LOGM_TAIL_CASE
+}
+
 // x[iL][T] of lane L for wave-uniform iL and L (T a compile-time slot after unrolling).
 __device__ __forceinline__ double read_owner_slot(const double (&x)[RPL][SL], int T, int iL, int L) {
 #define LOGM_SLOT_CASE(I) \
@@ -347,30 +367,23 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(1, 2))) void
 #pragma unroll
             for (int i = 0; i + w < RPL; i += 2 * w) k[i] = max(k[i], k[i + w]);
           const unsigned best = k[0];
-          // each lane's best row, slots t.. (select trees that run beside the wave
-          // maximum); the winning lane's selection is the pivot row
+          // each lane's best value of the column by a select tree (runs beside the
+          // wave maximum)
           const int bi = (int)(best & 7u);
-          double sr[SL];
+          double v[RPL];
 #pragma unroll
-          for (int c = t; c < SL; ++c) {
-            double v[RPL];
+          for (int i = 0; i < RPL; ++i) v[i] = x[i][t];
 #pragma unroll
-            for (int i = 0; i < RPL; ++i) v[i] = x[i][c];
+          for (int w = 1; w < RPL; w *= 2)
 #pragma unroll
-            for (int w = 1; w < RPL; w *= 2)
-#pragma unroll
-              for (int i = 0; i + w < RPL; i += 2 * w) v[i] = ((bi & w) != 0) ? v[i + w] : v[i];
-            sr[c] = v[0];
-          }
+            for (int i = 0; i + w < RPL; i += 2 * w) v[i] = ((bi & w) != 0) ? v[i + w] : v[i];
           const unsigned kmax = wave_max_u32(best);
           const unsigned long long bal = __ballot(best == kmax);
           const int L = bal ? (__ffsll((long long)bal) - 1) : 0;
           const int iL = (int)(kmax & 7u) & (RPL - 1);
-          if (lane == L) {
-#pragma unroll
-            for (int c = t + 1; c < SL; ++c) s_prow[wave][c] = sr[c];
-          }
-          const double rpj = pivot_recip(readlane_d(sr[t], L));
+          // the winning lane stores the rest of the pivot row for the broadcast below
+          if (t + 1 < SL && lane == L) store_row_tail(x, t + 1, iL, s_prow[wave]);
+          const double rpj = pivot_recip(readlane_d(v[0], L));
           if (lane == L) act &= ~(1u << iL);
           // every lane stores the same uniform values: no divergent branch
           s_rec[r].p = L + 64 * iL;
