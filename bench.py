@@ -146,6 +146,21 @@ def main():
     L = out.cpu().numpy()
     rel_err = float(np.linalg.norm(L - L_exact) / np.linalg.norm(L_exact))
 
+    # precision variant (untimed for the metric): graph products on the fp32 matrix cores
+    out32 = torch.empty_like(A)
+    torch.cuda.synchronize()
+    t32 = time.perf_counter()
+    lm.logm(A, out=out32, workspace=ws, graph_fp32=True)
+    torch.cuda.synchronize()
+    t32 = time.perf_counter() - t32
+    L32 = out32.cpu().numpy()
+    fp32_check = {
+        "graph_fp32_rel_err_vs_fp64_path": float(np.linalg.norm(L32 - L) / np.linalg.norm(L)),
+        "graph_fp32_rel_err_vs_exact_log": float(np.linalg.norm(L32 - L_exact) / np.linalg.norm(L_exact)),
+        "graph_fp32_ms": 1e3 * t32,
+    }
+    del out32
+
     achieved = prof["flops"] / (prof["ms"] * 1e-3) / 1e12 if prof["ms"] > 0 else None
     roofline = {
         "bound": "mfma",
@@ -186,7 +201,7 @@ def main():
             "algorithmic_flops_per_step": info["flops"],
             "event_ms_per_step": ev_ms / args.steps,
         },
-        "check": {"rel_frobenius_err_vs_exact_log": rel_err},
+        "check": {"rel_frobenius_err_vs_exact_log": rel_err, **fp32_check},
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:

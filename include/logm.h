@@ -64,7 +64,13 @@ typedef struct logm_opts {
   int32_t db_max_iter;  /* maximum Denman-Beavers iterations per root (default 30) */
   int32_t theta_source; /* 0: Theta values of Table 2 as printed (default);
                            1: Theta_5 = 0.2448 recomputed from Table 1 */
-  int32_t reserved[4];  /* must be zero */
+  int32_t graph_fp32;   /* 0: graph products in fp64 (default); 1: the k - 1 products of
+                           eq. five_mult_degopt on the fp32 matrix cores (operands rounded
+                           to fp32, fp32 accumulation); the linear combinations, the
+                           output sum and 2^s stay fp64, as do the square roots, the
+                           inverses and the norm estimates.  Result error about u_32 ||B||
+                           relative instead of u_64. */
+  int32_t reserved[3];  /* must be zero */
 } logm_opts;
 
 /* Decisions and counters of one call (host memory). */

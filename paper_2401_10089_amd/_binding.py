@@ -67,7 +67,8 @@ class LogmOpts(ctypes.Structure):
         ("max_sqrt", ctypes.c_int32),
         ("db_max_iter", ctypes.c_int32),
         ("theta_source", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 4),
+        ("graph_fp32", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
     ]
 
 
@@ -246,14 +247,17 @@ def _workspace(n: int, device, workspace=None):
 
 
 def logm(A, k_max: int = 5, max_sqrt: int = 50, db_max_iter: int = 30, theta_source: int = 0,
-         out=None, workspace=None):
-    """L = log(A) on the GPU (Algorithm 1).  Returns (L, info dict)."""
+         out=None, workspace=None, graph_fp32: bool = False):
+    """L = log(A) on the GPU (Algorithm 1).  Returns (L, info dict).
+
+    graph_fp32 runs the graph products on the fp32 matrix cores (see logm_opts)."""
     torch = _torch()
     A = _as_matrix(A)
     n = A.shape[0]
     L = out if out is not None else torch.empty((n, n), dtype=torch.float64, device=A.device)
     o = default_opts()
     o.k_max, o.max_sqrt, o.db_max_iter, o.theta_source = k_max, max_sqrt, db_max_iter, theta_source
+    o.graph_fp32 = 1 if graph_fp32 else 0
     ws = _workspace(n, A.device, workspace)
     info = LogmInfo()
     rc = lib().logm_forward(LOGM_R64, n, _vp(A.data_ptr()), A.stride(0), _vp(L.data_ptr()), L.stride(0),

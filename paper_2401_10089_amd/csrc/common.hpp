@@ -8,6 +8,7 @@ namespace logm {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // One CDNA matrix-core step: D(16x16) += A(16x4) * B(4x16) in fp64.
 // Lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]; lane l receives
@@ -15,6 +16,14 @@ typedef double f64x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ f64x4 mfma_f64_16x16x4(double a, double b, f64x4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
+
+// The fp32 matrix-core step of the same 16 x 16 x 4 shape: same operand layout,
+// but lane l receives D[4 * (l / 16) + r][l % 16] in element r.
+__device__ __forceinline__ f32x4 mfma_f32_16x16x4(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f64x4 mfma_16x16x4(double a, double b, f64x4 c) { return mfma_f64_16x16x4(a, b, c); }
+__device__ __forceinline__ f32x4 mfma_16x16x4(float a, float b, f32x4 c) { return mfma_f32_16x16x4(a, b, c); }
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 

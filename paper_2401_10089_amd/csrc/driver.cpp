@@ -679,7 +679,7 @@ Status select_degree(Estimator& est, const ThetaTable& T, const std::vector<int>
 // L = -2^s S_k(-B) with P_2 = -B and P_3 = B2 (eq. five_mult_degopt); L is the
 // caller's n x n matrix (ldl).  Accumulators live in the free workspace matrices.
 Status poly(Ctx& c, int k, int s, const double* B, const double* B2, double* L, int64_t ldl,
-            int* ngemm) {
+            int* ngemm, bool fp32 = false) {
   Status st;
   const Scheme& S = scheme(k);
   const int n = c.p.n;
@@ -757,7 +757,7 @@ Status poly(Ctx& c, int k, int s, const double* B, const double* B2, double* L, 
         pa.nvalid = n;
       }
       pa.nacc = na;
-      HIPCK(launch_gemm_poly(np, pa, c.s));
+      HIPCK(launch_gemm_poly(np, pa, fp32, c.s));
       ++*ngemm;
     }
     HIPCK(launch_check_finite(L, ldl, n, flag, c.s));
@@ -853,7 +853,7 @@ Status forward_r64(Ctx& c, const double* A, int64_t lda, double* L, int64_t ldl,
   PROPAGATE(norm1(c, B2, &n2));
   int k = ktop;
   PROPAGATE(select_degree(est, T, K, n1, n2, have_top, e_top, have_top1, e_top1, &k, &info.n_est));
-  PROPAGATE(poly(c, k, s, B, B2, L, ldl, &info.n_gemm));
+  PROPAGATE(poly(c, k, s, B, B2, L, ldl, &info.n_gemm, o.graph_fp32 != 0));
   info.s = s;
   info.k = k;
   info.m = T.m[k];
@@ -918,7 +918,8 @@ bool opts_ok(const logm_opts& o) {
   if (o.max_sqrt < 0 || o.max_sqrt > 64) return false;
   if (o.db_max_iter < 1 || o.db_max_iter > 1000) return false;
   if (o.theta_source != 0 && o.theta_source != 1) return false;
-  for (int i = 0; i < 4; ++i)
+  if (o.graph_fp32 != 0 && o.graph_fp32 != 1) return false;
+  for (int i = 0; i < 3; ++i)
     if (o.reserved[i] != 0) return false;
   return true;
 }

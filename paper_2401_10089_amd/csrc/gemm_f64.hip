@@ -10,6 +10,7 @@
 // k-slabs of 16 staged through LDS with a double buffer; each wave issues
 // 16 independent v_mfma_f64_16x16x4 per k-step of 4.
 #include <algorithm>
+#include <type_traits>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -49,14 +50,18 @@ struct TileCols {
 
 // Tile TM x TN per 256-thread workgroup: 2 x 2 waves of (TM/2) x (TN/2), each made
 // of MI x NI blocks of 16 x 16 (MI = TM/32, NI = TN/32).
-template <class Op, int TM = BM, int TN = BN>
+template <class Op, int TM = BM, int TN = BN, bool F32 = false>
 __global__ __launch_bounds__(256) void gemm_kernel(Op op, int M, int N, int K, TileCols tc) {
   constexpr int MI = TM / 32;
   constexpr int NI = TN / 32;
   constexpr int APT = TM * BK / 256;   // A elements per thread per k-slab
   constexpr int BPT = TN * BK / 256;   // B elements per thread per k-slab
-  __shared__ double As[2][BK][TM + PAD];
-  __shared__ double Bs[2][BK][TN + PAD];
+  // F32: operands rounded to fp32 when staged, fp32 matrix cores with fp32
+  // accumulation; the epilogue still receives the tile widened to fp64
+  using T = typename std::conditional<F32, float, double>::type;
+  using Acc = typename std::conditional<F32, f32x4, f64x4>::type;
+  __shared__ T As[2][BK][TM + PAD];
+  __shared__ T Bs[2][BK][TN + PAD];
 
   op.select(blockIdx.z);
   const int tid = threadIdx.x;
@@ -130,16 +135,16 @@ __global__ __launch_bounds__(256) void gemm_kernel(Op op, int M, int N, int K, T
   };
   auto sstore = [&](int buf) {
 #pragma unroll
-    for (int e = 0; e < APT; ++e) As[buf][ka + e][ra] = va[e];
+    for (int e = 0; e < APT; ++e) As[buf][ka + e][ra] = (T)va[e];
 #pragma unroll
-    for (int e = 0; e < BPT; ++e) Bs[buf][kb][cb + e] = vb[e];
+    for (int e = 0; e < BPT; ++e) Bs[buf][kb][cb + e] = (T)vb[e];
   };
 
-  f64x4 acc[MI][NI];
+  Acc acc[MI][NI];
 #pragma unroll
   for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
-    for (int ni = 0; ni < NI; ++ni) acc[mi][ni] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int ni = 0; ni < NI; ++ni) acc[mi][ni] = Acc{0, 0, 0, 0};
 
   const int nk = (K + BK - 1) / BK;
   gload(0);
@@ -153,7 +158,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(Op op, int M, int N, int K, T
     if (more) gload((kt + 1) * BK);
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
-      double af[MI], bf[NI];
+      T af[MI], bf[NI];
 #pragma unroll
       for (int mi = 0; mi < MI; ++mi) af[mi] = As[buf][kk * 4 + lk][wm * (TM / 2) + mi * 16 + lr];
 #pragma unroll
@@ -161,27 +166,29 @@ __global__ __launch_bounds__(256) void gemm_kernel(Op op, int M, int N, int K, T
 #pragma unroll
       for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
-        for (int ni = 0; ni < NI; ++ni) acc[mi][ni] = mfma_f64_16x16x4(af[mi], bf[ni], acc[mi][ni]);
+        for (int ni = 0; ni < NI; ++ni) acc[mi][ni] = mfma_16x16x4(af[mi], bf[ni], acc[mi][ni]);
     }
     if (more) sstore(buf ^ 1);
     __syncthreads();
     buf ^= 1;
   }
 
-  // epilogue: per 16-row group each lane owns rows 4r + lk (r < 4) and columns
+  // epilogue: per 16-row group each lane owns four rows -- 4r + lk for the fp64
+  // instruction, 4 lk + r for the fp32 one (element r of lane l) -- and columns
   // 16 ni + lr (ni < NI) of the wave's block
 #pragma unroll
   for (int mi = 0; mi < MI; ++mi) {
     int rows[4], cols[NI];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) rows[r] = row0 + wm * (TM / 2) + mi * 16 + 4 * r + lk;
+    for (int r = 0; r < 4; ++r)
+      rows[r] = row0 + wm * (TM / 2) + mi * 16 + (F32 ? 4 * lk + r : 4 * r + lk);
 #pragma unroll
     for (int ni = 0; ni < NI; ++ni) cols[ni] = col0 + wn * (TN / 2) + ni * 16 + lr;
     double v[4][NI];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
-      for (int ni = 0; ni < NI; ++ni) v[r][ni] = acc[mi][ni][r];
+      for (int ni = 0; ni < NI; ++ni) v[r][ni] = (double)acc[mi][ni][r];
     op.template store_group<NI>(rows, cols, v, M, N);
   }
   }
@@ -344,13 +351,14 @@ struct GjeOuterOp {
 };
 
 // max_wgs > 0 caps the workgroups per matrix (the kernel then loops over tiles).
-template <class Op, int TM = BM, int TN = BN>
+template <class Op, int TM = BM, int TN = BN, bool F32 = false>
 hipError_t launch(const Op& op, int M, int N, int K, int nz, TileCols tc, hipStream_t s,
                   int max_wgs = 0) {
   const int tiles = ((M + TM - 1) / TM) * (tc.na + tc.nb);
   if (tiles == 0) return hipSuccess;
   const int grid = (max_wgs > 0 && tiles > max_wgs) ? max_wgs : tiles;
-  hipLaunchKernelGGL((gemm_kernel<Op, TM, TN>), dim3(grid, 1, nz), dim3(256), 0, s, op, M, N, K, tc);
+  hipLaunchKernelGGL((gemm_kernel<Op, TM, TN, F32>), dim3(grid, 1, nz), dim3(256), 0, s, op, M,
+                     N, K, tc);
   return hipGetLastError();
 }
 
@@ -365,8 +373,9 @@ hipError_t launch_gemm_plain(int M, int N, int K, double alpha, const double* A,
   return launch(op, M, N, K, 1, all_cols(N), s);
 }
 
-hipError_t launch_gemm_poly(int n, const PolyGemmArgs& a, hipStream_t s) {
+hipError_t launch_gemm_poly(int n, const PolyGemmArgs& a, bool fp32, hipStream_t s) {
   PolyOp op{a};
+  if (fp32) return launch<PolyOp, BM, BN, true>(op, n, n, n, 1, all_cols(n), s);
   return launch(op, n, n, n, 1, all_cols(n), s);
 }
 

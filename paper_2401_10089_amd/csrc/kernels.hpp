@@ -31,7 +31,9 @@ struct PolyGemmArgs {
   double scale;
   int nvalid;
 };
-hipError_t launch_gemm_poly(int n, const PolyGemmArgs& a, hipStream_t s);
+// fp32: the product runs on the fp32 matrix cores (operands rounded to fp32, fp32
+// accumulation); the accumulators and the output stay fp64.
+hipError_t launch_gemm_poly(int n, const PolyGemmArgs& a, bool fp32, hipStream_t s);
 
 // ------------------------------------------------------ Gauss-Jordan ------
 // Per-matrix state of the blocked Gauss-Jordan inversion (see gje.hip).

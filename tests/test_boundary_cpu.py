@@ -86,6 +86,9 @@ def test_forward_argument_validation(lib):
     o = lm.default_opts()
     o.reserved[0] = 1
     assert fwd(lib, opts=o) == 1
+    o = lm.default_opts()
+    o.graph_fp32 = 2                                   # 0 or 1 only
+    assert fwd(lib, opts=o) == 1
     assert fwd(lib, ws=FAKE, ws_bytes=100) == 3        # workspace too small
 
 

@@ -217,6 +217,44 @@ def test_logm_rotscale1024():
     assert info["s"] >= 5
 
 
+# ---- fp32 graph products (the precision variant): error against the fp64 oracle and
+# against the fp64 GPU path, on the rotation-scaling construction with r in [1e-2, 1e2]
+TOL_GRAPH_FP32 = 1e-5
+
+
+@pytest.mark.parametrize("n,seed", [(64, 4101), (1024, 4102)])
+def test_logm_graph_fp32_vs_oracle(n, seed):
+    A, Lx = rotscale_matrix(n, seed, r_lo=1e-2, r_hi=1e2)
+    L32, i32 = lm.logm(dev(A), graph_fp32=True)
+    L64, i64 = lm.logm(dev(A))
+    # every decision is taken in fp64 before the polynomial, so they coincide
+    assert (i32["s"], i32["k"], i32["db_iters"]) == (i64["s"], i64["k"], i64["db_iters"])
+    Lo, io = oracle.logm(A, force={"s": i32["s"], "k": i32["k"], "db_iters": i32["db_iters"]})
+    e_or = relf(host(L32), Lo)
+    e_64 = relf(host(L32), host(L64))
+    print(f"n={n}: fp32 graph vs oracle {e_or:.2e}, vs fp64 GPU path {e_64:.2e}, "
+          f"vs exact {relf(host(L32), Lx):.2e}")
+    assert e_or < TOL_GRAPH_FP32 and e_64 < TOL_GRAPH_FP32
+    # the variant really is in fp32: visibly less accurate than the fp64 path
+    assert e_64 > 1e-12
+
+
+def test_logm_graph_fp32_n8192_vs_exact():
+    """n = 8192 (r in [1e-2, 1e2]): too large for the oracle; the exact logarithm of
+    the construction and the fp64 GPU path are the references."""
+    A, Lx = rotscale_matrix(8192, 5001, r_lo=1e-2, r_hi=1e2)
+    Ad = dev(A)
+    L32, i32 = lm.logm(Ad, graph_fp32=True)
+    e_x32 = relf(host(L32), Lx)
+    del L32
+    L64, i64 = lm.logm(Ad)
+    e_x64 = relf(host(L64), Lx)
+    print(f"n=8192: fp32 graph vs exact {e_x32:.2e}, fp64 path vs exact {e_x64:.2e}, s={i64['s']}, k={i64['k']}")
+    assert (i32["s"], i32["k"]) == (i64["s"], i64["k"])
+    assert e_x64 < 1e-11
+    assert e_x32 < TOL_GRAPH_FP32
+
+
 @pytest.mark.parametrize("kmax", [1, 2, 3])
 def test_logm_smaller_kmax(kmax):
     """Small k_max forces many roots (s = 26 for k_max = 1 here); the saved product
