@@ -105,6 +105,30 @@ int logm_workspace_size(int32_t dtype, int64_t n, const logm_opts* o, size_t* by
 int logm_forward(int32_t dtype, int64_t n, const void* A, int64_t lda, void* L, int64_t ldl,
                  const logm_opts* o, logm_info* info, void* ws, size_t ws_bytes, void* stream);
 
+/* ---- batched path: many small matrices in one launch ---- */
+
+/* Workspace bytes for logm_batched_f64 over `batch` matrices of size n_i <= n_max
+ * <= 128 whose n_i^2 sum to total_elems (13 * total_elems doubles plus 256 bytes). */
+int logm_batched_workspace_size(int32_t batch, int64_t total_elems, int32_t n_max, size_t* bytes);
+
+/* L_i = log(A_i), i < batch, by Algorithm 1 with every decision (roots, estimates,
+ * eq. alpha2term1 / normAm9plus1 finish test, degree selection) taken on the device:
+ * one persistent launch, one workgroup per matrix from a device work queue.
+ * dims (device int32[batch]): n_i, 1 <= n_i <= n_max <= 128.  offsets (device
+ * int64[batch]): element offset of matrix i in A and L, both packed row-major with
+ * ld = n_i; the blocks must not overlap and sum to total_elems.  status (device
+ * int32[4 * batch]): per matrix {LOGM_* code, s, k, iterations}, where iterations
+ * packs the Denman-Beavers iteration count of root r < 6 into bits 5r..5r+4
+ * (saturating at 31).  A matrix that fails gets its code and leaves L_i undefined;
+ * the other matrices are unaffected; a block with n_i outside [1, 128] or reaching
+ * outside [0, total_elems) gets LOGM_EINVAL and is not read or written.
+ * ws (device, required, logm_batched_workspace_size bytes).  Only o->graph_fp32 = 0.
+ * Enqueues work on `stream` and returns without synchronising (capturable into a
+ * HIP graph); argument errors are returned before any device work. */
+int logm_batched_f64(int32_t batch, int32_t n_max, int64_t total_elems, const int32_t* dims,
+                     const int64_t* offsets, const double* A, double* L, const logm_opts* o,
+                     int32_t* status, void* ws, size_t ws_bytes, void* stream);
+
 /* ---- components of the path (fp64, device pointers), used for step-level checks ---- */
 
 /* C = alpha * A * B + beta * C (m x k times k x n) on the fp64 matrix cores. */

@@ -7,6 +7,8 @@ All computation happens in the HIP library ``liblogm.so`` (C ABI in
 
 from ._binding import (  # noqa: F401
     EXPORTS,
+    BatchPlan,
+    logm_batched,
     LIB_PATH,
     STATUS,
     LibraryNotBuilt,

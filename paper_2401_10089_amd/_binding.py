@@ -34,6 +34,8 @@ EXPORTS = (
     "logm_strerror",
     "logm_workspace_size",
     "logm_forward",
+    "logm_batched_workspace_size",
+    "logm_batched_f64",
     "logm_gemm_f64",
     "logm_inverse_f64",
     "logm_sqrt_f64",
@@ -128,6 +130,9 @@ def load_library(path: str = LIB_PATH):
         "logm_workspace_size": (ctypes.c_int, [_i32, _i64, ctypes.POINTER(LogmOpts), ctypes.POINTER(_sz)]),
         "logm_forward": (ctypes.c_int, [_i32, _i64, _vp, _i64, _vp, _i64, ctypes.POINTER(LogmOpts),
                                         ctypes.POINTER(LogmInfo), _vp, _sz, _vp]),
+        "logm_batched_workspace_size": (ctypes.c_int, [_i32, _i64, _i32, ctypes.POINTER(_sz)]),
+        "logm_batched_f64": (ctypes.c_int, [_i32, _i32, _i64, _vp, _vp, _vp, _vp, ctypes.POINTER(LogmOpts),
+                                            _vp, _vp, _sz, _vp]),
         "logm_gemm_f64": (ctypes.c_int, [_i64, _i64, _i64, _f64, _vp, _i64, _vp, _i64, _f64, _vp, _i64, _vp]),
         "logm_inverse_f64": (ctypes.c_int, [_i64, _vp, _i64, _vp, _i64, ctypes.POINTER(_f64), _vp, _sz, _vp]),
         "logm_sqrt_f64": (ctypes.c_int, [_i64, _vp, _i64, _vp, _i64, _i32, ctypes.POINTER(_i32), _vp, _sz, _vp]),
@@ -265,6 +270,59 @@ def logm(A, k_max: int = 5, max_sqrt: int = 50, db_max_iter: int = 30, theta_sou
                             _stream_ptr(A))
     _check(rc, "logm_forward", info.status_detail)
     return L, info.as_dict()
+
+
+class BatchPlan:
+    """Device-side description of a batch of small matrices (packed row-major)."""
+
+    def __init__(self, dims, device):
+        torch = _torch()
+        self.dims_host = [int(d) for d in dims]
+        if not self.dims_host:
+            raise ValueError("empty batch")
+        offs, tot = [], 0
+        for d in self.dims_host:
+            offs.append(tot)
+            tot += d * d
+        self.offsets_host = offs
+        self.total = tot
+        self.n_max = max(self.dims_host)
+        self.device = device
+        self.dims = torch.tensor(self.dims_host, dtype=torch.int32, device=device)
+        self.offsets = torch.tensor(offs, dtype=torch.int64, device=device)
+        by = _sz()
+        _check(lib().logm_batched_workspace_size(len(dims), tot, self.n_max, ctypes.byref(by)),
+               "logm_batched_workspace_size")
+        self.ws = torch.empty(by.value, dtype=torch.uint8, device=device)
+        self.status = torch.empty(4 * len(dims), dtype=torch.int32, device=device)
+
+    def pack(self, mats):
+        torch = _torch()
+        flat = torch.empty(self.total, dtype=torch.float64, device=self.device)
+        for M, o, d in zip(mats, self.offsets_host, self.dims_host):
+            flat[o:o + d * d] = torch.as_tensor(M, dtype=torch.float64).reshape(-1).to(self.device)
+        return flat
+
+    def unpack(self, flat):
+        return [flat[o:o + d * d].reshape(d, d) for o, d in zip(self.offsets_host, self.dims_host)]
+
+
+def logm_batched(A_flat, plan: "BatchPlan", L_flat=None, k_max: int = 5, max_sqrt: int = 50,
+                 db_max_iter: int = 30, theta_source: int = 0):
+    """L_i = log(A_i) for a packed batch (one persistent launch, decisions on the
+    device).  Returns (L_flat, status tensor [batch, 4]: code, s, k, DB iterations);
+    does not synchronise."""
+    torch = _torch()
+    if L_flat is None:
+        L_flat = torch.empty_like(A_flat)
+    o = default_opts()
+    o.k_max, o.max_sqrt, o.db_max_iter, o.theta_source = k_max, max_sqrt, db_max_iter, theta_source
+    rc = lib().logm_batched_f64(len(plan.dims_host), plan.n_max, plan.total, _vp(plan.dims.data_ptr()),
+                                _vp(plan.offsets.data_ptr()), _vp(A_flat.data_ptr()), _vp(L_flat.data_ptr()),
+                                ctypes.byref(o), _vp(plan.status.data_ptr()), _vp(plan.ws.data_ptr()),
+                                plan.ws.numel(), _stream_ptr(A_flat))
+    _check(rc, "logm_batched_f64")
+    return L_flat, plan.status.view(-1, 4)
 
 
 def gemm(A, B, C=None, alpha: float = 1.0, beta: float = 0.0):

@@ -22,6 +22,7 @@
 #include <cstring>
 #include <vector>
 
+#include "algo.hpp"
 #include "kernels.hpp"
 #include "logm.h"
 
@@ -38,18 +39,6 @@ constexpr int kMats = 11;
 constexpr int kLookaheadWgs = LOGM_LOOKAHEAD_WGS;   // trailing-update workgroups beside a panel
 
 // ------------------------------------------------------------ constants ---
-// Table 2: k -> (m_k, Theta_{m_k}).
-struct ThetaRow {
-  int m;
-  double theta;
-};
-const ThetaRow kTable2[10] = {{0, 0.0},     {2, 1.83e-8},  {4, 1.53e-4},
-                              {8, 1.33e-2}, {14, 9.31e-2}, {14, 2.46e-1},
-                              {20, 3.72e-1}, {24, 5.86e-1}, {27, 6.69e-1},
-                              {28, 7.28e-1}};
-const int kTabmin[9] = {1, 2, 3, 4, 4, 5, 5, 6, 6};
-constexpr double kTheta5Recomputed = 0.2448;
-
 struct Scheme {
   int k = 0;
   std::vector<std::vector<double>> h, g;  // h[j-2]: coefficients on P_2..P_{j+1}
@@ -119,21 +108,6 @@ const Scheme& scheme(int k) {
 }
 
 bool shipped(int k) { return k == 1 || k == 2 || k == 3 || k == 5; }
-
-struct ThetaTable {
-  int m[10];
-  double th[10];
-};
-
-ThetaTable theta_table(int source) {
-  ThetaTable t;
-  for (int k = 0; k < 10; ++k) {
-    t.m[k] = kTable2[k].m;
-    t.th[k] = kTable2[k].theta;
-  }
-  if (source == 1) t.th[5] = kTheta5Recomputed;
-  return t;
-}
 
 // ------------------------------------------------------------ profiling ---
 struct Profiler {
@@ -483,8 +457,7 @@ Status db_sqrt(Ctx& c, const double* X0, double* Xout, int max_iter, int* iters,
       st.code = LOGM_ENONFINITE;
       return st;
     }
-    if (rel < 1e-2) scaled = false;
-    if (rel <= tol || (!scaled && rel < 1e-6 && rel > rel_prev / 2.0)) {
+    if (db_stop(rel, rel_prev, scaled, tol)) {
       *iters = it;
       return st;
     }
@@ -577,103 +550,15 @@ struct Estimator {
   }
 };
 
-// --------------------------------------------------- degree selection ----
-// Choose k among the shipped schemes <= k_max, following the procedure after
-// Algorithm 1: a lower index min_in from the estimates of the last scaling pass
-// (eqs. min_in, min_inp) or from ||B^2||^{1/2} with tabmin_im (eq. roughmin_in); an
-// upper index max_in from (||B^2||^{m/2} ||B||)^{1/(m+1)} (eqs.
-// alpharoughbound_even, roughmax_even); then candidates from min_in upward, with
-// estimates skipped whenever a bound already decides, and the "j+1" shortcut.
-Status select_degree(Estimator& est, const ThetaTable& T, const std::vector<int>& K, double n1,
-                     double n2, bool have_top, double e_top, bool have_top1, double e_top1,
-                     int* k_out, int* n_est) {
+// Estimator as the callable the shared control logic expects.
+struct EstCall {
+  Estimator& e;
   Status st;
-  const int ktop = K.back();
-  const int mtop = T.m[ktop];
-  const double sq2 = std::sqrt(n2);
-  auto first_pass = [&](double v) {
-    for (int j : K)
-      if (v <= T.th[j]) return j;
-    return ktop;
-  };
-  int min_in;
-  if (have_top) {
-    min_in = first_pass(std::pow(e_top, 1.0 / mtop));
-    if (have_top1) min_in = std::max(min_in, first_pass(std::pow(e_top1, 1.0 / (mtop + 1))));
-  } else {
-    const int r = first_pass(sq2);
-    const int t = kTabmin[r - 1];
-    min_in = K.front();
-    for (int j : K)
-      if (j <= t) min_in = j;
-    if (sq2 > T.th[1]) {
-      bool has2 = std::find(K.begin(), K.end(), 2) != K.end();
-      if (has2) min_in = std::max(min_in, 2);
-    } else {
-      min_in = K.front();
-    }
+  bool operator()(int q, int r, double* out) {
+    st = e.estimate(q, r, out);
+    return st.code == LOGM_OK;
   }
-  int max_in = ktop;
-  for (int j : K) {
-    const int m = T.m[j];
-    if (std::pow(std::pow(n2, m / 2.0) * n1, 1.0 / (m + 1)) <= T.th[j]) {
-      max_in = j;
-      break;
-    }
-  }
-  if (min_in >= max_in) {
-    *k_out = max_in;
-    return st;
-  }
-  size_t idx = std::find(K.begin(), K.end(), min_in) - K.begin();
-  while (K[idx] < max_in) {
-    const int j = K[idx];
-    const int nxt = K[idx + 1];
-    const double thj = T.th[j], thn = T.th[nxt];
-    const int m = T.m[j];
-    const int h = m / 2;
-    double e1, t1;
-    if (h == 1) {
-      e1 = n2;
-      t1 = sq2;
-    } else if (sq2 <= thj) {
-      e1 = std::pow(n2, h);
-      t1 = sq2;
-    } else {
-      PROPAGATE(est.estimate(h, 0, &e1));
-      ++*n_est;
-      t1 = std::pow(e1, 1.0 / m);
-    }
-    double alpha;
-    if (t1 > thn) {
-      alpha = t1;
-    } else {
-      const double tau = (t1 <= thj) ? thj : thn;
-      const double bound = std::pow(e1 * n1, 1.0 / (m + 1));
-      double t2;
-      if (bound <= tau) {
-        t2 = bound;
-      } else {
-        double e2;
-        PROPAGATE(est.estimate(h, 1, &e2));
-        ++*n_est;
-        t2 = std::pow(e2, 1.0 / (m + 1));
-      }
-      alpha = std::max(t1, t2);
-    }
-    if (alpha <= thj) {
-      *k_out = j;
-      return st;
-    }
-    if (alpha <= thn) {
-      *k_out = nxt;
-      return st;
-    }
-    ++idx;
-  }
-  *k_out = max_in;
-  return st;
-}
+};
 
 // ------------------------------------------------------- polynomial -----
 // L = -2^s S_k(-B) with P_2 = -B and P_3 = B2 (eq. five_mult_degopt); L is the
@@ -775,13 +660,10 @@ Status forward_r64(Ctx& c, const double* A, int64_t lda, double* L, int64_t ldl,
   const int n = c.p.n;
   const int np = c.p.n_pad;
   const ThetaTable T = theta_table(o.theta_source);
-  std::vector<int> K;
-  for (int k : {1, 2, 3, 5})
-    if (k <= o.k_max) K.push_back(k);
-  const int ktop = K.back();
+  const SchemeSet K = scheme_set(o.k_max);
+  const int ktop = K.k[K.n - 1];
   const int mtop = T.m[ktop];
   const double thtop = T.th[ktop];
-  const int htop = mtop / 2;
 
   double* X = c.mat(0);
   double* A2 = c.mat(2);
@@ -797,6 +679,7 @@ Status forward_r64(Ctx& c, const double* A, int64_t lda, double* L, int64_t ldl,
     return st;
   }
   Estimator est{c, B2, B};
+  EstCall ecall{est, Status{}};
   double n1, n2;
   HIPCK(launch_shift(X, B, n, np, c.part(), c.p.nblk, c.s));
   HIPCK(launch_colsum_max(c.part(), 1, c.p.nblk, n, c.scal() + 4, c.at<double>(c.p.bm), c.s));
@@ -809,31 +692,11 @@ Status forward_r64(Ctx& c, const double* A, int64_t lda, double* L, int64_t ldl,
   double e_top = 0.0, e_top1 = 0.0;
   bool finished = n1 <= thtop;
   while (!finished && s < o.max_sqrt) {
-    have_top = have_top1 = false;
     PROPAGATE(norm1(c, B2, &n2));
-    bool t1, t2 = false;
-    double base;
-    if (std::sqrt(n2) <= thtop) {  // eq. alpha2term1
-      t1 = true;
-      base = std::pow(n2, htop);
-    } else {
-      PROPAGATE(est.estimate(htop, 0, &e_top));
-      ++info.n_est;
-      have_top = true;
-      t1 = std::pow(e_top, 1.0 / mtop) <= thtop;
-      base = e_top;
-    }
-    if (t1) {  // eq. normAm9plus1
-      if (std::pow(base * n1, 1.0 / (mtop + 1)) <= thtop) {
-        t2 = true;
-      } else {
-        PROPAGATE(est.estimate(htop, 1, &e_top1));
-        ++info.n_est;
-        have_top1 = true;
-        t2 = std::pow(e_top1, 1.0 / (mtop + 1)) <= thtop;
-      }
-    }
-    finished = t1 && t2;
+    bool ok = true;
+    finished = finish_test(ecall, n1, n2, mtop, thtop, have_top, e_top, have_top1, e_top1,
+                           &info.n_est, &ok);
+    if (!ok) return ecall.st;
     if (!finished) {
       std::swap(X, A2);  // A2 keeps the matrix whose root is taken
       int iters = 0;
@@ -851,8 +714,10 @@ Status forward_r64(Ctx& c, const double* A, int64_t lda, double* L, int64_t ldl,
     return st;
   }
   PROPAGATE(norm1(c, B2, &n2));
-  int k = ktop;
-  PROPAGATE(select_degree(est, T, K, n1, n2, have_top, e_top, have_top1, e_top1, &k, &info.n_est));
+  bool ok = true;
+  const int k = select_degree(ecall, T, K, n1, n2, have_top, e_top, have_top1, e_top1,
+                              &info.n_est, &ok);
+  if (!ok) return ecall.st;
   PROPAGATE(poly(c, k, s, B, B2, L, ldl, &info.n_gemm, o.graph_fp32 != 0));
   info.s = s;
   info.k = k;
@@ -986,6 +851,49 @@ int logm_forward(int32_t dtype, int64_t n, const void* A, int64_t lda, void* L, 
                           ldl, opts, inf);
   inf.status_detail = st.detail;
   return st.code;
+}
+
+int logm_batched_workspace_size(int32_t batch, int64_t total_elems, int32_t n_max,
+                                size_t* bytes) {
+  if (batch < 1 || total_elems < 1 || n_max < 1 || n_max > 128 || bytes == nullptr)
+    return LOGM_EINVAL;
+  *bytes = batched_workspace_bytes(total_elems);
+  return LOGM_OK;
+}
+
+int logm_batched_f64(int32_t batch, int32_t n_max, int64_t total_elems, const int32_t* dims,
+                     const int64_t* offsets, const double* A, double* L, const logm_opts* o,
+                     int32_t* status, void* ws, size_t ws_bytes, void* stream) {
+  logm_opts opts;
+  logm_default_opts(&opts);
+  if (o != nullptr) opts = *o;
+  if (batch < 1 || total_elems < 1 || n_max < 1 || n_max > 128 || dims == nullptr ||
+      offsets == nullptr || A == nullptr || L == nullptr || status == nullptr || ws == nullptr)
+    return LOGM_EINVAL;
+  if (!opts_ok(opts) || opts.graph_fp32 != 0) return LOGM_EINVAL;
+  if (ws_bytes < batched_workspace_bytes(total_elems)) return LOGM_EWORKSPACE;
+  double h[4][4][5] = {}, g[4][4][5] = {}, y[4][7] = {};
+  const int ks[4] = {1, 2, 3, 5};
+  for (int i = 0; i < 4; ++i) {
+    const Scheme& S = scheme(ks[i]);
+    for (size_t r = 0; r < S.h.size(); ++r)
+      for (size_t c = 0; c < S.h[r].size(); ++c) {
+        h[i][r][c] = S.h[r][c];
+        g[i][r][c] = S.g[r][c];
+      }
+    for (size_t c = 0; c < S.y.size(); ++c) y[i][c] = S.y[c];
+  }
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+      ncu = v;
+  }
+  hipError_t e = launch_batched_logm(batch, dims, offsets, A, L, status, ws, total_elems,
+                                     opts.k_max, opts.max_sqrt, opts.db_max_iter,
+                                     opts.theta_source, h, g, y, 2 * ncu,
+                                     reinterpret_cast<hipStream_t>(stream));
+  return (e == hipSuccess) ? LOGM_OK : LOGM_EHIP;
 }
 
 int logm_gemm_f64(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_t lda,

@@ -104,6 +104,36 @@ def test_component_argument_validation(lib):
     assert lib.logm_normest_f64(4, FAKE, 4, FAKE, 4, 1, 2, ctypes.byref(est), None, None, 0, None) == 1
 
 
+def test_batched_argument_validation(lib):
+    b = ctypes.c_size_t(0)
+    assert lib.logm_batched_workspace_size(3, 300, 10, ctypes.byref(b)) == 0
+    assert b.value >= 13 * 300 * 8
+    assert lib.logm_batched_workspace_size(0, 300, 10, ctypes.byref(b)) == 1
+    assert lib.logm_batched_workspace_size(3, 300, 129, ctypes.byref(b)) == 1   # n <= 128
+    assert lib.logm_batched_workspace_size(3, 0, 10, ctypes.byref(b)) == 1
+
+    def call(batch=3, n_max=10, total=300, dims=FAKE, offs=FAKE, A=FAKE, L=FAKE, opts=None,
+             st=FAKE, ws=FAKE, ws_bytes=1 << 20):
+        return lib.logm_batched_f64(batch, n_max, total, dims, offs, A, L,
+                                    ctypes.byref(opts) if opts else None, st, ws, ws_bytes, None)
+
+    assert call(batch=0) == 1
+    assert call(n_max=129) == 1
+    assert call(dims=None) == 1
+    assert call(offs=None) == 1
+    assert call(A=None) == 1
+    assert call(L=None) == 1
+    assert call(st=None) == 1
+    assert call(ws=None) == 1
+    o = lm.default_opts()
+    o.graph_fp32 = 1                                   # fp64 only on this path
+    assert call(opts=o) == 1
+    o = lm.default_opts()
+    o.k_max = 4
+    assert call(opts=o) == 1
+    assert call(ws_bytes=100) == 3
+
+
 def test_library_table1_matches_paper(golden):
     t = golden("table1_k5.txt")
     h, g, y, m, th = lm.scheme(5)
