@@ -24,4 +24,6 @@ from .logm_oracle import (  # noqa: F401
     db_sqrt,
     select_degree,
     logm,
+    logm_backward,
+    frechet_block,
 )

@@ -53,6 +53,8 @@ R6  Degree selection: min_in is the *smallest* index whose Theta passes (the
     against the threshold being tested (Theta_j, or Theta_next for the "j+1"
     shortcut).
 R7  Balancing (steps 1 and 14) is off: log(T^{-1} A T) = T^{-1} log(A) T exactly.
+R8  Reverse mode: the decisions (s, k, iterations per root) and the scaling
+    factors mu are constants of the differentiated map.
 """
 
 from __future__ import annotations
@@ -525,3 +527,114 @@ def logm(A, k_max: int = 5, max_sqrt: int = 50, db_max_iter: int = 30,
     if not np.all(np.isfinite(L)):
         raise OracleError("ENONFINITE", "non-finite result")
     return L, info
+
+
+# ---------------------------------------------------------------------------
+# Reverse mode: gradient of <G, log A> with respect to A
+# ---------------------------------------------------------------------------
+
+def logm_backward(A, G, k_max: int = 5, max_sqrt: int = 50, db_max_iter: int = 30,
+                  theta_table=TABLE2, force: dict | None = None):
+    """Abar = d<G, logm(A)>_F / dA by reverse-mode differentiation of Algorithm 1.
+
+    For real A this is the adjoint Frechet derivative L_log(A^T, G).  The forward
+    decisions (s, k and the iterations per root) come from ``logm`` (or from
+    ``force``) and are constants of the differentiated map; so is each scaling
+    factor mu of eq. ScalDB (reading R8: the iteration reaches the same square
+    root for any positive mu sequence, so mu carries no derivative at
+    convergence).  The graph is differentiable as a composition of sums and
+    products (Section 3), each product P = L R giving Lbar = Pbar R^T and
+    Rbar = L^T Pbar; an inverse M = X^{-1} gives Xbar = -M^T Mbar M^T.
+
+    Returns (Abar, info) with info from the forward pass.
+    """
+    A = np.asarray(A, dtype=np.float64)
+    G = np.asarray(G, dtype=np.float64)
+    if A.shape != G.shape:
+        raise ValueError("A and G must have the same shape")
+    if force is None:
+        _, info = logm(A, k_max, max_sqrt, db_max_iter, theta_table)
+        force = {"s": info["s"], "k": info["k"], "db_iters": list(info["db_iters"])}
+    else:
+        info = dict(force)
+    s, k, its = force["s"], force["k"], force["db_iters"]
+    n = A.shape[0]
+    eye = np.eye(n)
+
+    # forward replay with a tape: root inputs, and per iteration the inverses and mu
+    roots = []            # roots[r] = (X_in, [(Xinv, Yinv or None, mu), ...])
+    X = A.copy()
+    for r in range(s):
+        X_in = X
+        Y = eye.copy()
+        steps = []
+        scaled = True
+        for it in range(1, its[r] + 1):
+            Xi, ldx = _inv_logdet(X)
+            if it == 1:
+                Yi, ldy = None, 0.0
+            else:
+                Yi, ldy = _inv_logdet(Y)
+            mu = math.exp(-(ldx + ldy) / (2.0 * n)) if scaled else 1.0
+            Xn = 0.5 * (mu * X + (Yi if Yi is not None else eye) / mu)
+            Yn = 0.5 * (mu * Y + Xi / mu)
+            rel = norm1(Xn - X) / norm1(Xn)
+            if rel < 1e-2:
+                scaled = False
+            steps.append((Xi, Yi, mu))
+            X, Y = Xn, Yn
+        roots.append((X_in, steps))
+    B = X - eye
+    B2 = B @ B if s == 0 else roots[-1][0] - 2.0 * X + eye       # eq. AI2
+
+    # graph forward with its intermediates (eq. five_mult_degopt)
+    h, g, y = scheme_coefficients(k)
+    P = [None, eye, -B, B2]
+    left, right = {}, {}
+    for j in range(2, k + 1):
+        left[j] = sum(h[j][i - 2] * P[i] for i in range(2, j + 2))
+        right[j] = sum(g[j][i - 2] * P[i] for i in range(2, j + 2))
+        P.append(left[j] @ right[j])
+
+    # graph reverse: L = -2^s Z, Z = sum_q y_q P_q
+    Zbar = -(2.0 ** s) * G
+    Pbar = [None] + [y[q - 1] * Zbar for q in range(1, k + 3)]
+    for j in range(k, 1, -1):
+        Lbar = Pbar[j + 2] @ right[j].T
+        Rbar = left[j].T @ Pbar[j + 2]
+        for i in range(2, j + 2):
+            Pbar[i] = Pbar[i] + h[j][i - 2] * Lbar + g[j][i - 2] * Rbar
+    Bbar = -Pbar[2]
+    B2bar = Pbar[3]
+    if s == 0:
+        Bbar = Bbar + B2bar @ B.T + B.T @ B2bar                    # B2 = B B
+        return Bbar, info
+
+    # B = X_s - I, B2 = X_{s-1} - 2 X_s + I
+    Xbar = Bbar - 2.0 * B2bar
+    for r in range(s - 1, -1, -1):
+        X_in, steps = roots[r]
+        Ybar = np.zeros((n, n))
+        for Xi, Yi, mu in reversed(steps):
+            # X' = (mu X + Yinv/mu)/2, Y' = (mu Y + Xinv/mu)/2
+            Xinv_bar = Ybar / (2.0 * mu)
+            Yinv_bar = Xbar / (2.0 * mu)
+            Xbar_prev = 0.5 * mu * Xbar - Xi.T @ Xinv_bar @ Xi.T
+            if Yi is not None:
+                Ybar = 0.5 * mu * Ybar - Yi.T @ Yinv_bar @ Yi.T
+            Xbar = Xbar_prev
+        if r == s - 1:
+            Xbar = Xbar + B2bar
+    return Xbar, info
+
+
+def frechet_block(A, E, **kw):
+    """L_log(A, E) as the upper-right block of log([[A, E], [0, A]]) (block-triangular
+    form of the Frechet derivative), computed with ``logm`` at size 2n."""
+    n = A.shape[0]
+    M = np.zeros((2 * n, 2 * n))
+    M[:n, :n] = A
+    M[n:, n:] = A
+    M[:n, n:] = E
+    L, _ = logm(M, **kw)
+    return L[:n, n:]
