@@ -105,6 +105,28 @@ int logm_workspace_size(int32_t dtype, int64_t n, const logm_opts* o, size_t* by
 int logm_forward(int32_t dtype, int64_t n, const void* A, int64_t lda, void* L, int64_t ldl,
                  const logm_opts* o, logm_info* info, void* ws, size_t ws_bytes, void* stream);
 
+/* ---- reverse mode ---- */
+
+/* Workspace bytes for logm_backward: the forward workspace plus
+ * (o->max_sqrt + 2 * o->db_max_iter + 26) padded n x n matrices (checkpointed root
+ * inputs, one root's taped inverses, the graph factors and the adjoints). */
+int logm_backward_workspace_size(int32_t dtype, int64_t n, const logm_opts* o, size_t* bytes);
+
+/* gradA = d<G, log A>_F / dA, for real A the adjoint Frechet derivative
+ * L_log(A^T, G), by reverse-mode differentiation of Algorithm 1 (Section 6)
+ * through the graph polynomial of eq. five_mult_degopt (a composition of sums and
+ * products, Section 3) and through the scaled Denman-Beavers iterates of eq.
+ * ScalDB.  The decisions (s, k, iterations per root) are those of the forward pass
+ * run inside this call, and each scaling factor mu is a constant of the map (the
+ * iteration reaches the same root for any positive mu sequence).  A, G (n x n,
+ * row-major, lda, ldg >= n) are read; gradA (ldga >= n) must not overlap A or G.
+ * The computation is FP64 whatever o->graph_fp32 says; info (host, may be NULL)
+ * receives the forward decisions and the flops of the whole call.  Synchronises
+ * `stream` at the decisions like logm_forward; LOGM_ENOTSUP for LOGM_C128. */
+int logm_backward(int32_t dtype, int64_t n, const void* A, int64_t lda, const void* G, int64_t ldg,
+                  void* gradA, int64_t ldga, const logm_opts* o, logm_info* info, void* ws,
+                  size_t ws_bytes, void* stream);
+
 /* ---- batched path: many small matrices in one launch ---- */
 
 /* Workspace bytes for logm_batched_f64 over `batch` matrices of size n_i <= n_max

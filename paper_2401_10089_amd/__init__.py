@@ -18,6 +18,9 @@ from ._binding import (  # noqa: F401
     inverse,
     load_library,
     logm,
+    logm_autograd,
+    logm_backward,
+    backward_workspace_size,
     normest,
     poly,
     profile_enable,

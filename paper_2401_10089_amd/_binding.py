@@ -34,6 +34,8 @@ EXPORTS = (
     "logm_strerror",
     "logm_workspace_size",
     "logm_forward",
+    "logm_backward_workspace_size",
+    "logm_backward",
     "logm_batched_workspace_size",
     "logm_batched_f64",
     "logm_gemm_f64",
@@ -130,6 +132,10 @@ def load_library(path: str = LIB_PATH):
         "logm_workspace_size": (ctypes.c_int, [_i32, _i64, ctypes.POINTER(LogmOpts), ctypes.POINTER(_sz)]),
         "logm_forward": (ctypes.c_int, [_i32, _i64, _vp, _i64, _vp, _i64, ctypes.POINTER(LogmOpts),
                                         ctypes.POINTER(LogmInfo), _vp, _sz, _vp]),
+        "logm_backward_workspace_size": (ctypes.c_int, [_i32, _i64, ctypes.POINTER(LogmOpts),
+                                                        ctypes.POINTER(_sz)]),
+        "logm_backward": (ctypes.c_int, [_i32, _i64, _vp, _i64, _vp, _i64, _vp, _i64, ctypes.POINTER(LogmOpts),
+                                         ctypes.POINTER(LogmInfo), _vp, _sz, _vp]),
         "logm_batched_workspace_size": (ctypes.c_int, [_i32, _i64, _i32, ctypes.POINTER(_sz)]),
         "logm_batched_f64": (ctypes.c_int, [_i32, _i32, _i64, _vp, _vp, _vp, _vp, ctypes.POINTER(LogmOpts),
                                             _vp, _vp, _sz, _vp]),
@@ -270,6 +276,71 @@ def logm(A, k_max: int = 5, max_sqrt: int = 50, db_max_iter: int = 30, theta_sou
                             _stream_ptr(A))
     _check(rc, "logm_forward", info.status_detail)
     return L, info.as_dict()
+
+
+def backward_workspace_size(n: int, opts: LogmOpts | None = None) -> int:
+    b = _sz(0)
+    _check(lib().logm_backward_workspace_size(LOGM_R64, n, ctypes.byref(opts) if opts else None,
+                                              ctypes.byref(b)), "logm_backward_workspace_size")
+    return b.value
+
+
+def logm_backward(A, G, k_max: int = 5, max_sqrt: int = 50, db_max_iter: int = 30,
+                  theta_source: int = 0, out=None, workspace=None):
+    """gradA = d<G, log A>/dA on the GPU (reverse mode of Algorithm 1).  Returns
+    (gradA, info dict of the forward pass run inside the call)."""
+    torch = _torch()
+    A = _as_matrix(A)
+    G = _as_matrix(G, "G")
+    n = A.shape[0]
+    if G.shape != A.shape or G.device != A.device:
+        raise ValueError("G must match A in shape and device")
+    gA = out if out is not None else torch.empty((n, n), dtype=torch.float64, device=A.device)
+    o = default_opts()
+    o.k_max, o.max_sqrt, o.db_max_iter, o.theta_source = k_max, max_sqrt, db_max_iter, theta_source
+    need = backward_workspace_size(n, o)
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=A.device)
+    elif workspace.numel() * workspace.element_size() < need:
+        raise ValueError(f"workspace needs {need} bytes")
+    info = LogmInfo()
+    rc = lib().logm_backward(LOGM_R64, n, _vp(A.data_ptr()), A.stride(0), _vp(G.data_ptr()), G.stride(0),
+                             _vp(gA.data_ptr()), gA.stride(0), ctypes.byref(o), ctypes.byref(info),
+                             _vp(workspace.data_ptr()), workspace.numel(), _stream_ptr(A))
+    _check(rc, "logm_backward", info.status_detail)
+    return gA, info.as_dict()
+
+
+def _autograd_function():
+    torch = _torch()
+
+    class LogmFunction(torch.autograd.Function):
+        """log(A) with the hand-written reverse mode of the HIP library."""
+
+        @staticmethod
+        def forward(ctx, A):
+            L, _ = logm(A)
+            ctx.save_for_backward(A)
+            return L
+
+        @staticmethod
+        def backward(ctx, gL):
+            (A,) = ctx.saved_tensors
+            gA, _ = logm_backward(A, gL.contiguous())
+            return gA
+
+    return LogmFunction
+
+
+_LOGM_FN = None
+
+
+def logm_autograd(A):
+    """log(A) as a differentiable torch op: forward logm_forward, backward logm_backward."""
+    global _LOGM_FN
+    if _LOGM_FN is None:
+        _LOGM_FN = _autograd_function()
+    return _LOGM_FN.apply(A)
 
 
 class BatchPlan:

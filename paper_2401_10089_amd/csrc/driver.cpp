@@ -20,6 +20,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <vector>
 
 #include "algo.hpp"
@@ -412,9 +413,19 @@ Status check_gje_err(Ctx& c, int nmat) {
 }
 
 // ------------------------------------------------------ square root -----
+// Recording of one root for reverse mode: the iteration count is replayed, and the
+// column-ordered inverses of X_{t-1} (z = 0) and Y_{t-1} (z = 1, t >= 2) and the
+// scaling factor of every iteration t = 1.. are kept.
+struct DbTape {
+  int force_iters = 0;
+  std::function<double*(int t, int z)> slot;
+  std::vector<double> mu;
+};
+
 // Xout = X0^{1/2} by the scaled Denman-Beavers iteration, eq. ScalDB.  X0 and Xout
 // are padded n_pad x n_pad workspace matrices (identity on the pad); Y uses mat(1).
-Status db_sqrt(Ctx& c, const double* X0, double* Xout, int max_iter, int* iters, int* ninv) {
+Status db_sqrt(Ctx& c, const double* X0, double* Xout, int max_iter, int* iters, int* ninv,
+               DbTape* tape = nullptr) {
   Status st;
   const int n = c.p.n;
   double* Y = c.mat(1);
@@ -430,6 +441,10 @@ Status db_sqrt(Ctx& c, const double* X0, double* Xout, int max_iter, int* iters,
     double* fin[2] = {nullptr, nullptr};
     PROPAGATE(gje_invert(c, nmat, src, fin));
     *ninv += nmat;
+    if (tape != nullptr)
+      for (int z = 0; z < nmat; ++z)
+        HIPCK(launch_gje_unpermute(fin[z], c.at<int>(c.p.pinv[z]), c.p.n_pad, tape->slot(it, z),
+                                   c.p.n_pad, n, c.s));
     DbArgs d{};
     d.Xin = Xcur;
     d.Xout = Xout;
@@ -449,15 +464,17 @@ Status db_sqrt(Ctx& c, const double* X0, double* Xout, int max_iter, int* iters,
     d.mu_out = c.scal() + 8;
     HIPCK(launch_db_update(d, c.p.nblk, c.s));
     HIPCK(launch_colsum_max(c.part(), 2, c.p.nblk, n, c.scal(), c.at<double>(c.p.bm), c.s));
-    double h[2];
-    PROPAGATE(sync_read(c, h, c.scal(), 2 * sizeof(double)));
+    double h[9];   // column-sum maxima in 0-1, the scaling factor used in 8
+    PROPAGATE(sync_read(c, h, c.scal(), 9 * sizeof(double)));
     PROPAGATE(check_gje_err(c, nmat));
     rel = h[0] / h[1];
     if (!std::isfinite(rel)) {
       st.code = LOGM_ENONFINITE;
       return st;
     }
-    if (db_stop(rel, rel_prev, scaled, tol)) {
+    if (tape != nullptr) tape->mu.push_back(h[8]);
+    const bool stop = db_stop(rel, rel_prev, scaled, tol);
+    if ((tape != nullptr && tape->force_iters > 0) ? it == tape->force_iters : stop) {
       *iters = it;
       return st;
     }
@@ -654,8 +671,14 @@ Status poly(Ctx& c, int k, int s, const double* B, const double* B2, double* L, 
 }
 
 // -------------------------------------------------------- Algorithm 1 ---
+// ckpt(r) receives the input of root r (reverse mode); the polynomial is then left
+// to the caller, with B and B2 in mat(3) and mat(4).
+struct RootCheckpoints {
+  std::function<double*(int r)> ckpt;
+};
+
 Status forward_r64(Ctx& c, const double* A, int64_t lda, double* L, int64_t ldl,
-                   const logm_opts& o, logm_info& info) {
+                   const logm_opts& o, logm_info& info, RootCheckpoints* rc = nullptr) {
   Status st;
   const int n = c.p.n;
   const int np = c.p.n_pad;
@@ -699,6 +722,7 @@ Status forward_r64(Ctx& c, const double* A, int64_t lda, double* L, int64_t ldl,
     if (!ok) return ecall.st;
     if (!finished) {
       std::swap(X, A2);  // A2 keeps the matrix whose root is taken
+      if (rc != nullptr) HIPCK(launch_copy(A2, rc->ckpt(s), (size_t)np * np, c.s));
       int iters = 0;
       PROPAGATE(db_sqrt(c, A2, X, o.db_max_iter, &iters, &info.n_inv));
       info.db_iters[s] = iters;
@@ -718,7 +742,7 @@ Status forward_r64(Ctx& c, const double* A, int64_t lda, double* L, int64_t ldl,
   const int k = select_degree(ecall, T, K, n1, n2, have_top, e_top, have_top1, e_top1,
                               &info.n_est, &ok);
   if (!ok) return ecall.st;
-  PROPAGATE(poly(c, k, s, B, B2, L, ldl, &info.n_gemm, o.graph_fp32 != 0));
+  if (rc == nullptr) PROPAGATE(poly(c, k, s, B, B2, L, ldl, &info.n_gemm, o.graph_fp32 != 0));
   info.s = s;
   info.k = k;
   info.m = T.m[k];
@@ -730,17 +754,184 @@ Status forward_r64(Ctx& c, const double* A, int64_t lda, double* L, int64_t ldl,
   return st;
 }
 
+// -------------------------------------------------------- reverse mode ---
+// Gradient of <G, log A>_F with respect to A (for real A, L_log(A^T, G)) by
+// reverse-mode differentiation of Algorithm 1: the decisions (s, k, iterations per
+// root) and every scaling factor mu of eq. ScalDB are constants of the map.  The
+// adjoints are carried transposed (Vh = Vbar^T), so that every product is a plain
+// one: a graph node P = L R gives Lh = R Ph and Rh = Ph L; an inverse M = X^{-1}
+// gives Xh = -M Mh M.  Root inputs are checkpointed by the forward pass; each root
+// is replayed with its recorded iteration count to tape its inverses.
+constexpr int kBwdFixed = 26;   // graph factors, products, adjoints and temporaries
+
+size_t bwd_mat_bytes(const Plan& p) { return align_up((size_t)p.n_pad * p.n_pad * sizeof(double), 256); }
+
+size_t bwd_extra_bytes(const Plan& p, const logm_opts& o) {
+  return (size_t)(o.max_sqrt + 2 * o.db_max_iter + kBwdFixed) * bwd_mat_bytes(p);
+}
+
+Status backward_r64(Ctx& c, const double* A, int64_t lda, const double* G, int64_t ldg,
+                    double* gradA, int64_t ldga, const logm_opts& o, logm_info& info) {
+  Status st;
+  const int n = c.p.n;
+  const int np = c.p.n_pad;
+  const size_t mb = bwd_mat_bytes(c.p);
+  char* ext = c.base + c.p.total;
+  auto M = [&](int i) { return reinterpret_cast<double*>(ext + (size_t)i * mb); };
+  const int ck0 = 0, inv0 = o.max_sqrt, fx = o.max_sqrt + 2 * o.db_max_iter;
+  // fixed slots
+  auto LJ = [&](int j) { return M(fx + (j - 2)); };        // left factor of P_{j+2}
+  auto RJ = [&](int j) { return M(fx + 4 + (j - 2)); };    // right factor
+  auto PP = [&](int i) { return M(fx + 8 + (i - 4)); };    // P_4 .. P_6
+  auto LH = [&](int j) { return M(fx + 11 + (j - 2)); };
+  auto RH = [&](int j) { return M(fx + 15 + (j - 2)); };
+  double* Zh = M(fx + 19);
+  double* Ph = M(fx + 20);
+  double* B2h = M(fx + 21);
+  double* Xh = M(fx + 22);
+  double* Yh = M(fx + 23);
+  double* T1 = M(fx + 24);
+  double* T2 = M(fx + 25);
+  int ngemm = 0;
+  auto gemm = [&](double alpha, const double* Aop, const double* Bop, double beta, double* C) {
+    ++ngemm;
+    return launch_gemm_plain(n, n, n, alpha, Aop, np, Bop, np, beta, C, np, c.s);
+  };
+
+  RootCheckpoints rc{[&](int r) { return M(ck0 + r); }};
+  PROPAGATE(forward_r64(c, A, lda, nullptr, 0, o, info, &rc));
+  const int s = info.s, k = info.k;
+  const double* B = c.mat(3);
+  const double* B2 = c.mat(4);
+  const Scheme& S = scheme(k);
+
+  // operand list of a linear combination of P_2 = -B, P_3 = B2 and stored P_i
+  auto add_P = [&](LincombGen& g, int i, double coef) {
+    if (coef == 0.0) return;
+    if (i == 2) {
+      g.in[g.m] = B;
+      g.c[g.m++] = -coef;
+    } else if (i == 3) {
+      g.in[g.m] = B2;
+      g.c[g.m++] = coef;
+    } else {
+      g.in[g.m] = PP(i);
+      g.c[g.m++] = coef;
+    }
+  };
+  auto lincomb = [&](LincombGen g, double* out, double beta) {
+    g.out = out;
+    g.beta = beta;
+    g.n = n;
+    g.ld = np;
+    return launch_lincomb_gen(g, c.s);
+  };
+
+  // graph forward with its factors (eq. five_mult_degopt)
+  for (int j = 2; j <= k; ++j) {
+    LincombGen gl{}, gr{};
+    for (int i = 2; i <= j + 1; ++i) {
+      add_P(gl, i, S.h[j - 2][i - 2]);
+      add_P(gr, i, S.g[j - 2][i - 2]);
+    }
+    HIPCK(lincomb(gl, LJ(j), 0.0));
+    HIPCK(lincomb(gr, RJ(j), 0.0));
+    if (j < k) HIPCK(gemm(1.0, LJ(j), RJ(j), 0.0, PP(j + 2)));
+  }
+
+  // graph reverse: L = -2^s Z, Z = sum_q y_q P_q
+  HIPCK(launch_transpose(G, ldg, Zh, np, n, -std::ldexp(1.0, s), c.s));
+  // Ph_i = y_i Zh + sum_{j' >= i-1} (h_{j',i} Lh_{j'} + g_{j',i} Rh_{j'})
+  auto p_hat = [&](int i, double sign, double* out) {
+    LincombGen g{};
+    g.in[g.m] = Zh;
+    g.c[g.m++] = sign * S.y[i - 1];
+    for (int jp = std::max(2, i - 1); jp <= k; ++jp) {
+      g.in[g.m] = LH(jp);
+      g.c[g.m++] = sign * S.h[jp - 2][i - 2];
+      g.in[g.m] = RH(jp);
+      g.c[g.m++] = sign * S.g[jp - 2][i - 2];
+    }
+    return lincomb(g, out, 0.0);
+  };
+  for (int j = k; j >= 2; --j) {
+    HIPCK(p_hat(j + 2, 1.0, Ph));
+    HIPCK(gemm(1.0, RJ(j), Ph, 0.0, LH(j)));
+    HIPCK(gemm(1.0, Ph, LJ(j), 0.0, RH(j)));
+  }
+  HIPCK(p_hat(3, 1.0, B2h));      // B2h
+  HIPCK(p_hat(2, -1.0, Xh));      // Bh = -P2h, kept in Xh
+
+  if (s == 0) {                   // B2 = B B
+    HIPCK(gemm(1.0, B, B2h, 1.0, Xh));
+    HIPCK(gemm(1.0, B2h, B, 1.0, Xh));
+  } else {                        // B = X_s - I, B2 = X_{s-1} - 2 X_s + I
+    LincombGen g{};
+    g.in[0] = B2h;
+    g.c[0] = -2.0;
+    g.m = 1;
+    HIPCK(lincomb(g, Xh, 1.0));
+    for (int r = s - 1; r >= 0; --r) {
+      DbTape tape;
+      tape.force_iters = info.db_iters[r];
+      tape.slot = [&](int t, int z) { return M(inv0 + 2 * (t - 1) + z); };
+      int iters = 0, ninv = 0;
+      PROPAGATE(db_sqrt(c, M(ck0 + r), c.mat(0), tape.force_iters, &iters, &ninv, &tape));
+      info.n_inv += ninv;
+      bool yh_zero = true;
+      for (int t = iters; t >= 1; --t) {
+        const double mu = tape.mu[t - 1];
+        const double* Xi = M(inv0 + 2 * (t - 1));
+        const double* Yi = (t >= 2) ? M(inv0 + 2 * (t - 1) + 1) : nullptr;
+        // X' = (mu X + Yi/mu)/2, Y' = (mu Y + Xi/mu)/2:
+        // Xh = mu/2 Xh' - Xi Yh' Xi/(2 mu), Yh = mu/2 Yh' - Yi Xh' Yi/(2 mu)
+        if (Yi != nullptr) HIPCK(gemm(1.0, Yi, Xh, 0.0, T2));
+        if (!yh_zero) {
+          HIPCK(gemm(1.0, Xi, Yh, 0.0, T1));
+          HIPCK(gemm(-0.5 / mu, T1, Xi, 0.5 * mu, Xh));
+        } else {
+          LincombGen sc{};
+          HIPCK(lincomb(sc, Xh, 0.5 * mu));
+        }
+        if (Yi != nullptr) {
+          HIPCK(gemm(-0.5 / mu, T2, Yi, yh_zero ? 0.0 : 0.5 * mu, Yh));
+          yh_zero = false;
+        }
+      }
+      if (r == s - 1) {
+        LincombGen g2{};
+        g2.in[0] = B2h;
+        g2.c[0] = 1.0;
+        g2.m = 1;
+        HIPCK(lincomb(g2, Xh, 1.0));
+      }
+    }
+  }
+  HIPCK(launch_transpose(Xh, np, gradA, ldga, n, 1.0, c.s));
+  int* flag = c.iflag() + 2;
+  HIPCK(hipMemsetAsync(flag, 0, sizeof(int), c.s));
+  HIPCK(launch_check_finite(gradA, ldga, n, flag, c.s));
+  int bad = 0;
+  PROPAGATE(sync_read(c, &bad, flag, sizeof(int)));
+  if (bad) st.code = LOGM_ENONFINITE;
+  info.n_gemm += ngemm;
+  const double nd = n;
+  info.flops = 2.0 * nd * nd * nd * (info.n_inv + info.n_gemm) + 2.0 * nd * nd * info.n_matvec;
+  return st;
+}
+
 // -------------------------------------------------------- call wrapper ---
 struct Call {
   Ctx c;
   bool owned = false;
   Status st;
-  Call(int64_t n, void* ws, size_t ws_bytes, void* stream) {
+  Call(int64_t n, void* ws, size_t ws_bytes, void* stream, const logm_opts* bwd = nullptr) {
     c.s = reinterpret_cast<hipStream_t>(stream);
     c.p = make_plan(n);
+    const size_t total = c.p.total + (bwd != nullptr ? bwd_extra_bytes(c.p, *bwd) : 0);
     if (ws == nullptr) {
       void* mem = nullptr;
-      hipError_t e = hipMallocAsync(&mem, c.p.total, c.s);
+      hipError_t e = hipMallocAsync(&mem, total, c.s);
       if (e != hipSuccess) {
         st.code = LOGM_EHIP;
         st.detail = (int)e;
@@ -749,7 +940,7 @@ struct Call {
       owned = true;
       c.base = static_cast<char*>(mem);
     } else {
-      if (ws_bytes < c.p.total) {
+      if (ws_bytes < total) {
         st.code = LOGM_EWORKSPACE;
         return;
       }
@@ -849,6 +1040,43 @@ int logm_forward(int32_t dtype, int64_t n, const void* A, int64_t lda, void* L, 
   }
   Status st = forward_r64(call.c, static_cast<const double*>(A), lda, static_cast<double*>(L),
                           ldl, opts, inf);
+  inf.status_detail = st.detail;
+  return st.code;
+}
+
+int logm_backward_workspace_size(int32_t dtype, int64_t n, const logm_opts* o, size_t* bytes) {
+  logm_opts opts;
+  logm_default_opts(&opts);
+  if (o != nullptr) opts = *o;
+  if (bytes == nullptr || n < 1 || n > (int64_t)1 << 20 || !opts_ok(opts)) return LOGM_EINVAL;
+  if (dtype != LOGM_R64 && dtype != LOGM_C128) return LOGM_EINVAL;
+  const Plan p = make_plan(n);
+  *bytes = p.total + bwd_extra_bytes(p, opts);
+  return LOGM_OK;
+}
+
+int logm_backward(int32_t dtype, int64_t n, const void* A, int64_t lda, const void* G, int64_t ldg,
+                  void* gradA, int64_t ldga, const logm_opts* o, logm_info* info, void* ws,
+                  size_t ws_bytes, void* stream) {
+  logm_opts opts;
+  logm_default_opts(&opts);
+  if (o != nullptr) opts = *o;
+  if (dtype != LOGM_R64 && dtype != LOGM_C128) return LOGM_EINVAL;
+  if (n < 1 || n > (int64_t)1 << 20 || A == nullptr || G == nullptr || gradA == nullptr ||
+      lda < n || ldg < n || ldga < n)
+    return LOGM_EINVAL;
+  if (!opts_ok(opts)) return LOGM_EINVAL;
+  if (dtype == LOGM_C128) return LOGM_ENOTSUP;
+  logm_info local{};
+  logm_info& inf = (info != nullptr) ? *info : local;
+  std::memset(&inf, 0, sizeof(inf));
+  Call call(n, ws, ws_bytes, stream, &opts);
+  if (call.st.code != LOGM_OK) {
+    inf.status_detail = call.st.detail;
+    return call.st.code;
+  }
+  Status st = backward_r64(call.c, static_cast<const double*>(A), lda, static_cast<const double*>(G),
+                           ldg, static_cast<double*>(gradA), ldga, opts, inf);
   inf.status_detail = st.detail;
   return st.code;
 }

@@ -244,6 +244,36 @@ __global__ void check_finite_kernel(const double* M, int64_t ld, int n, int* fla
   if (bad) atomicOr(flag, 1);
 }
 
+// out[e] = beta out[e] + sum_t c[t] in[t][e] over the valid n x n block (row stride ld);
+// out may be one of the inputs (each element is read before it is written).
+__global__ void lincomb_gen_kernel(LincombGen a) {
+  const int i = blockIdx.y;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < a.n; j += gridDim.x * blockDim.x) {
+    const int64_t o = (int64_t)i * a.ld + j;
+    double v = (a.beta != 0.0) ? a.beta * a.out[o] : 0.0;
+    for (int t = 0; t < a.m; ++t) v = fma(a.c[t], a.in[t][o], v);
+    a.out[o] = v;
+  }
+}
+
+// dst[j][i] = scale * src[i][j] for i, j < n, through 32 x 32 LDS tiles (one padding
+// column avoids bank conflicts); reads and writes are both coalesced.
+__global__ __launch_bounds__(256) void transpose_kernel(const double* src, int64_t lds, double* dst,
+                                                        int64_t ldd, int n, double scale) {
+  __shared__ double t[32][33];
+  const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 8 rows per pass
+  for (int r = ty; r < 32; r += 8) {
+    const int i = r0 + r, j = c0 + tx;
+    t[r][tx] = (i < n && j < n) ? src[(int64_t)i * lds + j] : 0.0;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int i = c0 + r, j = r0 + tx;   // dst row = src column
+    if (i < n && j < n) dst[(int64_t)i * ldd + j] = scale * t[tx][r];
+  }
+}
+
 inline dim3 row_grid(int n, int rows) { return dim3((unsigned)std::min(8, (n + 255) / 256), (unsigned)rows); }
 
 }  // namespace
@@ -283,6 +313,19 @@ hipError_t launch_load_padded(const double* src, int64_t lds, double* dst, int n
                               double padval, int* nonfinite, hipStream_t s) {
   hipLaunchKernelGGL(load_padded_kernel, row_grid(n_pad, n_pad), dim3(256), 0, s, src, lds, dst, n,
                      n_pad, padval, nonfinite);
+  return hipGetLastError();
+}
+
+hipError_t launch_lincomb_gen(const LincombGen& a, hipStream_t s) {
+  if (a.m < 0 || a.m > LincombGen::kMax || a.n < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(lincomb_gen_kernel, row_grid(a.n, a.n), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose(const double* src, int64_t lds, double* dst, int64_t ldd, int n,
+                            double scale, hipStream_t s) {
+  const unsigned t = (unsigned)((n + 31) / 32);
+  hipLaunchKernelGGL(transpose_kernel, dim3(t, t), dim3(256), 0, s, src, lds, dst, ldd, n, scale);
   return hipGetLastError();
 }
 

@@ -150,6 +150,24 @@ struct LincombArgs {
 };
 hipError_t launch_lincomb_init(const LincombArgs& a, hipStream_t s);
 
+// out = beta out + sum_{t < m} c[t] in[t] over the valid n x n block (row stride ld);
+// out may alias an input.
+struct LincombGen {
+  static constexpr int kMax = 12;
+  const double* in[kMax];
+  double c[kMax];
+  int m;
+  double beta;
+  double* out;
+  int n;
+  int64_t ld;
+};
+hipError_t launch_lincomb_gen(const LincombGen& a, hipStream_t s);
+
+// dst = scale * src^T for the n x n blocks (dst must not overlap src).
+hipError_t launch_transpose(const double* src, int64_t lds, double* dst, int64_t ldd, int n,
+                            double scale, hipStream_t s);
+
 // flag |= 1 if the valid n x n block of M holds a NaN or Inf.
 hipError_t launch_check_finite(const double* M, int64_t ld, int n, int* flag, hipStream_t s);
 

@@ -104,6 +104,33 @@ def test_component_argument_validation(lib):
     assert lib.logm_normest_f64(4, FAKE, 4, FAKE, 4, 1, 2, ctypes.byref(est), None, None, 0, None) == 1
 
 
+def test_backward_argument_validation(lib):
+    b = ctypes.c_size_t(0)
+    assert lib.logm_backward_workspace_size(0, 64, None, ctypes.byref(b)) == 0
+    fwd_b = ctypes.c_size_t(0)
+    assert lib.logm_workspace_size(0, 64, None, ctypes.byref(fwd_b)) == 0
+    # forward workspace + (50 + 2 * 30 + 26) padded matrices
+    assert b.value >= fwd_b.value + (50 + 60 + 26) * 64 * 64 * 8
+    assert lib.logm_backward_workspace_size(0, 0, None, ctypes.byref(b)) == 1
+
+    def call(dtype=0, n=8, A=FAKE, lda=8, G=FAKE, ldg=8, gA=FAKE, ldga=8, opts=None, ws=FAKE,
+             ws_bytes=100):
+        return lib.logm_backward(dtype, n, A, lda, G, ldg, gA, ldga,
+                                 ctypes.byref(opts) if opts else None, None, ws, ws_bytes, None)
+
+    assert call(n=0) == 1
+    assert call(A=None) == 1
+    assert call(G=None) == 1
+    assert call(gA=None) == 1
+    assert call(ldg=7) == 1
+    assert call(ldga=7) == 1
+    assert call(dtype=1) == 2
+    o = lm.default_opts()
+    o.k_max = 4
+    assert call(opts=o) == 1
+    assert call() == 3                                 # workspace too small
+
+
 def test_batched_argument_validation(lib):
     b = ctypes.c_size_t(0)
     assert lib.logm_batched_workspace_size(3, 300, 10, ctypes.byref(b)) == 0
