@@ -43,6 +43,9 @@ def traffic_per_launch():
 
 WORKLOAD = "rotscale4096"
 N = 4096
+BATCH_COUNT = 10000   # batched workload: SPD matrices, n ~ U{8..128}
+BATCH_SEED = 3001
+BWD_SEED = 4001      # differentiation workload
 
 
 def cpu_baseline(A, budget_s: float = 30.0):
@@ -80,12 +83,113 @@ def cpu_baseline(A, budget_s: float = 30.0):
     }
 
 
+def batched_section(lm, torch, dev, reps: int = 3, per_matrix_sample: int = 40):
+    """Batched forward over 10,000 SPD matrices (n ~ U{8..128}, seed 3001): logm/s of the
+    one-launch batched path against the single-matrix path on a sample of the same batch."""
+    import numpy as np
+    from workloads import spd_batch
+
+    mats = spd_batch(BATCH_COUNT, BATCH_SEED)
+    plan = lm.BatchPlan([m.shape[0] for m in mats], dev)
+    flat = torch.from_numpy(np.concatenate([m.reshape(-1) for m in mats])).to(dev)
+    L, st = lm.logm_batched(flat, plan)          # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        lm.logm_batched(flat, plan, L_flat=L)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    status = st.cpu().numpy()
+    Ls = [x.cpu().numpy() for x in plan.unpack(L)]
+    errs = []
+    for i in range(0, BATCH_COUNT, BATCH_COUNT // 20):
+        w, V = np.linalg.eigh(mats[i])
+        Le = (V * np.log(w)) @ V.T
+        errs.append(float(np.linalg.norm(Ls[i] - Le) / np.linalg.norm(Le)))
+    # the single-matrix path (host-driven decisions, one matrix per call) on a sample
+    sample = [torch.from_numpy(m).to(dev) for m in mats[:per_matrix_sample]]
+    lm.logm(sample[0])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for A in sample:
+        lm.logm(A)
+    torch.cuda.synchronize()
+    per_matrix_rate = per_matrix_sample / (time.perf_counter() - t1)
+    return {
+        "metric": "logm/s batched n<=128",
+        "value": BATCH_COUNT / dt,
+        "unit": "logm/s",
+        "ms_per_batch": 1e3 * dt,
+        "workload": f"spd_batch: {BATCH_COUNT} SPD A_i = X_i^T X_i / 64 + 1e-3 I, X_i 64 x n_i N(0,1), "
+                    f"n_i ~ U{{8..128}}, seed {BATCH_SEED}, packed row-major",
+        "status_codes": {str(c): int(v) for c, v in zip(*np.unique(status[:, 0], return_counts=True))},
+        "mean_s": float(status[:, 1].mean()),
+        "max_rel_err_vs_eigh_log_sample": max(errs),
+        "per_matrix_path_logm_per_s": per_matrix_rate,
+        "per_matrix_path_sample": per_matrix_sample,
+        "speedup_vs_per_matrix_path": (BATCH_COUNT / dt) / per_matrix_rate,
+    }
+
+
+def backward_section(lm, torch, dev, A_big, fwd_big_ms, sample: int = 32):
+    """fwd+bwd / fwd time ratio of the reverse mode (logm_backward): on a sample of
+    the differentiation batch (n = 64, rotation-scaling spectra with r in [1e-2, 1e2])
+    and on the n = 4096 matrix of the main metric."""
+    import numpy as np
+    from workloads import rotscale_matrix
+
+    rng = np.random.default_rng(BWD_SEED + 1)
+    mats = [torch.from_numpy(rotscale_matrix(64, BWD_SEED + i, 1e-2, 1e2)[0]).to(dev) for i in range(sample)]
+    grads = [torch.from_numpy(rng.standard_normal((64, 64))).to(dev) for _ in range(sample)]
+    ws = torch.empty(lm.backward_workspace_size(64), dtype=torch.uint8, device=dev)
+    lm.logm(mats[0])
+    lm.logm_backward(mats[0], grads[0], workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for A in mats:
+        lm.logm(A)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for A, G in zip(mats, grads):
+        lm.logm_backward(A, G, workspace=ws)
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t0
+    out = {
+        "metric": "fwd+bwd/fwd time ratio",
+        "value": (t_fwd + t_bwd) / t_fwd,
+        "workload": f"{sample} of the differentiation batch: n = 64, rotscale construction with "
+                    f"r ~ logU[1e-2, 1e2], seeds {BWD_SEED}+i, G iid N(0,1) seed {BWD_SEED + 1}",
+        "fwd_ms_per_matrix": 1e3 * t_fwd / sample,
+        "bwd_ms_per_matrix": 1e3 * t_bwd / sample,
+    }
+    del ws
+    G = torch.from_numpy(np.random.default_rng(BWD_SEED + 2).standard_normal(A_big.shape)).to(dev)
+    wsb = torch.empty(lm.backward_workspace_size(A_big.shape[0]), dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, info = lm.logm_backward(A_big, G, workspace=wsb)
+    torch.cuda.synchronize()
+    t_big = time.perf_counter() - t0
+    out["n4096"] = {
+        "fwd_ms": fwd_big_ms,
+        "bwd_ms": 1e3 * t_big,
+        "ratio": (fwd_big_ms + 1e3 * t_big) / fwd_big_ms,
+        "bwd_tflops": info["flops"] / t_big / 1e12,
+        "workspace_gib": wsb.numel() / 2 ** 30,
+    }
+    del wsb
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, run one plain copy (torch.neg) of 1 GiB so that "
                          "counter runs can scale FETCH_SIZE / WRITE_SIZE to bytes")
@@ -204,6 +308,11 @@ def main():
         "check": {"rel_frobenius_err_vs_exact_log": rel_err, **fp32_check},
         "roofline": roofline,
     }
+    if not args.no_batched:
+        line["batched"] = batched_section(lm, torch, dev)
+    if not args.no_backward:
+        del ws
+        line["backward"] = backward_section(lm, torch, dev, A, ms_per_step)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(A_np)
     print(json.dumps(line), flush=True)
