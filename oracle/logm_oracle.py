@@ -53,7 +53,7 @@ R6  Degree selection: min_in is the *smallest* index whose Theta passes (the
     against the threshold being tested (Theta_j, or Theta_next for the "j+1"
     shortcut).
 R7  Balancing (steps 1 and 14) is off: log(T^{-1} A T) = T^{-1} log(A) T exactly.
-R8  Reverse mode: the decisions (s, k, iterations per root) and the scaling
+R12 Reverse mode: the decisions (s, k, iterations per root) and the scaling
     factors mu are constants of the differentiated map.
 """
 
@@ -540,7 +540,7 @@ def logm_backward(A, G, k_max: int = 5, max_sqrt: int = 50, db_max_iter: int = 3
     For real A this is the adjoint Frechet derivative L_log(A^T, G).  The forward
     decisions (s, k and the iterations per root) come from ``logm`` (or from
     ``force``) and are constants of the differentiated map; so is each scaling
-    factor mu of eq. ScalDB (reading R8: the iteration reaches the same square
+    factor mu of eq. ScalDB (reading R12: the iteration reaches the same square
     root for any positive mu sequence, so mu carries no derivative at
     convergence).  The graph is differentiable as a composition of sums and
     products (Section 3), each product P = L R giving Lbar = Pbar R^T and
