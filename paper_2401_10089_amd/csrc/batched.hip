@@ -1,16 +1,23 @@
-// Batched matrix logarithm for many small matrices (n <= 128): one persistent
-// launch, one 256-thread workgroup per matrix at a time (taken from a device work
-// queue), every step of Algorithm 1 (Section 6) on the device, decisions included:
-// scaled Denman-Beavers roots (eq. ScalDB), the finish test and degree selection
-// (algo.hpp, shared with the single-matrix driver), the 1-norm estimator, and the
+// Batched matrix logarithm for many small matrices (n <= 128): persistent launches,
+// one workgroup per matrix at a time (taken from a device work queue),
+// every step of Algorithm 1 (Section 6) on the device, decisions included: scaled
+// Denman-Beavers roots (eq. ScalDB), the finish test and degree selection (algo.hpp,
+// shared with the single-matrix driver), the 1-norm estimator, and the
 // computation-graph polynomial (eq. five_mult_degopt) with the 2^s rescale.
 //
-// Register layout of an n x n matrix (n <= 128): thread (wave w, lane l) holds
-// rows l and l + 64, columns 32 w .. 32 w + 31, entry (a, b) = M[l + 64 a][32 w + b];
-// the pad beyond n is the identity.  Inversion is Gauss-Jordan with partial
-// pivoting in these registers; products stream the right factor through LDS in
-// 32-row chunks.  Per-matrix buffers live in the caller's workspace (L2-resident
-// at these sizes).
+// Two size classes, one kernel each: n <= 64 (4 waves), where thread (wave w, lane l)
+// holds row l and columns 16w..16w+15 of a register matrix, and 64 < n <= 128 (8
+// waves), where it holds rows l and l + 64 and columns 16w..16w+15; the pad beyond n
+// is the identity.
+// Inversion is Gauss-Jordan elimination in those registers with one barrier per
+// step: every wave finds the pivot itself (wave maximum of packed keys over the
+// pivot column in LDS), the pivot row travels inside each wave through LDS, and the
+// pivot row is left unscaled (its scale is applied when the inverse is stored), so
+// the step is a pure FMA update.  Products keep the accumulator tile in the same
+// layout and stream the right factor through LDS.  Per-workgroup buffers live in the
+// caller's workspace.
+#include <hip/hip_runtime.h>
+
 #include <algorithm>
 
 #include "algo.hpp"
@@ -21,242 +28,293 @@
 namespace logm {
 namespace {
 
-constexpr int BN_MAX = 128;   // largest n
-constexpr int CW = 32;        // columns per wave
-constexpr int KC = 32;        // rows of the right factor staged per chunk
+typedef double d16 __attribute__((ext_vector_type(16)));
 
-struct Shared {
-  double chunk[KC][BN_MAX + 2];     // product staging
-  double rowk[2][BN_MAX];           // Gauss-Jordan: row p (the new pivot row) per parity
-  double rowo[2][BN_MAX];           // Gauss-Jordan: old row k per parity
-  double colk[2][BN_MAX];           // Gauss-Jordan: column k before the step, per parity
-  int p[2];
-  double piv[2];
-  double vec[5][BN_MAX];            // estimator vectors
-  double red[256];                  // reductions
-  int flag;
-};
+constexpr int BN_MAX = 128;   // largest n
+constexpr int KC = 32;        // rows of a right factor staged per chunk
+constexpr int NBUF = 13;      // n x n buffers per workgroup
 
 __device__ __forceinline__ int tid() { return threadIdx.x; }
 
-// ---- block reductions (fixed order, deterministic) ----------------------------
-__device__ double wg_sum(Shared& sh, double v) {
-  sh.red[tid()] = v;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (tid() < s) sh.red[tid()] += sh.red[tid() + s];
-    __syncthreads();
-  }
-  const double r = sh.red[0];
-  __syncthreads();
-  return r;
+// Register matrix of a size class: RA rows per lane (N = 64 RA rows), CW = 16 columns
+// per wave (N / 16 waves, 256 RA threads); element (a, b) is row l + 64 a, column
+// 16 w + b.  A row slice is one 16-wide vector, so a wave-uniform column index
+// compiles to an indexed register move instead of scratch.
+template <int RA, int CW>
+struct RM {
+  static_assert(CW == 16, "one 16-wide vector per row slice");
+  d16 v[RA];
+};
+#define EL(m, a, b) ((m).v[a][b])
+
+// Element (a, b) for a wave-uniform column b (indexed register move).
+// Element (a, b) for a wave-uniform column b (indexed register move).
+template <int RA, int CW>
+__device__ __forceinline__ double dyn_get(const RM<RA, CW>& m, int a, int b) {
+  return m.v[a][__builtin_amdgcn_readfirstlane(b)];
 }
 
-__device__ double wg_max(Shared& sh, double v) {
-  sh.red[tid()] = v;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (tid() < s) sh.red[tid()] = fmax(sh.red[tid()], sh.red[tid() + s]);
-    __syncthreads();
-  }
-  const double r = sh.red[0];
-  __syncthreads();
-  return r;
+template <int RA, int CW>
+__device__ __forceinline__ void dyn_set(RM<RA, CW>& m, int a, int b, double val) {
+  m.v[a][__builtin_amdgcn_readfirstlane(b)] = val;
 }
 
-// ||M||_1: column sums in fixed order, then the maximum.
-__device__ double wg_norm1(Shared& sh, const double* M, int n) {
-  double cs = 0.0;
-  if (tid() < n)
-    for (int i = 0; i < n; ++i) cs += fabs(M[(size_t)i * n + tid()]);
-  return wg_max(sh, cs);
-}
-
-// ---- register layout -----------------------------------------------------------
-struct RegMat {
-  double x[2][CW];
+template <int RA, int CW>
+struct Shm {
+  static constexpr int N = 64 * RA;
+  double chunk[KC][N + 2];   // product staging
+  static constexpr int NW = N / CW;   // waves
+  static constexpr int NT = 64 * NW;  // threads
+  double colk[2][N];         // pivot column of the step, by step parity
+  double prow[2][NW][CW];    // pivot row slice per wave, from row half 0 or 1
+  double rscale[N];          // 1 / pivot of each row, applied when the inverse is stored
+  double vec[5][N];          // estimator vectors
+  double red[NT];            // reductions
+  int perm[N];               // pivot row of step k
+  int pinv[N];               // step at which row r was the pivot
 };
 
-__device__ void load_reg(RegMat& R, const double* M, int n) {
-  const int l = tid() & 63, w = tid() >> 6;
+// ---- workgroup reductions (fixed order, deterministic) ---------------------------
+__device__ __forceinline__ int nthreads() { return blockDim.x; }
+
+__device__ __forceinline__ double wg_sum(double* red, double v) {
+  v = wave_sum(v);
+  if ((tid() & 63) == 0) red[tid() >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+  for (int i = 0; i < nthreads() / 64; ++i) r += red[i];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ double wg_max(double* red, double v) {
+  v = wave_max(v);
+  if ((tid() & 63) == 0) red[tid() >> 6] = v;
+  __syncthreads();
+  double r = red[0];
+  for (int i = 1; i < nthreads() / 64; ++i) r = fmax(r, red[i]);
+  __syncthreads();
+  return r;
+}
+
+// Largest column sum from per-thread partial sums of column tid % N over the row
+// subset tid / N (threads / N = 4 subsets).
+template <int N>
+__device__ __forceinline__ double wg_colmax(double* red, double part) {
+  red[tid()] = part;
+  __syncthreads();
+  double cs = 0.0;
+  if (tid() < N)
+    for (int g = 0; g < nthreads() / N; ++g) cs += red[tid() + g * N];
+  __syncthreads();
+  return wg_max(red, cs);
+}
+
+// ||M||_1 (n x n, ld n)
+template <int N>
+__device__ __forceinline__ double wg_norm1(double* red, const double* M, int n) {
+  const int c = tid() % N, g = tid() / N;
+  double s = 0.0;
+  if (c < n)
+    for (int i = g; i < n; i += nthreads() / N) s += fabs(M[i * n + c]);
+  return wg_colmax<N>(red, s);
+}
+
+// ---- register matrices -----------------------------------------------------------
+// Wave index as a uniform value (keeps wave-dependent addresses in scalar registers).
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(tid() >> 6); }
+
+// R = M (n x n, ld n) with the identity on the pad.  M must be a per-workgroup buffer
+// of (64 RA)^2 elements: the N x N view with row stride n stays inside it, so every
+// load is unconditional (one row pointer per row, constant column offsets).
+template <int RA, int CW>
+__device__ __forceinline__ void load_rm(RM<RA, CW>& R, const double* M, int n) {
+  const int l = tid() & 63, w = wave_id();
 #pragma unroll
-  for (int a = 0; a < 2; ++a) {
+  for (int a = 0; a < RA; ++a) {
     const int i = l + 64 * a;
+    const double* row = M + i * n + CW * w;
 #pragma unroll
     for (int b = 0; b < CW; ++b) {
       const int j = CW * w + b;
-      R.x[a][b] = (i < n && j < n) ? M[(size_t)i * n + j] : (i == j ? 1.0 : 0.0);
+      const double v = row[b];
+      EL(R, a, b) = (i < n && j < n) ? v : (i == j ? 1.0 : 0.0);
     }
   }
 }
 
-__device__ void store_reg(const RegMat& R, double* M, int n) {
-  const int l = tid() & 63, w = tid() >> 6;
+template <int RA, int CW>
+__device__ __forceinline__ void store_rm(const RM<RA, CW>& R, double* M, int n) {
+  const int l = tid() & 63, w = wave_id();
 #pragma unroll
-  for (int a = 0; a < 2; ++a) {
+  for (int a = 0; a < RA; ++a) {
     const int i = l + 64 * a;
+    double* row = M + i * n + CW * w;
+    if (i < n) {
 #pragma unroll
-    for (int b = 0; b < CW; ++b) {
-      const int j = CW * w + b;
-      if (i < n && j < n) M[(size_t)i * n + j] = R.x[a][b];
+      for (int b = 0; b < CW; ++b)
+        if (CW * w + b < n) row[b] = EL(R, a, b);
     }
   }
 }
 
 // C (registers) = A * B, A and B n x n in global memory.
-__device__ void wg_gemm(Shared& sh, RegMat& C, const double* A, const double* B, int n) {
-  const int l = tid() & 63, w = tid() >> 6;
+template <int RA, int CW>
+__device__ __forceinline__ void wg_gemm(Shm<RA, CW>& sh, RM<RA, CW>& C, const double* A,
+                                        const double* B, int n) {
+  constexpr int N = 64 * RA;
+  const int l = tid() & 63, w = wave_id();
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < RA; ++a)
 #pragma unroll
-    for (int b = 0; b < CW; ++b) C.x[a][b] = 0.0;
+    for (int b = 0; b < CW; ++b) EL(C, a, b) = 0.0;
   for (int k0 = 0; k0 < n; k0 += KC) {
     const int kc = min(KC, n - k0);
-    for (int e = tid(); e < KC * BN_MAX; e += 256) {
-      const int r = e / BN_MAX, c = e % BN_MAX;
-      sh.chunk[r][c] = (r < kc && c < n) ? B[(size_t)(k0 + r) * n + c] : 0.0;
+    for (int e = tid(); e < KC * N; e += nthreads()) {
+      const int r = e / N, c = e % N;
+      sh.chunk[r][c] = (r < kc && c < n) ? B[(k0 + r) * n + c] : 0.0;
     }
     __syncthreads();
     for (int kk = 0; kk < kc; ++kk) {
-      double av[2];
+      double av[RA];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) {
+      for (int a = 0; a < RA; ++a) {   // in bounds for every lane (see load_rm)
         const int i = l + 64 * a;
-        av[a] = (i < n) ? A[(size_t)i * n + k0 + kk] : 0.0;
+        const double v = A[i * n + k0 + kk];
+        av[a] = (i < n) ? v : 0.0;
       }
 #pragma unroll
       for (int b = 0; b < CW; ++b) {
         const double bv = sh.chunk[kk][CW * w + b];
 #pragma unroll
-        for (int a = 0; a < 2; ++a) C.x[a][b] = fma(av[a], bv, C.x[a][b]);
+        for (int a = 0; a < RA; ++a) EL(C, a, b) = fma(av[a], bv, EL(C, a, b));
       }
     }
     __syncthreads();
   }
 }
 
-// Mi = M^{-1} by Gauss-Jordan elimination with partial pivoting (largest |entry|,
-// smallest row on ties) in registers; *logdet = sum log|pivot|.  Returns false on an
-// exact zero pivot.  One barrier per step: the LDS exchanges are double-buffered.
-__device__ bool wg_inverse(Shared& sh, const double* M, double* Mi, int n, double* logdet) {
-  const int l = tid() & 63, w = tid() >> 6;
-  RegMat R;
-  load_reg(R, M, n);
-  __shared__ int s_perm[BN_MAX];
-  double ld = 0.0;
+// Pivot key of row i: 1 + the high word of |v| without its low 7 bits (magnitudes
+// within a factor 1 + 2^-13 tie), then the reversed row index, so that the wave
+// maximum picks the largest magnitude and, among ties, the smallest row.  Every
+// candidate's key is nonzero.
+__device__ __forceinline__ unsigned pivot_key7(double v, int i) {
+  const unsigned hi = (unsigned)((unsigned long long)__double_as_longlong(v) >> 32) & 0x7fffffffu;
+  return (((hi >> 7) + 1u) << 7) | (unsigned)(127 - i);
+}
+
+// Mi = M^{-1} (n x n, ld n) by Gauss-Jordan elimination with partial pivoting (the
+// left division of eq. ScalDB) in registers; *logdet = log|det M|.  Returns false on
+// an exact zero pivot.  Rows are never exchanged: the pivot of step k is the unused
+// row p_k of largest magnitude in column k; it keeps its values (1 in column k), the
+// other rows take row - (c_i / pivot) * pivot row, and on output
+// Mi[k][p_c] = (row p_k)[c] / pivot_k.
+template <int RA, int CW>
+__device__ __forceinline__ bool wg_inverse(Shm<RA, CW>& sh, const double* M, double* Mi, int n,
+                                           double* logdet) {
+  const int l = tid() & 63, w = wave_id();
+  RM<RA, CW> x;
+  load_rm(x, M, n);
+  bool used[RA];
+#pragma unroll
+  for (int a = 0; a < RA; ++a) used[a] = false;
+  if (w == 0) {
+#pragma unroll
+    for (int a = 0; a < RA; ++a) sh.colk[0][l + 64 * a] = EL(x, a, 0);
+  }
+  __syncthreads();
+  double mant = 1.0;   // |det| = mant 2^expo
+  int expo = 0;
   bool ok = true;
   for (int k = 0; k < n; ++k) {
     const int q = k & 1;
-    const int wk = k / CW, bk = k % CW;
-    if (w == wk) {   // pivot search in the wave that owns column k
-      double best = -1.0;
-      int bi = BN_MAX;
+    double c[RA];
+    unsigned key = 0u;
 #pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        const int i = l + 64 * a;
-        double v = -1.0;
-#pragma unroll
-        for (int b = 0; b < CW; ++b)
-          if (b == bk) v = fabs(R.x[a][b]);
-        if (i >= k && i < n && (v > best || (v == best && i < bi))) {
-          best = v;
-          bi = i;
-        }
-      }
-      wave_argmax(best, bi);
-      if (l == 0) {
-        const int p = (bi < n) ? bi : k;
-        sh.p[q] = p;
-      }
-      // column k before the step, every row (the pivot value included)
-#pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        double v = 0.0;
-#pragma unroll
-        for (int b = 0; b < CW; ++b)
-          if (b == bk) v = R.x[a][b];
-        sh.colk[q][l + 64 * a] = v;
-      }
+    for (int a = 0; a < RA; ++a) {
+      const int i = l + 64 * a;
+      c[a] = sh.colk[q][i];
+      const unsigned kk = (!used[a] && i < n) ? pivot_key7(c[a], i) : 0u;
+      key = max(key, kk);
     }
-    // old row k: its owning lane publishes its slice (it moves to row p's place)
-    const int ak = k / 64, lk = k % 64;
-    if (l == lk) {
-#pragma unroll
-      for (int b = 0; b < CW; ++b) sh.rowo[q][CW * w + b] = (ak == 0) ? R.x[0][b] : R.x[1][b];
-    }
-    __syncthreads();
-    const int p = sh.p[q];
-    const int ap = p / 64, lp = p % 64;
-    // old row p (the new pivot row): its owning lane publishes its slice
+    key = wave_max_u32(key);   // every wave finds the same pivot
+    const int p = 127 - (int)(key & 127u);
+    const int lp = p & 63;
+    const double piv = readlane_d((RA == 2 && p >= 64) ? c[RA - 1] : c[0], lp);
+    ok = ok && (piv != 0.0);
+    const double rp = pivot_recip(piv);   // 0 for a zero pivot
+    int e1, e2;
+    mant *= frexp(fabs(piv), &e1);
+    mant = frexp(mant, &e2);
+    expo += e1 + e2;
+    const int wk = k / CW, bk = k - wk * CW;
+    // this wave's slice of the pivot row, with 1 in column k
+    const int hp = p >> 6;   // row half of the pivot (the read below picks it)
     if (l == lp) {
 #pragma unroll
-      for (int b = 0; b < CW; ++b) sh.rowk[q][CW * w + b] = (ap == 0) ? R.x[0][b] : R.x[1][b];
-    }
-    // the swap: row p's place takes the old row k
-    if (p != k && l == lp) {
+      for (int a = 0; a < RA; ++a)
 #pragma unroll
-      for (int b = 0; b < CW; ++b) {
-        const double v = sh.rowo[q][CW * w + b];
-        if (ap == 0) R.x[0][b] = v; else R.x[1][b] = v;
-      }
+        for (int b = 0; b < CW; ++b) sh.prow[a][w][b] = EL(x, a, b);
+      if (w == wk) sh.prow[hp][w][bk] = 1.0;
     }
-    const double piv = sh.colk[q][p];
-    if (piv == 0.0) ok = false;
-    const double rp = (piv != 0.0) ? 1.0 / piv : 0.0;
-    ld += log(fabs(piv));
-    if (tid() == 0) s_perm[k] = p;
-    __syncthreads();
-    // column k of the post-swap rows (row p now holds the old row k)
-    double f[2];
+    if (tid() == 0) {
+      sh.perm[k] = p;
+      sh.pinv[p] = k;
+      sh.rscale[p] = rp;
+    }
+    double g[RA];
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      const int i = l + 64 * a;
-      f[a] = (i == k) ? 0.0 : ((i == p) ? sh.colk[q][k] : sh.colk[q][i]);
+    for (int a = 0; a < RA; ++a) {
+      const bool isp = (l + 64 * a == p);
+      used[a] = used[a] || isp;
+      g[a] = isp ? 0.0 : c[a] * rp;
+      if (w == wk) dyn_set(x, a, bk, isp ? 1.0 : 0.0);
     }
+    __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int b = 0; b < CW; ++b) {
-      const int j = CW * w + b;
-      // the new row k scaled: its column k entry becomes 1 / piv
-      const double rkb = ((j == k) ? 1.0 : sh.rowk[q][j]) * rp;
+      const double r = sh.prow[hp][w][b];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        const int i = l + 64 * a;
-        const double xv = (j == k) ? 0.0 : R.x[a][b];
-        R.x[a][b] = (i == k) ? rkb : fma(-f[a], rkb, xv);
-      }
+      for (int a = 0; a < RA; ++a) EL(x, a, b) = fma(-g[a], r, EL(x, a, b));
     }
-  }
-  __syncthreads();
-  // undo the column permutation: the rows swapped at step k swap columns k and p
-  // of the result, in reverse order
-  store_reg(R, Mi, n);
-  __syncthreads();
-  for (int k = n - 1; k >= 0; --k) {
-    const int p = s_perm[k];
-    if (p != k && tid() < n) {
-      const size_t r = (size_t)tid() * n;
-      const double t = Mi[r + k];
-      Mi[r + k] = Mi[r + p];
-      Mi[r + p] = t;
+    if (k + 1 < n) {   // the owner of column k + 1 publishes it
+      const int w1 = (k + 1) / CW, b1 = (k + 1) - w1 * CW;
+      if (w == w1) {
+#pragma unroll
+        for (int a = 0; a < RA; ++a) sh.colk[q ^ 1][l + 64 * a] = dyn_get(x, a, b1);
+      }
     }
     __syncthreads();
   }
-  *logdet = ld;
+#pragma unroll
+  for (int a = 0; a < RA; ++a) {
+    const int r = l + 64 * a;
+    if (r < n) {
+      double* row = Mi + sh.pinv[r] * n;
+      const double sc = sh.rscale[r];
+#pragma unroll
+      for (int b = 0; b < CW; ++b)
+        if (CW * w + b < n) row[sh.perm[CW * w + b]] = sc * EL(x, a, b);
+    }
+  }
+  __syncthreads();
+  *logdet = log(mant) + expo * 0.69314718055994530942;
   return ok;
 }
 
 // y = op(B2^q B^r) x on LDS vectors (op = transpose when adj): the source slot is
 // preserved, the products ping-pong between slots s1 and s2; returns the result slot.
-__device__ int wg_apply(Shared& sh, const double* B2, const double* B, int n, int q, int r,
+template <int RA, int CW>
+__device__ int wg_apply(Shm<RA, CW>& sh, const double* B2, const double* B, int n, int q, int r,
                         bool adj, int src, int s1, int s2) {
   int cur = src, nxt = s1;
   auto step = [&](const double* M, bool t) {
     double acc = 0.0;
     if (tid() < n) {
       if (!t)
-        for (int k = 0; k < n; ++k) acc = fma(M[(size_t)tid() * n + k], sh.vec[cur][k], acc);
+        for (int k = 0; k < n; ++k) acc = fma(M[tid() * n + k], sh.vec[cur][k], acc);
       else
-        for (int k = 0; k < n; ++k) acc = fma(M[(size_t)k * n + tid()], sh.vec[cur][k], acc);
+        for (int k = 0; k < n; ++k) acc = fma(M[k * n + tid()], sh.vec[cur][k], acc);
     }
     __syncthreads();
     if (tid() < n) sh.vec[nxt][tid()] = acc;
@@ -278,13 +336,15 @@ __device__ int wg_apply(Shared& sh, const double* B2, const double* B, int n, in
 // single-matrix driver's estimator: start e/n, at most 5 sweeps, stop when the
 // estimate does not grow, the sign vector repeats or the subgradient test holds,
 // then the alternating-sign vector.  Slots: 0 x, 1-2 products, 3 sign, 4 previous sign.
+template <int RA, int CW>
 struct DevEstimator {
-  Shared& sh;
+  Shm<RA, CW>& sh;
   const double* B2;
   const double* B;
   int n;
   int nmv;
   __device__ bool operator()(int q, int r, double* out) {
+    constexpr int N = 64 * RA;
     const int t = tid();
     if (t < n) sh.vec[0][t] = (n == 1) ? 1.0 : 1.0 / n;
     __syncthreads();
@@ -300,21 +360,21 @@ struct DevEstimator {
     for (int it = 1; it <= 5; ++it) {
       const int y = wg_apply(sh, B2, B, n, q, r, false, 0, 1, 2);
       nmv += q + r;
-      const double ey = wg_sum(sh, t < n ? fabs(sh.vec[y][t]) : 0.0);
+      const double ey = wg_sum(sh.red, t < n ? fabs(sh.vec[y][t]) : 0.0);
       if (it > 1 && ey <= est) break;
       est = ey;
       const double xi = (t < n) ? ((sh.vec[y][t] >= 0.0) ? 1.0 : -1.0) : 0.0;
-      const double same = wg_sum(sh, (t < n && xi == sh.vec[4][t]) ? 1.0 : 0.0);
+      const double same = wg_sum(sh.red, (have_prev && t < n && xi == sh.vec[4][t]) ? 1.0 : 0.0);
       if (have_prev && same == (double)n) break;
       if (t < n) sh.vec[3][t] = xi;
       __syncthreads();
       const int z = wg_apply(sh, B2, B, n, q, r, true, 3, 1, 2);
       nmv += q + r;
       const double zv = (t < n) ? fabs(sh.vec[z][t]) : -1.0;
-      const double ztx = wg_sum(sh, t < n ? sh.vec[z][t] * sh.vec[0][t] : 0.0);
-      const double zmax = wg_max(sh, zv);
+      const double ztx = wg_sum(sh.red, t < n ? sh.vec[z][t] * sh.vec[0][t] : 0.0);
+      const double zmax = wg_max(sh.red, zv);
       // smallest index attaining the maximum
-      const int j = BN_MAX - (int)wg_max(sh, (t < n && zv == zmax) ? (double)(BN_MAX - t) : -1.0);
+      const int j = N - (int)wg_max(sh.red, (t < n && zv == zmax) ? (double)(N - t) : -1.0);
       if (it > 1 && zmax <= ztx) break;
       if (t < n) {
         sh.vec[0][t] = (t == j) ? 1.0 : 0.0;
@@ -327,72 +387,79 @@ struct DevEstimator {
     __syncthreads();
     const int y = wg_apply(sh, B2, B, n, q, r, false, 0, 1, 2);
     nmv += q + r;
-    const double ea = 2.0 * wg_sum(sh, t < n ? fabs(sh.vec[y][t]) : 0.0) / (3.0 * n);
+    const double ea = 2.0 * wg_sum(sh.red, t < n ? fabs(sh.vec[y][t]) : 0.0) / (3.0 * n);
     *out = fmax(est, ea);
     return true;
   }
 };
 
-// ---- graph schemes (eq. five_mult_degopt; Table 1 for k = 5) --------------------
-struct DevScheme {
-  int k;
-  double h[4][5], g[4][5];   // row j - 2: coefficients on P_2 .. P_{j+1}
-  double y[7];               // weights of P_1 .. P_{k+2}
+// Decision steps of Algorithm 1 (the finish test of the scaling loop and the degree
+// selection), out of line: they run once per root, and keeping the tables and the
+// estimator's state out of the kernel body keeps its register pressure down.
+struct Decision {
+  bool have_top = false, have_top1 = false;
+  double e_top = 0.0, e_top1 = 0.0;
 };
 
-// Scheme coefficients for schemes 1, 2, 3, 5, copied from the host tables before
-// every launch.
-__constant__ DevScheme c_sch[4];
+template <int RA, int CW>
+__device__ __attribute__((noinline)) bool dev_finish_test(Shm<RA, CW>& sh, const double* B2,
+                                                          const double* B, int n, double n1,
+                                                          double n2, int k_max, int theta_source,
+                                                          Decision* d) {
+  const ThetaTable T = theta_table(theta_source);
+  const SchemeSet K = scheme_set(k_max);
+  const int ktop = K.k[K.n - 1];
+  DevEstimator<RA, CW> est{sh, B2, B, n, 0};
+  int nest = 0;
+  bool ok = true;
+  return finish_test(est, n1, n2, T.m[ktop], T.th[ktop], d->have_top, d->e_top, d->have_top1,
+                     d->e_top1, &nest, &ok);
+}
 
-// Per-matrix buffers (n x n each) in the workspace: 0-1 X / A2 (they trade places
-// at every root), 2 B, 3 B2, 4-6 Y and the inverses, 7 the graph product, 8-12
-// with 4-6 and the free one of 0-1 the polynomial accumulators.
-constexpr int NBUF = 13;
+template <int RA, int CW>
+__device__ __attribute__((noinline)) int dev_select_degree(Shm<RA, CW>& sh, const double* B2,
+                                                           const double* B, int n, double n1,
+                                                           double n2, int k_max, int theta_source,
+                                                           const Decision* d) {
+  const ThetaTable T = theta_table(theta_source);
+  const SchemeSet K = scheme_set(k_max);
+  DevEstimator<RA, CW> est{sh, B2, B, n, 0};
+  int nest = 0;
+  bool ok = true;
+  return select_degree(est, T, K, n1, n2, d->have_top, d->e_top, d->have_top1, d->e_top1, &nest,
+                       &ok);
+}
 
-struct BatchArgs {
-  int batch;
-  const int* dims;
-  const int64_t* offsets;   // element offset of matrix i in A and L
-  const double* A;
-  double* L;
-  double* ws;               // NBUF * total elements
-  int* status;              // 4 per matrix: code, s, k, packed Denman-Beavers iterations
-  int* counter;             // work queue
-  int64_t total_elems;      // elements of A, L (and of each workspace buffer)
-  int k_max, max_sqrt, db_max_iter, theta_source;
-};
-
-// Elementwise helpers over n x n buffers.
-__device__ void wg_shift(double* B, const double* X, int n) {   // B = X - I
-  for (int e = tid(); e < n * n; e += 256) B[e] = X[e] - ((e / n == e % n) ? 1.0 : 0.0);
+__device__ __forceinline__ void wg_shift(double* B, const double* X, int n) {   // B = X - I
+  for (int e = tid(); e < n * n; e += nthreads()) B[e] = X[e] - ((e / n == e % n) ? 1.0 : 0.0);
   __syncthreads();
 }
 
 // Scaled Denman-Beavers square root of X0 into Xr (eq. ScalDB).  Y, Xi, Yi are
 // scratch.  Returns a status code; *iters receives the iterations used.
-__device__ int wg_db_sqrt(Shared& sh, const double* X0, double* Xr, double* Y, double* Xi,
-                          double* Yi, int n, int max_iter, int* iters) {
+template <int RA, int CW>
+__device__ __forceinline__ int wg_db_sqrt(Shm<RA, CW>& sh, const double* X0, double* Xr, double* Y,
+                                          double* Xi, double* Yi, int n, int max_iter, int* iters) {
+  constexpr int N = 64 * RA;
   const double tol = sqrt((double)n) * 1.1102230246251565e-16;
   bool scaled = true;
   double rel_prev = INFINITY, rel = INFINITY;
-  for (int e = tid(); e < n * n; e += 256) {
+  for (int e = tid(); e < n * n; e += nthreads()) {
     Y[e] = (e / n == e % n) ? 1.0 : 0.0;
     Xr[e] = X0[e];
   }
   __syncthreads();
   for (int it = 1; it <= max_iter; ++it) {
-    double ldx = 0.0, ldy = 0.0;
-    if (!wg_inverse(sh, Xr, Xi, n, &ldx)) return LOGM_ESINGULAR;
-    if (it > 1) {
-      if (!wg_inverse(sh, Y, Yi, n, &ldy)) return LOGM_ESINGULAR;
-    }
-    const double mu = scaled ? exp(-(ldx + ldy) / (2.0 * n)) : 1.0;
+    double ld[2] = {0.0, 0.0};
+    for (int z = 0; z < (it > 1 ? 2 : 1); ++z)
+      if (!wg_inverse(sh, z ? Y : Xr, z ? Yi : Xi, n, &ld[z])) return LOGM_ESINGULAR;
+    const double mu = scaled ? exp(-(ld[0] + ld[1]) / (2.0 * n)) : 1.0;
     // X' = (mu X + Y^{-1}/mu)/2, Y' = (mu Y + X^{-1}/mu)/2; column sums of |X'-X|, |X'|
+    const int j = tid() % N, g = tid() / N;
     double d = 0.0, a = 0.0;
-    if (tid() < n) {
-      const int j = tid();
-      for (int i = 0; i < n; ++i) {
-        const size_t e = (size_t)i * n + j;
+    if (j < n) {
+      for (int i = g; i < n; i += nthreads() / N) {
+        const int e = i * n + j;
         const double yi = (it > 1) ? Yi[e] : ((i == j) ? 1.0 : 0.0);
         const double xn = 0.5 * (mu * Xr[e] + yi / mu);
         const double yn = 0.5 * (mu * Y[e] + Xi[e] / mu);
@@ -402,8 +469,8 @@ __device__ int wg_db_sqrt(Shared& sh, const double* X0, double* Xr, double* Y, d
         Y[e] = yn;
       }
     }
-    const double dmax = wg_max(sh, d);
-    const double amax = wg_max(sh, a);
+    const double dmax = wg_colmax<N>(sh.red, d);
+    const double amax = wg_colmax<N>(sh.red, a);
     rel = dmax / amax;
     if (!isfinite(rel)) return LOGM_ENONFINITE;
     if (db_stop(rel, rel_prev, scaled, tol)) {
@@ -416,82 +483,100 @@ __device__ int wg_db_sqrt(Shared& sh, const double* X0, double* Xr, double* Y, d
   return (rel > 1e-6) ? LOGM_ENOCONV : LOGM_OK;
 }
 
-__global__ __launch_bounds__(256) void batched_logm_kernel(BatchArgs a) {
-  __shared__ Shared sh;
+// ---- graph schemes (eq. five_mult_degopt; Table 1 for k = 5) --------------------
+struct DevScheme {
+  double h[4][5], g[4][5];   // row j - 2: coefficients on P_2 .. P_{j+1}
+  double y[7];               // weights of P_1 .. P_{k+2}
+};
+
+struct BatchArgs {
+  int batch;
+  const int* dims;
+  const int64_t* offsets;   // element offset of matrix i in A and L
+  const double* A;
+  double* L;
+  double* ws;               // NBUF (64 RA)^2 doubles per workgroup
+  int* status;              // 4 per matrix: code, s, k, packed Denman-Beavers iterations
+  int* counter;             // work queue of this launch
+  int64_t total_elems;      // elements of A and L
+  int report_invalid;       // this launch reports blocks outside the arrays
+  int k_max, max_sqrt, db_max_iter, theta_source;
+  DevScheme sch[4];         // schemes 1, 2, 3, 5
+};
+
+template <int RA, int CW>
+__global__ __launch_bounds__(256 * RA, 4) void batched_logm_kernel(BatchArgs a) {
+  constexpr int N = 64 * RA;
+  __shared__ Shm<RA, CW> sh;
   __shared__ int s_item;
+  const int64_t nn_cap = (int64_t)N * N;
+  double* const base = a.ws + (int64_t)blockIdx.x * NBUF * nn_cap;
+  auto buf = [&](int t) { return base + t * nn_cap; };
   for (;;) {
     if (tid() == 0) s_item = atomicAdd(a.counter, 1);
     __syncthreads();
-    const int item = s_item;
+    // uniform in fact; readfirstlane keeps n, offsets and the loop bounds derived
+    // from them in scalar registers
+    const int item = __builtin_amdgcn_readfirstlane(s_item);
     __syncthreads();
     if (item >= a.batch) return;   // uniform: every wave leaves together
     const int n = a.dims[item];
     const int64_t off = a.offsets[item];
     // a block that lies outside the packed arrays is refused, never touched
     if (n < 1 || n > BN_MAX || off < 0 || off > a.total_elems - (int64_t)n * n) {
-      if (tid() == 0) {
+      if (a.report_invalid && tid() == 0) {
         a.status[4 * item + 0] = LOGM_EINVAL;
         a.status[4 * item + 1] = a.status[4 * item + 2] = a.status[4 * item + 3] = 0;
       }
       continue;
     }
-    double* const base = a.ws + (int64_t)NBUF * off;
-    const int64_t nn = (int64_t)n * n;
-    double* X = base;
-    double* A2 = base + nn;
-    double* B = base + 2 * nn;
-    double* B2 = base + 3 * nn;
-    double* Y = base + 4 * nn;
-    double* Xi = base + 5 * nn;
-    double* Yi = base + 6 * nn;
-    double* P = base + 7 * nn;
+    if (n > N || (N > 64 && n <= 64)) continue;   // the other size class
+    double* X = buf(0);
+    double* A2 = buf(1);
+    double* B = buf(2);
+    double* B2 = buf(3);
     const double* Ain = a.A + off;
     double* Lout = a.L + off;
     int code = LOGM_OK, s = 0, k = 0, dbits = 0;
-    // input, non-finite check
     double bad = 0.0;
-    for (int e = tid(); e < n * n; e += 256) {
+    for (int e = tid(); e < n * n; e += nthreads()) {
       const double v = Ain[e];
       X[e] = v;
       bad += isfinite(v) ? 0.0 : 1.0;
     }
-    if (wg_sum(sh, bad) != 0.0) code = LOGM_ENONFINITE;
-    const ThetaTable T = theta_table(a.theta_source);
-    const SchemeSet K = scheme_set(a.k_max);
-    const int ktop = K.k[K.n - 1];
-    const int mtop = T.m[ktop];
-    const double thtop = T.th[ktop];
-    DevEstimator est{sh, B2, B, n, 0};
+    if (wg_sum(sh.red, bad) != 0.0) code = LOGM_ENONFINITE;
+    double thtop;
+    {
+      const ThetaTable T = theta_table(a.theta_source);
+      const SchemeSet K = scheme_set(a.k_max);
+      thtop = T.th[K.k[K.n - 1]];
+    }
     double n1 = 0.0, n2 = 0.0;
-    bool have_top = false, have_top1 = false;
-    double e_top = 0.0, e_top1 = 0.0;
+    Decision dec;
     if (code == LOGM_OK) {
       wg_shift(B, X, n);
-      n1 = wg_norm1(sh, B, n);
+      n1 = wg_norm1<N>(sh.red, B, n);
       {
-        RegMat R;
+        RM<RA, CW> R;
         wg_gemm(sh, R, B, B, n);   // B^2 at s = 0
-        store_reg(R, B2, n);
+        store_rm(R, B2, n);
         __syncthreads();
       }
       bool finished = n1 <= thtop;
       while (code == LOGM_OK && !finished && s < a.max_sqrt) {
-        n2 = wg_norm1(sh, B2, n);
-        int nest = 0;
-        bool ok = true;
-        finished = finish_test(est, n1, n2, mtop, thtop, have_top, e_top, have_top1, e_top1,
-                               &nest, &ok);
+        n2 = wg_norm1<N>(sh.red, B2, n);
+        finished = dev_finish_test(sh, B2, B, n, n1, n2, a.k_max, a.theta_source, &dec);
         if (!finished) {
           double* t = X;   // A2 keeps the matrix whose root is taken
           X = A2;
           A2 = t;
           int its = 0;
-          code = wg_db_sqrt(sh, A2, X, Y, Xi, Yi, n, a.db_max_iter, &its);
+          code = wg_db_sqrt(sh, A2, X, buf(4), buf(5), buf(6), n, a.db_max_iter, &its);
           if (s < 6) dbits |= (its < 31 ? its : 31) << (5 * s);
           ++s;
           wg_shift(B, X, n);
-          n1 = wg_norm1(sh, B, n);
-          for (int e = tid(); e < n * n; e += 256)   // B2 = A2 - 2 X + I (eq. AI2)
+          n1 = wg_norm1<N>(sh.red, B, n);
+          for (int e = tid(); e < n * n; e += nthreads())   // B2 = A2 - 2 X + I (eq. AI2)
             B2[e] = A2[e] - 2.0 * X[e] + ((e / n == e % n) ? 1.0 : 0.0);
           __syncthreads();
         }
@@ -499,21 +584,18 @@ __global__ __launch_bounds__(256) void batched_logm_kernel(BatchArgs a) {
       if (code == LOGM_OK && !finished) code = LOGM_ENOCONV;
     }
     if (code == LOGM_OK) {
-      n2 = wg_norm1(sh, B2, n);
-      int nest = 0;
-      bool ok = true;
-      k = select_degree(est, T, K, n1, n2, have_top, e_top, have_top1, e_top1, &nest, &ok);
-      const DevScheme& S = c_sch[k == 5 ? 3 : k - 1];
+      n2 = wg_norm1<N>(sh.red, B2, n);
+      k = dev_select_degree(sh, B2, B, n, n1, n2, a.k_max, a.theta_source, &dec);
+      const DevScheme& S = a.sch[k == 5 ? 3 : k - 1];
       const double scale = -ldexp(1.0, s);
       // accumulators: L_j, R_j (j = 2..k) and Z in buffers 4-6, 8-12 and A2's
-      auto acc = [&](int t) -> double* {
-        return (t < 3) ? base + (4 + t) * nn : ((t < 8) ? base + (5 + t) * nn : A2);
-      };
+      auto acc = [&](int t) -> double* { return (t < 3) ? buf(4 + t) : ((t < 8) ? buf(5 + t) : A2); };
       auto Lacc = [&](int j) { return acc(2 * (j - 2)); };
       auto Racc = [&](int j) { return acc(2 * (j - 2) + 1); };
       double* Z = acc(2 * (k - 1));
+      double* P = buf(7);
       // P_1 = I, P_2 = x = -B, P_3 = B2
-      for (int e = tid(); e < n * n; e += 256) {
+      for (int e = tid(); e < n * n; e += nthreads()) {
         const double I = (e / n == e % n) ? 1.0 : 0.0;
         const double x = -B[e], x2 = B2[e];
         for (int j = 2; j <= k; ++j) {
@@ -524,11 +606,11 @@ __global__ __launch_bounds__(256) void batched_logm_kernel(BatchArgs a) {
       }
       __syncthreads();
       for (int j = 2; j <= k; ++j) {   // P_{j+2} = L_j R_j, folded into the later sums
-        RegMat R;
+        RM<RA, CW> R;
         wg_gemm(sh, R, Lacc(j), Racc(j), n);
-        store_reg(R, P, n);
+        store_rm(R, P, n);
         __syncthreads();
-        for (int e = tid(); e < n * n; e += 256) {
+        for (int e = tid(); e < n * n; e += nthreads()) {
           const double pv = P[e];
           for (int jp = j + 1; jp <= k; ++jp) {
             Lacc(jp)[e] = fma(S.h[jp - 2][j], pv, Lacc(jp)[e]);
@@ -539,12 +621,12 @@ __global__ __launch_bounds__(256) void batched_logm_kernel(BatchArgs a) {
         __syncthreads();
       }
       double bad2 = 0.0;
-      for (int e = tid(); e < n * n; e += 256) {
+      for (int e = tid(); e < n * n; e += nthreads()) {
         const double v = scale * Z[e];
         Lout[e] = v;
         bad2 += isfinite(v) ? 0.0 : 1.0;
       }
-      if (wg_sum(sh, bad2) != 0.0) code = LOGM_ENONFINITE;
+      if (wg_sum(sh.red, bad2) != 0.0) code = LOGM_ENONFINITE;
     }
     if (tid() == 0) {
       a.status[4 * item + 0] = code;
@@ -556,22 +638,48 @@ __global__ __launch_bounds__(256) void batched_logm_kernel(BatchArgs a) {
   }
 }
 
-__global__ void batched_reset_kernel(int* counter) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
+__global__ void batched_reset_kernel(int* counters) {
+  if (threadIdx.x < 2 && blockIdx.x == 0) counters[threadIdx.x] = 0;
+}
+
+// Resident workgroups of a size class over the whole device (the persistent grid).
+template <int RA, int CW>
+int class_blocks() {
+  int dev = 0, ncu = 256, per_cu = 1;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+      ncu = v;
+  }
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, batched_logm_kernel<RA, CW>, 256 * RA, 0) ==
+          hipSuccess &&
+      occ > 0)
+    per_cu = occ;
+  return per_cu * ncu;
 }
 
 }  // namespace
 
-size_t batched_workspace_bytes(int64_t total_elems) {
-  return (size_t)NBUF * (size_t)total_elems * sizeof(double) + 256;
+size_t batched_workspace_bytes(int batch, int n_max) {
+  const size_t small = (size_t)std::min(batch, class_blocks<1, 16>()) * NBUF * 64 * 64;
+  const size_t large =
+      (n_max > 64) ? (size_t)std::min(batch, class_blocks<2, 16>()) * NBUF * 128 * 128 : 0;
+  return std::max(small, large) * sizeof(double) + 256;
 }
 
-hipError_t launch_batched_logm(int batch, const int* dims, const int64_t* offsets,
-                               const double* A, double* L, int* status, void* ws,
+hipError_t launch_batched_logm(int batch, int n_max, const int* dims, const int64_t* offsets,
+                               const double* A, double* L, int* status, void* ws, size_t ws_bytes,
                                int64_t total_elems, int k_max, int max_sqrt, int db_max_iter,
-                               int theta_source, const double (*h)[4][5],
-                               const double (*g)[4][5], const double (*y)[7], int nblocks,
-                               hipStream_t s) {
+                               int theta_source, const double (*h)[4][5], const double (*g)[4][5],
+                               const double (*y)[7], hipStream_t s) {
+  const int nb_small = std::min(batch, class_blocks<1, 16>());
+  const int nb_large = std::min(batch, class_blocks<2, 16>());
+  if (ws_bytes < 256) return hipErrorInvalidValue;
+  const size_t data = (ws_bytes - 256) / 256 * 256;   // the counters stay aligned
+  if ((size_t)nb_small * NBUF * 64 * 64 * sizeof(double) > data ||
+      (n_max > 64 && (size_t)nb_large * NBUF * 128 * 128 * sizeof(double) > data))
+    return hipErrorInvalidValue;
   BatchArgs a{};
   a.batch = batch;
   a.dims = dims;
@@ -579,30 +687,30 @@ hipError_t launch_batched_logm(int batch, const int* dims, const int64_t* offset
   a.A = A;
   a.L = L;
   a.ws = static_cast<double*>(ws);
-  a.counter = reinterpret_cast<int*>(static_cast<char*>(ws) +
-                                     (size_t)NBUF * (size_t)total_elems * sizeof(double));
+  int* counters = reinterpret_cast<int*>(static_cast<char*>(ws) + data);
   a.status = status;
   a.total_elems = total_elems;
   a.k_max = k_max;
   a.max_sqrt = max_sqrt;
   a.db_max_iter = db_max_iter;
   a.theta_source = theta_source;
-  DevScheme sch[4];
-  const int ks[4] = {1, 2, 3, 5};
   for (int i = 0; i < 4; ++i) {
-    sch[i].k = ks[i];
     for (int r = 0; r < 4; ++r)
       for (int c = 0; c < 5; ++c) {
-        sch[i].h[r][c] = h[i][r][c];
-        sch[i].g[r][c] = g[i][r][c];
+        a.sch[i].h[r][c] = h[i][r][c];
+        a.sch[i].g[r][c] = g[i][r][c];
       }
-    for (int c = 0; c < 7; ++c) sch[i].y[c] = y[i][c];
+    for (int c = 0; c < 7; ++c) a.sch[i].y[c] = y[i][c];
   }
-  hipError_t e = hipMemcpyToSymbolAsync(HIP_SYMBOL(c_sch), sch, sizeof(sch), 0,
-                                        hipMemcpyHostToDevice, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(batched_reset_kernel, dim3(1), dim3(64), 0, s, a.counter);
-  hipLaunchKernelGGL(batched_logm_kernel, dim3(std::min(nblocks, batch)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(batched_reset_kernel, dim3(1), dim3(64), 0, s, counters);
+  a.counter = counters;
+  a.report_invalid = 1;
+  hipLaunchKernelGGL((batched_logm_kernel<1, 16>), dim3(nb_small), dim3(256), 0, s, a);
+  if (n_max > 64) {
+    a.counter = counters + 1;
+    a.report_invalid = 0;
+    hipLaunchKernelGGL((batched_logm_kernel<2, 16>), dim3(nb_large), dim3(512), 0, s, a);
+  }
   return hipGetLastError();
 }
 

@@ -1085,7 +1085,7 @@ int logm_batched_workspace_size(int32_t batch, int64_t total_elems, int32_t n_ma
                                 size_t* bytes) {
   if (batch < 1 || total_elems < 1 || n_max < 1 || n_max > 128 || bytes == nullptr)
     return LOGM_EINVAL;
-  *bytes = batched_workspace_bytes(total_elems);
+  *bytes = batched_workspace_bytes(batch, n_max);
   return LOGM_OK;
 }
 
@@ -1099,7 +1099,7 @@ int logm_batched_f64(int32_t batch, int32_t n_max, int64_t total_elems, const in
       offsets == nullptr || A == nullptr || L == nullptr || status == nullptr || ws == nullptr)
     return LOGM_EINVAL;
   if (!opts_ok(opts) || opts.graph_fp32 != 0) return LOGM_EINVAL;
-  if (ws_bytes < batched_workspace_bytes(total_elems)) return LOGM_EWORKSPACE;
+  if (ws_bytes < batched_workspace_bytes(batch, n_max)) return LOGM_EWORKSPACE;
   double h[4][4][5] = {}, g[4][4][5] = {}, y[4][7] = {};
   const int ks[4] = {1, 2, 3, 5};
   for (int i = 0; i < 4; ++i) {
@@ -1111,16 +1111,9 @@ int logm_batched_f64(int32_t batch, int32_t n_max, int64_t total_elems, const in
       }
     for (size_t c = 0; c < S.y.size(); ++c) y[i][c] = S.y[c];
   }
-  int dev = 0, ncu = 256;
-  if (hipGetDevice(&dev) == hipSuccess) {
-    int v = 0;
-    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
-      ncu = v;
-  }
-  hipError_t e = launch_batched_logm(batch, dims, offsets, A, L, status, ws, total_elems,
-                                     opts.k_max, opts.max_sqrt, opts.db_max_iter,
-                                     opts.theta_source, h, g, y, 2 * ncu,
-                                     reinterpret_cast<hipStream_t>(stream));
+  hipError_t e = launch_batched_logm(batch, n_max, dims, offsets, A, L, status, ws, ws_bytes,
+                                     total_elems, opts.k_max, opts.max_sqrt, opts.db_max_iter,
+                                     opts.theta_source, h, g, y, reinterpret_cast<hipStream_t>(stream));
   return (e == hipSuccess) ? LOGM_OK : LOGM_EHIP;
 }
 

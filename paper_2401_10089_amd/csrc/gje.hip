@@ -56,12 +56,6 @@ __device__ __forceinline__ int load_coherent(const int* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ double readlane_d(double v, int lane) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)b, lane);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
 
 // u[c] = x[iL][c] of lane L for slots c >= c_first (a compile-time value after
 // unrolling), for wave-uniform iL and L.  The uniform if-chain keeps every register
@@ -120,30 +114,6 @@ __device__ __forceinline__ double read_owner_slot(const double (&x)[RPL][SL], in
   LOGM_SLOT_CASE(7)
 #undef LOGM_SLOT_CASE
   return readlane_d(x[0][T], L);
-}
-
-// Wave-wide maximum of an unsigned key (DPP row shifts and broadcasts, the full
-// maximum lands in lane 63), returned to every lane.
-__device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
-  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false));  // row_shr:1
-  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false));  // row_shr:2
-  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x113, 0xf, 0xf, false));  // row_shr:3
-  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xe, false));  // row_shr:4
-  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xc, false));  // row_shr:8
-  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));  // row_bcast:15
-  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));  // row_bcast:31
-  return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
-}
-
-// Reciprocal for the multipliers: hardware estimate and two Newton steps (within
-// an ulp or so of 1/a); 0 for a zero pivot, whose singularity the root reports.
-__device__ __forceinline__ double pivot_recip(double a) {
-  double r = __builtin_amdgcn_rcp(a);
-  double e = fma(-a, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-a, r, 1.0);
-  r = fma(r, e, r);
-  return (a != 0.0) ? r : 0.0;
 }
 
 // Packed pivot key of candidate slot i: bits 31..3 hold 1 + the high word of |a|
