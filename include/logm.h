@@ -130,7 +130,10 @@ int logm_backward(int32_t dtype, int64_t n, const void* A, int64_t lda, const vo
 /* ---- batched path: many small matrices in one launch ---- */
 
 /* Workspace bytes for logm_batched_f64 over `batch` matrices of size n_i <= n_max
- * <= 128 whose n_i^2 sum to total_elems (13 * total_elems doubles plus 256 bytes). */
+ * <= 128: 13 buffers of 64 x 64 (n_max <= 64) or 128 x 128 doubles per workgroup
+ * resident on the current device, plus 256 bytes of queue counters; it does not
+ * grow with the batch beyond the device's resident workgroups.  total_elems is
+ * validated only. */
 int logm_batched_workspace_size(int32_t batch, int64_t total_elems, int32_t n_max, size_t* bytes);
 
 /* L_i = log(A_i), i < batch, by Algorithm 1 with every decision (roots, estimates,
@@ -144,7 +147,8 @@ int logm_batched_workspace_size(int32_t batch, int64_t total_elems, int32_t n_ma
  * (saturating at 31).  A matrix that fails gets its code and leaves L_i undefined;
  * the other matrices are unaffected; a block with n_i outside [1, 128] or reaching
  * outside [0, total_elems) gets LOGM_EINVAL and is not read or written.
- * ws (device, required, logm_batched_workspace_size bytes).  Only o->graph_fp32 = 0.
+ * ws (device, required, logm_batched_workspace_size bytes, queried on the device
+ * the call runs on).  Only o->graph_fp32 = 0.
  * Enqueues work on `stream` and returns without synchronising (capturable into a
  * HIP graph); argument errors are returned before any device work. */
 int logm_batched_f64(int32_t batch, int32_t n_max, int64_t total_elems, const int32_t* dims,
