@@ -24,6 +24,7 @@ from .logm_oracle import (  # noqa: F401
     db_sqrt,
     select_degree,
     logm,
+    balance,
     logm_backward,
     frechet_block,
 )

@@ -53,6 +53,13 @@ R6  Degree selection: min_in is the *smallest* index whose Theta passes (the
     against the threshold being tested (Theta_j, or Theta_next for the "j+1"
     shortcut).
 R7  Balancing (steps 1 and 14) is off: log(T^{-1} A T) = T^{-1} log(A) T exactly.
+R13 Balancing (steps 1 and 14, the paper calls MATLAB's balance): the
+    Parlett-Reinsch diagonal similarity with radix 2, reached by Gauss-Seidel
+    sweeps over the indices; index i takes the power of two f that brings its
+    column and row 2-norms within a factor 2 of each other, and keeps it only if
+    c + r falls below 0.95 of its old value; sweeps stop when no index changes
+    (at most 100).  The permutation step of balance, which only isolates
+    eigenvalues of reducible matrices, is not applied.  Off by default.
 R12 Reverse mode: the decisions (s, k, iterations per root) and the scaling
     factors mu are constants of the differentiated map.
 """
@@ -428,16 +435,57 @@ def select_degree(n1, n2, e_top, e_top1, estimate, kset, theta_table=TABLE2):
 # Algorithm 1
 # ---------------------------------------------------------------------------
 
+def balance(A, max_sweeps: int = 100):
+    """Diagonal similarity B = T^{-1} A T, T = diag(d) with powers of two (reading
+    R13).  Returns (B, d, sweeps).  Every operation on B is an exact scaling by a
+    power of two, so log(A) = T log(B) T^{-1} holds up to the rounding of log(B)."""
+    B = np.array(A, dtype=np.float64, copy=True)
+    n = B.shape[0]
+    d = np.ones(n)
+    sweeps = 0
+    for sweeps in range(1, max_sweeps + 1):
+        changed = False
+        for i in range(n):
+            c = math.sqrt(float(np.sum(B[:, i] * B[:, i])))
+            r = math.sqrt(float(np.sum(B[i, :] * B[i, :])))
+            if c == 0.0 or r == 0.0:
+                continue
+            before = c + r
+            f = 1.0
+            while c < r / 2.0:
+                c, r, f = c * 2.0, r / 2.0, f * 2.0
+            while c >= 2.0 * r:
+                c, r, f = c / 2.0, r * 2.0, f / 2.0
+            if c + r < 0.95 * before:
+                d[i] *= f
+                B[i, :] /= f
+                B[:, i] *= f
+                changed = True
+        if not changed:
+            break
+    return B, d, sweeps
+
+
 def logm(A, k_max: int = 5, max_sqrt: int = 50, db_max_iter: int = 30,
-         theta_table=TABLE2, force: dict | None = None):
+         theta_table=TABLE2, force: dict | None = None, balanced: bool = False):
     """Principal matrix logarithm by Algorithm 1 (Section 6).
 
     Returns (L, info).  ``force`` = {"s": int, "k": int, "db_iters": [..]}
     replays a given sequence of decisions (number of roots, iterations per root,
     scheme) instead of taking them, so that two implementations can be compared
-    without decision flips.
+    without decision flips.  ``balanced`` applies steps 1 and 14 (reading R13):
+    the method runs on T^{-1} A T and returns T L T^{-1}.
     """
     A = np.asarray(A)
+    if balanced:
+        if np.iscomplexobj(A):
+            raise ValueError("balancing is implemented for real input")
+        if A.ndim == 2 and not np.all(np.isfinite(A)):
+            raise OracleError("ENONFINITE", "input has non-finite entries")
+        Bal, d, sweeps = balance(A)
+        L, info = logm(Bal, k_max, max_sqrt, db_max_iter, theta_table, force)
+        info["balance_sweeps"] = sweeps
+        return L * d[:, None] / d[None, :], info
     if A.ndim != 2 or A.shape[0] != A.shape[1] or A.shape[0] < 1:
         raise ValueError("A must be a non-empty square matrix")
     if not np.all(np.isfinite(A)):
