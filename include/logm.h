@@ -70,7 +70,14 @@ typedef struct logm_opts {
                            output sum and 2^s stay fp64, as do the square roots, the
                            inverses and the norm estimates.  Result error about u_32 ||B||
                            relative instead of u_64. */
-  int32_t reserved[3];  /* must be zero */
+  int32_t balance;      /* 0: no preprocessing (default); 1: steps 1 and 14 of
+                           Algorithm 1, run on T^{-1} A T and return T L T^{-1}, T the
+                           power-of-two diagonal of Parlett-Reinsch balancing (the
+                           paper calls MATLAB's balance; its permutation step is not
+                           applied).  logm_forward only: logm_backward differentiates
+                           the unbalanced map (the same function) and logm_batched_f64
+                           rejects it. */
+  int32_t reserved[2];  /* must be zero */
 } logm_opts;
 
 /* Decisions and counters of one call (host memory). */
@@ -183,6 +190,14 @@ int logm_poly_f64(int64_t n, int32_t k, int32_t s, const double* B, int64_t ldb,
 int logm_normest_f64(int64_t n, const double* B2, int64_t ldb2, const double* B, int64_t ldb,
                      int32_t q, int32_t r, double* est, int32_t* nmatvec, void* ws,
                      size_t ws_bytes, void* stream);
+
+/* B = T^{-1} A T (n x n, row-major, lda, ldb >= n; B may equal A when lda == ldb)
+ * with T = diag(d) of powers of two: the balancing of steps 1 and 14 of Algorithm 1
+ * (Gauss-Seidel sweeps of the Parlett-Reinsch rule with 2-norms, at most 100).  d
+ * (device, n doubles) receives T's diagonal, *sweeps (host, may be NULL) the sweeps
+ * used.  Every update is an exact scaling, so B is exactly the similarity. */
+int logm_balance_f64(int64_t n, const double* A, int64_t lda, double* B, int64_t ldb, double* d,
+                     int32_t* sweeps, void* ws, size_t ws_bytes, void* stream);
 
 /* Host-side tables: the coefficients of scheme k (h and g rows j = 2..k on
  * P_2..P_{j+1}, concatenated; y on P_1..P_{k+2}), its order m_k and Theta_{m_k}.

@@ -448,7 +448,7 @@ def balance(A, max_sweeps: int = 100):
         for i in range(n):
             c = math.sqrt(float(np.sum(B[:, i] * B[:, i])))
             r = math.sqrt(float(np.sum(B[i, :] * B[i, :])))
-            if c == 0.0 or r == 0.0:
+            if c == 0.0 or r == 0.0 or not (math.isfinite(c) and math.isfinite(r)):
                 continue
             before = c + r
             f = 1.0

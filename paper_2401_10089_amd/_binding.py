@@ -43,6 +43,7 @@ EXPORTS = (
     "logm_sqrt_f64",
     "logm_poly_f64",
     "logm_normest_f64",
+    "logm_balance_f64",
     "logm_scheme",
     "logm_profile_enable",
     "logm_profile_reset",
@@ -72,7 +73,8 @@ class LogmOpts(ctypes.Structure):
         ("db_max_iter", ctypes.c_int32),
         ("theta_source", ctypes.c_int32),
         ("graph_fp32", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 3),
+        ("balance", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
 
@@ -145,6 +147,8 @@ def load_library(path: str = LIB_PATH):
         "logm_poly_f64": (ctypes.c_int, [_i64, _i32, _i32, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _sz, _vp]),
         "logm_normest_f64": (ctypes.c_int, [_i64, _vp, _i64, _vp, _i64, _i32, _i32, ctypes.POINTER(_f64),
                                             ctypes.POINTER(_i32), _vp, _sz, _vp]),
+        "logm_balance_f64": (ctypes.c_int, [_i64, _vp, _i64, _vp, _i64, _vp, ctypes.POINTER(_i32), _vp, _sz,
+                                            _vp]),
         "logm_scheme": (ctypes.c_int, [_i32, _i32, ctypes.POINTER(_f64), ctypes.POINTER(_f64),
                                        ctypes.POINTER(_f64), ctypes.POINTER(_i32), ctypes.POINTER(_i32),
                                        ctypes.POINTER(_f64)]),
@@ -258,7 +262,7 @@ def _workspace(n: int, device, workspace=None):
 
 
 def logm(A, k_max: int = 5, max_sqrt: int = 50, db_max_iter: int = 30, theta_source: int = 0,
-         out=None, workspace=None, graph_fp32: bool = False):
+         out=None, workspace=None, graph_fp32: bool = False, balance: bool = False):
     """L = log(A) on the GPU (Algorithm 1).  Returns (L, info dict).
 
     graph_fp32 runs the graph products on the fp32 matrix cores (see logm_opts)."""
@@ -269,6 +273,7 @@ def logm(A, k_max: int = 5, max_sqrt: int = 50, db_max_iter: int = 30, theta_sou
     o = default_opts()
     o.k_max, o.max_sqrt, o.db_max_iter, o.theta_source = k_max, max_sqrt, db_max_iter, theta_source
     o.graph_fp32 = 1 if graph_fp32 else 0
+    o.balance = 1 if balance else 0
     ws = _workspace(n, A.device, workspace)
     info = LogmInfo()
     rc = lib().logm_forward(LOGM_R64, n, _vp(A.data_ptr()), A.stride(0), _vp(L.data_ptr()), L.stride(0),
@@ -426,6 +431,22 @@ def inverse(A, workspace=None):
                                 ctypes.byref(ld), _vp(ws.data_ptr()), ws.numel(), _stream_ptr(A))
     _check(rc, "logm_inverse_f64")
     return Ai, ld.value
+
+
+def balance(A, workspace=None):
+    """(T^{-1} A T, diag(T), sweeps): the balancing of steps 1 and 14 on the GPU."""
+    torch = _torch()
+    A = _as_matrix(A)
+    n = A.shape[0]
+    B = torch.empty_like(A)
+    d = torch.empty(n, dtype=torch.float64, device=A.device)
+    sw = _i32(0)
+    ws = _workspace(n, A.device, workspace)
+    rc = lib().logm_balance_f64(n, _vp(A.data_ptr()), A.stride(0), _vp(B.data_ptr()), B.stride(0),
+                                _vp(d.data_ptr()), ctypes.byref(sw), _vp(ws.data_ptr()), ws.numel(),
+                                _stream_ptr(A))
+    _check(rc, "logm_balance_f64")
+    return B, d, sw.value
 
 
 def sqrtm(A, db_max_iter: int = 30, workspace=None):

@@ -160,7 +160,7 @@ struct Plan {
   size_t logdet[2];
   size_t pi[2][2];         // [matrix][outer-step parity]
   size_t ptot[2], pinv[2], qsel[2], vac[2], cand[2], cnt[2], err[2];
-  size_t part, bm, vec, scal, iflag;
+  size_t part, bm, vec, scal, iflag, bal;
   size_t total = 0;
 };
 
@@ -196,6 +196,7 @@ Plan make_plan(int64_t n) {
   p.vec = take(4 * np * sizeof(double));
   p.scal = take(16 * sizeof(double));
   p.iflag = take(16 * sizeof(int));
+  p.bal = take(np * sizeof(double) + 16 * sizeof(int));   // balancing diagonal, sweeps
   p.total = off;
   return p;
 }
@@ -701,6 +702,8 @@ Status forward_r64(Ctx& c, const double* A, int64_t lda, double* L, int64_t ldl,
     st.code = LOGM_ENONFINITE;
     return st;
   }
+  double* bal_d = c.at<double>(c.p.bal);
+  if (o.balance) HIPCK(launch_balance(X, np, n, bal_d, 100, nullptr, c.s));   // step 1
   Estimator est{c, B2, B};
   EstCall ecall{est, Status{}};
   double n1, n2;
@@ -742,7 +745,10 @@ Status forward_r64(Ctx& c, const double* A, int64_t lda, double* L, int64_t ldl,
   const int k = select_degree(ecall, T, K, n1, n2, have_top, e_top, have_top1, e_top1,
                               &info.n_est, &ok);
   if (!ok) return ecall.st;
-  if (rc == nullptr) PROPAGATE(poly(c, k, s, B, B2, L, ldl, &info.n_gemm, o.graph_fp32 != 0));
+  if (rc == nullptr) {
+    PROPAGATE(poly(c, k, s, B, B2, L, ldl, &info.n_gemm, o.graph_fp32 != 0));
+    if (o.balance) HIPCK(launch_unbalance(L, ldl, n, bal_d, c.s));   // step 14
+  }
   info.s = s;
   info.k = k;
   info.m = T.m[k];
@@ -975,7 +981,8 @@ bool opts_ok(const logm_opts& o) {
   if (o.db_max_iter < 1 || o.db_max_iter > 1000) return false;
   if (o.theta_source != 0 && o.theta_source != 1) return false;
   if (o.graph_fp32 != 0 && o.graph_fp32 != 1) return false;
-  for (int i = 0; i < 3; ++i)
+  if (o.balance != 0 && o.balance != 1) return false;
+  for (int i = 0; i < 2; ++i)
     if (o.reserved[i] != 0) return false;
   return true;
 }
@@ -1067,6 +1074,7 @@ int logm_backward(int32_t dtype, int64_t n, const void* A, int64_t lda, const vo
     return LOGM_EINVAL;
   if (!opts_ok(opts)) return LOGM_EINVAL;
   if (dtype == LOGM_C128) return LOGM_ENOTSUP;
+  opts.balance = 0;   // the gradient of the unbalanced map (the same function)
   logm_info local{};
   logm_info& inf = (info != nullptr) ? *info : local;
   std::memset(&inf, 0, sizeof(inf));
@@ -1098,7 +1106,7 @@ int logm_batched_f64(int32_t batch, int32_t n_max, int64_t total_elems, const in
   if (batch < 1 || total_elems < 1 || n_max < 1 || n_max > 128 || dims == nullptr ||
       offsets == nullptr || A == nullptr || L == nullptr || status == nullptr || ws == nullptr)
     return LOGM_EINVAL;
-  if (!opts_ok(opts) || opts.graph_fp32 != 0) return LOGM_EINVAL;
+  if (!opts_ok(opts) || opts.graph_fp32 != 0 || opts.balance != 0) return LOGM_EINVAL;
   if (ws_bytes < batched_workspace_bytes(batch, n_max)) return LOGM_EWORKSPACE;
   double h[4][4][5] = {}, g[4][4][5] = {}, y[4][7] = {};
   const int ks[4] = {1, 2, 3, 5};
@@ -1222,6 +1230,29 @@ int logm_normest_f64(int64_t n, const double* B2, int64_t ldb2, const double* B,
     Estimator e{c, c.mat(4), c.mat(3)};
     PROPAGATE(e.estimate(q, r, est));
     if (nmatvec != nullptr) *nmatvec = e.nmv;
+    return st;
+  }();
+  return st.code;
+}
+
+int logm_balance_f64(int64_t n, const double* A, int64_t lda, double* B, int64_t ldb, double* d,
+                     int32_t* sweeps, void* ws, size_t ws_bytes, void* stream) {
+  if (n < 1 || n > (int64_t)1 << 20 || A == nullptr || B == nullptr || d == nullptr || lda < n ||
+      ldb < n || (A == B && lda != ldb))
+    return LOGM_EINVAL;
+  Call call(n, ws, ws_bytes, stream);
+  if (call.st.code != LOGM_OK) return call.st.code;
+  Ctx& c = call.c;
+  Status st = [&]() -> Status {
+    Status st;
+    if (A != B)
+      HIPCK(hipMemcpy2DAsync(B, (size_t)ldb * sizeof(double), A, (size_t)lda * sizeof(double),
+                             (size_t)n * sizeof(double), (size_t)n, hipMemcpyDeviceToDevice, c.s));
+    int* sw = c.at<int>(c.p.bal + (size_t)c.p.n_pad * sizeof(double));
+    HIPCK(launch_balance(B, ldb, (int)n, d, 100, sw, c.s));
+    int h = 0;
+    PROPAGATE(sync_read(c, &h, sw, sizeof(int)));
+    if (sweeps != nullptr) *sweeps = h;
     return st;
   }();
   return st.code;

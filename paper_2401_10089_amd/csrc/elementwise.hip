@@ -274,6 +274,81 @@ __global__ __launch_bounds__(256) void transpose_kernel(const double* src, int64
   }
 }
 
+// Balancing (steps 1 and 14 of Algorithm 1), in place on the n x n block (row stride
+// ld): B = T^{-1} A T with T = diag(d), d_i powers of two, by Gauss-Seidel sweeps
+// over the indices in one workgroup.  Index i takes the power of two f that brings
+// the 2-norms of its column (c) and row (r) within a factor 2 of each other, and
+// keeps it only if c + r drops below 0.95 of its old value; an index with a zero or
+// overflowing norm is skipped; sweeps stop when no index changes (at most
+// max_sweeps).  Every update is an exact power-of-two scaling.
+constexpr int BAL_T = 1024;
+__global__ __launch_bounds__(BAL_T) void balance_kernel(double* M, int64_t ld, int n, double* d,
+                                                        int max_sweeps, int* sweeps_out) {
+  __shared__ double red[2][BAL_T / 64];
+  const int t = threadIdx.x;
+  for (int i = t; i < n; i += BAL_T) d[i] = 1.0;
+  int sweeps = 0;
+  for (int sw = 1; sw <= max_sweeps; ++sw) {
+    sweeps = sw;
+    bool changed = false;
+    for (int i = 0; i < n; ++i) {
+      double cs = 0.0, rs = 0.0;
+      for (int k = t; k < n; k += BAL_T) {
+        const double a = M[(int64_t)k * ld + i];
+        const double b = M[(int64_t)i * ld + k];
+        cs = fma(a, a, cs);
+        rs = fma(b, b, rs);
+      }
+      cs = wave_sum(cs);
+      rs = wave_sum(rs);
+      if ((t & 63) == 0) {
+        red[0][t >> 6] = cs;
+        red[1][t >> 6] = rs;
+      }
+      __syncthreads();
+      double c2 = 0.0, r2 = 0.0;
+      for (int w = 0; w < BAL_T / 64; ++w) {
+        c2 += red[0][w];
+        r2 += red[1][w];
+      }
+      __syncthreads();
+      double c = sqrt(c2), r = sqrt(r2);
+      if (c == 0.0 || r == 0.0 || !isfinite(c) || !isfinite(r)) continue;   // uniform
+      const double before = c + r;
+      double f = 1.0;
+      while (c < r / 2.0) {
+        c *= 2.0;
+        r /= 2.0;
+        f *= 2.0;
+      }
+      while (c >= 2.0 * r) {
+        c /= 2.0;
+        r *= 2.0;
+        f /= 2.0;
+      }
+      if (c + r < 0.95 * before) {   // uniform
+        changed = true;
+        const double g = 1.0 / f;    // exact: f is a power of two
+        if (t == 0) d[i] *= f;
+        // the same thread scales row i then column i at k = i, so a_ii comes back
+        for (int k = t; k < n; k += BAL_T) M[(int64_t)i * ld + k] *= g;
+        for (int k = t; k < n; k += BAL_T) M[(int64_t)k * ld + i] *= f;
+        __syncthreads();
+      }
+    }
+    if (!changed) break;
+  }
+  if (t == 0 && sweeps_out != nullptr) *sweeps_out = sweeps;
+}
+
+// L <- T L T^{-1}: L[i][j] *= d[i] / d[j] (exact, powers of two).
+__global__ void unbalance_kernel(double* L, int64_t ld, int n, const double* d) {
+  const int i = blockIdx.y;
+  const double di = d[i];
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x)
+    L[(int64_t)i * ld + j] *= di / d[j];
+}
+
 inline dim3 row_grid(int n, int rows) { return dim3((unsigned)std::min(8, (n + 255) / 256), (unsigned)rows); }
 
 }  // namespace
@@ -326,6 +401,17 @@ hipError_t launch_transpose(const double* src, int64_t lds, double* dst, int64_t
                             double scale, hipStream_t s) {
   const unsigned t = (unsigned)((n + 31) / 32);
   hipLaunchKernelGGL(transpose_kernel, dim3(t, t), dim3(256), 0, s, src, lds, dst, ldd, n, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_balance(double* M, int64_t ld, int n, double* d, int max_sweeps, int* sweeps,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(balance_kernel, dim3(1), dim3(BAL_T), 0, s, M, ld, n, d, max_sweeps, sweeps);
+  return hipGetLastError();
+}
+
+hipError_t launch_unbalance(double* L, int64_t ld, int n, const double* d, hipStream_t s) {
+  hipLaunchKernelGGL(unbalance_kernel, row_grid(n, n), dim3(256), 0, s, L, ld, n, d);
   return hipGetLastError();
 }
 

@@ -164,6 +164,13 @@ struct LincombGen {
 };
 hipError_t launch_lincomb_gen(const LincombGen& a, hipStream_t s);
 
+// Balancing in place on the n x n block (row stride ld): M <- T^{-1} M T, d = diag(T)
+// (n doubles, powers of two), *sweeps = sweeps used (device int, may be null).
+hipError_t launch_balance(double* M, int64_t ld, int n, double* d, int max_sweeps, int* sweeps,
+                          hipStream_t s);
+// L <- T L T^{-1} for d = diag(T).
+hipError_t launch_unbalance(double* L, int64_t ld, int n, const double* d, hipStream_t s);
+
 // dst = scale * src^T for the n x n blocks (dst must not overlap src).
 hipError_t launch_transpose(const double* src, int64_t lds, double* dst, int64_t ldd, int n,
                             double scale, hipStream_t s);

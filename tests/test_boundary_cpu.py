@@ -89,10 +89,17 @@ def test_forward_argument_validation(lib):
     o = lm.default_opts()
     o.graph_fp32 = 2                                   # 0 or 1 only
     assert fwd(lib, opts=o) == 1
+    o = lm.default_opts()
+    o.balance = 2                                      # 0 or 1 only
+    assert fwd(lib, opts=o) == 1
     assert fwd(lib, ws=FAKE, ws_bytes=100) == 3        # workspace too small
 
 
 def test_component_argument_validation(lib):
+    assert lib.logm_balance_f64(0, FAKE, 4, FAKE, 4, FAKE, None, None, 0, None) == 1
+    assert lib.logm_balance_f64(4, FAKE, 4, FAKE, 3, FAKE, None, None, 0, None) == 1
+    assert lib.logm_balance_f64(4, FAKE, 4, FAKE, 4, None, None, None, 0, None) == 1
+    assert lib.logm_balance_f64(4, FAKE, 4, FAKE, 5, FAKE, None, None, 0, None) == 1   # in place needs lda == ldb
     assert lib.logm_gemm_f64(0, 4, 4, 1.0, FAKE, 4, FAKE, 4, 0.0, FAKE, 4, None) == 1
     assert lib.logm_gemm_f64(4, 4, 4, 1.0, FAKE, 3, FAKE, 4, 0.0, FAKE, 4, None) == 1
     assert lib.logm_inverse_f64(4, None, 4, FAKE, 4, None, None, 0, None) == 1
@@ -154,6 +161,9 @@ def test_batched_argument_validation(lib):
     assert call(ws=None) == 1
     o = lm.default_opts()
     o.graph_fp32 = 1                                   # fp64 only on this path
+    assert call(opts=o) == 1
+    o = lm.default_opts()
+    o.balance = 1                                      # no balancing on this path
     assert call(opts=o) == 1
     o = lm.default_opts()
     o.k_max = 4
