@@ -114,9 +114,14 @@ int logm_forward(int32_t dtype, int64_t n, const void* A, int64_t lda, void* L, 
 
 /* ---- reverse mode ---- */
 
-/* Workspace bytes for logm_backward: the forward workspace plus
+/* Minimum workspace bytes for logm_backward: the forward workspace plus
  * (o->max_sqrt + 2 * o->db_max_iter + 26) padded n x n matrices (checkpointed root
- * inputs, one root's taped inverses, the graph factors and the adjoints). */
+ * inputs, the graph factors and adjoints, and a ring of taped inverses that holds
+ * one root).  Any workspace beyond the minimum lengthens the ring by one inverse per
+ * n_pad * n_pad * 8 bytes (n_pad = n rounded up to a multiple of 64, rounded up to
+ * 256 bytes): a root whose inverses from the forward pass are still in the ring is
+ * not replayed, so with room for all of them (info->n_inv) the call costs one
+ * forward pass plus the adjoint products. */
 int logm_backward_workspace_size(int32_t dtype, int64_t n, const logm_opts* o, size_t* bytes);
 
 /* gradA = d<G, log A>_F / dA, for real A the adjoint Frechet derivative
@@ -133,6 +138,22 @@ int logm_backward_workspace_size(int32_t dtype, int64_t n, const logm_opts* o, s
 int logm_backward(int32_t dtype, int64_t n, const void* A, int64_t lda, const void* G, int64_t ldg,
                   void* gradA, int64_t ldga, const logm_opts* o, logm_info* info, void* ws,
                   size_t ws_bytes, void* stream);
+
+/* The same reverse mode split in two calls, for callers that run the forward first
+ * (autograd): logm_forward_taped computes L = log A like logm_forward and leaves in
+ * ws (logm_backward_workspace_size bytes or more, required) the root checkpoints, the
+ * taped inverses and a record of the decisions; logm_backward_taped then computes
+ * gradA = d<G, log A>/dA from that tape without running the forward again.  Between
+ * the two calls ws must not be touched, and n, the options and ws_bytes must be the
+ * same; otherwise logm_backward_taped returns LOGM_EINVAL.  The tape stays valid, so
+ * several G may follow one forward.  info of logm_backward_taped: the forward's
+ * decisions, and the counters and flops of this call only.  o->balance must be 0. */
+int logm_forward_taped(int32_t dtype, int64_t n, const void* A, int64_t lda, void* L, int64_t ldl,
+                       const logm_opts* o, logm_info* info, void* ws, size_t ws_bytes,
+                       void* stream);
+int logm_backward_taped(int32_t dtype, int64_t n, const void* G, int64_t ldg, void* gradA,
+                        int64_t ldga, const logm_opts* o, logm_info* info, void* ws,
+                        size_t ws_bytes, void* stream);
 
 /* ---- batched path: many small matrices in one launch ---- */
 

@@ -21,6 +21,9 @@ from ._binding import (  # noqa: F401
     logm,
     logm_autograd,
     logm_backward,
+    logm_backward_taped,
+    logm_forward_taped,
+    Tape,
     backward_workspace_size,
     normest,
     poly,

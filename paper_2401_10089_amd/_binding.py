@@ -36,6 +36,8 @@ EXPORTS = (
     "logm_forward",
     "logm_backward_workspace_size",
     "logm_backward",
+    "logm_forward_taped",
+    "logm_backward_taped",
     "logm_batched_workspace_size",
     "logm_batched_f64",
     "logm_gemm_f64",
@@ -138,6 +140,10 @@ def load_library(path: str = LIB_PATH):
                                                         ctypes.POINTER(_sz)]),
         "logm_backward": (ctypes.c_int, [_i32, _i64, _vp, _i64, _vp, _i64, _vp, _i64, ctypes.POINTER(LogmOpts),
                                          ctypes.POINTER(LogmInfo), _vp, _sz, _vp]),
+        "logm_forward_taped": (ctypes.c_int, [_i32, _i64, _vp, _i64, _vp, _i64, ctypes.POINTER(LogmOpts),
+                                              ctypes.POINTER(LogmInfo), _vp, _sz, _vp]),
+        "logm_backward_taped": (ctypes.c_int, [_i32, _i64, _vp, _i64, _vp, _i64, ctypes.POINTER(LogmOpts),
+                                               ctypes.POINTER(LogmInfo), _vp, _sz, _vp]),
         "logm_batched_workspace_size": (ctypes.c_int, [_i32, _i64, _i32, ctypes.POINTER(_sz)]),
         "logm_batched_f64": (ctypes.c_int, [_i32, _i32, _i64, _vp, _vp, _vp, _vp, ctypes.POINTER(LogmOpts),
                                             _vp, _vp, _sz, _vp]),
@@ -283,17 +289,28 @@ def logm(A, k_max: int = 5, max_sqrt: int = 50, db_max_iter: int = 30, theta_sou
     return L, info.as_dict()
 
 
-def backward_workspace_size(n: int, opts: LogmOpts | None = None) -> int:
+def backward_workspace_size(n: int, opts: LogmOpts | None = None, tape_mats: int = 0) -> int:
+    """Workspace bytes of the reverse mode; ``tape_mats`` extra matrices lengthen the
+    ring of taped inverses (see logm_backward)."""
     b = _sz(0)
     _check(lib().logm_backward_workspace_size(LOGM_R64, n, ctypes.byref(opts) if opts else None,
                                               ctypes.byref(b)), "logm_backward_workspace_size")
-    return b.value
+    return b.value + tape_mats * _bwd_mat_bytes(n)
+
+
+def _bwd_mat_bytes(n: int) -> int:
+    n_pad = (n + 63) // 64 * 64
+    return (n_pad * n_pad * 8 + 255) // 256 * 256
 
 
 def logm_backward(A, G, k_max: int = 5, max_sqrt: int = 50, db_max_iter: int = 30,
-                  theta_source: int = 0, out=None, workspace=None):
+                  theta_source: int = 0, out=None, workspace=None, tape_mats: int | None = None):
     """gradA = d<G, log A>/dA on the GPU (reverse mode of Algorithm 1).  Returns
-    (gradA, info dict of the forward pass run inside the call)."""
+    (gradA, info dict of the forward pass run inside the call).
+
+    ``tape_mats`` extra matrices lengthen the ring of taped inverses (default: room
+    for 100 inverses in all), so that roots whose inverses are still in the ring are
+    not replayed."""
     torch = _torch()
     A = _as_matrix(A)
     G = _as_matrix(G, "G")
@@ -303,11 +320,13 @@ def logm_backward(A, G, k_max: int = 5, max_sqrt: int = 50, db_max_iter: int = 3
     gA = out if out is not None else torch.empty((n, n), dtype=torch.float64, device=A.device)
     o = default_opts()
     o.k_max, o.max_sqrt, o.db_max_iter, o.theta_source = k_max, max_sqrt, db_max_iter, theta_source
-    need = backward_workspace_size(n, o)
+    if tape_mats is None:
+        tape_mats = max(0, 100 - 2 * db_max_iter)
+    need = backward_workspace_size(n, o, tape_mats)
     if workspace is None:
         workspace = torch.empty(need, dtype=torch.uint8, device=A.device)
-    elif workspace.numel() * workspace.element_size() < need:
-        raise ValueError(f"workspace needs {need} bytes")
+    elif workspace.numel() * workspace.element_size() < backward_workspace_size(n, o):
+        raise ValueError("workspace smaller than logm_backward_workspace_size")
     info = LogmInfo()
     rc = lib().logm_backward(LOGM_R64, n, _vp(A.data_ptr()), A.stride(0), _vp(G.data_ptr()), G.stride(0),
                              _vp(gA.data_ptr()), gA.stride(0), ctypes.byref(o), ctypes.byref(info),
@@ -316,22 +335,72 @@ def logm_backward(A, G, k_max: int = 5, max_sqrt: int = 50, db_max_iter: int = 3
     return gA, info.as_dict()
 
 
+class Tape:
+    """Workspace of a taped forward pass (logm_forward_taped), consumed by
+    logm_backward_taped; holds the root checkpoints and taped inverses on the GPU."""
+
+    def __init__(self, n: int, device, tape_mats: int | None = None, k_max: int = 5, max_sqrt: int = 50,
+                 db_max_iter: int = 30, theta_source: int = 0):
+        torch = _torch()
+        self.n = n
+        self.opts = default_opts()
+        o = self.opts
+        o.k_max, o.max_sqrt, o.db_max_iter, o.theta_source = k_max, max_sqrt, db_max_iter, theta_source
+        if tape_mats is None:
+            tape_mats = max(0, 100 - 2 * db_max_iter)
+        self.ws = torch.empty(backward_workspace_size(n, o, tape_mats), dtype=torch.uint8, device=device)
+
+
+def logm_forward_taped(A, tape: Tape, out=None):
+    """L = log(A), leaving the reverse-mode tape in ``tape``.  Returns (L, info)."""
+    torch = _torch()
+    A = _as_matrix(A)
+    n = A.shape[0]
+    if n != tape.n:
+        raise ValueError("tape built for another size")
+    L = out if out is not None else torch.empty((n, n), dtype=torch.float64, device=A.device)
+    info = LogmInfo()
+    rc = lib().logm_forward_taped(LOGM_R64, n, _vp(A.data_ptr()), A.stride(0), _vp(L.data_ptr()), L.stride(0),
+                                  ctypes.byref(tape.opts), ctypes.byref(info), _vp(tape.ws.data_ptr()),
+                                  tape.ws.numel(), _stream_ptr(A))
+    _check(rc, "logm_forward_taped", info.status_detail)
+    return L, info.as_dict()
+
+
+def logm_backward_taped(G, tape: Tape, out=None):
+    """gradA = d<G, log A>/dA from the tape of the last logm_forward_taped."""
+    torch = _torch()
+    G = _as_matrix(G, "G")
+    n = G.shape[0]
+    if n != tape.n:
+        raise ValueError("tape built for another size")
+    gA = out if out is not None else torch.empty((n, n), dtype=torch.float64, device=G.device)
+    info = LogmInfo()
+    rc = lib().logm_backward_taped(LOGM_R64, n, _vp(G.data_ptr()), G.stride(0), _vp(gA.data_ptr()), gA.stride(0),
+                                   ctypes.byref(tape.opts), ctypes.byref(info), _vp(tape.ws.data_ptr()),
+                                   tape.ws.numel(), _stream_ptr(G))
+    _check(rc, "logm_backward_taped", info.status_detail)
+    return gA, info.as_dict()
+
+
 def _autograd_function():
     torch = _torch()
 
     class LogmFunction(torch.autograd.Function):
-        """log(A) with the hand-written reverse mode of the HIP library."""
+        """log(A) with the hand-written reverse mode of the HIP library: the forward
+        tapes what the backward needs (logm_forward_taped / logm_backward_taped)."""
 
         @staticmethod
         def forward(ctx, A):
-            L, _ = logm(A)
-            ctx.save_for_backward(A)
+            tape = Tape(A.shape[0], A.device)
+            L, _ = logm_forward_taped(A, tape)
+            ctx.tape = tape
             return L
 
         @staticmethod
         def backward(ctx, gL):
-            (A,) = ctx.saved_tensors
-            gA, _ = logm_backward(A, gL.contiguous())
+            gA, _ = logm_backward_taped(gL.contiguous(), ctx.tape)
+            ctx.tape = None
             return gA
 
     return LogmFunction
@@ -341,7 +410,7 @@ _LOGM_FN = None
 
 
 def logm_autograd(A):
-    """log(A) as a differentiable torch op: forward logm_forward, backward logm_backward."""
+    """log(A) as a differentiable torch op (the forward keeps its tape until backward)."""
     global _LOGM_FN
     if _LOGM_FN is None:
         _LOGM_FN = _autograd_function()

@@ -231,6 +231,7 @@ struct Ctx {
   hipEvent_t ev_pan = nullptr;    // next panel factored (on side)
   Plan p;
   char* base = nullptr;
+  size_t bytes = 0;               // usable workspace (the plan and any reverse-mode region)
   double* mat(int i) const { return reinterpret_cast<double*>(base + p.mat[i]); }
   template <class T>
   T* at(size_t off) const {
@@ -672,11 +673,20 @@ Status poly(Ctx& c, int k, int s, const double* B, const double* B2, double* L, 
 }
 
 // -------------------------------------------------------- Algorithm 1 ---
-// ckpt(r) receives the input of root r (reverse mode); the polynomial is then left
-// to the caller, with B and B2 in mat(3) and mat(4).
+// ckpt(r) receives the input of root r (reverse mode).  With L == nullptr the
+// polynomial is left to the caller; either way B and B2 end in mat(3) and mat(4).
 struct RootCheckpoints {
   std::function<double*(int r)> ckpt;
+  // ring of `cap` matrices for the column-ordered inverses of every iteration (X of
+  // iterations 1.., Y of 2..), written in order at positions written, written + 1, ...
+  std::function<double*(int64_t pos)> ring;
+  int64_t cap = 0, written = 0;
+  int64_t first[64];               // ring position of each root's first inverse
+  std::vector<double> mu[64];      // scaling factor of each iteration of each root
 };
+
+// Position of iteration t's inverse of X (z = 0) or Y (z = 1) within its root.
+inline int64_t tape_index(int t, int z) { return (t == 1) ? 0 : 2 * t - 3 + z; }
 
 Status forward_r64(Ctx& c, const double* A, int64_t lda, double* L, int64_t ldl,
                    const logm_opts& o, logm_info& info, RootCheckpoints* rc = nullptr) {
@@ -725,9 +735,19 @@ Status forward_r64(Ctx& c, const double* A, int64_t lda, double* L, int64_t ldl,
     if (!ok) return ecall.st;
     if (!finished) {
       std::swap(X, A2);  // A2 keeps the matrix whose root is taken
-      if (rc != nullptr) HIPCK(launch_copy(A2, rc->ckpt(s), (size_t)np * np, c.s));
       int iters = 0;
-      PROPAGATE(db_sqrt(c, A2, X, o.db_max_iter, &iters, &info.n_inv));
+      if (rc != nullptr) {
+        HIPCK(launch_copy(A2, rc->ckpt(s), (size_t)np * np, c.s));
+        DbTape tape;
+        const int64_t first = rc->written;
+        tape.slot = [&](int t, int z) { return rc->ring(first + tape_index(t, z)); };
+        PROPAGATE(db_sqrt(c, A2, X, o.db_max_iter, &iters, &info.n_inv, &tape));
+        rc->first[s] = first;
+        rc->mu[s] = tape.mu;
+        rc->written += 2 * iters - 1;
+      } else {
+        PROPAGATE(db_sqrt(c, A2, X, o.db_max_iter, &iters, &info.n_inv));
+      }
       info.db_iters[s] = iters;
       ++s;
       HIPCK(launch_shift(X, B, n, np, c.part(), c.p.nblk, c.s));
@@ -745,7 +765,7 @@ Status forward_r64(Ctx& c, const double* A, int64_t lda, double* L, int64_t ldl,
   const int k = select_degree(ecall, T, K, n1, n2, have_top, e_top, have_top1, e_top1,
                               &info.n_est, &ok);
   if (!ok) return ecall.st;
-  if (rc == nullptr) {
+  if (L != nullptr) {
     PROPAGATE(poly(c, k, s, B, B2, L, ldl, &info.n_gemm, o.graph_fp32 != 0));
     if (o.balance) HIPCK(launch_unbalance(L, ldl, n, bal_d, c.s));   // step 14
   }
@@ -772,19 +792,113 @@ constexpr int kBwdFixed = 26;   // graph factors, products, adjoints and tempora
 
 size_t bwd_mat_bytes(const Plan& p) { return align_up((size_t)p.n_pad * p.n_pad * sizeof(double), 256); }
 
+// Host record of a taped forward pass, stored at the start of the reverse-mode region
+// so that the backward call of the taped pair finds it.
+constexpr uint32_t kTapeMagic = 0x4c4f474du;
+constexpr int kTapeMu = 4096;
+struct TapeHeader {
+  uint32_t magic;
+  int32_t n, k_max, max_sqrt, db_max_iter, theta_source;
+  int64_t cap, written;
+  int64_t first[64];        // ring position of each root's first inverse
+  int32_t mu_off[65];       // mu of root r: mu[mu_off[r] .. mu_off[r + 1]); -1: not kept
+  double mu[kTapeMu];
+  logm_info info;           // decisions and counters of the forward pass
+};
+size_t tape_header_bytes() { return align_up(sizeof(TapeHeader), 256); }
+
+// Minimum reverse-mode region: the header, root checkpoints, the fixed slots and a
+// ring that holds one root's inverses; a larger workspace lengthens the ring, so that
+// more roots keep their inverses from the forward pass and need no replay.
 size_t bwd_extra_bytes(const Plan& p, const logm_opts& o) {
-  return (size_t)(o.max_sqrt + 2 * o.db_max_iter + kBwdFixed) * bwd_mat_bytes(p);
+  return tape_header_bytes() + (size_t)(o.max_sqrt + 2 * o.db_max_iter + kBwdFixed) * bwd_mat_bytes(p);
 }
 
-Status backward_r64(Ctx& c, const double* A, int64_t lda, const double* G, int64_t ldg,
-                    double* gradA, int64_t ldga, const logm_opts& o, logm_info& info) {
+struct BwdLayout {
+  char* ext;
+  size_t mb;
+  int ck0, fx, inv0;
+  int64_t cap;
+  double* M(int i) const { return reinterpret_cast<double*>(ext + (size_t)i * mb); }
+};
+
+BwdLayout bwd_layout(Ctx& c, const logm_opts& o) {
+  BwdLayout L;
+  L.ext = c.base + c.p.total + tape_header_bytes();
+  L.mb = bwd_mat_bytes(c.p);
+  L.ck0 = 0;
+  L.fx = o.max_sqrt;
+  L.inv0 = o.max_sqrt + kBwdFixed;
+  L.cap = (int64_t)((c.bytes - c.p.total - tape_header_bytes()) / L.mb) - L.inv0;   // >= 2 db_max_iter
+  return L;
+}
+
+TapeHeader* tape_header(Ctx& c) { return reinterpret_cast<TapeHeader*>(c.base + c.p.total); }
+
+// Forward pass of the taped pair: Algorithm 1 with every root input checkpointed and
+// every inverse taped in the ring; L (may be null) receives log A.  The record goes to
+// the header in the workspace.
+Status taped_forward(Ctx& c, const double* A, int64_t lda, double* L, int64_t ldl,
+                     const logm_opts& o, logm_info& info) {
+  Status st;
+  const BwdLayout lay = bwd_layout(c, o);
+  RootCheckpoints rc;
+  rc.ckpt = [&](int r) { return lay.M(lay.ck0 + r); };
+  rc.ring = [&](int64_t pos) { return lay.M(lay.inv0 + (int)(pos % lay.cap)); };
+  rc.cap = lay.cap;
+  PROPAGATE(forward_r64(c, A, lda, L, ldl, o, info, &rc));
+  std::vector<char> buf(sizeof(TapeHeader), 0);
+  TapeHeader& h = *reinterpret_cast<TapeHeader*>(buf.data());
+  h.magic = kTapeMagic;
+  h.n = c.p.n;
+  h.k_max = o.k_max;
+  h.max_sqrt = o.max_sqrt;
+  h.db_max_iter = o.db_max_iter;
+  h.theta_source = o.theta_source;
+  h.cap = rc.cap;
+  h.written = rc.written;
+  int off = 0;
+  for (int r = 0; r < info.s; ++r) {
+    h.first[r] = rc.first[r];
+    const int cnt = (int)rc.mu[r].size();
+    if (off + cnt <= kTapeMu) {
+      h.mu_off[r] = off;
+      for (int t = 0; t < cnt; ++t) h.mu[off + t] = rc.mu[r][t];
+      off += cnt;
+    } else {
+      h.mu_off[r] = -1;   // replayed in the backward pass
+    }
+  }
+  h.mu_off[info.s] = off;
+  h.info = info;
+  HIPCK(hipMemcpyAsync(tape_header(c), buf.data(), sizeof(TapeHeader), hipMemcpyHostToDevice, c.s));
+  HIPCK(hipStreamSynchronize(c.s));
+  return st;
+}
+
+// Backward pass of the taped pair: needs the workspace as the taped forward left it
+// (same n, options and workspace size).  Roots whose inverses were overwritten in the
+// ring are replayed; the header is then updated, so the tape serves further calls.
+Status taped_backward(Ctx& c, const double* G, int64_t ldg, double* gradA, int64_t ldga,
+                      const logm_opts& o, logm_info& info) {
   Status st;
   const int n = c.p.n;
   const int np = c.p.n_pad;
-  const size_t mb = bwd_mat_bytes(c.p);
-  char* ext = c.base + c.p.total;
-  auto M = [&](int i) { return reinterpret_cast<double*>(ext + (size_t)i * mb); };
-  const int ck0 = 0, inv0 = o.max_sqrt, fx = o.max_sqrt + 2 * o.db_max_iter;
+  const BwdLayout lay = bwd_layout(c, o);
+  auto M = [&](int i) { return lay.M(i); };
+  const int ck0 = lay.ck0, fx = lay.fx, inv0 = lay.inv0;
+  const int64_t cap = lay.cap;
+  std::vector<char> hbuf(sizeof(TapeHeader));
+  TapeHeader& h = *reinterpret_cast<TapeHeader*>(hbuf.data());
+  HIPCK(hipMemcpyAsync(hbuf.data(), tape_header(c), sizeof(TapeHeader), hipMemcpyDeviceToHost, c.s));
+  HIPCK(hipStreamSynchronize(c.s));
+  if (h.magic != kTapeMagic || h.n != n || h.k_max != o.k_max || h.max_sqrt != o.max_sqrt ||
+      h.db_max_iter != o.db_max_iter || h.theta_source != o.theta_source || h.cap != cap) {
+    st.code = LOGM_EINVAL;   // no matching taped forward pass in this workspace
+    return st;
+  }
+  info = h.info;             // the forward's decisions; the counters are this call's
+  info.n_inv = info.n_gemm = info.n_matvec = info.n_est = 0;
   // fixed slots
   auto LJ = [&](int j) { return M(fx + (j - 2)); };        // left factor of P_{j+2}
   auto RJ = [&](int j) { return M(fx + 4 + (j - 2)); };    // right factor
@@ -804,9 +918,27 @@ Status backward_r64(Ctx& c, const double* A, int64_t lda, const double* G, int64
     return launch_gemm_plain(n, n, n, alpha, Aop, np, Bop, np, beta, C, np, c.s);
   };
 
-  RootCheckpoints rc{[&](int r) { return M(ck0 + r); }};
-  PROPAGATE(forward_r64(c, A, lda, nullptr, 0, o, info, &rc));
+  RootCheckpoints rc;
+  rc.ckpt = [&](int r) { return M(ck0 + r); };
+  rc.ring = [&](int64_t pos) { return M(inv0 + (int)(pos % cap)); };
+  rc.cap = cap;
+  rc.written = h.written;
+  for (int r = 0; r < info.s; ++r) {
+    rc.first[r] = h.first[r];
+    if (h.mu_off[r] >= 0) {
+      int end = h.mu_off[info.s];
+      for (int q = r + 1; q <= info.s; ++q)
+        if (h.mu_off[q] >= 0) {
+          end = h.mu_off[q];
+          break;
+        }
+      rc.mu[r].assign(h.mu + h.mu_off[r], h.mu + end);
+    } else {
+      rc.first[r] = rc.written - cap - 1;   // force a replay
+    }
+  }
   const int s = info.s, k = info.k;
+  const int64_t written0 = rc.written;
   const double* B = c.mat(3);
   const double* B2 = c.mat(4);
   const Scheme& S = scheme(k);
@@ -878,17 +1010,30 @@ Status backward_r64(Ctx& c, const double* A, int64_t lda, const double* G, int64
     g.m = 1;
     HIPCK(lincomb(g, Xh, 1.0));
     for (int r = s - 1; r >= 0; --r) {
-      DbTape tape;
-      tape.force_iters = info.db_iters[r];
-      tape.slot = [&](int t, int z) { return M(inv0 + 2 * (t - 1) + z); };
-      int iters = 0, ninv = 0;
-      PROPAGATE(db_sqrt(c, M(ck0 + r), c.mat(0), tape.force_iters, &iters, &ninv, &tape));
-      info.n_inv += ninv;
+      const int iters = info.db_iters[r];
+      int64_t first = rc.first[r];
+      std::vector<double> mus = rc.mu[r];
+      if (first < rc.written - cap) {
+        // overwritten in the ring: replay the root from its checkpoint (bit-identical:
+        // every kernel is deterministic) onto the ring's oldest slots; every later root
+        // is done and every earlier one is overwritten as well
+        DbTape tape;
+        tape.force_iters = iters;
+        first = rc.written;
+        tape.slot = [&](int t, int z) { return rc.ring(first + tape_index(t, z)); };
+        int it2 = 0, ninv = 0;
+        PROPAGATE(db_sqrt(c, M(ck0 + r), c.mat(0), iters, &it2, &ninv, &tape));
+        info.n_inv += ninv;
+        rc.written += 2 * iters - 1;
+        mus = tape.mu;
+        rc.first[r] = first;
+        rc.mu[r] = mus;
+      }
       bool yh_zero = true;
       for (int t = iters; t >= 1; --t) {
-        const double mu = tape.mu[t - 1];
-        const double* Xi = M(inv0 + 2 * (t - 1));
-        const double* Yi = (t >= 2) ? M(inv0 + 2 * (t - 1) + 1) : nullptr;
+        const double mu = mus[t - 1];
+        const double* Xi = rc.ring(first + tape_index(t, 0));
+        const double* Yi = (t >= 2) ? rc.ring(first + tape_index(t, 1)) : nullptr;
         // X' = (mu X + Yi/mu)/2, Y' = (mu Y + Xi/mu)/2:
         // Xh = mu/2 Xh' - Xi Yh' Xi/(2 mu), Yh = mu/2 Yh' - Yi Xh' Yi/(2 mu)
         if (Yi != nullptr) HIPCK(gemm(1.0, Yi, Xh, 0.0, T2));
@@ -913,6 +1058,23 @@ Status backward_r64(Ctx& c, const double* A, int64_t lda, const double* G, int64
       }
     }
   }
+  if (rc.written != written0) {   // replays moved the ring: record where each root is now
+    h.written = rc.written;
+    int off = 0;
+    for (int r = 0; r < s; ++r) {
+      h.first[r] = rc.first[r];
+      const int cnt = (int)rc.mu[r].size();
+      if (off + cnt <= kTapeMu) {
+        h.mu_off[r] = off;
+        for (int t = 0; t < cnt; ++t) h.mu[off + t] = rc.mu[r][t];
+        off += cnt;
+      } else {
+        h.mu_off[r] = -1;
+      }
+    }
+    h.mu_off[s] = off;
+    HIPCK(hipMemcpyAsync(tape_header(c), hbuf.data(), sizeof(TapeHeader), hipMemcpyHostToDevice, c.s));
+  }
   HIPCK(launch_transpose(Xh, np, gradA, ldga, n, 1.0, c.s));
   int* flag = c.iflag() + 2;
   HIPCK(hipMemsetAsync(flag, 0, sizeof(int), c.s));
@@ -922,6 +1084,21 @@ Status backward_r64(Ctx& c, const double* A, int64_t lda, const double* G, int64
   if (bad) st.code = LOGM_ENONFINITE;
   info.n_gemm += ngemm;
   const double nd = n;
+  info.flops = 2.0 * nd * nd * nd * (info.n_inv + info.n_gemm) + 2.0 * nd * nd * info.n_matvec;
+  return st;
+}
+
+Status backward_r64(Ctx& c, const double* A, int64_t lda, const double* G, int64_t ldg,
+                    double* gradA, int64_t ldga, const logm_opts& o, logm_info& info) {
+  Status st;
+  PROPAGATE(taped_forward(c, A, lda, nullptr, 0, o, info));
+  const logm_info fwd = info;
+  PROPAGATE(taped_backward(c, G, ldg, gradA, ldga, o, info));
+  info.n_inv += fwd.n_inv;
+  info.n_gemm += fwd.n_gemm;
+  info.n_matvec += fwd.n_matvec;
+  info.n_est += fwd.n_est;
+  const double nd = c.p.n;
   info.flops = 2.0 * nd * nd * nd * (info.n_inv + info.n_gemm) + 2.0 * nd * nd * info.n_matvec;
   return st;
 }
@@ -945,12 +1122,14 @@ struct Call {
       }
       owned = true;
       c.base = static_cast<char*>(mem);
+      c.bytes = total;
     } else {
       if (ws_bytes < total) {
         st.code = LOGM_EWORKSPACE;
         return;
       }
       c.base = static_cast<char*>(ws);
+      c.bytes = ws_bytes;
     }
     // look-ahead resources; without them the inversion runs on the main stream only
     if (hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking) != hipSuccess) c.side = nullptr;
@@ -1085,6 +1264,58 @@ int logm_backward(int32_t dtype, int64_t n, const void* A, int64_t lda, const vo
   }
   Status st = backward_r64(call.c, static_cast<const double*>(A), lda, static_cast<const double*>(G),
                            ldg, static_cast<double*>(gradA), ldga, opts, inf);
+  inf.status_detail = st.detail;
+  return st.code;
+}
+
+int logm_forward_taped(int32_t dtype, int64_t n, const void* A, int64_t lda, void* L, int64_t ldl,
+                       const logm_opts* o, logm_info* info, void* ws, size_t ws_bytes,
+                       void* stream) {
+  logm_opts opts;
+  logm_default_opts(&opts);
+  if (o != nullptr) opts = *o;
+  if (dtype != LOGM_R64 && dtype != LOGM_C128) return LOGM_EINVAL;
+  if (n < 1 || n > (int64_t)1 << 20 || A == nullptr || L == nullptr || ws == nullptr || lda < n ||
+      ldl < n)
+    return LOGM_EINVAL;
+  if (!opts_ok(opts) || opts.balance != 0) return LOGM_EINVAL;
+  if (dtype == LOGM_C128) return LOGM_ENOTSUP;
+  logm_info local{};
+  logm_info& inf = (info != nullptr) ? *info : local;
+  std::memset(&inf, 0, sizeof(inf));
+  Call call(n, ws, ws_bytes, stream, &opts);
+  if (call.st.code != LOGM_OK) {
+    inf.status_detail = call.st.detail;
+    return call.st.code;
+  }
+  Status st = taped_forward(call.c, static_cast<const double*>(A), lda, static_cast<double*>(L),
+                            ldl, opts, inf);
+  inf.status_detail = st.detail;
+  return st.code;
+}
+
+int logm_backward_taped(int32_t dtype, int64_t n, const void* G, int64_t ldg, void* gradA,
+                        int64_t ldga, const logm_opts* o, logm_info* info, void* ws,
+                        size_t ws_bytes, void* stream) {
+  logm_opts opts;
+  logm_default_opts(&opts);
+  if (o != nullptr) opts = *o;
+  if (dtype != LOGM_R64 && dtype != LOGM_C128) return LOGM_EINVAL;
+  if (n < 1 || n > (int64_t)1 << 20 || G == nullptr || gradA == nullptr || ws == nullptr ||
+      ldg < n || ldga < n)
+    return LOGM_EINVAL;
+  if (!opts_ok(opts) || opts.balance != 0) return LOGM_EINVAL;
+  if (dtype == LOGM_C128) return LOGM_ENOTSUP;
+  logm_info local{};
+  logm_info& inf = (info != nullptr) ? *info : local;
+  std::memset(&inf, 0, sizeof(inf));
+  Call call(n, ws, ws_bytes, stream, &opts);
+  if (call.st.code != LOGM_OK) {
+    inf.status_detail = call.st.detail;
+    return call.st.code;
+  }
+  Status st = taped_backward(call.c, static_cast<const double*>(G), ldg, static_cast<double*>(gradA),
+                             ldga, opts, inf);
   inf.status_detail = st.detail;
   return st.code;
 }

@@ -136,6 +136,14 @@ def test_backward_argument_validation(lib):
     o.k_max = 4
     assert call(opts=o) == 1
     assert call() == 3                                 # workspace too small
+    # taped pair: the workspace is required (it carries the tape)
+    assert lib.logm_forward_taped(0, 8, FAKE, 8, FAKE, 8, None, None, None, 0, None) == 1
+    assert lib.logm_forward_taped(0, 8, FAKE, 8, FAKE, 8, None, None, FAKE, 100, None) == 3
+    assert lib.logm_backward_taped(0, 8, FAKE, 8, FAKE, 8, None, None, None, 0, None) == 1
+    assert lib.logm_backward_taped(0, 8, FAKE, 7, FAKE, 8, None, None, FAKE, 100, None) == 1
+    o = lm.default_opts()
+    o.balance = 1
+    assert lib.logm_forward_taped(0, 8, FAKE, 8, FAKE, 8, ctypes.byref(o), None, FAKE, 100, None) == 1
 
 
 def test_batched_argument_validation(lib):

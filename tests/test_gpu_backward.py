@@ -123,3 +123,38 @@ def test_backward_nonfinite_G(lm):
     with pytest.raises(lm.LogmError) as e:
         gpu_backward(lm, A, G)
     assert e.value.code == 4
+
+
+def test_taped_pair_matches_self_contained_backward(lm):
+    """logm_forward_taped + logm_backward_taped give the same L and gradient as
+    logm_forward and logm_backward, bit for bit, also with a ring too short for the
+    whole tape (roots replayed) and for several G after one forward."""
+    import torch
+
+    n = 96
+    A = rotscale_matrix(n, 4800, 1e-2, 1e2)[0]
+    rng = np.random.default_rng(4801)
+    Gs = [rng.standard_normal((n, n)) for _ in range(2)]
+    dev = torch.device("cuda:0")
+    At = torch.from_numpy(A).to(dev)
+    L_ref, _ = lm.logm(At)
+    for tape_mats in (None, 0):
+        tape = lm.Tape(n, dev, tape_mats=tape_mats)
+        L, info = lm.logm_forward_taped(At, tape)
+        assert torch.equal(L, L_ref)
+        for G in Gs + Gs[:1]:          # a G repeated after another: the tape stays valid
+            gA, ib = lm.logm_backward_taped(torch.from_numpy(G).to(dev), tape)
+            ref, _ = lm.logm_backward(At, torch.from_numpy(G).to(dev))
+            assert torch.equal(gA, ref)
+            assert (ib["s"], ib["k"]) == (info["s"], info["k"])
+
+
+def test_taped_backward_needs_its_forward(lm):
+    import torch
+
+    dev = torch.device("cuda:0")
+    tape = lm.Tape(32, dev)
+    tape.ws.zero_()
+    with pytest.raises(lm.LogmError) as e:
+        lm.logm_backward_taped(torch.ones((32, 32), dtype=torch.float64, device=dev), tape)
+    assert e.value.code == 1
