@@ -102,13 +102,17 @@ void logm_default_opts(logm_opts* o);
 /* Human-readable name of a status code (static string). */
 const char* logm_strerror(int code);
 
-/* Workspace bytes for logm_forward on an n x n matrix; also sufficient for every
- * component entry point below with the same n.  Returns LOGM_EINVAL for n < 1. */
+/* Workspace bytes for logm_forward on an n x n matrix of the given dtype (for
+ * LOGM_R64 also sufficient for every component entry point below with the same n).
+ * Returns LOGM_EINVAL for n < 1. */
 int logm_workspace_size(int32_t dtype, int64_t n, const logm_opts* o, size_t* bytes);
 
 /* L = log(A) (Algorithm 1).  A (device, n x n, lda) is not modified; L (device,
  * n x n, ldl) must not overlap A.  o may be NULL (defaults); info (host) may be
- * NULL.  dtype LOGM_R64 only (LOGM_C128 returns LOGM_ENOTSUP). */
+ * NULL.  LOGM_C128: A and L interleaved (re, im) like torch.complex128, lda and ldl
+ * in complex elements; the method runs on the real representation
+ * P = [[Re A, -Im A], [Im A, Re A]] (2n x 2n), whose logarithm is the representation
+ * of log A, so info describes that 2n x 2n run (decisions, counts, real flops). */
 int logm_forward(int32_t dtype, int64_t n, const void* A, int64_t lda, void* L, int64_t ldl,
                  const logm_opts* o, logm_info* info, void* ws, size_t ws_bytes, void* stream);
 

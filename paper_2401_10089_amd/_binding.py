@@ -196,9 +196,9 @@ def version() -> str:
     return lib().logm_version().decode()
 
 
-def workspace_size(n: int, opts: LogmOpts | None = None) -> int:
+def workspace_size(n: int, opts: LogmOpts | None = None, dtype: int = LOGM_R64) -> int:
     b = _sz(0)
-    _check(lib().logm_workspace_size(LOGM_R64, n, ctypes.byref(opts) if opts else None, ctypes.byref(b)),
+    _check(lib().logm_workspace_size(dtype, n, ctypes.byref(opts) if opts else None, ctypes.byref(b)),
            "logm_workspace_size")
     return b.value
 
@@ -244,12 +244,13 @@ def _stream_ptr(t):
     return _vp(torch.cuda.current_stream(t.device).cuda_stream)
 
 
-def _as_matrix(A, name="A"):
+def _as_matrix(A, name="A", allow_complex: bool = False):
     torch = _torch()
     if not isinstance(A, torch.Tensor) or A.device.type != "cuda":
         raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
-    if A.dtype != torch.float64:
-        raise TypeError(f"{name} must be float64 (complex input is not built)")
+    ok = (torch.float64, torch.complex128) if allow_complex else (torch.float64,)
+    if A.dtype not in ok:
+        raise TypeError(f"{name} must be " + (" or ".join(str(t) for t in ok)))
     if A.dim() != 2 or A.shape[0] != A.shape[1]:
         raise ValueError(f"{name} must be a square matrix")
     if A.stride(1) != 1:
@@ -257,9 +258,9 @@ def _as_matrix(A, name="A"):
     return A
 
 
-def _workspace(n: int, device, workspace=None):
+def _workspace(n: int, device, workspace=None, dtype: int = LOGM_R64):
     torch = _torch()
-    need = workspace_size(n)
+    need = workspace_size(n, dtype=dtype)
     if workspace is not None:
         if workspace.numel() * workspace.element_size() < need:
             raise ValueError(f"workspace needs {need} bytes")
@@ -269,20 +270,21 @@ def _workspace(n: int, device, workspace=None):
 
 def logm(A, k_max: int = 5, max_sqrt: int = 50, db_max_iter: int = 30, theta_source: int = 0,
          out=None, workspace=None, graph_fp32: bool = False, balance: bool = False):
-    """L = log(A) on the GPU (Algorithm 1).  Returns (L, info dict).
-
-    graph_fp32 runs the graph products on the fp32 matrix cores (see logm_opts)."""
+    """L = log(A) on the GPU (Algorithm 1), A float64 or complex128.  Returns (L, info
+    dict).  graph_fp32 runs the graph products on the fp32 matrix cores (see
+    logm_opts); complex A runs on its 2n x 2n real representation."""
     torch = _torch()
-    A = _as_matrix(A)
+    A = _as_matrix(A, allow_complex=True)
     n = A.shape[0]
-    L = out if out is not None else torch.empty((n, n), dtype=torch.float64, device=A.device)
+    dt = LOGM_C128 if A.dtype == torch.complex128 else LOGM_R64
+    L = out if out is not None else torch.empty((n, n), dtype=A.dtype, device=A.device)
     o = default_opts()
     o.k_max, o.max_sqrt, o.db_max_iter, o.theta_source = k_max, max_sqrt, db_max_iter, theta_source
     o.graph_fp32 = 1 if graph_fp32 else 0
     o.balance = 1 if balance else 0
-    ws = _workspace(n, A.device, workspace)
+    ws = _workspace(n, A.device, workspace, dt)
     info = LogmInfo()
-    rc = lib().logm_forward(LOGM_R64, n, _vp(A.data_ptr()), A.stride(0), _vp(L.data_ptr()), L.stride(0),
+    rc = lib().logm_forward(dt, n, _vp(A.data_ptr()), A.stride(0), _vp(L.data_ptr()), L.stride(0),
                             ctypes.byref(o), ctypes.byref(info), _vp(ws.data_ptr()), ws.numel(),
                             _stream_ptr(A))
     _check(rc, "logm_forward", info.status_detail)

@@ -1108,10 +1108,11 @@ struct Call {
   Ctx c;
   bool owned = false;
   Status st;
-  Call(int64_t n, void* ws, size_t ws_bytes, void* stream, const logm_opts* bwd = nullptr) {
+  Call(int64_t n, void* ws, size_t ws_bytes, void* stream, const logm_opts* bwd = nullptr,
+       size_t extra = 0) {
     c.s = reinterpret_cast<hipStream_t>(stream);
     c.p = make_plan(n);
-    const size_t total = c.p.total + (bwd != nullptr ? bwd_extra_bytes(c.p, *bwd) : 0);
+    const size_t total = c.p.total + (bwd != nullptr ? bwd_extra_bytes(c.p, *bwd) : 0) + extra;
     if (ws == nullptr) {
       void* mem = nullptr;
       hipError_t e = hipMallocAsync(&mem, total, c.s);
@@ -1198,11 +1199,15 @@ const char* logm_strerror(int code) {
 
 const char* logm_version(void) { return "logm-mi355x 0.1 (gfx950)"; }
 
+// Complex input runs the real path on its 2n x 2n real representation; the workspace
+// adds that matrix and the real result.
+size_t complex_extra_bytes(int64_t n) { return 2 * align_up((size_t)(2 * n) * (size_t)(2 * n) * sizeof(double), 256); }
+
 int logm_workspace_size(int32_t dtype, int64_t n, const logm_opts* o, size_t* bytes) {
   if (n < 1 || n > (int64_t)1 << 20 || bytes == nullptr) return LOGM_EINVAL;
   if (dtype != LOGM_R64 && dtype != LOGM_C128) return LOGM_EINVAL;
   if (o != nullptr && !opts_ok(*o)) return LOGM_EINVAL;
-  *bytes = make_plan(n).total;
+  *bytes = (dtype == LOGM_C128) ? make_plan(2 * n).total + complex_extra_bytes(n) : make_plan(n).total;
   return LOGM_OK;
 }
 
@@ -1215,10 +1220,33 @@ int logm_forward(int32_t dtype, int64_t n, const void* A, int64_t lda, void* L, 
   if (n < 1 || n > (int64_t)1 << 20 || A == nullptr || L == nullptr || lda < n || ldl < n)
     return LOGM_EINVAL;
   if (!opts_ok(opts)) return LOGM_EINVAL;
-  if (dtype == LOGM_C128) return LOGM_ENOTSUP;
+  if (dtype == LOGM_C128 && 2 * n > (int64_t)1 << 20) return LOGM_EINVAL;
   logm_info local{};
   logm_info& inf = (info != nullptr) ? *info : local;
   std::memset(&inf, 0, sizeof(inf));
+  if (dtype == LOGM_C128) {
+    // log of the real representation P = [[Re A, -Im A], [Im A, Re A]] is the
+    // representation of log A (A has no eigenvalue on R^- iff P has none)
+    const int64_t n2 = 2 * n;
+    Call call(n2, ws, ws_bytes, stream, nullptr, complex_extra_bytes(n));
+    if (call.st.code != LOGM_OK) {
+      inf.status_detail = call.st.detail;
+      return call.st.code;
+    }
+    Ctx& c = call.c;
+    double* P = reinterpret_cast<double*>(c.base + c.p.total);
+    double* R = P + (size_t)n2 * n2;
+    Status st = [&]() -> Status {
+      Status st;
+      HIPCK(launch_embed_complex(static_cast<const double*>(A), lda, (int)n, P, n2, c.s));
+      PROPAGATE(forward_r64(c, P, n2, R, n2, opts, inf));
+      HIPCK(launch_extract_complex(R, n2, (int)n, static_cast<double*>(L), ldl, c.s));
+      HIPCK(hipStreamSynchronize(c.s));
+      return st;
+    }();
+    inf.status_detail = st.detail;
+    return st.code;
+  }
   Call call(n, ws, ws_bytes, stream);
   if (call.st.code != LOGM_OK) {
     inf.status_detail = call.st.detail;

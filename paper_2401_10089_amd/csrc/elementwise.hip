@@ -349,6 +349,32 @@ __global__ void unbalance_kernel(double* L, int64_t ld, int n, const double* d) 
     L[(int64_t)i * ld + j] *= di / d[j];
 }
 
+// Complex input through its real representation: P (2n x 2n, row stride ldp) =
+// [[Re A, -Im A], [Im A, Re A]] from A (n x n complex, interleaved (re, im), row
+// stride lda in complex elements).  The map is an injective algebra homomorphism,
+// so P^{1/2}, P^{-1} and log P are the images of A^{1/2}, A^{-1} and log A.
+__global__ void embed_complex_kernel(const double* A, int64_t lda, int n, double* P, int64_t ldp) {
+  const int i = blockIdx.y;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+    const double re = A[2 * ((int64_t)i * lda + j)];
+    const double im = A[2 * ((int64_t)i * lda + j) + 1];
+    P[(int64_t)i * ldp + j] = re;
+    P[(int64_t)i * ldp + n + j] = -im;
+    P[(int64_t)(n + i) * ldp + j] = im;
+    P[(int64_t)(n + i) * ldp + n + j] = re;
+  }
+}
+
+// L (n x n complex, interleaved, row stride ldl) from the left block column of its
+// real representation R (2n x 2n, row stride ldr): Re L = R[0:n, 0:n], Im L = R[n:2n, 0:n].
+__global__ void extract_complex_kernel(const double* R, int64_t ldr, int n, double* L, int64_t ldl) {
+  const int i = blockIdx.y;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+    L[2 * ((int64_t)i * ldl + j)] = R[(int64_t)i * ldr + j];
+    L[2 * ((int64_t)i * ldl + j) + 1] = R[(int64_t)(n + i) * ldr + j];
+  }
+}
+
 inline dim3 row_grid(int n, int rows) { return dim3((unsigned)std::min(8, (n + 255) / 256), (unsigned)rows); }
 
 }  // namespace
@@ -412,6 +438,18 @@ hipError_t launch_balance(double* M, int64_t ld, int n, double* d, int max_sweep
 
 hipError_t launch_unbalance(double* L, int64_t ld, int n, const double* d, hipStream_t s) {
   hipLaunchKernelGGL(unbalance_kernel, row_grid(n, n), dim3(256), 0, s, L, ld, n, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_embed_complex(const double* A, int64_t lda, int n, double* P, int64_t ldp,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(embed_complex_kernel, row_grid(n, n), dim3(256), 0, s, A, lda, n, P, ldp);
+  return hipGetLastError();
+}
+
+hipError_t launch_extract_complex(const double* R, int64_t ldr, int n, double* L, int64_t ldl,
+                                  hipStream_t s) {
+  hipLaunchKernelGGL(extract_complex_kernel, row_grid(n, n), dim3(256), 0, s, R, ldr, n, L, ldl);
   return hipGetLastError();
 }
 

@@ -171,6 +171,13 @@ hipError_t launch_balance(double* M, int64_t ld, int n, double* d, int max_sweep
 // L <- T L T^{-1} for d = diag(T).
 hipError_t launch_unbalance(double* L, int64_t ld, int n, const double* d, hipStream_t s);
 
+// P (2n x 2n) = [[Re A, -Im A], [Im A, Re A]] for complex A (interleaved, lda in
+// complex elements); L (complex) = the left block column of R (2n x 2n).
+hipError_t launch_embed_complex(const double* A, int64_t lda, int n, double* P, int64_t ldp,
+                                hipStream_t s);
+hipError_t launch_extract_complex(const double* R, int64_t ldr, int n, double* L, int64_t ldl,
+                                  hipStream_t s);
+
 // dst = scale * src^T for the n x n blocks (dst must not overlap src).
 hipError_t launch_transpose(const double* src, int64_t lds, double* dst, int64_t ldd, int n,
                             double scale, hipStream_t s);

@@ -76,7 +76,11 @@ def test_forward_argument_validation(lib):
     assert fwd(lib, lda=7) == 1
     assert fwd(lib, ldl=3) == 1
     assert fwd(lib, dtype=5) == 1
-    assert fwd(lib, dtype=1) == 2                      # complex not built
+    assert fwd(lib, dtype=1, ws=FAKE, ws_bytes=100) == 3   # complex: workspace of the 2n run
+    b_r, b_c = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert lib.logm_workspace_size(0, 100, None, ctypes.byref(b_r)) == 0
+    assert lib.logm_workspace_size(1, 100, None, ctypes.byref(b_c)) == 0
+    assert b_c.value > 2 * b_r.value
     o = lm.default_opts()
     o.k_max = 4                                        # no printed coefficients for k = 4
     assert fwd(lib, opts=o) == 1

@@ -1,0 +1,59 @@
+"""Complex logm on the GPU (LOGM_C128): the library runs Algorithm 1 on the real
+representation P of A; the result must match the oracle on P (same decisions,
+element by element), the closed form, and the oracle's complex Algorithm 1."""
+
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import complex_matrix, real_representation
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lm():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2401_10089_amd as lm
+
+    lm.load_library()
+    return lm
+
+
+def relf(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("n", [1, 8, 50, 130])
+def test_complex_logm_vs_oracle_on_real_representation(lm, n):
+    import torch
+
+    A, Lx = complex_matrix(n, 8100 + n)
+    L, info = lm.logm(torch.from_numpy(A).to("cuda:0"))
+    assert L.dtype == torch.complex128
+    L = L.cpu().numpy()
+    P = real_representation(A)
+    LP, io = oracle.logm(P)
+    if (info["s"], info["k"], info["db_iters"]) != (io["s"], io["k"], io["db_iters"]):
+        LP, _ = oracle.logm(P, force={"s": info["s"], "k": info["k"], "db_iters": info["db_iters"]})
+    Lo = LP[:n, :n] + 1j * LP[n:, :n]
+    assert relf(L, Lo) < 1e-12
+    assert relf(L, Lx) < 1e-11
+    Lc, _ = oracle.logm(A)
+    assert relf(L, Lc) < 1e-11
+
+
+def test_complex_logm_strided_input(lm):
+    import torch
+
+    n = 40
+    A, Lx = complex_matrix(n, 8200)
+    big = torch.zeros((n, n + 7), dtype=torch.complex128, device="cuda:0")
+    big[:, :n] = torch.from_numpy(A).to("cuda:0")
+    L, _ = lm.logm(big[:, :n])
+    assert relf(L.cpu().numpy(), Lx) < 1e-11

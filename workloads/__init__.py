@@ -5,6 +5,8 @@ method's arithmetic.
 
 from .matrices import (  # noqa: F401
     CONFIG_SEEDS,
+    complex_matrix,
+    real_representation,
     disk_matrix,
     rotscale_matrix,
     spd_batch,

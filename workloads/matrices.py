@@ -93,3 +93,23 @@ def named_workload(name: str):
     if name == "rotscale8192":
         return rotscale_matrix(8192, seed, 1e-2, 1e2)
     raise KeyError(name)
+
+
+def complex_matrix(n: int, seed: int, r_lo: float = 1e-2, r_hi: float = 1e2):
+    """Complex A = V diag(lambda) V^{-1} with V = I + 0.1 (N + iN)/sqrt(2n) and
+    lambda = r e^{i theta}, log r uniform in [log r_lo, log r_hi], theta uniform in
+    (-0.9 pi, 0.9 pi); returns (A, log A exact) with log A = V diag(log lambda) V^{-1}."""
+    rng = np.random.default_rng(seed)
+    V = np.eye(n) + 0.1 * (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(2 * n)
+    logr = rng.uniform(np.log(r_lo), np.log(r_hi), size=n)
+    theta = rng.uniform(-0.9 * np.pi, 0.9 * np.pi, size=n)
+    loglam = logr + 1j * theta
+    Vi = np.linalg.inv(V)
+    A = (V * np.exp(loglam)) @ Vi
+    L = (V * loglam) @ Vi
+    return A, L
+
+
+def real_representation(A: np.ndarray) -> np.ndarray:
+    """[[Re A, -Im A], [Im A, Re A]]: the 2n x 2n real matrix of the complex A."""
+    return np.block([[A.real, -A.imag], [A.imag, A.real]])
