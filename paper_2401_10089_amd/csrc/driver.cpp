@@ -192,7 +192,7 @@ Plan make_plan(int64_t n) {
     p.err[z] = take(4 * sizeof(int));
   }
   p.part = take(2 * (size_t)p.nblk * np * sizeof(double));
-  p.bm = take(2 * (np / 256 + 2) * sizeof(double));
+  p.bm = take(2 * (np / 64 + 2) * sizeof(double));
   p.vec = take(4 * np * sizeof(double));
   p.scal = take(16 * sizeof(double));
   p.iflag = take(16 * sizeof(int));

@@ -79,23 +79,31 @@ __global__ __launch_bounds__(TPB) void db_update_kernel(DbArgs a, int nblk) {
   }
 }
 
+// Sum over the nblk row-block partials part[b][c] for the 64 columns of this
+// workgroup: wave w adds blocks w, w + 4, ... for column c = 64 blockIdx.x + lane
+// (coalesced rows), then the four wave sums are added in a fixed order.  The result
+// is valid in wave 0.
+constexpr int CS_COLS = 64;
+__device__ __forceinline__ double colsum64(const double* part, int nblk, int n, double* s_red) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int c = blockIdx.x * CS_COLS + lane;
+  double s = 0.0;
+  if (c < n)
+    for (int b = w; b < nblk; b += TPB / 64) s += part[(int64_t)b * n + c];
+  s_red[w * 64 + lane] = s;
+  __syncthreads();
+  return (s_red[lane] + s_red[64 + lane]) + (s_red[128 + lane] + s_red[192 + lane]);
+}
+
 __global__ __launch_bounds__(TPB) void colsum_blockmax_kernel(const double* part, int nblk, int n,
                                                               double* bm) {
-  __shared__ double s_red[TPB / 64];
+  __shared__ double s_red[TPB];
   const int q = blockIdx.y;
-  const int c = blockIdx.x * TPB + threadIdx.x;
-  double s = 0.0;
-  if (c < n) {
-    const double* p = part + (int64_t)q * nblk * n + c;
-    for (int b = 0; b < nblk; ++b) s += p[(int64_t)b * n];
-  }
-  s = wave_max(s);
-  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double m = s_red[0];
-    for (int w = 1; w < TPB / 64; ++w) m = fmax(m, s_red[w]);
-    bm[q * gridDim.x + blockIdx.x] = m;
+  const double t = colsum64(part + (int64_t)q * nblk * n, nblk, n, s_red);
+  if (threadIdx.x < 64) {
+    const int c = blockIdx.x * CS_COLS + threadIdx.x;
+    const double m = wave_max(c < n ? t : 0.0);
+    if (threadIdx.x == 0) bm[q * gridDim.x + blockIdx.x] = m;
   }
 }
 
@@ -203,12 +211,12 @@ __global__ __launch_bounds__(TPB) void gemv_t_part_kernel(const double* M, int64
   part[(int64_t)blockIdx.x * n + c] = s;
 }
 
-__global__ void gemv_t_reduce_kernel(const double* part, int nblk, int n, double* z) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n) return;
-  double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * n + c];
-  z[c] = s;
+__global__ __launch_bounds__(TPB) void gemv_t_reduce_kernel(const double* part, int nblk, int n,
+                                                            double* z) {
+  __shared__ double s_red[TPB];
+  const double t = colsum64(part, nblk, n, s_red);
+  const int c = blockIdx.x * CS_COLS + threadIdx.x;
+  if (threadIdx.x < 64 && c < n) z[c] = t;
 }
 
 __global__ void lincomb_init_kernel(LincombArgs a) {
@@ -386,7 +394,7 @@ hipError_t launch_db_update(const DbArgs& a, int nblk, hipStream_t s) {
 
 hipError_t launch_colsum_max(const double* part, int nq, int nblk, int n, double* out,
                              double* bm, hipStream_t s) {
-  const int gx = (n + TPB - 1) / TPB;
+  const int gx = (n + CS_COLS - 1) / CS_COLS;
   hipLaunchKernelGGL(colsum_blockmax_kernel, dim3(gx, nq), dim3(TPB), 0, s, part, nblk, n, bm);
   hipLaunchKernelGGL(max_reduce_kernel, dim3(nq), dim3(64), 0, s, bm, gx, out);
   return hipGetLastError();
@@ -466,8 +474,8 @@ hipError_t launch_gemv(const double* M, int64_t ld, int n, const double* x, doub
   } else {
     hipLaunchKernelGGL(gemv_t_part_kernel, dim3(nblk, (n + TPB - 1) / TPB), dim3(TPB), 0, s, M, ld,
                        n, x, part, nblk);
-    hipLaunchKernelGGL(gemv_t_reduce_kernel, dim3((n + 255) / 256), dim3(256), 0, s, part, nblk, n,
-                       y);
+    hipLaunchKernelGGL(gemv_t_reduce_kernel, dim3((n + CS_COLS - 1) / CS_COLS), dim3(TPB), 0, s, part,
+                       nblk, n, y);
   }
   return hipGetLastError();
 }

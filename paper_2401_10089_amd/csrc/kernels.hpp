@@ -109,7 +109,7 @@ struct DbArgs {
 hipError_t launch_db_update(const DbArgs& a, int nblk, hipStream_t s);
 
 // Reduce partial column sums part[q][b][c] (q < nq, b < nblk, c < n) to
-// out[q] = max_c sum_b part[q][b][c]; bm is scratch of nq * ceil(n / 256) doubles.
+// out[q] = max_c sum_b part[q][b][c]; bm is scratch of nq * ceil(n / 64) doubles.
 hipError_t launch_colsum_max(const double* part, int nq, int nblk, int n, double* out,
                              double* bm, hipStream_t s);
 
