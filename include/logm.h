@@ -138,7 +138,11 @@ int logm_backward_workspace_size(int32_t dtype, int64_t n, const logm_opts* o, s
  * row-major, lda, ldg >= n) are read; gradA (ldga >= n) must not overlap A or G.
  * The computation is FP64 whatever o->graph_fp32 says; info (host, may be NULL)
  * receives the forward decisions and the flops of the whole call.  Synchronises
- * `stream` at the decisions like logm_forward; LOGM_ENOTSUP for LOGM_C128. */
+ * `stream` at the decisions like logm_forward.  LOGM_C128 (interleaved, ld in complex
+ * elements): gradA = L_log(A^H, G), the adjoint for the inner product Re tr(X^H Y)
+ * (the gradient convention of holomorphic functions), computed by the real reverse
+ * mode on the 2n x 2n representation, whose transpose is the representation of A^H;
+ * logm_backward_workspace_size takes the dtype into account. */
 int logm_backward(int32_t dtype, int64_t n, const void* A, int64_t lda, const void* G, int64_t ldg,
                   void* gradA, int64_t ldga, const logm_opts* o, logm_info* info, void* ws,
                   size_t ws_bytes, void* stream);

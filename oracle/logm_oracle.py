@@ -680,7 +680,7 @@ def frechet_block(A, E, **kw):
     """L_log(A, E) as the upper-right block of log([[A, E], [0, A]]) (block-triangular
     form of the Frechet derivative), computed with ``logm`` at size 2n."""
     n = A.shape[0]
-    M = np.zeros((2 * n, 2 * n))
+    M = np.zeros((2 * n, 2 * n), dtype=np.result_type(A, E))
     M[:n, :n] = A
     M[n:, n:] = A
     M[:n, n:] = E

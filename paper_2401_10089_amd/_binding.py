@@ -291,13 +291,14 @@ def logm(A, k_max: int = 5, max_sqrt: int = 50, db_max_iter: int = 30, theta_sou
     return L, info.as_dict()
 
 
-def backward_workspace_size(n: int, opts: LogmOpts | None = None, tape_mats: int = 0) -> int:
+def backward_workspace_size(n: int, opts: LogmOpts | None = None, tape_mats: int = 0,
+                            dtype: int = LOGM_R64) -> int:
     """Workspace bytes of the reverse mode; ``tape_mats`` extra matrices lengthen the
     ring of taped inverses (see logm_backward)."""
     b = _sz(0)
-    _check(lib().logm_backward_workspace_size(LOGM_R64, n, ctypes.byref(opts) if opts else None,
+    _check(lib().logm_backward_workspace_size(dtype, n, ctypes.byref(opts) if opts else None,
                                               ctypes.byref(b)), "logm_backward_workspace_size")
-    return b.value + tape_mats * _bwd_mat_bytes(n)
+    return b.value + tape_mats * _bwd_mat_bytes(2 * n if dtype == LOGM_C128 else n)
 
 
 def _bwd_mat_bytes(n: int) -> int:
@@ -308,29 +309,31 @@ def _bwd_mat_bytes(n: int) -> int:
 def logm_backward(A, G, k_max: int = 5, max_sqrt: int = 50, db_max_iter: int = 30,
                   theta_source: int = 0, out=None, workspace=None, tape_mats: int | None = None):
     """gradA = d<G, log A>/dA on the GPU (reverse mode of Algorithm 1).  Returns
-    (gradA, info dict of the forward pass run inside the call).
+    (gradA, info dict of the forward pass run inside the call).  Complex A, G give
+    gradA = L_log(A^H, G).
 
     ``tape_mats`` extra matrices lengthen the ring of taped inverses (default: room
     for 100 inverses in all), so that roots whose inverses are still in the ring are
     not replayed."""
     torch = _torch()
-    A = _as_matrix(A)
-    G = _as_matrix(G, "G")
+    A = _as_matrix(A, allow_complex=True)
+    G = _as_matrix(G, "G", allow_complex=True)
     n = A.shape[0]
-    if G.shape != A.shape or G.device != A.device:
-        raise ValueError("G must match A in shape and device")
-    gA = out if out is not None else torch.empty((n, n), dtype=torch.float64, device=A.device)
+    if G.shape != A.shape or G.device != A.device or G.dtype != A.dtype:
+        raise ValueError("G must match A in shape, dtype and device")
+    dt = LOGM_C128 if A.dtype == torch.complex128 else LOGM_R64
+    gA = out if out is not None else torch.empty((n, n), dtype=A.dtype, device=A.device)
     o = default_opts()
     o.k_max, o.max_sqrt, o.db_max_iter, o.theta_source = k_max, max_sqrt, db_max_iter, theta_source
     if tape_mats is None:
         tape_mats = max(0, 100 - 2 * db_max_iter)
-    need = backward_workspace_size(n, o, tape_mats)
+    need = backward_workspace_size(n, o, tape_mats, dt)
     if workspace is None:
         workspace = torch.empty(need, dtype=torch.uint8, device=A.device)
-    elif workspace.numel() * workspace.element_size() < backward_workspace_size(n, o):
+    elif workspace.numel() * workspace.element_size() < backward_workspace_size(n, o, 0, dt):
         raise ValueError("workspace smaller than logm_backward_workspace_size")
     info = LogmInfo()
-    rc = lib().logm_backward(LOGM_R64, n, _vp(A.data_ptr()), A.stride(0), _vp(G.data_ptr()), G.stride(0),
+    rc = lib().logm_backward(dt, n, _vp(A.data_ptr()), A.stride(0), _vp(G.data_ptr()), G.stride(0),
                              _vp(gA.data_ptr()), gA.stride(0), ctypes.byref(o), ctypes.byref(info),
                              _vp(workspace.data_ptr()), workspace.numel(), _stream_ptr(A))
     _check(rc, "logm_backward", info.status_detail)
@@ -394,6 +397,11 @@ def _autograd_function():
 
         @staticmethod
         def forward(ctx, A):
+            if A.dtype == torch.complex128:   # no taped pair for complex input
+                L, _ = logm(A)
+                ctx.save_for_backward(A)
+                ctx.tape = None
+                return L
             tape = Tape(A.shape[0], A.device)
             L, _ = logm_forward_taped(A, tape)
             ctx.tape = tape
@@ -401,6 +409,10 @@ def _autograd_function():
 
         @staticmethod
         def backward(ctx, gL):
+            if ctx.tape is None:
+                (A,) = ctx.saved_tensors
+                gA, _ = logm_backward(A, gL.contiguous())
+                return gA
             gA, _ = logm_backward_taped(gL.contiguous(), ctx.tape)
             ctx.tape = None
             return gA

@@ -1202,6 +1202,8 @@ const char* logm_version(void) { return "logm-mi355x 0.1 (gfx950)"; }
 // Complex input runs the real path on its 2n x 2n real representation; the workspace
 // adds that matrix and the real result.
 size_t complex_extra_bytes(int64_t n) { return 2 * align_up((size_t)(2 * n) * (size_t)(2 * n) * sizeof(double), 256); }
+// reverse mode: the representations of A and G and the real gradient
+size_t complex_bwd_bytes(int64_t n) { return 3 * align_up((size_t)(2 * n) * (size_t)(2 * n) * sizeof(double), 256); }
 
 int logm_workspace_size(int32_t dtype, int64_t n, const logm_opts* o, size_t* bytes) {
   if (n < 1 || n > (int64_t)1 << 20 || bytes == nullptr) return LOGM_EINVAL;
@@ -1264,6 +1266,11 @@ int logm_backward_workspace_size(int32_t dtype, int64_t n, const logm_opts* o, s
   if (o != nullptr) opts = *o;
   if (bytes == nullptr || n < 1 || n > (int64_t)1 << 20 || !opts_ok(opts)) return LOGM_EINVAL;
   if (dtype != LOGM_R64 && dtype != LOGM_C128) return LOGM_EINVAL;
+  if (dtype == LOGM_C128) {
+    const Plan p = make_plan(2 * n);
+    *bytes = p.total + bwd_extra_bytes(p, opts) + complex_bwd_bytes(n);
+    return LOGM_OK;
+  }
   const Plan p = make_plan(n);
   *bytes = p.total + bwd_extra_bytes(p, opts);
   return LOGM_OK;
@@ -1280,11 +1287,39 @@ int logm_backward(int32_t dtype, int64_t n, const void* A, int64_t lda, const vo
       lda < n || ldg < n || ldga < n)
     return LOGM_EINVAL;
   if (!opts_ok(opts)) return LOGM_EINVAL;
-  if (dtype == LOGM_C128) return LOGM_ENOTSUP;
+  if (dtype == LOGM_C128 && 2 * n > (int64_t)1 << 20) return LOGM_EINVAL;
   opts.balance = 0;   // the gradient of the unbalanced map (the same function)
   logm_info local{};
   logm_info& inf = (info != nullptr) ? *info : local;
   std::memset(&inf, 0, sizeof(inf));
+  if (dtype == LOGM_C128) {
+    // the real reverse mode at P = rep(A) with rep(G) gives rep(L_log(A^H, G)), since
+    // rep(A)^T = rep(A^H); the complex gradient is its left block column
+    const int64_t n2 = 2 * n;
+    const size_t cb = complex_bwd_bytes(n);
+    Call call(n2, ws, ws_bytes, stream, &opts, cb);
+    if (call.st.code != LOGM_OK) {
+      inf.status_detail = call.st.detail;
+      return call.st.code;
+    }
+    Ctx& c = call.c;
+    c.bytes -= cb;   // the representations live past the reverse-mode region
+    const size_t mb = cb / 3;
+    double* P = reinterpret_cast<double*>(c.base + c.bytes);
+    double* Gp = reinterpret_cast<double*>(c.base + c.bytes + mb);
+    double* R = reinterpret_cast<double*>(c.base + c.bytes + 2 * mb);
+    Status st = [&]() -> Status {
+      Status st;
+      HIPCK(launch_embed_complex(static_cast<const double*>(A), lda, (int)n, P, n2, c.s));
+      HIPCK(launch_embed_complex(static_cast<const double*>(G), ldg, (int)n, Gp, n2, c.s));
+      PROPAGATE(backward_r64(c, P, n2, Gp, n2, R, n2, opts, inf));
+      HIPCK(launch_extract_complex(R, n2, (int)n, static_cast<double*>(gradA), ldga, c.s));
+      HIPCK(hipStreamSynchronize(c.s));
+      return st;
+    }();
+    inf.status_detail = st.detail;
+    return st.code;
+  }
   Call call(n, ws, ws_bytes, stream, &opts);
   if (call.st.code != LOGM_OK) {
     inf.status_detail = call.st.detail;

@@ -135,7 +135,7 @@ def test_backward_argument_validation(lib):
     assert call(gA=None) == 1
     assert call(ldg=7) == 1
     assert call(ldga=7) == 1
-    assert call(dtype=1) == 2
+    assert call(dtype=1) == 3                          # complex: workspace of the 2n run
     o = lm.default_opts()
     o.k_max = 4
     assert call(opts=o) == 1

@@ -57,3 +57,37 @@ def test_complex_logm_strided_input(lm):
     big[:, :n] = torch.from_numpy(A).to("cuda:0")
     L, _ = lm.logm(big[:, :n])
     assert relf(L.cpu().numpy(), Lx) < 1e-11
+
+
+def test_complex_backward_vs_oracle_and_block_form(lm):
+    """gradA = L_log(A^H, G) for complex A: the real reverse mode on the
+    representation against the oracle's on the same 2n matrices, and against the
+    block form log([[A^H, G], [0, A^H]]) of the oracle's complex Algorithm 1."""
+    import torch
+
+    n = 24
+    A, _ = complex_matrix(n, 8300)
+    rng = np.random.default_rng(8301)
+    G = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    dev = torch.device("cuda:0")
+    gA, info = lm.logm_backward(torch.from_numpy(A).to(dev), torch.from_numpy(G).to(dev))
+    gA = gA.cpu().numpy()
+    gP, _ = oracle.logm_backward(real_representation(A), real_representation(G),
+                                 force={"s": info["s"], "k": info["k"], "db_iters": info["db_iters"]})
+    assert relf(gA, gP[:n, :n] + 1j * gP[n:, :n]) < 1e-12
+    ref = oracle.frechet_block(A.conj().T, G)
+    assert relf(gA, ref) < 1e-11
+
+
+def test_complex_autograd(lm):
+    import torch
+
+    n = 12
+    A, _ = complex_matrix(n, 8400)
+    dev = torch.device("cuda:0")
+    At = torch.from_numpy(A).to(dev).requires_grad_(True)
+    G = torch.from_numpy(np.random.default_rng(8401).standard_normal((n, n)) + 0j).to(dev)
+    L = lm.logm_autograd(At)
+    L.backward(G)
+    gA, _ = lm.logm_backward(torch.from_numpy(A).to(dev), G)
+    assert torch.equal(At.grad, gA)

@@ -28,3 +28,16 @@ def test_real_representation_logm_is_representation_of_logm(n, seed):
     # the block structure is kept to rounding
     assert np.abs(LP[:n, :n] - LP[n:, n:]).max() < 1e-12 * np.abs(LP).max()
     assert np.abs(LP[:n, n:] + LP[n:, :n]).max() < 1e-12 * np.abs(LP).max()
+
+
+def test_real_representation_gradient_is_complex_adjoint():
+    """The real reverse mode at P = rep(A) with rep(G) is rep(L_log(A^H, G)): checked
+    against the block form of the complex Frechet derivative."""
+    n = 7
+    A, _ = complex_matrix(n, 8500)
+    rng = np.random.default_rng(8501)
+    G = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    gP, _ = oracle.logm_backward(real_representation(A), real_representation(G))
+    ref = oracle.frechet_block(A.conj().T, G)
+    assert rel(gP[:n, :n] + 1j * gP[n:, :n], ref) < 1e-12
+    assert rel(gP, real_representation(ref)) < 1e-12
