@@ -228,6 +228,17 @@ int logm_normest_f64(int64_t n, const double* B2, int64_t ldb2, const double* B,
 int logm_balance_f64(int64_t n, const double* A, int64_t lda, double* B, int64_t ldb, double* d,
                      int32_t* sweeps, void* ws, size_t ws_bytes, void* stream);
 
+/* Launch-shape autotuner: for matrices padded like n, times the inversion of two
+ * synthetic n x n matrices (the shape of a Denman-Beavers iteration) with each
+ * candidate cap on the workgroups of the trailing-update GEMM that runs beside the
+ * panel factorization (96 .. 256), and keeps the fastest for all later calls of
+ * this process with that padded size (the compile-time default, overridable by
+ * LOGM_LOOKAHEAD_WGS at build time, applies until then).  *best_wgs (host) receives
+ * the cap, *best_ms (host, may be NULL) the time of one inversion pair.  ws as for
+ * logm_forward with the same n (NULL: allocated and freed).  Synchronises `stream`. */
+int logm_autotune(int64_t n, void* ws, size_t ws_bytes, void* stream, int32_t* best_wgs,
+                  double* best_ms);
+
 /* Host-side tables: the coefficients of scheme k (h and g rows j = 2..k on
  * P_2..P_{j+1}, concatenated; y on P_1..P_{k+2}), its order m_k and Theta_{m_k}.
  * Any output pointer may be NULL.  *nh receives the number of h (= g) values. */

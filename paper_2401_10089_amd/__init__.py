@@ -8,6 +8,7 @@ All computation happens in the HIP library ``liblogm.so`` (C ABI in
 from ._binding import (  # noqa: F401
     EXPORTS,
     BatchPlan,
+    autotune,
     balance,
     logm_batched,
     LIB_PATH,

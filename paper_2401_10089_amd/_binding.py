@@ -46,6 +46,7 @@ EXPORTS = (
     "logm_poly_f64",
     "logm_normest_f64",
     "logm_balance_f64",
+    "logm_autotune",
     "logm_scheme",
     "logm_profile_enable",
     "logm_profile_reset",
@@ -155,6 +156,7 @@ def load_library(path: str = LIB_PATH):
                                             ctypes.POINTER(_i32), _vp, _sz, _vp]),
         "logm_balance_f64": (ctypes.c_int, [_i64, _vp, _i64, _vp, _i64, _vp, ctypes.POINTER(_i32), _vp, _sz,
                                             _vp]),
+        "logm_autotune": (ctypes.c_int, [_i64, _vp, _sz, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_f64)]),
         "logm_scheme": (ctypes.c_int, [_i32, _i32, ctypes.POINTER(_f64), ctypes.POINTER(_f64),
                                        ctypes.POINTER(_f64), ctypes.POINTER(_i32), ctypes.POINTER(_i32),
                                        ctypes.POINTER(_f64)]),
@@ -530,6 +532,20 @@ def balance(A, workspace=None):
                                 _stream_ptr(A))
     _check(rc, "logm_balance_f64")
     return B, d, sw.value
+
+
+def autotune(n: int, device=None, workspace=None):
+    """Choose the trailing-update workgroup cap for size n by timing (see
+    logm_autotune); returns (cap, ms per inversion pair)."""
+    torch = _torch()
+    device = device or torch.device("cuda:0")
+    ws = workspace if workspace is not None else torch.empty(workspace_size(n), dtype=torch.uint8, device=device)
+    best = _i32(0)
+    ms = _f64(0)
+    rc = lib().logm_autotune(n, _vp(ws.data_ptr()), ws.numel(),
+                             _vp(torch.cuda.current_stream(device).cuda_stream), ctypes.byref(best), ctypes.byref(ms))
+    _check(rc, "logm_autotune")
+    return best.value, ms.value
 
 
 def sqrtm(A, db_max_iter: int = 30, workspace=None):

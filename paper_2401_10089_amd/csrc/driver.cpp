@@ -21,6 +21,8 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "algo.hpp"
@@ -38,6 +40,15 @@ constexpr int kMats = 11;
 #define LOGM_LOOKAHEAD_WGS 192
 #endif
 constexpr int kLookaheadWgs = LOGM_LOOKAHEAD_WGS;   // trailing-update workgroups beside a panel
+
+// The cap per padded size chosen by logm_autotune (process-wide); the default otherwise.
+std::mutex g_cap_mu;
+std::map<int, int> g_cap;
+int lookahead_wgs(int n_pad) {
+  std::lock_guard<std::mutex> lk(g_cap_mu);
+  const auto it = g_cap.find(n_pad);
+  return it == g_cap.end() ? kLookaheadWgs : it->second;
+}
 
 // ------------------------------------------------------------ constants ---
 struct Scheme {
@@ -384,7 +395,7 @@ Status gje_invert(Ctx& c, int nmat, const double* const src[2], double* fin[2]) 
       HIPCK(hipEventRecord(c.ev_pan, c.side));
       // the rest of the update runs beside the next panel's factorization, which is
       // the critical path: cap its workgroups so that the panel kernels find free CUs
-      PROPAGATE(outer_update(c, a, n_lo, n_hi, false, kLookaheadWgs / a.nmat));
+      PROPAGATE(outer_update(c, a, n_lo, n_hi, false, lookahead_wgs(c.p.n_pad) / a.nmat));
     } else {
       PROPAGATE(outer_update(c, a, 0, np, true));
     }
@@ -1547,6 +1558,65 @@ int logm_balance_f64(int64_t n, const double* A, int64_t lda, double* B, int64_t
     int h = 0;
     PROPAGATE(sync_read(c, &h, sw, sizeof(int)));
     if (sweeps != nullptr) *sweeps = h;
+    return st;
+  }();
+  return st.code;
+}
+
+int logm_autotune(int64_t n, void* ws, size_t ws_bytes, void* stream, int32_t* best_wgs,
+                  double* best_ms) {
+  if (n < 1 || n > (int64_t)1 << 20 || best_wgs == nullptr) return LOGM_EINVAL;
+  Call call(n, ws, ws_bytes, stream);
+  if (call.st.code != LOGM_OK) return call.st.code;
+  Ctx& c = call.c;
+  Status st = [&]() -> Status {
+    Status st;
+    const int np = c.p.n_pad;
+    HIPCK(launch_fill_test_matrix(c.mat(0), (int)n, np, 12345u, c.s));
+    HIPCK(launch_fill_test_matrix(c.mat(1), (int)n, np, 67890u, c.s));
+    const double* src[2] = {c.mat(0), c.mat(1)};
+    double* fin[2] = {nullptr, nullptr};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCK(hipEventCreate(&e0));
+    HIPCK(hipEventCreate(&e1));
+    const int cand[] = {96, 128, 160, 192, 224, 256};
+    int best = kLookaheadWgs;
+    float best_t = 0.0f;
+    for (int wgs : cand) {
+      {
+        std::lock_guard<std::mutex> lk(g_cap_mu);
+        g_cap[np] = wgs;
+      }
+      Status s1 = gje_invert(c, 2, src, fin);   // warm-up
+      if (s1.code != LOGM_OK) st = s1;
+      if (hipEventRecord(e0, c.s) != hipSuccess) st.code = LOGM_EHIP;
+      for (int r = 0; r < 2 && st.code == LOGM_OK; ++r) {
+        Status s2 = gje_invert(c, 2, src, fin);
+        if (s2.code != LOGM_OK) st = s2;
+      }
+      float t = 0.0f;
+      if (st.code == LOGM_OK && (hipEventRecord(e1, c.s) != hipSuccess ||
+                                 hipEventSynchronize(e1) != hipSuccess ||
+                                 hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+        st.code = LOGM_EHIP;
+      if (st.code != LOGM_OK) break;
+      if (best_t == 0.0f || t < best_t) {
+        best_t = t;
+        best = wgs;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    {
+      std::lock_guard<std::mutex> lk(g_cap_mu);
+      if (st.code == LOGM_OK)
+        g_cap[np] = best;
+      else
+        g_cap.erase(np);
+    }
+    if (st.code == LOGM_OK) PROPAGATE(check_gje_err(c, 2));
+    *best_wgs = best;
+    if (best_ms != nullptr) *best_ms = best_t / 2.0;
     return st;
   }();
   return st.code;

@@ -383,6 +383,25 @@ __global__ void extract_complex_kernel(const double* R, int64_t ldr, int n, doub
   }
 }
 
+// Well-conditioned test matrix for timing runs: I + 0.5 u_ij / sqrt(n) with u_ij in
+// [-1, 1) from an integer hash of (seed, i, j); identity on the pad.
+__global__ void fill_test_matrix_kernel(double* M, int n, int n_pad, unsigned seed) {
+  const int i = blockIdx.y;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n_pad; j += gridDim.x * blockDim.x) {
+    double v = (i == j) ? 1.0 : 0.0;
+    if (i < n && j < n) {
+      unsigned h = seed ^ (0x9e3779b9u * (unsigned)(i + 1)) ^ (0x85ebca6bu * (unsigned)(j + 7));
+      h ^= h >> 16;
+      h *= 0x7feb352du;
+      h ^= h >> 15;
+      h *= 0x846ca68bu;
+      h ^= h >> 16;
+      v += 0.5 * ((double)h * (2.0 / 4294967296.0) - 1.0) / sqrt((double)n);
+    }
+    M[(int64_t)i * n_pad + j] = v;
+  }
+}
+
 inline dim3 row_grid(int n, int rows) { return dim3((unsigned)std::min(8, (n + 255) / 256), (unsigned)rows); }
 
 }  // namespace
@@ -458,6 +477,11 @@ hipError_t launch_embed_complex(const double* A, int64_t lda, int n, double* P, 
 hipError_t launch_extract_complex(const double* R, int64_t ldr, int n, double* L, int64_t ldl,
                                   hipStream_t s) {
   hipLaunchKernelGGL(extract_complex_kernel, row_grid(n, n), dim3(256), 0, s, R, ldr, n, L, ldl);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_test_matrix(double* M, int n, int n_pad, unsigned seed, hipStream_t s) {
+  hipLaunchKernelGGL(fill_test_matrix_kernel, row_grid(n_pad, n_pad), dim3(256), 0, s, M, n, n_pad, seed);
   return hipGetLastError();
 }
 

@@ -178,6 +178,10 @@ hipError_t launch_embed_complex(const double* A, int64_t lda, int n, double* P, 
 hipError_t launch_extract_complex(const double* R, int64_t ldr, int n, double* L, int64_t ldl,
                                   hipStream_t s);
 
+// Padded n_pad x n_pad test matrix I + 0.5 u / sqrt(n) (u hashed from seed), identity
+// on the pad; for timing runs only.
+hipError_t launch_fill_test_matrix(double* M, int n, int n_pad, unsigned seed, hipStream_t s);
+
 // dst = scale * src^T for the n x n blocks (dst must not overlap src).
 hipError_t launch_transpose(const double* src, int64_t lds, double* dst, int64_t ldd, int n,
                             double scale, hipStream_t s);
