@@ -166,10 +166,11 @@ int logm_backward_taped(int32_t dtype, int64_t n, const void* G, int64_t ldg, vo
 /* ---- batched path: many small matrices in one launch ---- */
 
 /* Workspace bytes for logm_batched_f64 over `batch` matrices of size n_i <= n_max
- * <= 128: 13 buffers of 64 x 64 (n_max <= 64) or 128 x 128 doubles per workgroup
- * resident on the current device, plus 256 bytes of queue counters; it does not
- * grow with the batch beyond the device's resident workgroups.  total_elems is
- * validated only. */
+ * <= 128: 13 buffers of 64 x 64 doubles per resident workgroup of the n <= 64 class,
+ * plus (n_max > 64) 13 buffers of 128 x 128 doubles per resident workgroup of the
+ * 64 < n <= 128 class (the classes run concurrently), plus 256 bytes of queue
+ * counters; it does not grow with the batch beyond the device's resident
+ * workgroups.  total_elems is validated only. */
 int logm_batched_workspace_size(int32_t batch, int64_t total_elems, int32_t n_max, size_t* bytes);
 
 /* L_i = log(A_i), i < batch, by Algorithm 1 with every decision (roots, estimates,

@@ -19,6 +19,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 
 #include "algo.hpp"
 #include "common.hpp"
@@ -661,12 +663,54 @@ int class_blocks() {
 
 }  // namespace
 
-size_t batched_workspace_bytes(int batch, int n_max) {
-  const size_t small = (size_t)std::min(batch, class_blocks<1, 16>()) * NBUF * 64 * 64;
-  const size_t large =
-      (n_max > 64) ? (size_t)std::min(batch, class_blocks<2, 16>()) * NBUF * 128 * 128 : 0;
-  return std::max(small, large) * sizeof(double) + 256;
+// The two classes run concurrently (the small one on a second stream, forked and
+// joined with events, so the call stays capturable), each in its own region.
+size_t class_region_bytes(int batch, int nmax_class, int blocks) {
+  return ((size_t)std::min(batch, blocks) * NBUF * nmax_class * nmax_class * sizeof(double) + 255) /
+         256 * 256;
 }
+
+size_t batched_workspace_bytes(int batch, int n_max) {
+  const size_t small = class_region_bytes(batch, 64, class_blocks<1, 16>());
+  const size_t large = (n_max > 64) ? class_region_bytes(batch, 128, class_blocks<2, 16>()) : 0;
+  return small + large + 256;
+}
+
+namespace {
+// Second stream and fork/join events per device, created on first use.
+struct ForkRes {
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+std::mutex g_fork_mu;
+std::map<int, ForkRes> g_fork;
+
+// Creates nothing while `s` is being captured (the first call on a device then
+// runs the classes one after the other).
+bool fork_res(ForkRes& r, hipStream_t s) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  std::lock_guard<std::mutex> lk(g_fork_mu);
+  ForkRes& f = g_fork[dev];
+  if (f.side == nullptr) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+      return false;
+    if (hipStreamCreateWithFlags(&f.side, hipStreamNonBlocking) != hipSuccess) {
+      f.side = nullptr;
+      return false;
+    }
+    if (hipEventCreateWithFlags(&f.fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&f.join, hipEventDisableTiming) != hipSuccess) {
+      (void)hipStreamDestroy(f.side);
+      f = ForkRes{};
+      return false;
+    }
+  }
+  r = f;
+  return true;
+}
+}  // namespace
 
 hipError_t launch_batched_logm(int batch, int n_max, const int* dims, const int64_t* offsets,
                                const double* A, double* L, int* status, void* ws, size_t ws_bytes,
@@ -675,19 +719,16 @@ hipError_t launch_batched_logm(int batch, int n_max, const int* dims, const int6
                                const double (*y)[7], hipStream_t s) {
   const int nb_small = std::min(batch, class_blocks<1, 16>());
   const int nb_large = std::min(batch, class_blocks<2, 16>());
-  if (ws_bytes < 256) return hipErrorInvalidValue;
-  const size_t data = (ws_bytes - 256) / 256 * 256;   // the counters stay aligned
-  if ((size_t)nb_small * NBUF * 64 * 64 * sizeof(double) > data ||
-      (n_max > 64 && (size_t)nb_large * NBUF * 128 * 128 * sizeof(double) > data))
-    return hipErrorInvalidValue;
+  const size_t small_bytes = class_region_bytes(batch, 64, class_blocks<1, 16>());
+  const size_t large_bytes = (n_max > 64) ? class_region_bytes(batch, 128, class_blocks<2, 16>()) : 0;
+  if (ws_bytes < small_bytes + large_bytes + 256) return hipErrorInvalidValue;
   BatchArgs a{};
   a.batch = batch;
   a.dims = dims;
   a.offsets = offsets;
   a.A = A;
   a.L = L;
-  a.ws = static_cast<double*>(ws);
-  int* counters = reinterpret_cast<int*>(static_cast<char*>(ws) + data);
+  int* counters = reinterpret_cast<int*>(static_cast<char*>(ws) + small_bytes + large_bytes);
   a.status = status;
   a.total_elems = total_elems;
   a.k_max = k_max;
@@ -703,15 +744,31 @@ hipError_t launch_batched_logm(int batch, int n_max, const int* dims, const int6
     for (int c = 0; c < 7; ++c) a.sch[i].y[c] = y[i][c];
   }
   hipLaunchKernelGGL(batched_reset_kernel, dim3(1), dim3(64), 0, s, counters);
-  a.counter = counters;
-  a.report_invalid = 1;
-  hipLaunchKernelGGL((batched_logm_kernel<1, 16>), dim3(nb_small), dim3(256), 0, s, a);
-  if (n_max > 64) {
-    a.counter = counters + 1;
-    a.report_invalid = 0;
-    hipLaunchKernelGGL((batched_logm_kernel<2, 16>), dim3(nb_large), dim3(512), 0, s, a);
+  BatchArgs as = a, al = a;
+  as.ws = static_cast<double*>(ws);
+  as.counter = counters;
+  as.report_invalid = 1;
+  if (n_max <= 64) {
+    hipLaunchKernelGGL((batched_logm_kernel<1, 16>), dim3(nb_small), dim3(256), 0, s, as);
+    return hipGetLastError();
   }
-  return hipGetLastError();
+  al.ws = reinterpret_cast<double*>(static_cast<char*>(ws) + small_bytes);
+  al.counter = counters + 1;
+  al.report_invalid = 0;
+  ForkRes f;
+  if (!fork_res(f, s)) {   // one stream: the classes one after the other
+    hipLaunchKernelGGL((batched_logm_kernel<2, 16>), dim3(nb_large), dim3(512), 0, s, al);
+    hipLaunchKernelGGL((batched_logm_kernel<1, 16>), dim3(nb_small), dim3(256), 0, s, as);
+    return hipGetLastError();
+  }
+  hipError_t e;
+  if ((e = hipEventRecord(f.fork, s)) != hipSuccess) return e;
+  if ((e = hipStreamWaitEvent(f.side, f.fork, 0)) != hipSuccess) return e;
+  hipLaunchKernelGGL((batched_logm_kernel<2, 16>), dim3(nb_large), dim3(512), 0, s, al);
+  hipLaunchKernelGGL((batched_logm_kernel<1, 16>), dim3(nb_small), dim3(256), 0, f.side, as);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = hipEventRecord(f.join, f.side)) != hipSuccess) return e;
+  return hipStreamWaitEvent(s, f.join, 0);
 }
 
 }  // namespace logm

@@ -195,14 +195,15 @@ hipError_t launch_scale_out(const double* src, int64_t ld, double* dst, int64_t 
 
 // ---------------------------------------------------------------- batched --
 // Workspace bytes of the batched path: 13 buffers of the size class's largest
-// matrix per resident workgroup of the device (small class n <= 64 always, large
-// class when n_max > 64; they run one after the other and share the space), plus
-// two work-queue counters.
+// matrix per resident workgroup of the device, one region per class (n <= 64
+// always, 64 < n <= 128 when n_max > 64; the classes run concurrently), plus two
+// work-queue counters.
 size_t batched_workspace_bytes(int batch, int n_max);
 // Persistent launches over the batch (n_i <= 128): L_i = log(A_i) by Algorithm 1
 // on the device, one workgroup per matrix from a work queue; a counter-reset kernel,
-// the n <= 64 class, then (n_max > 64) the 64 < n <= 128 class.  No host
-// synchronisation and no memset, so the sequence can be captured in a graph.  h, g:
+// then the 64 < n <= 128 class on `s` beside the n <= 64 class on a second stream
+// (forked and joined with events).  No host synchronisation and no memset, so the
+// sequence can be captured in a graph.  h, g:
 // [scheme 1, 2, 3, 5][row j - 2][P_2..P_{j+1}], y: [scheme][P_1..P_{k+2}].
 hipError_t launch_batched_logm(int batch, int n_max, const int* dims, const int64_t* offsets,
                                const double* A, double* L, int* status, void* ws, size_t ws_bytes,
