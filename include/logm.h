@@ -13,9 +13,12 @@
  *     degree-selection procedure after Algorithm 1),
  *   - log(I+B) ~ -S(-B) (eqs. Taylor_log, logipASTM) evaluated as the
  *     degree-optimal computation graph of eq. five_mult_degopt (schemes with
- *     k = 1, 2, 3 and 5 matrix products; k = 5 uses Table 1),
+ *     k = 1 to 5 matrix products; k = 5 uses Table 1, k = 4 a fit of the same form
+ *     with b_i = 1/i for i <= 14, since Table 2 gives its order and Theta_4 but no
+ *     coefficients),
  *   - the squaring phase L = 2^s L.
- * Balancing (the pre- and post-processing steps of Algorithm 1) is not applied.
+ * Balancing (the pre- and post-processing steps of Algorithm 1) is optional
+ * (logm_opts.balance, forward entry points only) and off by default.
  *
  * Conventions (all entry points):
  *   - Matrices are row-major with a leading dimension ld >= n (elements between
@@ -59,7 +62,7 @@ typedef enum { LOGM_R64 = 0, LOGM_C128 = 1 } logm_dtype;
 
 /* Options of Algorithm 1 (Section 6). */
 typedef struct logm_opts {
-  int32_t k_max;        /* largest scheme (matrix products) allowed: 1, 2, 3 or 5 (default 5) */
+  int32_t k_max;        /* largest scheme (matrix products) allowed: 1 to 5 (default 5) */
   int32_t max_sqrt;     /* maximum number of square roots, "maxiter" (default 50, at most 64) */
   int32_t db_max_iter;  /* maximum Denman-Beavers iterations per root (default 30) */
   int32_t theta_source; /* 0: Theta values of Table 2 as printed (default);
@@ -211,7 +214,7 @@ int logm_sqrt_f64(int64_t n, const double* A, int64_t lda, double* X, int64_t ld
                   int32_t db_max_iter, int32_t* iters, void* ws, size_t ws_bytes, void* stream);
 
 /* L = -2^s S_k(-B) with P_3 = B2 = B*B supplied (eq. five_mult_degopt with the
- * saved product of eq. AI2); k in {1, 2, 3, 5}, 0 <= s <= 64. */
+ * saved product of eq. AI2); 1 <= k <= 5, 0 <= s <= 64. */
 int logm_poly_f64(int64_t n, int32_t k, int32_t s, const double* B, int64_t ldb, const double* B2,
                   int64_t ldb2, double* L, int64_t ldl, void* ws, size_t ws_bytes, void* stream);
 

@@ -26,11 +26,15 @@ explicit column sums, and the 1-norm estimator as a Python loop.
 Readings of points where the paper is silent or garbled (each is restated in
 DESIGN.md):
 
-R1  Schemes shipped: k in {1, 2, 3, 5}.  The paper prints coefficients only for
-    k = 5 (Table 1); k = 1, 2 are the Taylor polynomials T_2, T_4 written in the
-    degree-optimal form; k = 3 is the three-product scheme eq. eqP8pol solved for
-    T_8 (Section 2.2).  k = 4 and k = 6..9 are not printed, so "m_9" in
-    Algorithm 1 is read as m_{k_max} = m_5 = 14 with Theta_5.
+R1  Schemes shipped: k in {1, 2, 3, 4, 5}.  The paper prints coefficients only
+    for k = 5 (Table 1); k = 1, 2 are the Taylor polynomials T_2, T_4 written in
+    the degree-optimal form; k = 3 is the three-product scheme eq. eqP8pol solved
+    for T_8 (Section 2.2); k = 4 (Table 2: order 14+, degree 16, Theta_4 = 9.31e-2,
+    no coefficients printed) is our own fit in the same degree-optimal form: b_i =
+    1/i for i <= 14, b_15 and b_16 on the branch of largest Theta_4 (0.0936 when
+    recomputed by eq. theta_Eb, at or above the printed 9.31e-2, which is used), made
+    by ``oracle/fit_k4.py``.  k = 6..9 are not built, so "m_9" in Algorithm 1 is
+    read as m_{k_max} = m_5 = 14 with Theta_5.
 R2  k = 3: eq. eqP8pol has two distinct real solutions with c_4 > 0; the one with
     the smaller coefficients (e_0 ~ 0.729) is used (its stability indicator,
     eq. stability_error, is the smaller of the two).
@@ -102,7 +106,7 @@ TABLE2 = {
 }
 
 # Schemes with coefficients available (reading R1).
-SHIPPED_K = (1, 2, 3, 5)
+SHIPPED_K = (1, 2, 3, 4, 5)
 
 # tabmin_im from the degree-selection procedure after Algorithm 1 (1-based in k).
 TABMIN_IM = (1, 2, 3, 4, 4, 5, 5, 6, 6)
@@ -127,6 +131,22 @@ _TABLE1_G = {
 }
 _TABLE1_Y = (0.0, 1.0, 5.065546620208965e-01, 3.832512052972577e-01,
              1.088307723749078e+00, 2.787461897212877e-01, 8.157421998489228e-01)
+
+
+# k = 4 (reading R1): coefficients of our own fit (oracle/fit_k4.py output), rows
+# j = 2..4 acting on P_2..P_{j+1}; y_1..y_6 acting on P_1..P_6.
+_K4_H = {
+    2: (-0.00796402295873935, -1.196175325283278),
+    3: (-0.8020687408541339, -1.160687121448432, -1.3144855920188723),
+    4: (-0.5271367962617531, -0.2805091819212849, -1.4479288324742332, -0.13817707964654286),
+}
+_K4_G = {
+    2: (-0.9282620550832184, -0.8598030880069331),
+    3: (-0.20776693015026781, 0.6911260475049842, -1.0119839425008987),
+    4: (-0.38678557796025353, 0.2517180068065143, -1.2588914341240445, 0.15709317865130096),
+}
+_K4_Y = (0.0, 1.0, 0.48615543620029184, 0.3864758392414079, 0.3371503075537971,
+         -0.22167167535004684)
 
 
 class OracleError(RuntimeError):
@@ -180,6 +200,8 @@ def scheme_coefficients(k: int):
         return {2: (0.0, 1.0)}, {2: (1.0 / 3.0, 0.25)}, (0.0, 1.0, 0.5, 1.0)
     if k == 3:
         return _k3_coefficients()
+    if k == 4:
+        return dict(_K4_H), dict(_K4_G), tuple(_K4_Y)
     if k == 5:
         return dict(_TABLE1_H), dict(_TABLE1_G), tuple(_TABLE1_Y)
     raise ValueError(f"no coefficients for k={k}")

@@ -30,18 +30,17 @@ __host__ __device__ inline ThetaTable theta_table(int source) {
   return t;
 }
 
-// Schemes available up to k_max, increasing (shipped: 1, 2, 3, 5).
+// Schemes available up to k_max, increasing (shipped: 1 to 5).
 struct SchemeSet {
-  int k[4];
+  int k[5];
   int n;
 };
 
 __host__ __device__ inline SchemeSet scheme_set(int k_max) {
   SchemeSet s;
   s.n = 0;
-  const int all[4] = {1, 2, 3, 5};
-  for (int i = 0; i < 4; ++i)
-    if (all[i] <= k_max) s.k[s.n++] = all[i];
+  for (int k = 1; k <= 5; ++k)
+    if (k <= k_max) s.k[s.n++] = k;
   return s;
 }
 

@@ -503,7 +503,7 @@ struct BatchArgs {
   int64_t total_elems;      // elements of A and L
   int report_invalid;       // this launch reports blocks outside the arrays
   int k_max, max_sqrt, db_max_iter, theta_source;
-  DevScheme sch[4];         // schemes 1, 2, 3, 5
+  DevScheme sch[5];         // schemes k = 1 .. 5
 };
 
 template <int RA, int CW>
@@ -588,7 +588,7 @@ __global__ __launch_bounds__(256 * RA, 4) void batched_logm_kernel(BatchArgs a) 
     if (code == LOGM_OK) {
       n2 = wg_norm1<N>(sh.red, B2, n);
       k = dev_select_degree(sh, B2, B, n, n1, n2, a.k_max, a.theta_source, &dec);
-      const DevScheme& S = a.sch[k == 5 ? 3 : k - 1];
+      const DevScheme& S = a.sch[k - 1];
       const double scale = -ldexp(1.0, s);
       // accumulators: L_j, R_j (j = 2..k) and Z in buffers 4-6, 8-12 and A2's
       auto acc = [&](int t) -> double* { return (t < 3) ? buf(4 + t) : ((t < 8) ? buf(5 + t) : A2); };
@@ -735,7 +735,7 @@ hipError_t launch_batched_logm(int batch, int n_max, const int* dims, const int6
   a.max_sqrt = max_sqrt;
   a.db_max_iter = db_max_iter;
   a.theta_source = theta_source;
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < 5; ++i) {
     for (int r = 0; r < 4; ++r)
       for (int c = 0; c < 5; ++c) {
         a.sch[i].h[r][c] = h[i][r][c];

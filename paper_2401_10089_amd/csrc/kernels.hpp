@@ -204,7 +204,7 @@ size_t batched_workspace_bytes(int batch, int n_max);
 // then the 64 < n <= 128 class on `s` beside the n <= 64 class on a second stream
 // (forked and joined with events).  No host synchronisation and no memset, so the
 // sequence can be captured in a graph.  h, g:
-// [scheme 1, 2, 3, 5][row j - 2][P_2..P_{j+1}], y: [scheme][P_1..P_{k+2}].
+// [scheme k - 1 for k = 1..5][row j - 2][P_2..P_{j+1}], y: [scheme][P_1..P_{k+2}].
 hipError_t launch_batched_logm(int batch, int n_max, const int* dims, const int64_t* offsets,
                                const double* A, double* L, int* status, void* ws, size_t ws_bytes,
                                int64_t total_elems, int k_max, int max_sqrt, int db_max_iter,

@@ -48,11 +48,11 @@ def db_iters(packed, s):
     return [(packed >> (5 * r)) & 31 for r in range(min(s, 6))]
 
 
-def check_against_oracle(Lg, st, A, tol=TOL):
+def check_against_oracle(Lg, st, A, tol=TOL, k_max=5):
     code, s, k, packed = (int(v) for v in st)
     assert code == 0, ("status", code)
     its = db_iters(packed, s)
-    Lo, io = oracle.logm(A)
+    Lo, io = oracle.logm(A, k_max=k_max)
     same = (s, k, its) == (io["s"], io["k"], io["db_iters"][:6])
     if not same:
         # a threshold decided the other way by rounding: replay the device's
@@ -122,6 +122,22 @@ def test_batched_repeatable(lm):
     assert (s1 == s2).all()
     for a, b in zip(L1, L2):
         assert np.array_equal(a, b)
+
+
+def test_batched_k4_selected_and_kmax4(lm):
+    """Matrices near the identity take the four-product scheme on the device; with
+    k_max = 4 every matrix runs with k <= 4 and more roots (disk matrices, whose
+    root counts stay within the six the status word records for a replay)."""
+    mats = [disk_matrix(n, 300 + n, rho) for n in (7, 40, 64, 90, 128) for rho in (0.05, 0.09)]
+    L, st = run_batch(lm, mats)
+    for Lg, s, A in zip(L, st, mats):
+        check_against_oracle(Lg, s, A)
+    assert (st[:, 2] == 4).sum() >= 8
+    mats = [disk_matrix(n, 500 + n, rho) for n in (9, 33, 64, 100, 128) for rho in (0.5, 0.8)]
+    L, st = run_batch(lm, mats, k_max=4)
+    for Lg, s, A in zip(L, st, mats):
+        check_against_oracle(Lg, s, A, k_max=4)
+    assert (st[:, 2] <= 4).all()
 
 
 def test_batched_graph_capture_replays(lm):

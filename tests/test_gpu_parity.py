@@ -149,7 +149,7 @@ def test_sqrt_spd():
 
 
 # ------------------------------------------------------------- polynomial -
-@pytest.mark.parametrize("k", [1, 2, 3, 5])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
 @pytest.mark.parametrize("n,s", [(1, 0), (64, 0), (100, 3), (257, 1)])
 def test_poly_matches_oracle(k, n, s):
     rng = np.random.default_rng(100 * k + n)
@@ -207,7 +207,7 @@ def test_logm_rotscale_vs_oracle_and_exact(n, seed):
     A, Lx = rotscale_matrix(n, seed)
     Lg, info, same = compare_with_oracle(A)
     assert relf(Lg, Lx) < 1e-11
-    assert info["k"] in (1, 2, 3, 5)
+    assert info["k"] in (1, 2, 3, 4, 5)
 
 
 def test_logm_rotscale1024():
@@ -255,7 +255,7 @@ def test_logm_graph_fp32_n8192_vs_exact():
     assert e_x32 < TOL_GRAPH_FP32
 
 
-@pytest.mark.parametrize("kmax", [1, 2, 3])
+@pytest.mark.parametrize("kmax", [1, 2, 3, 4])
 def test_logm_smaller_kmax(kmax):
     """Small k_max forces many roots (s = 26 for k_max = 1 here); the saved product
     B^2 = A_2 - 2X + I then cancels to about u/||B|| relative accuracy, which bounds
@@ -272,6 +272,15 @@ def test_logm_smaller_kmax(kmax):
     if (info["s"], info["k"], info["db_iters"]) == (io["s"], io["k"], io["db_iters"]):
         assert relf(host(L), Lo) < tol
     assert relf(host(L), ref) < tol
+
+
+@pytest.mark.parametrize("n,rho", [(64, 0.05), (200, 0.09), (333, 0.12)])
+def test_logm_selects_k4(n, rho):
+    """||A - I|| just above Theta_4's neighbourhood: no root is taken and the four-product
+    scheme (our fit, reading R1) is selected on both sides."""
+    A = disk_matrix(n, 31, rho)
+    Lg, info, same = compare_with_oracle(A)
+    assert same and info["s"] == 0 and info["k"] == 4
 
 
 def test_logm_closed_forms():

@@ -208,7 +208,7 @@ def test_k3_equals_paterson_stockmeyer():
 def test_degrees_of_freedom_layout():
     """Section 3: k^2+4k+2 coefficients in the full form, k^2+2k-2 free ones after the
     normalisation theorem, the conjecture and y_1 = 0, y_2 = 1."""
-    for k in (2, 3, 5):
+    for k in (2, 3, 4, 5):
         h, g, y = scheme_coefficients(k)
         stored = sum(len(v) for v in h.values()) + sum(len(v) for v in g.values()) + len(y)
         assert stored == k * k + 2 * k       # rows j=2..k on P_2..P_{j+1}, plus y
@@ -245,7 +245,7 @@ def test_k3_root_choice_by_stability_indicator():
     assert abs(y[3] - 0.7290085258759623) < 1e-12
 
 
-@pytest.mark.parametrize("k", [1, 2, 3, 5])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
 def test_scalar_backward_error_at_theta(k):
     """eq. Des_Eb on the scalar case: |exp(-S(-x)) - 1 - x| / |x| <= ~u at |x| = Theta."""
     mpmath.mp.dps = 50
@@ -258,3 +258,63 @@ def test_scalar_backward_error_at_theta(k):
         delta = mpmath.exp(-S) - 1 - x
         worst = max(worst, float(abs(delta) / abs(x)))
     assert worst <= 1.2 * U, worst / U
+
+
+# ------------------------------------------------------- k = 4 (own fit) ---
+def test_k4_fit_matches_taylor_to_order_14():
+    """Reading R1: the k = 4 scheme (our fit, the paper prints none) is degree 16 with
+    b_i = 1/i for i <= 14 (Table 2: order 14+) within a few u after rounding every
+    coefficient to double, and the approximated terms 15, 16 obey the paper's
+    |(1/i - b_i) i| <= 1 condition."""
+    b = expand_exact(4)
+    assert len(b) - 1 == 16 and b[0] == 0 and b[1] == 1
+    for i in range(2, 15):
+        assert abs((b[i] - Fraction(1, i)) * i) <= 8 * U, (i, float((b[i] - Fraction(1, i)) * i / U))
+    for i in (15, 16):
+        e = abs(float((Fraction(1, i) - b[i]) * i))
+        assert 1e-3 < e <= 1.0, (i, e)   # approximated, not matched
+
+
+def test_k4_theta_recomputed_not_below_printed():
+    """Theta_4 of eq. theta_Eb recomputed from the fitted coefficients is at least the
+    printed 9.31e-2 of Table 2 (so the printed threshold is safe for this polynomial)
+    and within 1% of it."""
+    mpmath.mp.dps = 40
+    b = expand_exact(4)
+    c = backward_series(b, 120)
+    assert max(abs(c[i]) for i in range(2, 15)) < 1e-14   # orders <= 14 matched
+    th = theta_from_series(c, 14)
+    printed = oracle.TABLE2[4][1]
+    assert th >= printed, th
+    assert (th - printed) / printed < 0.01, th
+    # and it beats the plain Taylor T_14 bound ((15 u)^(1/14) ~ 0.0879)
+    assert th > (15 * U) ** (1 / 14)
+
+
+def test_k4_rounding_indicator_small():
+    """eq. stability_error for k = 4: the expansion evaluated in double rounding stays
+    within a few u of 1/i on the matched orders (coefficients of modulus <= 1.5)."""
+    h, g, y = scheme_coefficients(4)
+    assert max(abs(v) for row in list(h.values()) + list(g.values()) for v in row) < 1.5
+    bt = expand_float(4)
+    assert max(abs(bt[i] - 1.0 / i) * i for i in range(1, 15)) < 16 * U
+
+
+def test_k4_matrix_accuracy_at_theta():
+    """On a nonnormal 12x12 matrix with ||x||_1 = Theta_4 the four-product scheme gives
+    -log(I - x) to a few u (reference: the series sum_i x^i / i summed to 89 terms in
+    40-digit arithmetic)."""
+    rng = np.random.default_rng(44)
+    n = 12
+    x = np.triu(rng.standard_normal((n, n)), 1) + np.diag(rng.uniform(-1, 1, n))
+    x *= oracle.TABLE2[4][1] / np.abs(x).sum(axis=0).max()
+    z = oracle.eval_scheme(4, x, x @ x)
+    mpmath.mp.dps = 40
+    X = mpmath.matrix(x.tolist())
+    term = mpmath.eye(n)
+    ref = mpmath.zeros(n, n)
+    for i in range(1, 90):
+        term = term * X
+        ref += term / i
+    ref = np.array(ref.tolist(), dtype=float)
+    assert np.linalg.norm(z - ref) / np.linalg.norm(ref) < 20 * U
