@@ -542,7 +542,7 @@ __device__ __forceinline__ void mm32x64(const double (*As)[LDA], const double (*
 // Inner Gauss-Jordan step on the panel, IU_ROWS rows per workgroup (see the file
 // comment): C U = Acol and G L = C are solved by 16-column block substitution with
 // explicit inverses of the 16 x 16 diagonal blocks only, then out = base - G R.
-__global__ __launch_bounds__(256) void inner_update_kernel(GjeArgs A) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void inner_update_kernel(GjeArgs A) {
   // LU and Di/Ts live during the solves, Rs during the output chunks: the regions
   // alias so that two workgroups fit in one CU's LDS
   __shared__ __attribute__((aligned(16))) double s_a[NB * LDA];
@@ -632,40 +632,61 @@ __global__ __launch_bounds__(256) void inner_update_kernel(GjeArgs A) {
   }
   __syncthreads();
 
-  // C U = Acol, blocks left to right: C_b = (Acol_b - C_{<b} U_{<b,b}) inv(U_bb)
+  // C U = Acol, blocks left to right: C_b = (Acol_b - C_{<b} U_{<b,b}) inv(U_bb).
+  // Every loop has a compile-time trip count (each thread owns IU_ROWS * 16 / 256
+  // elements per block), so the LDS loads are issued ahead of the FMA chains (the
+  // long sums unrolled by 8: fully unrolled they spill); the products with the
+  // diagonal-block inverses run over all 16 terms, the inverses holding exact zeros
+  // outside their triangle (the nonzero terms keep their order).
+  static_assert(IU_ROWS * 16 % 256 == 0, "whole elements per thread");
+  constexpr int EPT = IU_ROWS * 16 / 256;
+#pragma unroll
   for (int b = 0; b < 4; ++b) {
-    for (int e = tid; e < IU_ROWS * 16; e += 256) {
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      const int e = tid + 256 * k;
       const int r = e >> 4;
       const int c = b * 16 + (e & 15);
       double acc = Cs[r][c];
+#pragma unroll 8
       for (int t = 0; t < b * 16; ++t) acc = fma(-Cs[r][t], LU[t][c], acc);
       Ts[r][e & 15] = acc;
     }
     __syncthreads();
-    for (int e = tid; e < IU_ROWS * 16; e += 256) {
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      const int e = tid + 256 * k;
       const int r = e >> 4;
       const int cl = e & 15;
       double acc = 0.0;
-      for (int t = 0; t <= cl; ++t) acc = fma(Ts[r][t], Di[b][t][cl], acc);
+#pragma unroll
+      for (int t = 0; t < 16; ++t) acc = fma(Ts[r][t], Di[b][t][cl], acc);
       Cs[r][b * 16 + cl] = acc;
     }
     __syncthreads();
   }
   // G L = C, blocks right to left: G_b = (C_b - G_{>b} L_{>b,b}) inv(L_bb)
+#pragma unroll
   for (int b = 3; b >= 0; --b) {
-    for (int e = tid; e < IU_ROWS * 16; e += 256) {
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      const int e = tid + 256 * k;
       const int r = e >> 4;
       const int c = b * 16 + (e & 15);
       double acc = Cs[r][c];
+#pragma unroll 8
       for (int t = (b + 1) * 16; t < NB; ++t) acc = fma(-Cs[r][t], LU[t][c], acc);
       Ts[r][e & 15] = acc;
     }
     __syncthreads();
-    for (int e = tid; e < IU_ROWS * 16; e += 256) {
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      const int e = tid + 256 * k;
       const int r = e >> 4;
       const int cl = e & 15;
       double acc = 0.0;
-      for (int t = cl; t < 16; ++t) acc = fma(Ts[r][t], Di[4 + b][t][cl], acc);
+#pragma unroll
+      for (int t = 0; t < 16; ++t) acc = fma(Ts[r][t], Di[4 + b][t][cl], acc);
       Cs[r][b * 16 + cl] = acc;
     }
     __syncthreads();
