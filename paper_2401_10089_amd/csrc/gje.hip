@@ -80,42 +80,6 @@ __device__ __forceinline__ void read_owner_row(const double (&x)[RPL][SL], int c
   _Pragma("unroll") for (int c = c_first; c < SL; ++c) u[c] = readlane_d(x[0][c], L);
 }
 
-// dst[c] = x[iL][c] for c >= c_first (compile-time after unrolling), iL wave-uniform:
-// a scalar if-chain keeps every register index static.
-__device__ __forceinline__ void store_row_tail(const double (&x)[RPL][SL], int c_first, int iL,
-                                               double* dst) {
-#define LOGM_TAIL_CASE(I)                                                                  \
-  if (I < RPL && iL == I) {                                                                \
-    _Pragma("unroll") for (int c = c_first; c < SL; ++c) dst[c] = x[(I < RPL) ? I : 0][c]; \
-    return;                                                                                \
-  }
-  LOGM_TAIL_CASE(0)
-  LOGM_TAIL_CASE(1)
-  LOGM_TAIL_CASE(2)
-  LOGM_TAIL_CASE(3)
-  LOGM_TAIL_CASE(4)
-  LOGM_TAIL_CASE(5)
-  LOGM_TAIL_CASE(6)
-  LOGM_TAIL_CASE(7)
-#undef LOGM_TAIL_CASE
-}
-
-// x[iL][T] of lane L for wave-uniform iL and L (T a compile-time slot after unrolling).
-__device__ __forceinline__ double read_owner_slot(const double (&x)[RPL][SL], int T, int iL, int L) {
-#define LOGM_SLOT_CASE(I) \
-  if (I < RPL && iL == I) return readlane_d(x[(I < RPL) ? I : 0][T], L);
-  LOGM_SLOT_CASE(0)
-  LOGM_SLOT_CASE(1)
-  LOGM_SLOT_CASE(2)
-  LOGM_SLOT_CASE(3)
-  LOGM_SLOT_CASE(4)
-  LOGM_SLOT_CASE(5)
-  LOGM_SLOT_CASE(6)
-  LOGM_SLOT_CASE(7)
-#undef LOGM_SLOT_CASE
-  return readlane_d(x[0][T], L);
-}
-
 // Packed pivot key of candidate slot i: bits 31..3 hold 1 + the high word of |a|
 // shifted right by 3 (exponent and 17 leading mantissa bits), bits 2..0 the slot;
 // rows that are no longer candidates get 0.  The chosen pivot is therefore within a
@@ -127,19 +91,11 @@ __device__ __forceinline__ unsigned pivot_key(double a, int i, unsigned act) {
   return ((act >> i) & 1u) ? k : 0u;
 }
 
-// Branch-free selects on the bit patterns: v if bit else +0, and a if bit else b.
+// Branch-free select on the bit pattern: v if bit else +0.
 __device__ __forceinline__ double masked(double v, unsigned bit) {
   const unsigned m = 0u - (bit & 1u);
   const unsigned long long b = (unsigned long long)__double_as_longlong(v);
   const unsigned lo = (unsigned)b & m, hi = (unsigned)(b >> 32) & m;
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-__device__ __forceinline__ double blend(double a, double b, unsigned bit) {
-  const unsigned m = 0u - (bit & 1u);
-  const unsigned long long ab = (unsigned long long)__double_as_longlong(a);
-  const unsigned long long bb = (unsigned long long)__double_as_longlong(b);
-  const unsigned lo = ((unsigned)ab & m) | ((unsigned)bb & ~m);
-  const unsigned hi = ((unsigned)(ab >> 32) & m) | ((unsigned)(bb >> 32) & ~m);
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
@@ -153,8 +109,6 @@ struct __attribute__((aligned(16))) StepRec {
 constexpr int RING = 16;                      // steps in flight
 constexpr int SPIN_LIMIT = 1 << 22;           // bounded waits (about 0.3 s)
 
-// Wait until the LDS word *f reaches target; false if the bound is hit (the caller
-// records an error and carries on with whatever is there, all indices stay clamped).
 // Wait until the LDS word *f reaches target; false if the bound is hit (the caller
 // records an error and carries on with whatever is there, all indices stay clamped).
 // The polled value is made wave-uniform, so the loop is a scalar loop.
@@ -207,7 +161,6 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(1, 2))) void
   __shared__ double s_raw[RING][TR];
   __shared__ StepRec s_rec[RING];  // step j in slot j % RING, stamp j + 1 once published
   __shared__ int s_bcons[NW];      // waves done with all steps of a block
-  __shared__ double s_prow[NW][SL];   // per-wave broadcast of the current pivot row
   __shared__ int s_rid[TR];
   __shared__ int s_stepof[TR];
   __shared__ int s_sel[NB];
@@ -303,11 +256,17 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(1, 2))) void
         const int Lp = pp & 63;
         const int iLp = (pp >> 6) & (RPL - 1);
         if (lane == Lp) act &= ~(1u << iLp);
+        // rows chosen earlier hold garbage from here on (their slices were saved when
+        // they were chosen), so the multipliers need no masking
         double lp[RPL];
 #pragma unroll
-        for (int i = 0; i < RPL; ++i) lp[i] = masked(rv[i] * rp, (act >> i) & 1u);
+        for (int i = 0; i < RPL; ++i) lp[i] = rv[i] * rp;
         double u[SL];
         read_owner_row(x, 0, iLp, Lp, u);
+        if (lane == 0) {   // this wave's slice of pivot row j, final from now on
+#pragma unroll
+          for (int c = 0; c < SL; ++c) s_lu[j][SL * wave + c] = u[c];
+        }
 #pragma unroll
         for (int t = 0; t < SL; ++t) {
 #pragma unroll
@@ -351,8 +310,17 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(1, 2))) void
           const unsigned long long bal = __ballot(best == kmax);
           const int L = bal ? (__ffsll((long long)bal) - 1) : 0;
           const int iL = (int)(kmax & 7u) & (RPL - 1);
-          // the winning lane stores the rest of the pivot row for the broadcast below
-          if (t + 1 < SL && lane == L) store_row_tail(x, t + 1, iL, s_prow[wave]);
+          // the winning lane saves this wave's slice of the pivot row (multipliers left
+          // of column t, U entries from t on: final, the row is never updated again)
+          // for the LU factors and for the broadcast below
+          if (lane == L) {
+#pragma unroll
+            for (int i = 0; i < RPL; ++i)
+              if (i == iL) {
+#pragma unroll
+                for (int c = 0; c < SL; ++c) s_lu[j][SL * wave + c] = x[i][c];
+              }
+          }
           const double rpj = pivot_recip(readlane_d(v[0], L));
           if (lane == L) act &= ~(1u << iL);
           // every lane stores the same uniform values: no divergent branch
@@ -361,11 +329,13 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(1, 2))) void
           s_sel[j] = L + 64 * iL;
           __hip_atomic_store(&s_rec[r].stamp, j + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
           asm volatile("s_wakeup" ::: "memory");   // end the sleep of waiting waves
+          // this column's multipliers (L factor); the rows chosen so far, this pivot
+          // row included, take garbage, their slices being saved already
           double l[RPL];
 #pragma unroll
-          for (int i = 0; i < RPL; ++i) {   // this column's multipliers (L factor)
-            l[i] = masked(x[i][t] * rpj, (act >> i) & 1u);
-            x[i][t] = blend(l[i], x[i][t], (act >> i) & 1u);
+          for (int i = 0; i < RPL; ++i) {
+            l[i] = x[i][t] * rpj;
+            x[i][t] = l[i];
           }
           if (t + 1 < SL) {   // step j on the rest of the block, the next column first
             double u[SL];
@@ -374,7 +344,7 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(1, 2))) void
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-            for (int c = t + 1; c < SL; ++c) u[c] = s_prow[wave][c];   // broadcast loads
+            for (int c = t + 1; c < SL; ++c) u[c] = s_lu[j][SL * wave + c];   // broadcast loads
 #pragma unroll
             for (int c = t + 1; c < SL; ++c) {
 #pragma unroll
@@ -386,8 +356,9 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(1, 2))) void
       __builtin_amdgcn_s_setprio(0);
       if (stuck && lane == 0) atomicOr(&m.err[0], 2);
       __syncthreads();
-      // A pivot row is left alone by every later step, so the LU factors of the
-      // node are its pivot rows as they stand now: each owning lane stores its slice.
+      // A pivot row is left alone by every later step: the slices of rows chosen up
+      // to a wave's last step were saved when chosen, the rows chosen after it hold
+      // their final values in that wave's columns now.
       for (int r = tid; r < TR; r += TT) s_stepof[r] = -1;
       __syncthreads();
       if (tid < npiv) s_stepof[min(max(s_sel[tid], 0), TR - 1)] = tid;
@@ -395,7 +366,7 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(1, 2))) void
 #pragma unroll
       for (int i = 0; i < RPL; ++i) {
         const int st = s_stepof[lane + 64 * i];
-        if (st >= 0) {
+        if (st >= jb + SL) {
 #pragma unroll
           for (int t = 0; t < SL; ++t) s_lu[st][SL * wave + t] = x[i][t];
         }
