@@ -21,7 +21,7 @@ once and prints the table.  The oracle's table and the library's own copy are th
 output; the tests pin it independently (exact expansion, Theta_4, scalar and matrix
 accuracy).
 
-Run:  python oracle/fit_k4.py            (about a minute)
+Run:  python oracle/fit_k4.py            (a few seconds)
       python oracle/fit_k4.py --search   (re-derives the starting point, minutes)
 """
 
@@ -171,9 +171,10 @@ def search(seed=1, trials=3000):
     return best[1]
 
 
-def main():
-    start = search() if "--search" in sys.argv else np.array(START)
-    p, ok = newton_float(start)
+def fit(start=None):
+    """The fitted coefficients, each rounded to double once: (h, g, y) with h[j], g[j]
+    for j = 2, 3, 4 on P_2..P_{j+1} and y on P_1..P_6, plus the exact expansion b."""
+    p, ok = newton_float(np.array(START if start is None else start))
     assert ok, "no solution near the starting point"
     b = expand(p, 0.0, 1.0)
     e15 = (1 / 15 - b[15]) * 15
@@ -195,6 +196,16 @@ def main():
     from fractions import Fraction
     bex = expand([Fraction(v) for v in coef], Fraction(0), Fraction(1))
     u = unpack(coef)
+    h = {j: tuple(float(v) for v in u["h"][j]) for j in (2, 3, 4)}
+    g = {j: tuple(float(v) for v in u["g"][j]) for j in (2, 3, 4)}
+    y = tuple(float(v) for v in u["y"])
+    return h, g, y, bex
+
+
+def main():
+    from fractions import Fraction
+    h, g, y, bex = fit(search() if "--search" in sys.argv else None)
+    u = {"h": h, "g": g, "y": y}
     print("# k = 4: h_{j,i}, g_{j,i} for i = 2..j+1; y_1..y_6")
     for j in (2, 3, 4):
         print(f"H[{j}] = ({', '.join(repr(v) for v in u['h'][j])})")

@@ -318,3 +318,17 @@ def test_k4_matrix_accuracy_at_theta():
         ref += term / i
     ref = np.array(ref.tolist(), dtype=float)
     assert np.linalg.norm(z - ref) / np.linalg.norm(ref) < 20 * U
+
+
+def test_k4_table_is_the_fit_output():
+    """The stored k = 4 table is what the committed generator produces (re-run here;
+    the minimum-norm Newton path may land on neighbouring doubles on another LAPACK,
+    hence the tolerance)."""
+    from oracle.fit_k4 import fit
+
+    h, g, y, _ = fit()
+    H, G, Y = scheme_coefficients(4)
+    for j in (2, 3, 4):
+        assert np.allclose(h[j], H[j], rtol=1e-12, atol=1e-15), j
+        assert np.allclose(g[j], G[j], rtol=1e-12, atol=1e-15), j
+    assert np.allclose(y, Y, rtol=1e-12, atol=1e-15)
