@@ -195,6 +195,28 @@ int logm_batched_f64(int32_t batch, int32_t n_max, int64_t total_elems, const in
                      const int64_t* offsets, const double* A, double* L, const logm_opts* o,
                      int32_t* status, void* ws, size_t ws_bytes, void* stream);
 
+/* Workspace bytes for logm_batched_c128 over `batch` complex matrices of size
+ * n_i <= n_max <= 64 whose packed blocks span total_elems complex elements: the real
+ * batched path's workspace at size 2 n_max, two real buffers of 4 total_elems
+ * doubles (the real representations of A and L) and the real sizes and offsets. */
+int logm_batched_c128_workspace_size(int32_t batch, int64_t total_elems, int32_t n_max,
+                                     size_t* bytes);
+
+/* Complex batch (LOGM_C128 matrices, interleaved (re, im) like torch.complex128):
+ * L_i = log(A_i) through the real representation P_i = [[Re A_i, -Im A_i],
+ * [Im A_i, Re A_i]] (2 n_i x 2 n_i), as logm_forward does for one complex matrix:
+ * the embedding, logm_batched_f64's persistent launch on the P_i and the extraction
+ * of the left block column of log P_i, all on `stream`, no host synchronisation
+ * (capturable).  dims, offsets, total_elems as for logm_batched_f64 with complex
+ * elements, 1 <= n_i <= n_max <= 64 (P_i must fit the batched path's 128).  status
+ * as for logm_batched_f64, with the decisions (s, k, iterations) of P_i; a block
+ * with n_i outside [1, n_max] or reaching outside [0, total_elems) gets
+ * LOGM_EINVAL and is not read or written.  ws (device, required,
+ * logm_batched_c128_workspace_size bytes).  Only o->graph_fp32 = 0, o->balance = 0. */
+int logm_batched_c128(int32_t batch, int32_t n_max, int64_t total_elems, const int32_t* dims,
+                      const int64_t* offsets, const void* A, void* L, const logm_opts* o,
+                      int32_t* status, void* ws, size_t ws_bytes, void* stream);
+
 /* ---- components of the path (fp64, device pointers), used for step-level checks ---- */
 
 /* C = alpha * A * B + beta * C (m x k times k x n) on the fp64 matrix cores. */

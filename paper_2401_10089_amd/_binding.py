@@ -40,6 +40,8 @@ EXPORTS = (
     "logm_backward_taped",
     "logm_batched_workspace_size",
     "logm_batched_f64",
+    "logm_batched_c128_workspace_size",
+    "logm_batched_c128",
     "logm_gemm_f64",
     "logm_inverse_f64",
     "logm_sqrt_f64",
@@ -148,6 +150,9 @@ def load_library(path: str = LIB_PATH):
         "logm_batched_workspace_size": (ctypes.c_int, [_i32, _i64, _i32, ctypes.POINTER(_sz)]),
         "logm_batched_f64": (ctypes.c_int, [_i32, _i32, _i64, _vp, _vp, _vp, _vp, ctypes.POINTER(LogmOpts),
                                             _vp, _vp, _sz, _vp]),
+        "logm_batched_c128_workspace_size": (ctypes.c_int, [_i32, _i64, _i32, ctypes.POINTER(_sz)]),
+        "logm_batched_c128": (ctypes.c_int, [_i32, _i32, _i64, _vp, _vp, _vp, _vp, ctypes.POINTER(LogmOpts),
+                                             _vp, _vp, _sz, _vp]),
         "logm_gemm_f64": (ctypes.c_int, [_i64, _i64, _i64, _f64, _vp, _i64, _vp, _i64, _f64, _vp, _i64, _vp]),
         "logm_inverse_f64": (ctypes.c_int, [_i64, _vp, _i64, _vp, _i64, ctypes.POINTER(_f64), _vp, _sz, _vp]),
         "logm_sqrt_f64": (ctypes.c_int, [_i64, _vp, _i64, _vp, _i64, _i32, ctypes.POINTER(_i32), _vp, _sz, _vp]),
@@ -434,9 +439,10 @@ def logm_autograd(A):
 
 
 class BatchPlan:
-    """Device-side description of a batch of small matrices (packed row-major)."""
+    """Device-side description of a batch of small matrices (packed row-major);
+    complex=True plans a complex128 batch (n_i <= 64, through real representations)."""
 
-    def __init__(self, dims, device):
+    def __init__(self, dims, device, complex: bool = False):
         torch = _torch()
         self.dims_host = [int(d) for d in dims]
         if not self.dims_host:
@@ -451,17 +457,23 @@ class BatchPlan:
         self.device = device
         self.dims = torch.tensor(self.dims_host, dtype=torch.int32, device=device)
         self.offsets = torch.tensor(offs, dtype=torch.int64, device=device)
+        self.complex = bool(complex)
+        self.dtype = torch.complex128 if self.complex else torch.float64
         by = _sz()
-        _check(lib().logm_batched_workspace_size(len(dims), tot, self.n_max, ctypes.byref(by)),
-               "logm_batched_workspace_size")
+        if self.complex:
+            _check(lib().logm_batched_c128_workspace_size(len(dims), tot, self.n_max, ctypes.byref(by)),
+                   "logm_batched_c128_workspace_size")
+        else:
+            _check(lib().logm_batched_workspace_size(len(dims), tot, self.n_max, ctypes.byref(by)),
+                   "logm_batched_workspace_size")
         self.ws = torch.empty(by.value, dtype=torch.uint8, device=device)
         self.status = torch.empty(4 * len(dims), dtype=torch.int32, device=device)
 
     def pack(self, mats):
         torch = _torch()
-        flat = torch.empty(self.total, dtype=torch.float64, device=self.device)
+        flat = torch.empty(self.total, dtype=self.dtype, device=self.device)
         for M, o, d in zip(mats, self.offsets_host, self.dims_host):
-            flat[o:o + d * d] = torch.as_tensor(M, dtype=torch.float64).reshape(-1).to(self.device)
+            flat[o:o + d * d] = torch.as_tensor(M, dtype=self.dtype).reshape(-1).to(self.device)
         return flat
 
     def unpack(self, flat):
@@ -472,17 +484,23 @@ def logm_batched(A_flat, plan: "BatchPlan", L_flat=None, k_max: int = 5, max_sqr
                  db_max_iter: int = 30, theta_source: int = 0):
     """L_i = log(A_i) for a packed batch (one persistent launch, decisions on the
     device).  Returns (L_flat, status tensor [batch, 4]: code, s, k, DB iterations);
-    does not synchronise."""
+    does not synchronise.  A complex128 batch needs a plan made with complex=True."""
     torch = _torch()
+    if A_flat.dtype != plan.dtype or A_flat.numel() != plan.total or not A_flat.is_contiguous():
+        raise ValueError("A_flat must be a contiguous packed batch of the plan's dtype and size")
     if L_flat is None:
         L_flat = torch.empty_like(A_flat)
+    if L_flat.dtype != plan.dtype or L_flat.numel() != plan.total or not L_flat.is_contiguous():
+        raise ValueError("L_flat must be a contiguous packed batch of the plan's dtype and size")
     o = default_opts()
     o.k_max, o.max_sqrt, o.db_max_iter, o.theta_source = k_max, max_sqrt, db_max_iter, theta_source
-    rc = lib().logm_batched_f64(len(plan.dims_host), plan.n_max, plan.total, _vp(plan.dims.data_ptr()),
-                                _vp(plan.offsets.data_ptr()), _vp(A_flat.data_ptr()), _vp(L_flat.data_ptr()),
-                                ctypes.byref(o), _vp(plan.status.data_ptr()), _vp(plan.ws.data_ptr()),
-                                plan.ws.numel(), _stream_ptr(A_flat))
-    _check(rc, "logm_batched_f64")
+    fn, name = ((lib().logm_batched_c128, "logm_batched_c128") if plan.complex
+                else (lib().logm_batched_f64, "logm_batched_f64"))
+    rc = fn(len(plan.dims_host), plan.n_max, plan.total, _vp(plan.dims.data_ptr()),
+            _vp(plan.offsets.data_ptr()), _vp(A_flat.data_ptr()), _vp(L_flat.data_ptr()),
+            ctypes.byref(o), _vp(plan.status.data_ptr()), _vp(plan.ws.data_ptr()),
+            plan.ws.numel(), _stream_ptr(A_flat))
+    _check(rc, name)
     return L_flat, plan.status.view(-1, 4)
 
 

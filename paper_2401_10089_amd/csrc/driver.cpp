@@ -1194,7 +1194,43 @@ bool opts_ok(const logm_opts& o) {
   return true;
 }
 
+// The schemes as the batched kernel takes them, and its launch.
+hipError_t batched_launch(int batch, int n_max, const int32_t* dims, const int64_t* offsets,
+                          const double* A, double* L, int32_t* status, void* ws, size_t ws_bytes,
+                          int64_t total_elems, const logm_opts& opts, hipStream_t s) {
+  double h[5][4][5] = {}, g[5][4][5] = {}, y[5][7] = {};
+  for (int i = 0; i < 5; ++i) {
+    const Scheme& S = scheme(i + 1);
+    for (size_t r = 0; r < S.h.size(); ++r)
+      for (size_t c = 0; c < S.h[r].size(); ++c) {
+        h[i][r][c] = S.h[r][c];
+        g[i][r][c] = S.g[r][c];
+      }
+    for (size_t c = 0; c < S.y.size(); ++c) y[i][c] = S.y[c];
+  }
+  return launch_batched_logm(batch, n_max, dims, offsets, A, L, status, ws, ws_bytes, total_elems,
+                             opts.k_max, opts.max_sqrt, opts.db_max_iter, opts.theta_source, h, g,
+                             y, s);
+}
+
+// Workspace of the complex batch: the real path's at twice the size, then the real
+// representations of A and L and the real sizes and offsets.
+struct BatchC128Layout {
+  size_t real_ws, a2, l2, off2, dims2, total;
+};
+inline size_t al256(size_t b) { return (b + 255) / 256 * 256; }
+BatchC128Layout batch_c128_layout(int batch, int64_t total_elems, int n_max) {
+  BatchC128Layout w;
+  w.real_ws = 0;
+  w.a2 = al256(batched_workspace_bytes(batch, 2 * n_max));
+  w.l2 = w.a2 + al256((size_t)total_elems * 4 * sizeof(double));
+  w.off2 = w.l2 + al256((size_t)total_elems * 4 * sizeof(double));
+  w.dims2 = w.off2 + al256((size_t)batch * sizeof(int64_t));
+  w.total = w.dims2 + al256((size_t)batch * sizeof(int32_t));
+  return w;
+}
 }  // namespace
+
 }  // namespace logm
 
 using namespace logm;
@@ -1429,19 +1465,47 @@ int logm_batched_f64(int32_t batch, int32_t n_max, int64_t total_elems, const in
     return LOGM_EINVAL;
   if (!opts_ok(opts) || opts.graph_fp32 != 0 || opts.balance != 0) return LOGM_EINVAL;
   if (ws_bytes < batched_workspace_bytes(batch, n_max)) return LOGM_EWORKSPACE;
-  double h[5][4][5] = {}, g[5][4][5] = {}, y[5][7] = {};
-  for (int i = 0; i < 5; ++i) {
-    const Scheme& S = scheme(i + 1);
-    for (size_t r = 0; r < S.h.size(); ++r)
-      for (size_t c = 0; c < S.h[r].size(); ++c) {
-        h[i][r][c] = S.h[r][c];
-        g[i][r][c] = S.g[r][c];
-      }
-    for (size_t c = 0; c < S.y.size(); ++c) y[i][c] = S.y[c];
-  }
-  hipError_t e = launch_batched_logm(batch, n_max, dims, offsets, A, L, status, ws, ws_bytes,
-                                     total_elems, opts.k_max, opts.max_sqrt, opts.db_max_iter,
-                                     opts.theta_source, h, g, y, reinterpret_cast<hipStream_t>(stream));
+  hipError_t e = batched_launch(batch, n_max, dims, offsets, A, L, status, ws, ws_bytes,
+                                total_elems, opts, reinterpret_cast<hipStream_t>(stream));
+  return (e == hipSuccess) ? LOGM_OK : LOGM_EHIP;
+}
+
+int logm_batched_c128_workspace_size(int32_t batch, int64_t total_elems, int32_t n_max,
+                                     size_t* bytes) {
+  if (batch < 1 || total_elems < 1 || n_max < 1 || n_max > 64 || bytes == nullptr)
+    return LOGM_EINVAL;
+  if (total_elems > (int64_t)1 << 40) return LOGM_EINVAL;
+  *bytes = batch_c128_layout(batch, total_elems, n_max).total;
+  return LOGM_OK;
+}
+
+int logm_batched_c128(int32_t batch, int32_t n_max, int64_t total_elems, const int32_t* dims,
+                      const int64_t* offsets, const void* A, void* L, const logm_opts* o,
+                      int32_t* status, void* ws, size_t ws_bytes, void* stream) {
+  logm_opts opts;
+  logm_default_opts(&opts);
+  if (o != nullptr) opts = *o;
+  if (batch < 1 || total_elems < 1 || total_elems > (int64_t)1 << 40 || n_max < 1 || n_max > 64 ||
+      dims == nullptr || offsets == nullptr || A == nullptr || L == nullptr || status == nullptr ||
+      ws == nullptr)
+    return LOGM_EINVAL;
+  if (!opts_ok(opts) || opts.graph_fp32 != 0 || opts.balance != 0) return LOGM_EINVAL;
+  const BatchC128Layout w = batch_c128_layout(batch, total_elems, n_max);
+  if (ws_bytes < w.total) return LOGM_EWORKSPACE;
+  char* base = static_cast<char*>(ws);
+  double* A2 = reinterpret_cast<double*>(base + w.a2);
+  double* L2 = reinterpret_cast<double*>(base + w.l2);
+  int64_t* off2 = reinterpret_cast<int64_t*>(base + w.off2);
+  int32_t* dims2 = reinterpret_cast<int32_t*>(base + w.dims2);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = launch_batch_complex_prep(batch, n_max, total_elems, dims, offsets, dims2, off2, s);
+  if (e == hipSuccess)
+    e = launch_batch_embed_complex(batch, static_cast<const double*>(A), dims2, off2, A2, s);
+  if (e == hipSuccess)
+    e = batched_launch(batch, 2 * n_max, dims2, off2, A2, L2, status, base + w.real_ws, w.a2,
+                       4 * total_elems, opts, s);
+  if (e == hipSuccess)
+    e = launch_batch_extract_complex(batch, L2, dims2, off2, static_cast<double*>(L), s);
   return (e == hipSuccess) ? LOGM_OK : LOGM_EHIP;
 }
 

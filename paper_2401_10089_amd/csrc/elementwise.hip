@@ -383,6 +383,58 @@ __global__ void extract_complex_kernel(const double* R, int64_t ldr, int n, doub
   }
 }
 
+// Batched real representations (complex batch, n_i <= 64): matrix i of the complex
+// packing (n_i x n_i interleaved at element offset off[i]) becomes the 2n_i x 2n_i
+// real block at offset 4 off[i] (non-overlapping when the complex blocks are).  A
+// matrix whose size or block is out of range gets real size 0, which the batched
+// kernel reports as invalid and leaves alone.
+__global__ void batch_complex_prep_kernel(int batch, int n_lim, int64_t total, const int* dims,
+                                          const int64_t* off, int* dims2, int64_t* off2) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < batch; i += gridDim.x * blockDim.x) {
+    const int n = dims[i];
+    const int64_t o = off[i];
+    const bool ok = n >= 1 && n <= n_lim && o >= 0 && o + (int64_t)n * n <= total;
+    dims2[i] = ok ? 2 * n : 0;
+    off2[i] = ok ? 4 * o : 0;
+  }
+}
+
+// One workgroup per matrix: P_i = [[Re A_i, -Im A_i], [Im A_i, Re A_i]].
+__global__ void batch_embed_complex_kernel(const double* A, const int* dims2, const int64_t* off2,
+                                           double* P) {
+  const int i = blockIdx.x;
+  const int m = dims2[i];
+  if (m == 0) return;
+  const int n = m / 2;
+  const int64_t oc = off2[i] / 4;
+  double* Pi = P + off2[i];
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int r = e / n, c = e % n;
+    const double re = A[2 * (oc + e)];
+    const double im = A[2 * (oc + e) + 1];
+    Pi[(int64_t)r * m + c] = re;
+    Pi[(int64_t)r * m + n + c] = -im;
+    Pi[(int64_t)(n + r) * m + c] = im;
+    Pi[(int64_t)(n + r) * m + n + c] = re;
+  }
+}
+
+// One workgroup per matrix: L_i from the left block column of log P_i.
+__global__ void batch_extract_complex_kernel(const double* R, const int* dims2, const int64_t* off2,
+                                             double* L) {
+  const int i = blockIdx.x;
+  const int m = dims2[i];
+  if (m == 0) return;
+  const int n = m / 2;
+  const int64_t oc = off2[i] / 4;
+  const double* Ri = R + off2[i];
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int r = e / n, c = e % n;
+    L[2 * (oc + e)] = Ri[(int64_t)r * m + c];
+    L[2 * (oc + e) + 1] = Ri[(int64_t)(n + r) * m + c];
+  }
+}
+
 // Well-conditioned test matrix for timing runs: I + 0.5 u_ij / sqrt(n) with u_ij in
 // [-1, 1) from an integer hash of (seed, i, j); identity on the pad.
 __global__ void fill_test_matrix_kernel(double* M, int n, int n_pad, unsigned seed) {
@@ -477,6 +529,26 @@ hipError_t launch_embed_complex(const double* A, int64_t lda, int n, double* P, 
 hipError_t launch_extract_complex(const double* R, int64_t ldr, int n, double* L, int64_t ldl,
                                   hipStream_t s) {
   hipLaunchKernelGGL(extract_complex_kernel, row_grid(n, n), dim3(256), 0, s, R, ldr, n, L, ldl);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_complex_prep(int batch, int n_lim, int64_t total, const int* dims,
+                                     const int64_t* off, int* dims2, int64_t* off2, hipStream_t s) {
+  const int blocks = std::min((batch + 255) / 256, 1024);
+  hipLaunchKernelGGL(batch_complex_prep_kernel, dim3(blocks), dim3(256), 0, s, batch, n_lim, total,
+                     dims, off, dims2, off2);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_embed_complex(int batch, const double* A, const int* dims2,
+                                      const int64_t* off2, double* P, hipStream_t s) {
+  hipLaunchKernelGGL(batch_embed_complex_kernel, dim3(batch), dim3(256), 0, s, A, dims2, off2, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_extract_complex(int batch, const double* R, const int* dims2,
+                                        const int64_t* off2, double* L, hipStream_t s) {
+  hipLaunchKernelGGL(batch_extract_complex_kernel, dim3(batch), dim3(256), 0, s, R, dims2, off2, L);
   return hipGetLastError();
 }
 

@@ -177,6 +177,15 @@ hipError_t launch_embed_complex(const double* A, int64_t lda, int n, double* P, 
                                 hipStream_t s);
 hipError_t launch_extract_complex(const double* R, int64_t ldr, int n, double* L, int64_t ldl,
                                   hipStream_t s);
+// Complex batch through real representations (n_i <= n_lim): real sizes and offsets
+// (2 n_i, 4 off_i; 0 for an invalid block), the embedding, and the extraction of the
+// left block column; one workgroup per matrix for the latter two.
+hipError_t launch_batch_complex_prep(int batch, int n_lim, int64_t total, const int* dims,
+                                     const int64_t* off, int* dims2, int64_t* off2, hipStream_t s);
+hipError_t launch_batch_embed_complex(int batch, const double* A, const int* dims2,
+                                      const int64_t* off2, double* P, hipStream_t s);
+hipError_t launch_batch_extract_complex(int batch, const double* R, const int* dims2,
+                                        const int64_t* off2, double* L, hipStream_t s);
 
 // Padded n_pad x n_pad test matrix I + 0.5 u / sqrt(n) (u hashed from seed), identity
 // on the pad; for timing runs only.

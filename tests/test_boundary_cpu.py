@@ -187,6 +187,38 @@ def test_batched_argument_validation(lib):
     assert call(ws_bytes=100) == 3
 
 
+def test_batched_c128_argument_validation(lib):
+    by = ctypes.c_size_t(0)
+    assert lib.logm_batched_c128_workspace_size(4, 100, 64, ctypes.byref(by)) == 0
+    b_real = ctypes.c_size_t(0)
+    assert lib.logm_batched_workspace_size(4, 400, 128, ctypes.byref(b_real)) == 0
+    assert by.value >= b_real.value + 2 * 400 * 8          # the real run plus both representations
+    assert lib.logm_batched_c128_workspace_size(4, 100, 65, ctypes.byref(by)) == 1   # 2n > 128
+    assert lib.logm_batched_c128_workspace_size(0, 100, 8, ctypes.byref(by)) == 1
+    assert lib.logm_batched_c128_workspace_size(4, 100, 8, None) == 1
+
+    def call(**kw):
+        a = dict(batch=4, n_max=8, total=100, dims=FAKE, offs=FAKE, A=FAKE, L=FAKE, opts=None,
+                 status=FAKE, ws=FAKE, ws_bytes=1 << 40)
+        a.update(kw)
+        o = a["opts"]
+        return lib.logm_batched_c128(a["batch"], a["n_max"], a["total"], a["dims"], a["offs"], a["A"],
+                                     a["L"], ctypes.byref(o) if o is not None else None, a["status"],
+                                     a["ws"], a["ws_bytes"], None)
+
+    assert call(n_max=65) == 1
+    assert call(dims=None) == 1
+    assert call(A=None) == 1
+    assert call(ws=None) == 1
+    assert call(ws_bytes=100) == 3
+    o = lm.default_opts()
+    o.graph_fp32 = 1
+    assert call(opts=o) == 1
+    o = lm.default_opts()
+    o.balance = 1
+    assert call(opts=o) == 1
+
+
 def test_library_table1_matches_paper(golden):
     t = golden("table1_k5.txt")
     h, g, y, m, th = lm.scheme(5)

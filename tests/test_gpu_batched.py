@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import oracle
-from workloads import disk_matrix, rotscale_matrix, spd_batch
+from workloads import complex_matrix, disk_matrix, real_representation, rotscale_matrix, spd_batch
 
 pytestmark = pytest.mark.gpu
 
@@ -175,3 +175,87 @@ def test_batched_graph_capture_replays(lm):
         lm.logm_batched(flat, plan, L_flat=scratch)   # eager work between replays
         torch.cuda.synchronize()
         assert torch.equal(scratch, L_ref)
+
+
+# ------------------------------------------------------------ complex batch ---
+def run_complex_batch(lm, mats, **kw):
+    import torch
+
+    plan = lm.BatchPlan([m.shape[0] for m in mats], torch.device("cuda:0"), complex=True)
+    flat = plan.pack(mats)
+    L, st = lm.logm_batched(flat, plan, **kw)
+    torch.cuda.synchronize()
+    return plan, flat, [x.cpu().numpy() for x in plan.unpack(L)], st.cpu().numpy()
+
+
+def test_batched_complex_vs_oracle_and_exact(lm):
+    """Complex matrices go through their real representations P_i (2n_i <= 128): each
+    result is the left block column of the oracle's log P_i on the device's decisions,
+    and matches the exact logarithm and the single-matrix complex path."""
+    import torch
+
+    sizes = [1, 2, 5, 17, 33, 64, 40, 64]
+    mats, exact = [], []
+    for i, n in enumerate(sizes):
+        A, Lx = complex_matrix(n, 8400 + i)
+        mats.append(A)
+        exact.append(Lx)
+    _, _, L, st = run_complex_batch(lm, mats)
+    for Lg, s, A, Lx in zip(L, st, mats, exact):
+        n = A.shape[0]
+        code, sr, k, packed = (int(v) for v in s)
+        assert code == 0
+        P = real_representation(A)
+        its = db_iters(packed, sr)
+        LP, io = oracle.logm(P)
+        if (sr, k, its) != (io["s"], io["k"], io["db_iters"][:6]):
+            assert sr <= 6
+            LP, _ = oracle.logm(P, force={"s": sr, "k": k, "db_iters": its})
+        Lo = LP[:n, :n] + 1j * LP[n:, :n]
+        assert relf(Lg, Lo) < TOL, (n, relf(Lg, Lo))
+        assert relf(Lg, Lx) < 1e-11, (n, relf(Lg, Lx))
+        Ls, _ = lm.logm(torch.from_numpy(A).to("cuda:0"))
+        assert relf(Lg, Ls.cpu().numpy()) < 1e-12
+
+
+def test_batched_complex_invalid_block_and_capture(lm):
+    """A block whose size exceeds the plan's limit gets LOGM_EINVAL and is left
+    untouched while the others are computed; the complex call is capturable and every
+    replay reproduces the eager result bit for bit."""
+    import torch
+
+    mats = [complex_matrix(n, 8500 + n)[0] for n in (3, 20, 64, 9)]
+    plan, flat, L, st = run_complex_batch(lm, mats)
+    assert (st[:, 0] == 0).all()
+    L_ref = torch.cat([torch.from_numpy(x.reshape(-1)) for x in L]).to("cuda:0")
+    # graph capture and replays
+    out = torch.empty_like(flat)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        lm.logm_batched(flat, plan, L_flat=out)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        lm.logm_batched(flat, plan, L_flat=out)
+    for _ in range(3):
+        out.zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, L_ref)
+        lm.logm_batched(flat, plan)          # eager work between replays
+        torch.cuda.synchronize()
+    # an out-of-range size on the device: that block is reported and not written
+    plan.dims[1] = 65
+    sentinel = torch.full_like(flat, 7.0)
+    lm.logm_batched(flat, plan, L_flat=sentinel)
+    torch.cuda.synchronize()
+    st2 = plan.status.view(-1, 4).cpu().numpy()
+    assert st2[1, 0] == 1 and (st2[[0, 2, 3], 0] == 0).all()
+    o1, n1 = plan.offsets_host[1], plan.dims_host[1]
+    assert bool((sentinel[o1:o1 + n1 * n1] == 7.0).all())
+    for i in (0, 2, 3):
+        o, n = plan.offsets_host[i], plan.dims_host[i]
+        assert torch.equal(sentinel[o:o + n * n], L_ref[o:o + n * n])
