@@ -158,7 +158,9 @@ int logm_backward(int32_t dtype, int64_t n, const void* A, int64_t lda, const vo
  * the two calls ws must not be touched, and n, the options and ws_bytes must be the
  * same; otherwise logm_backward_taped returns LOGM_EINVAL.  The tape stays valid, so
  * several G may follow one forward.  info of logm_backward_taped: the forward's
- * decisions, and the counters and flops of this call only.  o->balance must be 0. */
+ * decisions, and the counters and flops of this call only.  o->balance must be 0.
+ * LOGM_C128 runs both halves on the real representation with logm_backward's layout
+ * (same workspace size query) and returns gradA = L_log(A^H, G). */
 int logm_forward_taped(int32_t dtype, int64_t n, const void* A, int64_t lda, void* L, int64_t ldl,
                        const logm_opts* o, logm_info* info, void* ws, size_t ws_bytes,
                        void* stream);

@@ -349,30 +349,34 @@ def logm_backward(A, G, k_max: int = 5, max_sqrt: int = 50, db_max_iter: int = 3
 
 class Tape:
     """Workspace of a taped forward pass (logm_forward_taped), consumed by
-    logm_backward_taped; holds the root checkpoints and taped inverses on the GPU."""
+    logm_backward_taped; holds the root checkpoints and taped inverses on the GPU.
+    complex=True tapes a complex128 pass (run on the 2n x 2n real representation)."""
 
     def __init__(self, n: int, device, tape_mats: int | None = None, k_max: int = 5, max_sqrt: int = 50,
-                 db_max_iter: int = 30, theta_source: int = 0):
+                 db_max_iter: int = 30, theta_source: int = 0, complex: bool = False):
         torch = _torch()
         self.n = n
+        self.dt = LOGM_C128 if complex else LOGM_R64
+        self.dtype = torch.complex128 if complex else torch.float64
         self.opts = default_opts()
         o = self.opts
         o.k_max, o.max_sqrt, o.db_max_iter, o.theta_source = k_max, max_sqrt, db_max_iter, theta_source
         if tape_mats is None:
             tape_mats = max(0, 100 - 2 * db_max_iter)
-        self.ws = torch.empty(backward_workspace_size(n, o, tape_mats), dtype=torch.uint8, device=device)
+        self.ws = torch.empty(backward_workspace_size(n, o, tape_mats, self.dt), dtype=torch.uint8,
+                              device=device)
 
 
 def logm_forward_taped(A, tape: Tape, out=None):
     """L = log(A), leaving the reverse-mode tape in ``tape``.  Returns (L, info)."""
     torch = _torch()
-    A = _as_matrix(A)
+    A = _as_matrix(A, allow_complex=True)
     n = A.shape[0]
-    if n != tape.n:
-        raise ValueError("tape built for another size")
-    L = out if out is not None else torch.empty((n, n), dtype=torch.float64, device=A.device)
+    if n != tape.n or A.dtype != tape.dtype:
+        raise ValueError("tape built for another size or dtype")
+    L = out if out is not None else torch.empty((n, n), dtype=A.dtype, device=A.device)
     info = LogmInfo()
-    rc = lib().logm_forward_taped(LOGM_R64, n, _vp(A.data_ptr()), A.stride(0), _vp(L.data_ptr()), L.stride(0),
+    rc = lib().logm_forward_taped(tape.dt, n, _vp(A.data_ptr()), A.stride(0), _vp(L.data_ptr()), L.stride(0),
                                   ctypes.byref(tape.opts), ctypes.byref(info), _vp(tape.ws.data_ptr()),
                                   tape.ws.numel(), _stream_ptr(A))
     _check(rc, "logm_forward_taped", info.status_detail)
@@ -382,13 +386,13 @@ def logm_forward_taped(A, tape: Tape, out=None):
 def logm_backward_taped(G, tape: Tape, out=None):
     """gradA = d<G, log A>/dA from the tape of the last logm_forward_taped."""
     torch = _torch()
-    G = _as_matrix(G, "G")
+    G = _as_matrix(G, "G", allow_complex=True)
     n = G.shape[0]
-    if n != tape.n:
-        raise ValueError("tape built for another size")
-    gA = out if out is not None else torch.empty((n, n), dtype=torch.float64, device=G.device)
+    if n != tape.n or G.dtype != tape.dtype:
+        raise ValueError("tape built for another size or dtype")
+    gA = out if out is not None else torch.empty((n, n), dtype=G.dtype, device=G.device)
     info = LogmInfo()
-    rc = lib().logm_backward_taped(LOGM_R64, n, _vp(G.data_ptr()), G.stride(0), _vp(gA.data_ptr()), gA.stride(0),
+    rc = lib().logm_backward_taped(tape.dt, n, _vp(G.data_ptr()), G.stride(0), _vp(gA.data_ptr()), gA.stride(0),
                                    ctypes.byref(tape.opts), ctypes.byref(info), _vp(tape.ws.data_ptr()),
                                    tape.ws.numel(), _stream_ptr(G))
     _check(rc, "logm_backward_taped", info.status_detail)
@@ -404,22 +408,13 @@ def _autograd_function():
 
         @staticmethod
         def forward(ctx, A):
-            if A.dtype == torch.complex128:   # no taped pair for complex input
-                L, _ = logm(A)
-                ctx.save_for_backward(A)
-                ctx.tape = None
-                return L
-            tape = Tape(A.shape[0], A.device)
+            tape = Tape(A.shape[0], A.device, complex=A.dtype == torch.complex128)
             L, _ = logm_forward_taped(A, tape)
             ctx.tape = tape
             return L
 
         @staticmethod
         def backward(ctx, gL):
-            if ctx.tape is None:
-                (A,) = ctx.saved_tensors
-                gA, _ = logm_backward(A, gL.contiguous())
-                return gA
             gA, _ = logm_backward_taped(gL.contiguous(), ctx.tape)
             ctx.tape = None
             return gA

@@ -1405,10 +1405,37 @@ int logm_forward_taped(int32_t dtype, int64_t n, const void* A, int64_t lda, voi
       ldl < n)
     return LOGM_EINVAL;
   if (!opts_ok(opts) || opts.balance != 0) return LOGM_EINVAL;
-  if (dtype == LOGM_C128) return LOGM_ENOTSUP;
+  if (dtype == LOGM_C128 && 2 * n > (int64_t)1 << 20) return LOGM_EINVAL;
   logm_info local{};
   logm_info& inf = (info != nullptr) ? *info : local;
   std::memset(&inf, 0, sizeof(inf));
+  if (dtype == LOGM_C128) {
+    // the real taped forward on P = rep(A), in the layout logm_backward uses (the
+    // representations past the reverse-mode region), so that the taped backward finds
+    // the tape where the self-contained one keeps it
+    const int64_t n2 = 2 * n;
+    const size_t cb = complex_bwd_bytes(n);
+    Call call(n2, ws, ws_bytes, stream, &opts, cb);
+    if (call.st.code != LOGM_OK) {
+      inf.status_detail = call.st.detail;
+      return call.st.code;
+    }
+    Ctx& c = call.c;
+    c.bytes -= cb;
+    const size_t mb = cb / 3;
+    double* P = reinterpret_cast<double*>(c.base + c.bytes);
+    double* R = reinterpret_cast<double*>(c.base + c.bytes + 2 * mb);
+    Status st = [&]() -> Status {
+      Status st;
+      HIPCK(launch_embed_complex(static_cast<const double*>(A), lda, (int)n, P, n2, c.s));
+      PROPAGATE(taped_forward(c, P, n2, R, n2, opts, inf));
+      HIPCK(launch_extract_complex(R, n2, (int)n, static_cast<double*>(L), ldl, c.s));
+      HIPCK(hipStreamSynchronize(c.s));
+      return st;
+    }();
+    inf.status_detail = st.detail;
+    return st.code;
+  }
   Call call(n, ws, ws_bytes, stream, &opts);
   if (call.st.code != LOGM_OK) {
     inf.status_detail = call.st.detail;
@@ -1431,10 +1458,35 @@ int logm_backward_taped(int32_t dtype, int64_t n, const void* G, int64_t ldg, vo
       ldg < n || ldga < n)
     return LOGM_EINVAL;
   if (!opts_ok(opts) || opts.balance != 0) return LOGM_EINVAL;
-  if (dtype == LOGM_C128) return LOGM_ENOTSUP;
+  if (dtype == LOGM_C128 && 2 * n > (int64_t)1 << 20) return LOGM_EINVAL;
   logm_info local{};
   logm_info& inf = (info != nullptr) ? *info : local;
   std::memset(&inf, 0, sizeof(inf));
+  if (dtype == LOGM_C128) {
+    // rep(G) through the real reverse sweep gives rep(L_log(A^H, G)) (see logm_backward)
+    const int64_t n2 = 2 * n;
+    const size_t cb = complex_bwd_bytes(n);
+    Call call(n2, ws, ws_bytes, stream, &opts, cb);
+    if (call.st.code != LOGM_OK) {
+      inf.status_detail = call.st.detail;
+      return call.st.code;
+    }
+    Ctx& c = call.c;
+    c.bytes -= cb;
+    const size_t mb = cb / 3;
+    double* Gp = reinterpret_cast<double*>(c.base + c.bytes + mb);
+    double* R = reinterpret_cast<double*>(c.base + c.bytes + 2 * mb);
+    Status st = [&]() -> Status {
+      Status st;
+      HIPCK(launch_embed_complex(static_cast<const double*>(G), ldg, (int)n, Gp, n2, c.s));
+      PROPAGATE(taped_backward(c, Gp, n2, R, n2, opts, inf));
+      HIPCK(launch_extract_complex(R, n2, (int)n, static_cast<double*>(gradA), ldga, c.s));
+      HIPCK(hipStreamSynchronize(c.s));
+      return st;
+    }();
+    inf.status_detail = st.detail;
+    return st.code;
+  }
   Call call(n, ws, ws_bytes, stream, &opts);
   if (call.st.code != LOGM_OK) {
     inf.status_detail = call.st.detail;

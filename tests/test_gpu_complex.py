@@ -91,3 +91,31 @@ def test_complex_autograd(lm):
     L.backward(G)
     gA, _ = lm.logm_backward(torch.from_numpy(A).to(dev), G)
     assert torch.equal(At.grad, gA)
+
+
+def test_complex_taped_pair(lm):
+    """The taped pair on complex input: the forward equals logm_forward, the backward
+    equals the self-contained logm_backward bit for bit, and one tape serves several
+    G (each checked against the block form of the oracle's complex Algorithm 1)."""
+    import torch
+
+    n = 20
+    A, _ = complex_matrix(n, 8600)
+    dev = torch.device("cuda:0")
+    Ad = torch.from_numpy(A).to(dev)
+    tape = lm.Tape(n, dev, complex=True)
+    L, info = lm.logm_forward_taped(Ad, tape)
+    L_plain, _ = lm.logm(Ad)
+    assert L.dtype == torch.complex128
+    assert torch.equal(L, L_plain)
+    rng = np.random.default_rng(8601)
+    for _ in range(2):
+        G = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+        Gd = torch.from_numpy(G).to(dev)
+        gA, _ = lm.logm_backward_taped(Gd, tape)
+        gS, _ = lm.logm_backward(Ad, Gd)
+        assert torch.equal(gA, gS)
+        ref = oracle.frechet_block(A.conj().T, G)
+        assert relf(gA.cpu().numpy(), ref) < 1e-11
+    with pytest.raises(ValueError):
+        lm.logm_backward_taped(torch.zeros((n, n), dtype=torch.float64, device=dev), tape)
