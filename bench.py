@@ -83,7 +83,7 @@ def cpu_baseline(A, budget_s: float = 30.0):
     }
 
 
-def batched_section(lm, torch, dev, reps: int = 3, per_matrix_sample: int = 40):
+def batched_section(lm, torch, dev, reps: int = 3, per_matrix_sample: int = 40, autotune: bool = True):
     """Batched forward over 10,000 SPD matrices (n ~ U{8..128}, seed 3001): logm/s of the
     one-launch batched path against the single-matrix path on a sample of the same batch."""
     import numpy as np
@@ -92,6 +92,12 @@ def batched_section(lm, torch, dev, reps: int = 3, per_matrix_sample: int = 40):
     mats = spd_batch(BATCH_COUNT, BATCH_SEED)
     plan = lm.BatchPlan([m.shape[0] for m in mats], dev)
     flat = torch.from_numpy(np.concatenate([m.reshape(-1) for m in mats])).to(dev)
+    # the class boundary (8-wave kernel above it) is chosen by timing this batch
+    if autotune:
+        split, _ = lm.autotune_batched(flat, plan)
+    else:
+        lm.set_batched_split(64)
+        split = 64
     L, st = lm.logm_batched(flat, plan)          # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -122,6 +128,8 @@ def batched_section(lm, torch, dev, reps: int = 3, per_matrix_sample: int = 40):
         "ms_per_batch": 1e3 * dt,
         "workload": f"spd_batch: {BATCH_COUNT} SPD A_i = X_i^T X_i / 64 + 1e-3 I, X_i 64 x n_i N(0,1), "
                     f"n_i ~ U{{8..128}}, seed {BATCH_SEED}, packed row-major",
+        "class_split": split,
+        "class_split_autotuned": bool(autotune),
         "status_codes": {str(c): int(v) for c, v in zip(*np.unique(status[:, 0], return_counts=True))},
         "mean_s": float(status[:, 1].mean()),
         "max_rel_err_vs_eigh_log_sample": max(errs),
@@ -343,7 +351,7 @@ def main():
         "roofline": roofline,
     }
     if not args.no_batched:
-        line["batched"] = batched_section(lm, torch, dev)
+        line["batched"] = batched_section(lm, torch, dev, autotune=not args.no_autotune)
     if not args.no_backward:
         del ws
         line["backward"] = backward_section(lm, torch, dev, A, ms_per_step)

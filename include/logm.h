@@ -197,6 +197,22 @@ int logm_batched_f64(int32_t batch, int32_t n_max, int64_t total_elems, const in
                      const int64_t* offsets, const double* A, double* L, const logm_opts* o,
                      int32_t* status, void* ws, size_t ws_bytes, void* stream);
 
+/* Launch-shape autotuner of the batched path.  When a batch holds matrices above 64,
+ * both kernels run: the 4-wave kernel takes n_i <= split and the 8-wave kernel the
+ * rest (split = 64 by default).  logm_batched_autotune runs logm_batched_f64 on the
+ * caller's batch (same arguments; L and status are overwritten) with split in
+ * {64, 56, 48, 40, 32}, one warm-up and one timed run each (HIP events on `stream`),
+ * keeps the fastest for later batched calls on the current device (process-wide,
+ * complex batches included) and returns it in *best_split (host) with its time in
+ * *best_ms (host, may be NULL).  With n_max <= 64 only 64 is timed.  Synchronises
+ * `stream`; not capturable.  logm_batched_set_split sets the boundary directly
+ * (1..64) and returns the previous one, or -1 for an out-of-range value. */
+int logm_batched_autotune(int32_t batch, int32_t n_max, int64_t total_elems, const int32_t* dims,
+                          const int64_t* offsets, const double* A, double* L, const logm_opts* o,
+                          int32_t* status, void* ws, size_t ws_bytes, void* stream,
+                          int32_t* best_split, double* best_ms);
+int32_t logm_batched_set_split(int32_t split);
+
 /* Workspace bytes for logm_batched_c128 over `batch` complex matrices of size
  * n_i <= n_max <= 64 whose packed blocks span total_elems complex elements: the real
  * batched path's workspace at size 2 n_max, two real buffers of 4 total_elems

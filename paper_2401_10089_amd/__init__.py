@@ -9,6 +9,8 @@ from ._binding import (  # noqa: F401
     EXPORTS,
     BatchPlan,
     autotune,
+    autotune_batched,
+    set_batched_split,
     balance,
     logm_batched,
     LIB_PATH,

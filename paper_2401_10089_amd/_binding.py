@@ -40,6 +40,8 @@ EXPORTS = (
     "logm_backward_taped",
     "logm_batched_workspace_size",
     "logm_batched_f64",
+    "logm_batched_autotune",
+    "logm_batched_set_split",
     "logm_batched_c128_workspace_size",
     "logm_batched_c128",
     "logm_gemm_f64",
@@ -150,6 +152,10 @@ def load_library(path: str = LIB_PATH):
         "logm_batched_workspace_size": (ctypes.c_int, [_i32, _i64, _i32, ctypes.POINTER(_sz)]),
         "logm_batched_f64": (ctypes.c_int, [_i32, _i32, _i64, _vp, _vp, _vp, _vp, ctypes.POINTER(LogmOpts),
                                             _vp, _vp, _sz, _vp]),
+        "logm_batched_autotune": (ctypes.c_int, [_i32, _i32, _i64, _vp, _vp, _vp, _vp, ctypes.POINTER(LogmOpts),
+                                                 _vp, _vp, _sz, _vp, ctypes.POINTER(_i32),
+                                                 ctypes.POINTER(_f64)]),
+        "logm_batched_set_split": (_i32, [_i32]),
         "logm_batched_c128_workspace_size": (ctypes.c_int, [_i32, _i64, _i32, ctypes.POINTER(_sz)]),
         "logm_batched_c128": (ctypes.c_int, [_i32, _i32, _i64, _vp, _vp, _vp, _vp, ctypes.POINTER(LogmOpts),
                                              _vp, _vp, _sz, _vp]),
@@ -497,6 +503,35 @@ def logm_batched(A_flat, plan: "BatchPlan", L_flat=None, k_max: int = 5, max_sqr
             plan.ws.numel(), _stream_ptr(A_flat))
     _check(rc, name)
     return L_flat, plan.status.view(-1, 4)
+
+
+def autotune_batched(A_flat, plan: "BatchPlan", k_max: int = 5, max_sqrt: int = 50,
+                     db_max_iter: int = 30, theta_source: int = 0):
+    """Choose the batched class boundary by timing the caller's real batch (see
+    logm_batched_autotune); returns (split, ms of the best run).  The choice holds for
+    later batched calls on the device."""
+    torch = _torch()
+    if plan.complex or A_flat.dtype != torch.float64 or A_flat.numel() != plan.total:
+        raise ValueError("autotune_batched takes a real packed batch of the plan's size")
+    L_flat = torch.empty_like(A_flat)
+    o = default_opts()
+    o.k_max, o.max_sqrt, o.db_max_iter, o.theta_source = k_max, max_sqrt, db_max_iter, theta_source
+    best = _i32(0)
+    ms = _f64(0)
+    rc = lib().logm_batched_autotune(len(plan.dims_host), plan.n_max, plan.total, _vp(plan.dims.data_ptr()),
+                                     _vp(plan.offsets.data_ptr()), _vp(A_flat.data_ptr()), _vp(L_flat.data_ptr()),
+                                     ctypes.byref(o), _vp(plan.status.data_ptr()), _vp(plan.ws.data_ptr()),
+                                     plan.ws.numel(), _stream_ptr(A_flat), ctypes.byref(best), ctypes.byref(ms))
+    _check(rc, "logm_batched_autotune")
+    return best.value, ms.value
+
+
+def set_batched_split(split: int) -> int:
+    """Set the batched class boundary (1..64); returns the previous one."""
+    old = lib().logm_batched_set_split(int(split))
+    if old < 0:
+        raise ValueError("split must be in 1..64")
+    return old
 
 
 def gemm(A, B, C=None, alpha: float = 1.0, beta: float = 0.0):

@@ -502,6 +502,7 @@ struct BatchArgs {
   int* counter;             // work queue of this launch
   int64_t total_elems;      // elements of A and L
   int report_invalid;       // this launch reports blocks outside the arrays
+  int split;                // class boundary: the n <= 64 class takes n <= split
   int k_max, max_sqrt, db_max_iter, theta_source;
   DevScheme sch[5];         // schemes k = 1 .. 5
 };
@@ -532,7 +533,7 @@ __global__ __launch_bounds__(256 * RA, 4) void batched_logm_kernel(BatchArgs a) 
       }
       continue;
     }
-    if (n > N || (N > 64 && n <= 64)) continue;   // the other size class
+    if ((N == 64) ? (n > a.split) : (n <= a.split)) continue;   // the other size class
     double* X = buf(0);
     double* A2 = buf(1);
     double* B = buf(2);
@@ -716,7 +717,7 @@ hipError_t launch_batched_logm(int batch, int n_max, const int* dims, const int6
                                const double* A, double* L, int* status, void* ws, size_t ws_bytes,
                                int64_t total_elems, int k_max, int max_sqrt, int db_max_iter,
                                int theta_source, const double (*h)[4][5], const double (*g)[4][5],
-                               const double (*y)[7], hipStream_t s) {
+                               const double (*y)[7], int split, hipStream_t s) {
   const int nb_small = std::min(batch, class_blocks<1, 16>());
   const int nb_large = std::min(batch, class_blocks<2, 16>());
   const size_t small_bytes = class_region_bytes(batch, 64, class_blocks<1, 16>());
@@ -735,6 +736,7 @@ hipError_t launch_batched_logm(int batch, int n_max, const int* dims, const int6
   a.max_sqrt = max_sqrt;
   a.db_max_iter = db_max_iter;
   a.theta_source = theta_source;
+  a.split = (n_max <= 64) ? 64 : std::min(std::max(split, 1), 64);
   for (int i = 0; i < 5; ++i) {
     for (int r = 0; r < 4; ++r)
       for (int c = 0; c < 5; ++c) {

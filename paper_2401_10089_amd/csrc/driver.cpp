@@ -51,6 +51,27 @@ int lookahead_wgs(int n_pad) {
   return it == g_cap.end() ? kLookaheadWgs : it->second;
 }
 
+// Batched class boundary per device chosen by logm_batched_autotune (process-wide):
+// matrices with n <= split run in the 4-wave class when the batch also holds n > 64.
+std::mutex g_split_mu;
+std::map<int, int> g_split;
+int batched_split() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 64;
+  std::lock_guard<std::mutex> lk(g_split_mu);
+  const auto it = g_split.find(dev);
+  return it == g_split.end() ? 64 : it->second;
+}
+int set_batched_split(int split) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 64;
+  std::lock_guard<std::mutex> lk(g_split_mu);
+  const auto it = g_split.find(dev);
+  const int old = (it == g_split.end()) ? 64 : it->second;
+  g_split[dev] = split;
+  return old;
+}
+
 // ------------------------------------------------------------ constants ---
 struct Scheme {
   int k = 0;
@@ -1197,7 +1218,7 @@ bool opts_ok(const logm_opts& o) {
 // The schemes as the batched kernel takes them, and its launch.
 hipError_t batched_launch(int batch, int n_max, const int32_t* dims, const int64_t* offsets,
                           const double* A, double* L, int32_t* status, void* ws, size_t ws_bytes,
-                          int64_t total_elems, const logm_opts& opts, hipStream_t s) {
+                          int64_t total_elems, const logm_opts& opts, int split, hipStream_t s) {
   double h[5][4][5] = {}, g[5][4][5] = {}, y[5][7] = {};
   for (int i = 0; i < 5; ++i) {
     const Scheme& S = scheme(i + 1);
@@ -1210,7 +1231,7 @@ hipError_t batched_launch(int batch, int n_max, const int32_t* dims, const int64
   }
   return launch_batched_logm(batch, n_max, dims, offsets, A, L, status, ws, ws_bytes, total_elems,
                              opts.k_max, opts.max_sqrt, opts.db_max_iter, opts.theta_source, h, g,
-                             y, s);
+                             y, split, s);
 }
 
 // Workspace of the complex batch: the real path's at twice the size, then the real
@@ -1518,8 +1539,63 @@ int logm_batched_f64(int32_t batch, int32_t n_max, int64_t total_elems, const in
   if (!opts_ok(opts) || opts.graph_fp32 != 0 || opts.balance != 0) return LOGM_EINVAL;
   if (ws_bytes < batched_workspace_bytes(batch, n_max)) return LOGM_EWORKSPACE;
   hipError_t e = batched_launch(batch, n_max, dims, offsets, A, L, status, ws, ws_bytes,
-                                total_elems, opts, reinterpret_cast<hipStream_t>(stream));
+                                total_elems, opts, batched_split(), reinterpret_cast<hipStream_t>(stream));
   return (e == hipSuccess) ? LOGM_OK : LOGM_EHIP;
+}
+
+int logm_batched_autotune(int32_t batch, int32_t n_max, int64_t total_elems, const int32_t* dims,
+                          const int64_t* offsets, const double* A, double* L, const logm_opts* o,
+                          int32_t* status, void* ws, size_t ws_bytes, void* stream,
+                          int32_t* best_split, double* best_ms) {
+  logm_opts opts;
+  logm_default_opts(&opts);
+  if (o != nullptr) opts = *o;
+  if (batch < 1 || total_elems < 1 || n_max < 1 || n_max > 128 || dims == nullptr ||
+      offsets == nullptr || A == nullptr || L == nullptr || status == nullptr || ws == nullptr ||
+      best_split == nullptr)
+    return LOGM_EINVAL;
+  if (!opts_ok(opts) || opts.graph_fp32 != 0 || opts.balance != 0) return LOGM_EINVAL;
+  if (ws_bytes < batched_workspace_bytes(batch, n_max)) return LOGM_EWORKSPACE;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0 != nullptr) (void)hipEventDestroy(e0);
+    return LOGM_EHIP;
+  }
+  // the class boundary matters only when both classes run
+  const int cands[5] = {64, 56, 48, 40, 32};
+  const int ncand = (n_max > 64) ? 5 : 1;
+  int best = 64;
+  float best_t = 0.0f;
+  hipError_t e = hipSuccess;
+  for (int c = 0; c < ncand && e == hipSuccess; ++c) {
+    for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {   // a warm-up run, then the timed one
+      if (rep == 1) e = hipEventRecord(e0, s);
+      if (e == hipSuccess)
+        e = batched_launch(batch, n_max, dims, offsets, A, L, status, ws, ws_bytes, total_elems,
+                           opts, cands[c], s);
+      if (e == hipSuccess && rep == 1) e = hipEventRecord(e1, s);
+    }
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e == hipSuccess && (c == 0 || ms < best_t)) {
+      best_t = ms;
+      best = cands[c];
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return LOGM_EHIP;
+  set_batched_split(best);
+  *best_split = best;
+  if (best_ms != nullptr) *best_ms = best_t;
+  return LOGM_OK;
+}
+
+int32_t logm_batched_set_split(int32_t split) {
+  if (split < 1 || split > 64) return -1;
+  return set_batched_split(split);
 }
 
 int logm_batched_c128_workspace_size(int32_t batch, int64_t total_elems, int32_t n_max,
@@ -1555,7 +1631,7 @@ int logm_batched_c128(int32_t batch, int32_t n_max, int64_t total_elems, const i
     e = launch_batch_embed_complex(batch, static_cast<const double*>(A), dims2, off2, A2, s);
   if (e == hipSuccess)
     e = batched_launch(batch, 2 * n_max, dims2, off2, A2, L2, status, base + w.real_ws, w.a2,
-                       4 * total_elems, opts, s);
+                       4 * total_elems, opts, batched_split(), s);
   if (e == hipSuccess)
     e = launch_batch_extract_complex(batch, L2, dims2, off2, static_cast<double*>(L), s);
   return (e == hipSuccess) ? LOGM_OK : LOGM_EHIP;

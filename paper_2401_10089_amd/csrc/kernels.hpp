@@ -210,14 +210,15 @@ hipError_t launch_scale_out(const double* src, int64_t ld, double* dst, int64_t 
 size_t batched_workspace_bytes(int batch, int n_max);
 // Persistent launches over the batch (n_i <= 128): L_i = log(A_i) by Algorithm 1
 // on the device, one workgroup per matrix from a work queue; a counter-reset kernel,
-// then the 64 < n <= 128 class on `s` beside the n <= 64 class on a second stream
-// (forked and joined with events).  No host synchronisation and no memset, so the
-// sequence can be captured in a graph.  h, g:
+// then the large class (8 waves, n > split) on `s` beside the small class (4 waves,
+// n <= split) on a second stream (forked and joined with events); split (1..64)
+// applies when n_max > 64, otherwise every matrix is in the small class.  No host
+// synchronisation and no memset, so the sequence can be captured in a graph.  h, g:
 // [scheme k - 1 for k = 1..5][row j - 2][P_2..P_{j+1}], y: [scheme][P_1..P_{k+2}].
 hipError_t launch_batched_logm(int batch, int n_max, const int* dims, const int64_t* offsets,
                                const double* A, double* L, int* status, void* ws, size_t ws_bytes,
                                int64_t total_elems, int k_max, int max_sqrt, int db_max_iter,
                                int theta_source, const double (*h)[4][5], const double (*g)[4][5],
-                               const double (*y)[7], hipStream_t s);
+                               const double (*y)[7], int split, hipStream_t s);
 
 }  // namespace logm

@@ -187,6 +187,24 @@ def test_batched_argument_validation(lib):
     assert call(ws_bytes=100) == 3
 
 
+def test_batched_autotune_argument_validation(lib):
+    best = ctypes.c_int32(0)
+    ms = ctypes.c_double(0)
+
+    def call(**kw):
+        a = dict(batch=4, n_max=100, total=1000, ws_bytes=1 << 40, best=ctypes.byref(best))
+        a.update(kw)
+        return lib.logm_batched_autotune(a["batch"], a["n_max"], a["total"], FAKE, FAKE, FAKE, FAKE, None,
+                                         FAKE, FAKE, a["ws_bytes"], None, a["best"], ctypes.byref(ms))
+
+    assert call(best=None) == 1
+    assert call(n_max=129) == 1
+    assert call(batch=0) == 1
+    assert call(ws_bytes=100) == 3
+    assert lib.logm_batched_set_split(0) == -1
+    assert lib.logm_batched_set_split(65) == -1
+
+
 def test_batched_c128_argument_validation(lib):
     by = ctypes.c_size_t(0)
     assert lib.logm_batched_c128_workspace_size(4, 100, 64, ctypes.byref(by)) == 0

@@ -259,3 +259,28 @@ def test_batched_complex_invalid_block_and_capture(lm):
     for i in (0, 2, 3):
         o, n = plan.offsets_host[i], plan.dims_host[i]
         assert torch.equal(sentinel[o:o + n * n], L_ref[o:o + n * n])
+
+
+# ------------------------------------------------------- class boundary ---
+def test_batched_split_forced_and_autotuned(lm):
+    """The class boundary moves matrices with 32 < n <= 64 to the 8-wave kernel: the
+    results stay within the tolerance of the oracle either way, and the autotuner
+    returns one of its candidates and leaves it in force."""
+    import torch
+
+    mats = spd_batch(40, 97) + [disk_matrix(n, 700 + n) for n in (33, 40, 48, 57, 64, 65, 100)]
+    old = lm.set_batched_split(32)
+    try:
+        L, st = run_batch(lm, mats)
+        for Lg, s, A in zip(L, st, mats):
+            check_against_oracle(Lg, s, A)
+        plan = lm.BatchPlan([m.shape[0] for m in mats], torch.device("cuda:0"))
+        flat = plan.pack(mats)
+        split, ms = lm.autotune_batched(flat, plan)
+        assert split in (64, 56, 48, 40, 32) and ms > 0
+        assert lm.set_batched_split(split) == split
+        L, st = run_batch(lm, mats)
+        for Lg, s, A in zip(L, st, mats):
+            check_against_oracle(Lg, s, A)
+    finally:
+        lm.set_batched_split(old)
