@@ -53,24 +53,46 @@ __global__ __launch_bounds__(TPB) void db_update_kernel(DbArgs a, int nblk) {
     const int qx = a.px[c];
     const int qy = (a.py != nullptr) ? a.py[c] : -1;
     double sdiff = 0.0, snew = 0.0;
-    for (int i = i0; i < i1; ++i) {
-      const int64_t o = (int64_t)i * a.ld;
-      if (i >= n || c >= n) {
-        const double d = (i == c) ? 1.0 : 0.0;
-        a.Xout[o + c] = d;
-        a.Yout[o + c] = d;
-        continue;
+    if (c >= n) {   // pad column: identity
+      for (int i = i0; i < i1; ++i) {
+        const int64_t o = (int64_t)i * a.ld;
+        a.Xout[o + c] = (i == c) ? 1.0 : 0.0;
+        a.Yout[o + c] = (i == c) ? 1.0 : 0.0;
       }
-      const double x = a.Xin[o + c];
-      const double y = (a.Yin != nullptr) ? a.Yin[o + c] : (i == c ? 1.0 : 0.0);
-      const double xi = a.Xinv[o + qx];
-      const double yi = (qy >= 0) ? a.Yinv[o + qy] : (i == c ? 1.0 : 0.0);
-      const double xn = 0.5 * (mu * x + yi / mu);
-      const double yn = 0.5 * (mu * y + xi / mu);
-      a.Xout[o + c] = xn;
-      a.Yout[o + c] = yn;
-      sdiff += fabs(xn - x);
-      snew += fabs(xn);
+      continue;
+    }
+    // groups of RG rows: every load of the group is issued before its stores (the
+    // update is in place, so loads may not pass stores otherwise); sums in row order
+    constexpr int RG = 4;
+    for (int ib = i0; ib < i1; ib += RG) {
+      double x[RG], y[RG], xi[RG], yi[RG];
+#pragma unroll
+      for (int r = 0; r < RG; ++r) {
+        const int i = min(ib + r, i1 - 1);
+        const int64_t o = (int64_t)i * a.ld;
+        const bool valid = i < n;
+        x[r] = valid ? a.Xin[o + c] : 0.0;
+        y[r] = (valid && a.Yin != nullptr) ? a.Yin[o + c] : (i == c ? 1.0 : 0.0);
+        xi[r] = valid ? a.Xinv[o + qx] : 0.0;
+        yi[r] = (valid && qy >= 0) ? a.Yinv[o + qy] : (i == c ? 1.0 : 0.0);
+      }
+#pragma unroll
+      for (int r = 0; r < RG; ++r) {
+        const int i = ib + r;
+        if (i >= i1) break;
+        const int64_t o = (int64_t)i * a.ld;
+        if (i >= n) {   // pad row: identity
+          a.Xout[o + c] = (i == c) ? 1.0 : 0.0;
+          a.Yout[o + c] = (i == c) ? 1.0 : 0.0;
+          continue;
+        }
+        const double xn = 0.5 * (mu * x[r] + yi[r] / mu);
+        const double yn = 0.5 * (mu * y[r] + xi[r] / mu);
+        a.Xout[o + c] = xn;
+        a.Yout[o + c] = yn;
+        sdiff += fabs(xn - x[r]);
+        snew += fabs(xn);
+      }
     }
     if (c < n) {
       p0[c] = sdiff;
