@@ -50,7 +50,7 @@ extern "C" {
 enum {
   LOGM_OK = 0,
   LOGM_EINVAL = 1,      /* bad argument: n < 1, NULL pointer, ld < n, bad option */
-  LOGM_ENOTSUP = 2,     /* data type not built (complex input) */
+  LOGM_ENOTSUP = 2,     /* reserved: not returned (entry points with a dtype take both types) */
   LOGM_EWORKSPACE = 3,  /* ws_bytes smaller than required */
   LOGM_ENONFINITE = 4,  /* NaN or Inf in the input or the result */
   LOGM_ESINGULAR = 5,   /* exact zero pivot: singular matrix, log undefined */
