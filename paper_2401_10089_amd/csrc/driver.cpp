@@ -444,13 +444,18 @@ Status gje_invert(Ctx& c, int nmat, const double* const src[2], double* fin[2]) 
   return st;
 }
 
-Status check_gje_err(Ctx& c, int nmat) {
+// The inversions' error flags: enqueue_gje_err copies them to host memory on the
+// stream (valid after the next synchronisation), gje_err_status reads them.
+Status enqueue_gje_err(Ctx& c, int nmat, int* h) {
   Status st;
-  int h[8] = {0};
   for (int z = 0; z < nmat; ++z)
     HIPCK(hipMemcpyAsync(h + 4 * z, c.at<int>(c.p.err[z]), 4 * sizeof(int), hipMemcpyDeviceToHost,
                          c.s));
-  HIPCK(hipStreamSynchronize(c.s));
+  return st;
+}
+
+Status gje_err_status(const int* h, int nmat) {
+  Status st;
   for (int z = 0; z < nmat; ++z) {
     if (h[4 * z] & 2) {   // a bounded wait in the pivot search gave up
       st.code = LOGM_EHIP;
@@ -460,6 +465,14 @@ Status check_gje_err(Ctx& c, int nmat) {
     if (h[4 * z] & 1) st.code = LOGM_ESINGULAR;
   }
   return st;
+}
+
+Status check_gje_err(Ctx& c, int nmat) {
+  Status st;
+  int h[8] = {0};
+  PROPAGATE(enqueue_gje_err(c, nmat, h));
+  HIPCK(hipStreamSynchronize(c.s));
+  return gje_err_status(h, nmat);
 }
 
 // ------------------------------------------------------ square root -----
@@ -515,8 +528,10 @@ Status db_sqrt(Ctx& c, const double* X0, double* Xout, int max_iter, int* iters,
     HIPCK(launch_db_update(d, c.p.nblk, c.s));
     HIPCK(launch_colsum_max(c.part(), 2, c.p.nblk, n, c.scal(), c.at<double>(c.p.bm), c.s));
     double h[9];   // column-sum maxima in 0-1, the scaling factor used in 8
+    int herr[8] = {0};
+    PROPAGATE(enqueue_gje_err(c, nmat, herr));   // one synchronisation for both reads
     PROPAGATE(sync_read(c, h, c.scal(), 9 * sizeof(double)));
-    PROPAGATE(check_gje_err(c, nmat));
+    PROPAGATE(gje_err_status(herr, nmat));
     rel = h[0] / h[1];
     if (!std::isfinite(rel)) {
       st.code = LOGM_ENONFINITE;
