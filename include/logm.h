@@ -174,7 +174,8 @@ int logm_backward_taped(int32_t dtype, int64_t n, const void* G, int64_t ldg, vo
  * <= 128: 13 buffers of 64 x 64 doubles per resident workgroup of the n <= 64 class,
  * plus (n_max > 64) 13 buffers of 128 x 128 doubles per resident workgroup of the
  * 64 < n <= 128 class (the classes run concurrently), plus 256 bytes of queue
- * counters; it does not grow with the batch beyond the device's resident
+ * counters and one int per matrix for the processing order (largest matrices
+ * first); the buffers do not grow with the batch beyond the device's resident
  * workgroups.  total_elems is validated only. */
 int logm_batched_workspace_size(int32_t batch, int64_t total_elems, int32_t n_max, size_t* bytes);
 

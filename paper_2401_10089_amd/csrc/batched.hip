@@ -493,6 +493,7 @@ struct DevScheme {
 
 struct BatchArgs {
   int batch;
+  const int* order;         // processing order: largest matrices first
   const int* dims;
   const int64_t* offsets;   // element offset of matrix i in A and L
   const double* A;
@@ -520,9 +521,10 @@ __global__ __launch_bounds__(256 * RA, 4) void batched_logm_kernel(BatchArgs a) 
     __syncthreads();
     // uniform in fact; readfirstlane keeps n, offsets and the loop bounds derived
     // from them in scalar registers
-    const int item = __builtin_amdgcn_readfirstlane(s_item);
+    const int q = __builtin_amdgcn_readfirstlane(s_item);
     __syncthreads();
-    if (item >= a.batch) return;   // uniform: every wave leaves together
+    if (q >= a.batch) return;   // uniform: every wave leaves together
+    const int item = __builtin_amdgcn_readfirstlane(a.order[q]);
     const int n = a.dims[item];
     const int64_t off = a.offsets[item];
     // a block that lies outside the packed arrays is refused, never touched
@@ -641,8 +643,36 @@ __global__ __launch_bounds__(256 * RA, 4) void batched_logm_kernel(BatchArgs a) 
   }
 }
 
-__global__ void batched_reset_kernel(int* counters) {
-  if (threadIdx.x < 2 && blockIdx.x == 0) counters[threadIdx.x] = 0;
+// Work-queue counters to zero and the processing order: a counting sort of the
+// matrices by decreasing n (one workgroup; invalid sizes first, they are refused at
+// once), so that the persistent workgroups take the longest matrices first and the
+// batch does not end waiting for one large matrix started late.  Within a size the
+// order is unspecified; every matrix's result is independent of it.
+constexpr int ORDER_THREADS = 1024;
+__global__ __launch_bounds__(ORDER_THREADS) void batched_reset_kernel(int* counters, int batch,
+                                                                      const int* dims, int* order) {
+  __shared__ int s_hist[BN_MAX + 2];
+  __shared__ int s_pos[BN_MAX + 2];
+  const int tid = threadIdx.x;
+  if (tid < 2) counters[tid] = 0;
+  for (int b = tid; b < BN_MAX + 2; b += ORDER_THREADS) s_hist[b] = 0;
+  __syncthreads();
+  // bucket 0: invalid size; bucket 1 + (BN_MAX - n): size n, largest first
+  auto bucket = [&](int n) { return (n < 1 || n > BN_MAX) ? 0 : 1 + (BN_MAX - n); };
+  for (int i = tid; i < batch; i += ORDER_THREADS) atomicAdd(&s_hist[bucket(dims[i])], 1);
+  __syncthreads();
+  if (tid == 0) {
+    int acc = 0;
+    for (int b = 0; b < BN_MAX + 1; ++b) {
+      s_pos[b] = acc;
+      acc += s_hist[b];
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < batch; i += ORDER_THREADS) {
+    const int slot = atomicAdd(&s_pos[bucket(dims[i])], 1);
+    order[min(max(slot, 0), batch - 1)] = i;
+  }
 }
 
 // Resident workgroups of a size class over the whole device (the persistent grid).
@@ -674,7 +704,7 @@ size_t class_region_bytes(int batch, int nmax_class, int blocks) {
 size_t batched_workspace_bytes(int batch, int n_max) {
   const size_t small = class_region_bytes(batch, 64, class_blocks<1, 16>());
   const size_t large = (n_max > 64) ? class_region_bytes(batch, 128, class_blocks<2, 16>()) : 0;
-  return small + large + 256;
+  return small + large + 256 + ((size_t)batch * sizeof(int) + 255) / 256 * 256;
 }
 
 namespace {
@@ -722,7 +752,8 @@ hipError_t launch_batched_logm(int batch, int n_max, const int* dims, const int6
   const int nb_large = std::min(batch, class_blocks<2, 16>());
   const size_t small_bytes = class_region_bytes(batch, 64, class_blocks<1, 16>());
   const size_t large_bytes = (n_max > 64) ? class_region_bytes(batch, 128, class_blocks<2, 16>()) : 0;
-  if (ws_bytes < small_bytes + large_bytes + 256) return hipErrorInvalidValue;
+  const size_t order_bytes = ((size_t)batch * sizeof(int) + 255) / 256 * 256;
+  if (ws_bytes < small_bytes + large_bytes + 256 + order_bytes) return hipErrorInvalidValue;
   BatchArgs a{};
   a.batch = batch;
   a.dims = dims;
@@ -730,6 +761,8 @@ hipError_t launch_batched_logm(int batch, int n_max, const int* dims, const int6
   a.A = A;
   a.L = L;
   int* counters = reinterpret_cast<int*>(static_cast<char*>(ws) + small_bytes + large_bytes);
+  int* order = reinterpret_cast<int*>(static_cast<char*>(ws) + small_bytes + large_bytes + 256);
+  a.order = order;
   a.status = status;
   a.total_elems = total_elems;
   a.k_max = k_max;
@@ -745,7 +778,8 @@ hipError_t launch_batched_logm(int batch, int n_max, const int* dims, const int6
       }
     for (int c = 0; c < 7; ++c) a.sch[i].y[c] = y[i][c];
   }
-  hipLaunchKernelGGL(batched_reset_kernel, dim3(1), dim3(64), 0, s, counters);
+  hipLaunchKernelGGL(batched_reset_kernel, dim3(1), dim3(ORDER_THREADS), 0, s, counters, batch, dims,
+                     order);
   BatchArgs as = a, al = a;
   as.ws = static_cast<double*>(ws);
   as.counter = counters;

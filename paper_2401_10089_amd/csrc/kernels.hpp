@@ -206,11 +206,12 @@ hipError_t launch_scale_out(const double* src, int64_t ld, double* dst, int64_t 
 // Workspace bytes of the batched path: 13 buffers of the size class's largest
 // matrix per resident workgroup of the device, one region per class (n <= 64
 // always, 64 < n <= 128 when n_max > 64; the classes run concurrently), plus two
-// work-queue counters.
+// work-queue counters and the processing order (one int per matrix).
 size_t batched_workspace_bytes(int batch, int n_max);
 // Persistent launches over the batch (n_i <= 128): L_i = log(A_i) by Algorithm 1
-// on the device, one workgroup per matrix from a work queue; a counter-reset kernel,
-// then the large class (8 waves, n > split) on `s` beside the small class (4 waves,
+// on the device, one workgroup per matrix from a work queue; a kernel that zeroes the
+// queue counters and orders the matrices by decreasing n (largest first), then the
+// large class (8 waves, n > split) on `s` beside the small class (4 waves,
 // n <= split) on a second stream (forked and joined with events); split (1..64)
 // applies when n_max > 64, otherwise every matrix is in the small class.  No host
 // synchronisation and no memset, so the sequence can be captured in a graph.  h, g:
