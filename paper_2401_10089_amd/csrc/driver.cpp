@@ -38,7 +38,7 @@ constexpr int kNB = 64;
 constexpr int kNBO = 256;
 constexpr int kMats = 11;
 #ifndef LOGM_LOOKAHEAD_WGS
-#define LOGM_LOOKAHEAD_WGS 192
+#define LOGM_LOOKAHEAD_WGS 224   // the autotuner's choice at n = 4096 with the two-wave GEMM
 #endif
 constexpr int kLookaheadWgs = LOGM_LOOKAHEAD_WGS;   // trailing-update workgroups beside a panel
 
