@@ -70,6 +70,7 @@ struct Shm {
   double colk[2][N];         // pivot column of the step, by step parity
   double prow[2][NW][CW];    // pivot row slice per wave, from row half 0 or 1
   double rscale[N];          // 1 / pivot of each row, applied when the inverse is stored
+  double pivabs[N];          // |pivot| of step k, for log|det| after the elimination
   double vec[5][N];          // estimator vectors
   double red[NT];            // reductions
   int perm[N];               // pivot row of step k
@@ -225,8 +226,6 @@ __device__ __forceinline__ bool wg_inverse(Shm<RA, CW>& sh, const double* M, dou
     for (int a = 0; a < RA; ++a) sh.colk[0][l + 64 * a] = EL(x, a, 0);
   }
   __syncthreads();
-  double mant = 1.0;   // |det| = mant 2^expo
-  int expo = 0;
   bool ok = true;
   for (int k = 0; k < n; ++k) {
     const int q = k & 1;
@@ -245,10 +244,6 @@ __device__ __forceinline__ bool wg_inverse(Shm<RA, CW>& sh, const double* M, dou
     const double piv = readlane_d((RA == 2 && p >= 64) ? c[RA - 1] : c[0], lp);
     ok = ok && (piv != 0.0);
     const double rp = pivot_recip(piv);   // 0 for a zero pivot
-    int e1, e2;
-    mant *= frexp(fabs(piv), &e1);
-    mant = frexp(mant, &e2);
-    expo += e1 + e2;
     const int wk = k / CW, bk = k - wk * CW;
     // this wave's slice of the pivot row, with 1 in column k
     const int hp = p >> 6;   // row half of the pivot (the read below picks it)
@@ -263,6 +258,7 @@ __device__ __forceinline__ bool wg_inverse(Shm<RA, CW>& sh, const double* M, dou
       sh.perm[k] = p;
       sh.pinv[p] = k;
       sh.rscale[p] = rp;
+      sh.pivabs[k] = fabs(piv);
     }
     double g[RA];
 #pragma unroll
@@ -300,7 +296,11 @@ __device__ __forceinline__ bool wg_inverse(Shm<RA, CW>& sh, const double* M, dou
     }
   }
   __syncthreads();
-  *logdet = log(mant) + expo * 0.69314718055994530942;
+  // log|det M| = sum of log|pivot_k|, off the elimination's critical path, in a fixed
+  // order (strided per thread, then the workgroup sum); -inf for a zero pivot
+  double lsum = 0.0;
+  for (int k = tid(); k < n; k += nthreads()) lsum += log(sh.pivabs[k]);
+  *logdet = wg_sum(sh.red, lsum);
   return ok;
 }
 
