@@ -247,11 +247,14 @@ __device__ __forceinline__ bool wg_inverse(Shm<RA, CW>& sh, const double* M, dou
     const int wk = k / CW, bk = k - wk * CW;
     // this wave's slice of the pivot row, with 1 in column k
     const int hp = p >> 6;   // row half of the pivot (the read below picks it)
-    if (l == lp) {
+    if (l == lp) {   // hp is wave-uniform: a scalar branch keeps the register index static
+      if (RA == 1 || hp == 0) {
 #pragma unroll
-      for (int a = 0; a < RA; ++a)
+        for (int b = 0; b < CW; ++b) sh.prow[0][w][b] = EL(x, 0, b);
+      } else {
 #pragma unroll
-        for (int b = 0; b < CW; ++b) sh.prow[a][w][b] = EL(x, a, b);
+        for (int b = 0; b < CW; ++b) sh.prow[1][w][b] = EL(x, RA - 1, b);
+      }
       if (w == wk) sh.prow[hp][w][bk] = 1.0;
     }
     if (tid() == 0) {
