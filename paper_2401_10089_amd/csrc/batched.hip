@@ -68,7 +68,6 @@ struct Shm {
   static constexpr int NW = N / CW;   // waves
   static constexpr int NT = 64 * NW;  // threads
   double colk[2][N];         // pivot column of the step, by step parity
-  double prow[2][NW][CW];    // pivot row slice per wave, from row half 0 or 1
   double rscale[N];          // 1 / pivot of each row, applied when the inverse is stored
   double pivabs[N];          // |pivot| of step k, for log|det| after the elimination
   double vec[5][N];          // estimator vectors
@@ -247,16 +246,6 @@ __device__ __forceinline__ bool wg_inverse(Shm<RA, CW>& sh, const double* M, dou
     const int wk = k / CW, bk = k - wk * CW;
     // this wave's slice of the pivot row, with 1 in column k
     const int hp = p >> 6;   // row half of the pivot (the read below picks it)
-    if (l == lp) {   // hp is wave-uniform: a scalar branch keeps the register index static
-      if (RA == 1 || hp == 0) {
-#pragma unroll
-        for (int b = 0; b < CW; ++b) sh.prow[0][w][b] = EL(x, 0, b);
-      } else {
-#pragma unroll
-        for (int b = 0; b < CW; ++b) sh.prow[1][w][b] = EL(x, RA - 1, b);
-      }
-      if (w == wk) sh.prow[hp][w][bk] = 1.0;
-    }
     if (tid() == 0) {
       sh.perm[k] = p;
       sh.pinv[p] = k;
@@ -271,12 +260,20 @@ __device__ __forceinline__ bool wg_inverse(Shm<RA, CW>& sh, const double* M, dou
       g[a] = isp ? 0.0 : c[a] * rp;
       if (w == wk) dyn_set(x, a, bk, isp ? 1.0 : 0.0);
     }
-    __builtin_amdgcn_wave_barrier();
+    // this wave's slice of the pivot row straight from lane lp's registers (column k
+    // already holds its 1); hp is wave-uniform, so the branch keeps indices static
+    double rrow[CW];
+    if (RA == 1 || hp == 0) {
+#pragma unroll
+      for (int b = 0; b < CW; ++b) rrow[b] = readlane_d(EL(x, 0, b), lp);
+    } else {
+#pragma unroll
+      for (int b = 0; b < CW; ++b) rrow[b] = readlane_d(EL(x, RA - 1, b), lp);
+    }
 #pragma unroll
     for (int b = 0; b < CW; ++b) {
-      const double r = sh.prow[hp][w][b];
 #pragma unroll
-      for (int a = 0; a < RA; ++a) EL(x, a, b) = fma(-g[a], r, EL(x, a, b));
+      for (int a = 0; a < RA; ++a) EL(x, a, b) = fma(-g[a], rrow[b], EL(x, a, b));
     }
     if (k + 1 < n) {   // the owner of column k + 1 publishes it
       const int w1 = (k + 1) / CW, b1 = (k + 1) - w1 * CW;
