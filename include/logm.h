@@ -188,7 +188,7 @@ int logm_batched_workspace_size(int32_t batch, int64_t total_elems, int32_t n_ma
  * int32[4 * batch]): per matrix {LOGM_* code, s, k, iterations}, where iterations
  * packs the Denman-Beavers iteration count of root r < 6 into bits 5r..5r+4
  * (saturating at 31).  A matrix that fails gets its code and leaves L_i undefined;
- * the other matrices are unaffected; a block with n_i outside [1, 128] or reaching
+ * the other matrices are unaffected; a block with n_i outside [1, n_max] or reaching
  * outside [0, total_elems) gets LOGM_EINVAL and is not read or written.
  * ws (device, required, logm_batched_workspace_size bytes, queried on the device
  * the call runs on).  Only o->graph_fp32 = 0.

@@ -66,6 +66,12 @@ R13 Balancing (steps 1 and 14, the paper calls MATLAB's balance): the
     eigenvalues of reducible matrices, is not applied.  Off by default.
 R12 Reverse mode: the decisions (s, k, iterations per root) and the scaling
     factors mu are constants of the differentiated map.
+R14 maxiter: Algorithm 1's loop takes at most maxiter (``max_sqrt``) roots and
+    evaluates the finish test after every root, the last one included (the loop
+    condition alone would leave the last root untested); when the test still fails
+    after maxiter roots, the approximation would fall outside the backward-error
+    bound of Section 5, and the method reports non-convergence instead of returning
+    it.  With maxiter = 0 the finish test is still evaluated once on A itself.
 """
 
 from __future__ import annotations
@@ -489,14 +495,16 @@ def balance(A, max_sweeps: int = 100):
 
 
 def logm(A, k_max: int = 5, max_sqrt: int = 50, db_max_iter: int = 30,
-         theta_table=TABLE2, force: dict | None = None, balanced: bool = False):
+         theta_table=TABLE2, force: dict | None = None, balanced: bool = False,
+         progress=None):
     """Principal matrix logarithm by Algorithm 1 (Section 6).
 
     Returns (L, info).  ``force`` = {"s": int, "k": int, "db_iters": [..]}
     replays a given sequence of decisions (number of roots, iterations per root,
     scheme) instead of taking them, so that two implementations can be compared
     without decision flips.  ``balanced`` applies steps 1 and 14 (reading R13):
-    the method runs on T^{-1} A T and returns T L T^{-1}.
+    the method runs on T^{-1} A T and returns T L T^{-1}.  ``progress``, if given, is
+    called with a short message after every square root (long runs report progress).
     """
     A = np.asarray(A)
     if balanced:
@@ -505,7 +513,7 @@ def logm(A, k_max: int = 5, max_sqrt: int = 50, db_max_iter: int = 30,
         if A.ndim == 2 and not np.all(np.isfinite(A)):
             raise OracleError("ENONFINITE", "input has non-finite entries")
         Bal, d, sweeps = balance(A)
-        L, info = logm(Bal, k_max, max_sqrt, db_max_iter, theta_table, force)
+        L, info = logm(Bal, k_max, max_sqrt, db_max_iter, theta_table, force, progress=progress)
         info["balance_sweeps"] = sweeps
         return L * d[:, None] / d[None, :], info
     if A.ndim != 2 or A.shape[0] != A.shape[1] or A.shape[0] < 1:
@@ -539,7 +547,7 @@ def logm(A, k_max: int = 5, max_sqrt: int = 50, db_max_iter: int = 30,
     e_top = e_top1 = None
     if force is None:
         finished = n1 <= th_top
-        while not finished and s < max_sqrt:
+        while not finished:
             e_top = e_top1 = None
             n2 = norm1(B2)
             # first term of eq. alphaapprox, with the shortcut of eq. alpha2term1
@@ -558,6 +566,8 @@ def logm(A, k_max: int = 5, max_sqrt: int = 50, db_max_iter: int = 30,
                     e_top1 = estimate(h_top, 1)
                     t2 = e_top1 ** (1.0 / (mtop + 1)) <= th_top
             finished = t1 and t2
+            if not finished and s == max_sqrt:   # reading R14
+                break
             if not finished:
                 A2 = X
                 X, it, hist, ninv = db_sqrt(X, db_max_iter)
@@ -568,6 +578,8 @@ def logm(A, k_max: int = 5, max_sqrt: int = 50, db_max_iter: int = 30,
                 B = X - eye
                 B2 = A2 - 2.0 * X + eye           # eq. AI2
                 n1 = norm1(B)
+                if progress is not None:
+                    progress(f"oracle: root {s} after {it} Denman-Beavers iterations")
         if not finished:
             raise OracleError("ENOCONV", "no convergence within max_sqrt roots")
         n2 = norm1(B2)
@@ -582,6 +594,8 @@ def logm(A, k_max: int = 5, max_sqrt: int = 50, db_max_iter: int = 30,
             info["n_inv"] += ninv
             B = X - eye
             B2 = A2 - 2.0 * X + eye
+            if progress is not None:
+                progress(f"oracle: replayed root {s} ({it} iterations)")
         k = force["k"]
 
     # Step 12: L = -S(-B) with P_2 = -B, P_3 = B^2 (eqs. logipASTM, five_mult_degopt)

@@ -504,6 +504,7 @@ struct BatchArgs {
   int64_t total_elems;      // elements of A and L
   int report_invalid;       // this launch reports blocks outside the arrays
   int split;                // class boundary: the n <= 64 class takes n <= split
+  int n_max;                // largest size the workspace was sized for (<= BN_MAX)
   int k_max, max_sqrt, db_max_iter, theta_source;
   DevScheme sch[5];         // schemes k = 1 .. 5
 };
@@ -528,7 +529,7 @@ __global__ __launch_bounds__(256 * RA, 4) void batched_logm_kernel(BatchArgs a) 
     const int n = a.dims[item];
     const int64_t off = a.offsets[item];
     // a block that lies outside the packed arrays is refused, never touched
-    if (n < 1 || n > BN_MAX || off < 0 || off > a.total_elems - (int64_t)n * n) {
+    if (n < 1 || n > a.n_max || off < 0 || off > a.total_elems - (int64_t)n * n) {
       if (a.report_invalid && tid() == 0) {
         a.status[4 * item + 0] = LOGM_EINVAL;
         a.status[4 * item + 1] = a.status[4 * item + 2] = a.status[4 * item + 3] = 0;
@@ -568,9 +569,11 @@ __global__ __launch_bounds__(256 * RA, 4) void batched_logm_kernel(BatchArgs a) 
         __syncthreads();
       }
       bool finished = n1 <= thtop;
-      while (code == LOGM_OK && !finished && s < a.max_sqrt) {
+      // at most max_sqrt roots, the finish test evaluated after each of them
+      while (code == LOGM_OK && !finished) {
         n2 = wg_norm1<N>(sh.red, B2, n);
         finished = dev_finish_test(sh, B2, B, n, n1, n2, a.k_max, a.theta_source, &dec);
+        if (!finished && s == a.max_sqrt) break;
         if (!finished) {
           double* t = X;   // A2 keeps the matrix whose root is taken
           X = A2;
@@ -770,6 +773,7 @@ hipError_t launch_batched_logm(int batch, int n_max, const int* dims, const int6
   a.db_max_iter = db_max_iter;
   a.theta_source = theta_source;
   a.split = (n_max <= 64) ? 64 : std::min(std::max(split, 1), 64);
+  a.n_max = n_max;
   for (int i = 0; i < 5; ++i) {
     for (int r = 0; r < 4; ++r)
       for (int c = 0; c < 5; ++c) {

@@ -790,12 +790,15 @@ Status forward_r64(Ctx& c, const double* A, int64_t lda, double* L, int64_t ldl,
   bool have_top = false, have_top1 = false;
   double e_top = 0.0, e_top1 = 0.0;
   bool finished = n1 <= thtop;
-  while (!finished && s < o.max_sqrt) {
+  // at most max_sqrt roots, the finish test evaluated after each of them (the last
+  // one included), so that maxiter roots suffice when the last one passes
+  while (!finished) {
     PROPAGATE(norm1(c, B2, &n2));
     bool ok = true;
     finished = finish_test(ecall, n1, n2, mtop, thtop, have_top, e_top, have_top1, e_top1,
                            &info.n_est, &ok);
     if (!ok) return ecall.st;
+    if (!finished && s == o.max_sqrt) break;
     if (!finished) {
       std::swap(X, A2);  // A2 keeps the matrix whose root is taken
       int iters = 0;

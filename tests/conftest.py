@@ -32,3 +32,17 @@ def read_golden(name):
 @pytest.fixture
 def golden():
     return read_golden
+
+
+def decision_cases(read):
+    """The hand-derived decision cases: name -> (A, expected, options), where expected
+    is (s, k, n_est) or an error code such as "ENOCONV" and options holds max_sqrt."""
+    import numpy as np
+
+    out = {}
+    for name, (mat, n, s, k, nest, *opts) in read("decisions.txt").items():
+        kw = dict(o.split("=", 1) for o in opts)
+        A = np.array([float(v) for v in mat.split(",")]).reshape(int(n), int(n))
+        expected = kw["status"] if "status" in kw else (int(s), int(k), int(nest))
+        out[name] = (A, expected, {"max_sqrt": int(kw.get("max_sqrt", 50))})
+    return out

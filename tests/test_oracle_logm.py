@@ -9,6 +9,7 @@ import pytest
 import scipy.linalg as sl
 
 import oracle
+from conftest import decision_cases
 from workloads import disk_matrix, rotscale_matrix
 
 
@@ -134,15 +135,42 @@ def _parse_matrix(txt, n):
 
 
 def test_hand_derived_decisions(golden):
-    """(s, k, number of estimates) from the paper's inequalities, derived by hand."""
-    cases = golden("decisions.txt")
-    assert len(cases) >= 6
-    for name, (mat, n, s, k, nest) in cases.items():
-        A = _parse_matrix(mat, int(n))
-        L, info = oracle.logm(A)
-        assert (info["s"], info["k"], info["n_est"]) == (int(s), int(k), int(nest)), name
-        if int(n) == 1:
+    """(s, k, number of estimates) from the paper's inequalities, derived by hand.
+    Together the cases reach every statement of the finish test and of the degree
+    selection except first_pass's fallback, which Algorithm 1 cannot reach (the
+    finish test leaves every value it is given at or below Theta of the top scheme)."""
+    cases = decision_cases(golden)
+    assert len(cases) >= 15
+    for name, (A, expected, kw) in cases.items():
+        if isinstance(expected, str):
+            with pytest.raises(oracle.OracleError) as e:
+                oracle.logm(A, **kw)
+            assert e.value.code == expected, name
+            continue
+        L, info = oracle.logm(A, **kw)
+        assert (info["s"], info["k"], info["n_est"]) == expected, name
+        if A.shape[0] == 1:
             assert L[0, 0] == pytest.approx(math.log(A[0, 0]), rel=4e-15)
+
+
+def test_hand_derived_decisions_are_accurate(golden):
+    """Each decision is also a valid one: the logarithm it yields matches the
+    50-digit logm of the same matrix."""
+    for name, (A, expected, kw) in decision_cases(golden).items():
+        if isinstance(expected, str):
+            continue
+        L, _ = oracle.logm(A, **kw)
+        with mpmath.workdps(50):
+            Le = np.array(mpmath.logm(mpmath.matrix(A.tolist())).tolist(), dtype=float)
+        assert np.linalg.norm(L - Le) <= 1e-14 * max(np.linalg.norm(Le), 1.0), name
+
+
+def test_select_degree_fallback_above_top_theta():
+    """first_pass's fallback: a value above every Theta maps to the top scheme (only a
+    direct call reaches it)."""
+    est = lambda q, r: pytest.fail("no estimate expected")  # noqa: E731
+    # e_top above Theta_5: min_in falls back to 5, max_in is 5, so k = 5 at once
+    assert oracle.select_degree(10.0, 1.0, 0.5 ** 14, None, est, (1, 2, 3, 4, 5)) == 5
 
 
 def test_forced_replay_reproduces():
