@@ -252,6 +252,7 @@ def main():
     # the library's launch-shape autotuner picks the trailing-update workgroup cap for
     # this size (outside the timed region)
     lookahead_wgs, _ = lm.autotune(N, dev, ws) if not args.no_autotune else (None, None)
+    lookahead_wgs = dict(zip(("search", "reordered"), lookahead_wgs)) if lookahead_wgs else None
     torch.cuda.synchronize()
 
     info = None
@@ -343,6 +344,8 @@ def main():
             "n_inv": info["n_inv"],
             "n_gemm": info["n_gemm"],
             "n_matvec": info["n_matvec"],
+            "n_inv_reordered": info["n_inv_reordered"],
+            "n_order_rejected": info["n_order_rejected"],
             "algorithmic_flops_per_step": info["flops"],
             "event_ms_per_step": ev_ms / args.steps,
             "lookahead_wgs": lookahead_wgs,

@@ -80,7 +80,14 @@ typedef struct logm_opts {
                            applied).  logm_forward only: logm_backward differentiates
                            the unbalanced map (the same function) and logm_batched_f64
                            rejects it. */
-  int32_t reserved[2];  /* must be zero */
+  int32_t pivot_search; /* 0 (default): an inversion of the square-root iteration may
+                           take the row order of the previous inversion of the same
+                           iterate (X or Y) instead of searching for pivots; the result
+                           is kept only if every elimination multiplier is at most 2 in
+                           magnitude, otherwise the inversion is redone with the search
+                           (logm_forward only; the reverse mode always searches);
+                           1: pivot search (tournament) for every inversion */
+  int32_t reserved;     /* must be zero */
 } logm_opts;
 
 /* Decisions and counters of one call (host memory). */
@@ -97,6 +104,9 @@ typedef struct logm_info {
   double norm1_b;        /* ||A^{1/2^s} - I||_1 */
   double norm1_b2;       /* ||(A^{1/2^s} - I)^2||_1 (saved-product form, eq. AI2) */
   int32_t status_detail; /* hipError_t when LOGM_EHIP */
+  int32_t n_inv_reordered; /* inverses computed in a previous inversion's row order */
+  int32_t n_order_rejected; /* such attempts rejected by the multiplier check (and redone
+                               with the pivot search; not counted in n_inv twice) */
 } logm_info;
 
 /* Fill *o with the defaults listed above. */
@@ -276,11 +286,15 @@ int logm_balance_f64(int64_t n, const double* A, int64_t lda, double* B, int64_t
 /* Launch-shape autotuner: for matrices padded like n, times the inversion of two
  * synthetic n x n matrices (the shape of a Denman-Beavers iteration) with each
  * candidate cap on the workgroups of the trailing-update GEMM that runs beside the
- * panel factorization (96 .. 256), and keeps the fastest for all later calls of
- * this process with that padded size (the compile-time default, overridable by
- * LOGM_LOOKAHEAD_WGS at build time, applies until then).  *best_wgs (host) receives
- * the cap, *best_ms (host, may be NULL) the time of one inversion pair.  ws as for
- * logm_forward with the same n (NULL: allocated and freed).  Synchronises `stream`. */
+ * panel factorization, once with the pivot search (caps 96 .. 256) and once in the
+ * row order the search left (caps 224 .. 512: that panel chain is shorter, so the
+ * GEMM may take more of the device), and keeps the fastest of each for all later
+ * calls of this process with that padded size (the compile-time defaults,
+ * overridable by LOGM_LOOKAHEAD_WGS and LOGM_LOOKAHEAD_WGS_REORDERED at build time,
+ * apply until then).  best_wgs (host, 2 entries) receives the caps [search, given
+ * order], best_ms (host, 2 entries, may be NULL) the time of one inversion pair in
+ * each mode.  ws as for logm_forward with the same n (NULL: allocated and freed).
+ * Synchronises `stream`. */
 int logm_autotune(int64_t n, void* ws, size_t ws_bytes, void* stream, int32_t* best_wgs,
                   double* best_ms);
 

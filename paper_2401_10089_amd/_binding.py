@@ -81,7 +81,8 @@ class LogmOpts(ctypes.Structure):
         ("theta_source", ctypes.c_int32),
         ("graph_fp32", ctypes.c_int32),
         ("balance", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 2),
+        ("pivot_search", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -99,6 +100,8 @@ class LogmInfo(ctypes.Structure):
         ("norm1_b", ctypes.c_double),
         ("norm1_b2", ctypes.c_double),
         ("status_detail", ctypes.c_int32),
+        ("n_inv_reordered", ctypes.c_int32),
+        ("n_order_rejected", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -114,6 +117,8 @@ class LogmInfo(ctypes.Structure):
             "flops": self.flops,
             "norm1_b": self.norm1_b,
             "norm1_b2": self.norm1_b2,
+            "n_inv_reordered": self.n_inv_reordered,
+            "n_order_rejected": self.n_order_rejected,
         }
 
 
@@ -282,10 +287,12 @@ def _workspace(n: int, device, workspace=None, dtype: int = LOGM_R64):
 
 
 def logm(A, k_max: int = 5, max_sqrt: int = 50, db_max_iter: int = 30, theta_source: int = 0,
-         out=None, workspace=None, graph_fp32: bool = False, balance: bool = False):
+         out=None, workspace=None, graph_fp32: bool = False, balance: bool = False,
+         pivot_search: bool = False):
     """L = log(A) on the GPU (Algorithm 1), A float64 or complex128.  Returns (L, info
     dict).  graph_fp32 runs the graph products on the fp32 matrix cores (see
-    logm_opts); complex A runs on its 2n x 2n real representation."""
+    logm_opts); complex A runs on its 2n x 2n real representation; pivot_search
+    searches pivots in every inversion instead of trying the previous row order."""
     torch = _torch()
     A = _as_matrix(A, allow_complex=True)
     n = A.shape[0]
@@ -295,6 +302,7 @@ def logm(A, k_max: int = 5, max_sqrt: int = 50, db_max_iter: int = 30, theta_sou
     o.k_max, o.max_sqrt, o.db_max_iter, o.theta_source = k_max, max_sqrt, db_max_iter, theta_source
     o.graph_fp32 = 1 if graph_fp32 else 0
     o.balance = 1 if balance else 0
+    o.pivot_search = 1 if pivot_search else 0
     ws = _workspace(n, A.device, workspace, dt)
     info = LogmInfo()
     rc = lib().logm_forward(dt, n, _vp(A.data_ptr()), A.stride(0), _vp(L.data_ptr()), L.stride(0),
@@ -583,17 +591,18 @@ def balance(A, workspace=None):
 
 
 def autotune(n: int, device=None, workspace=None):
-    """Choose the trailing-update workgroup cap for size n by timing (see
-    logm_autotune); returns (cap, ms per inversion pair)."""
+    """Choose the trailing-update workgroup caps for size n by timing (see
+    logm_autotune); returns ((cap with the pivot search, cap in a given row order),
+    (ms per inversion pair in each mode))."""
     torch = _torch()
     device = device or torch.device("cuda:0")
     ws = workspace if workspace is not None else torch.empty(workspace_size(n), dtype=torch.uint8, device=device)
-    best = _i32(0)
-    ms = _f64(0)
+    best = (_i32 * 2)()
+    ms = (_f64 * 2)()
     rc = lib().logm_autotune(n, _vp(ws.data_ptr()), ws.numel(),
-                             _vp(torch.cuda.current_stream(device).cuda_stream), ctypes.byref(best), ctypes.byref(ms))
+                             _vp(torch.cuda.current_stream(device).cuda_stream), best, ms)
     _check(rc, "logm_autotune")
-    return best.value, ms.value
+    return (best[0], best[1]), (ms[0], ms[1])
 
 
 def sqrtm(A, db_max_iter: int = 30, workspace=None):

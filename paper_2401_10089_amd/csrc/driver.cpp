@@ -40,15 +40,28 @@ constexpr int kMats = 11;
 #ifndef LOGM_LOOKAHEAD_WGS
 #define LOGM_LOOKAHEAD_WGS 224   // the autotuner's choice at n = 4096 with the two-wave GEMM
 #endif
-constexpr int kLookaheadWgs = LOGM_LOOKAHEAD_WGS;   // trailing-update workgroups beside a panel
+#ifndef LOGM_LOOKAHEAD_WGS_REORDERED
+#define LOGM_LOOKAHEAD_WGS_REORDERED 384
+#endif
+// trailing-update workgroups beside a panel factorization: with the pivot search,
+// and with a given row order (a shorter panel chain, so more room for the GEMM)
+constexpr int kLookaheadWgs[2] = {LOGM_LOOKAHEAD_WGS, LOGM_LOOKAHEAD_WGS_REORDERED};
+// Pivot order reuse: an inversion in the previous one's row order is kept only if
+// every multiplier is at most kReuseTau in magnitude (threshold partial pivoting);
+// it is tried when the previous Denman-Beavers step changed the iterate by less
+// than kReuseTry relative (by less than kReuseRetry after a rejected attempt).
+constexpr double kReuseTau = 2.0;
+constexpr double kReuseTry = 1.0;
+constexpr double kReuseRetry = 0.5;
 
-// The cap per padded size chosen by logm_autotune (process-wide); the default otherwise.
+// The cap per padded size and mode (0: search, 1: given order) chosen by
+// logm_autotune (process-wide); the default otherwise.
 std::mutex g_cap_mu;
-std::map<int, int> g_cap;
-int lookahead_wgs(int n_pad) {
+std::map<std::pair<int, int>, int> g_cap;
+int lookahead_wgs(int n_pad, int known) {
   std::lock_guard<std::mutex> lk(g_cap_mu);
-  const auto it = g_cap.find(n_pad);
-  return it == g_cap.end() ? kLookaheadWgs : it->second;
+  const auto it = g_cap.find({n_pad, known});
+  return it == g_cap.end() ? kLookaheadWgs[known] : it->second;
 }
 
 // Batched class boundary per device chosen by logm_batched_autotune (process-wide):
@@ -207,7 +220,7 @@ struct Plan {
   size_t W[2];
   size_t logdet[2];
   size_t pi[2][2];         // [matrix][outer-step parity]
-  size_t ptot[2], pinv[2], qsel[2], vac[2], cand[2], cnt[2], err[2];
+  size_t ptot[2], pinv[2], qsel[2], vac[2], cand[2], cnt[2], err[2], order[2];
   size_t part, bm, vec, scal, iflag, bal;
   size_t total = 0;
 };
@@ -228,7 +241,7 @@ Plan make_plan(int64_t n) {
   for (int z = 0; z < 2; ++z) {
     for (int q = 0; q < 2; ++q)
       for (int b = 0; b < 2; ++b) p.panel[z][q][b] = take(np * kNBO * sizeof(double));
-    p.W[z] = take(kNB * kNB * sizeof(double));
+    p.W[z] = take(2 * kNB * kNB * sizeof(double));   // two slots: a given order alternates
     p.logdet[z] = take(np / kNB * sizeof(double));
     for (int q = 0; q < 2; ++q) p.pi[z][q] = take(np * sizeof(int));
     p.ptot[z] = take(np * sizeof(int));
@@ -238,6 +251,7 @@ Plan make_plan(int64_t n) {
     p.cand[z] = take((size_t)gje_cand_ints(p.n_pad) * sizeof(int));
     p.cnt[z] = take((size_t)gje_cnt_ints(p.n_pad) * sizeof(int));
     p.err[z] = take(4 * sizeof(int));
+    p.order[z] = take(np * sizeof(int));
   }
   p.part = take(2 * (size_t)p.nblk * np * sizeof(double));
   p.bm = take(2 * (np / 64 + 2) * sizeof(double));
@@ -285,6 +299,12 @@ struct Ctx {
   T* at(size_t off) const {
     return reinterpret_cast<T*>(base + off);
   }
+  // Pivot order reuse (forward only): an inversion may take the row order of the
+  // previous inversion of the same matrix sequence (X or Y), checked by its
+  // multipliers, instead of searching for pivots.
+  bool reuse = false;
+  bool have_order[2] = {false, false};   // order[z] holds a previous inversion's rows
+  int reuse_tries = 0, reuse_fails = 0;
   double* part() const { return at<double>(p.part); }
   double* scal() const { return at<double>(p.scal); }
   int* iflag() const { return at<int>(p.iflag); }
@@ -308,10 +328,12 @@ Status norm1(Ctx& c, const double* M, double* out) {
 }
 
 // ------------------------------------------------------- Gauss-Jordan ----
-GjeArgs gje_args(Ctx& c, int nmat, int parity) {
+GjeArgs gje_args(Ctx& c, int nmat, int parity, bool known) {
   GjeArgs a{};
   a.nmat = nmat;
   a.n_pad = c.p.n_pad;
+  a.known = known ? 1 : 0;
+  a.tau = kReuseTau;
   for (int z = 0; z < nmat; ++z) {
     GjeMat& m = a.m[z];
     m.P[0] = c.at<double>(c.p.panel[z][parity][0]);
@@ -326,6 +348,7 @@ GjeArgs gje_args(Ctx& c, int nmat, int parity) {
     m.cnt = c.at<int>(c.p.cnt[z]);
     m.logdet = c.at<double>(c.p.logdet[z]);
     m.err = c.at<int>(c.p.err[z]);
+    m.order = c.at<int>(c.p.order[z]);
   }
   return a;
 }
@@ -335,23 +358,28 @@ struct OuterStep {
   int k0, nbo;
 };
 
-// Panel of one outer step: copy the block column, then the inner 64-wide steps
-// (tournament pivot selection + panel update).  pcur ends on the processed panel.
-Status factor_panel(GjeArgs& a, hipStream_t s) {
+// Panel of one outer step: copy the block column (unless the look-ahead update wrote
+// it: panel_written) and, in a given row order, factor its first pivot block; then
+// the inner 64-wide steps: tournament pivot selection + panel update, or in a given
+// order the panel update alone (each launch also factors the next pivot block).
+// pcur ends on the processed panel.
+Status factor_panel(GjeArgs& a, hipStream_t s, bool panel_written = false) {
   Status st;
   a.pcur = 0;
-  HIPCK(launch_gje_panel_copy(a, s));
+  if (!panel_written) HIPCK(launch_gje_panel_copy(a, s));
+  if (a.known) HIPCK(launch_gje_lu64(a, s));
   for (int c0 = 0; c0 < a.nbo; c0 += kNB) {
     a.c0 = c0;
     a.r0 = a.k0 + c0;
-    HIPCK(launch_gje_tournament(a, s));
+    if (!a.known) HIPCK(launch_gje_tournament(a, s));
     HIPCK(launch_gje_inner_update(a, s));
     a.pcur ^= 1;
   }
   return st;
 }
 
-Status outer_update(Ctx& c, const GjeArgs& a, int c_lo, int c_hi, bool inside, int max_wgs = 0) {
+Status outer_update(Ctx& c, const GjeArgs& a, int c_lo, int c_hi, bool inside, int max_wgs = 0,
+                    double* const* next_panel = nullptr, int next_nbo = 0) {
   Status st;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (g_prof.on) {
@@ -359,7 +387,7 @@ Status outer_update(Ctx& c, const GjeArgs& a, int c_lo, int c_hi, bool inside, i
     e1 = g_prof.get();
     if (e0) HIPCK(hipEventRecord(e0, c.s));
   }
-  HIPCK(launch_gje_outer_update(a, c_lo, c_hi, inside, max_wgs, c.s));
+  HIPCK(launch_gje_outer_update(a, c_lo, c_hi, inside, max_wgs, c.s, next_panel, next_nbo));
   if (g_prof.on && e0 && e1) {
     HIPCK(hipEventRecord(e1, c.s));
     // algorithmic work: the columns outside the step's block get a rank-nbo update
@@ -384,30 +412,36 @@ Status outer_update(Ctx& c, const GjeArgs& a, int c_lo, int c_hi, bool inside, i
 }
 
 // Invert nmat padded matrices src[z] (identity on the pad).  The permuted result is
-// left in fin[z]; pinv, logdet slots and error flags are in the workspace.
+// left in fin[z]; pinv, logdet slots and error flags are in the workspace, and the
+// row order in order[z].  known: the pivot rows are taken in the order of order[z]
+// (no search); err[z][1] then reports whether that order kept every multiplier
+// within kReuseTau (otherwise the result must not be used).
 //
 // Look-ahead: the outer update of step K first updates the columns of step K+1's
 // panel; the side stream then factors that panel while the rest of step K's update
 // runs on the main stream.  Panels and gather maps alternate between two buffers
 // by step parity, so the side stream never touches what the running update reads.
-Status gje_invert(Ctx& c, int nmat, const double* const src[2], double* fin[2]) {
+Status gje_invert(Ctx& c, int nmat, const double* const src[2], double* fin[2],
+                  bool known = false) {
   Status st;
   const int np = c.p.n_pad;
   std::vector<OuterStep> steps;
   for (int k0 = 0; k0 < np; k0 += kNBO) steps.push_back({k0, std::min(kNBO, np - k0)});
   const int nsteps = (int)steps.size();
-  GjeArgs a0 = gje_args(c, nmat, 0);
+  GjeArgs a0 = gje_args(c, nmat, 0, known);
   HIPCK(launch_gje_begin(a0, c.s));
   const double* cur[2] = {src[0], nmat > 1 ? src[1] : nullptr};
   int flip = 0;
   const bool ahead = nsteps > 1 && c.side != nullptr;
   for (int K = 0; K < nsteps; ++K) {
-    GjeArgs a = gje_args(c, nmat, K & 1);
+    GjeArgs a = gje_args(c, nmat, K & 1, known);
     a.k0 = steps[K].k0;
     a.nbo = steps[K].nbo;
     for (int z = 0; z < nmat; ++z) {
       a.m[z].Min = cur[z];
       a.m[z].Mout = c.mat(5 + 2 * z + flip);
+      // a given order moves no row after the first step's gather
+      if (known && K > 0) a.m[z].pi = nullptr;
     }
     if (K == 0 || !ahead) {
       PROPAGATE(factor_panel(a, c.s));
@@ -418,23 +452,25 @@ Status gje_invert(Ctx& c, int nmat, const double* const src[2], double* fin[2]) 
     if (ahead && K + 1 < nsteps) {
       const int n_lo = steps[K + 1].k0;
       const int n_hi = n_lo + steps[K + 1].nbo;
-      PROPAGATE(outer_update(c, a, n_lo, n_hi, true));
-      HIPCK(hipEventRecord(c.ev_upd, c.s));
-      GjeArgs b = gje_args(c, nmat, (K + 1) & 1);
+      GjeArgs b = gje_args(c, nmat, (K + 1) & 1, known);
       b.k0 = steps[K + 1].k0;
       b.nbo = steps[K + 1].nbo;
       for (int z = 0; z < nmat; ++z) {
         b.m[z].Min = a.m[z].Mout;
         b.m[z].Mout = nullptr;
       }
+      // in a given order the look-ahead columns go straight into the next panel
+      double* next_panel[2] = {b.m[0].P[0], nmat > 1 ? b.m[1].P[0] : nullptr};
+      PROPAGATE(outer_update(c, a, n_lo, n_hi, true, 0, known ? next_panel : nullptr, b.nbo));
+      HIPCK(hipEventRecord(c.ev_upd, c.s));
       HIPCK(hipStreamWaitEvent(c.side, c.ev_upd, 0));
-      PROPAGATE(factor_panel(b, c.side));
+      PROPAGATE(factor_panel(b, c.side, known));
       HIPCK(hipEventRecord(c.ev_pan, c.side));
       // the rest of the update runs beside the next panel's factorization, which is
       // the critical path: cap its workgroups so that the panel kernels find free CUs
-      PROPAGATE(outer_update(c, a, n_lo, n_hi, false, lookahead_wgs(c.p.n_pad) / a.nmat));
+      PROPAGATE(outer_update(c, a, n_lo, n_hi, false, lookahead_wgs(c.p.n_pad, a.known) / a.nmat));
     } else {
-      PROPAGATE(outer_update(c, a, 0, np, true));
+      PROPAGATE(outer_update(c, a, 0, 0, false));   // every column, full tiles
     }
     for (int z = 0; z < nmat; ++z) cur[z] = a.m[z].Mout;
     flip ^= 1;
@@ -496,13 +532,33 @@ Status db_sqrt(Ctx& c, const double* X0, double* Xout, int max_iter, int* iters,
   double rel_prev = INFINITY;
   const double tol = std::sqrt((double)n) * kU;
   double rel = INFINITY;
+  // change of the iterate before the first iteration: X_0 is the previous root's
+  // converged iterate, whose last inversion left its order in order[0]
+  double rel_last = c.have_order[0] ? 0.0 : INFINITY;
+  double try_below = kReuseTry;
   int it = 1;
   for (; it <= max_iter; ++it) {
     const int nmat = (it == 1) ? 1 : 2;
     const double* Xcur = (it == 1) ? X0 : Xout;
     const double* src[2] = {Xcur, Y};
     double* fin[2] = {nullptr, nullptr};
-    PROPAGATE(gje_invert(c, nmat, src, fin));
+    const bool known = c.reuse && c.have_order[0] && (nmat == 1 || c.have_order[1]) &&
+                       rel_last < try_below;
+    PROPAGATE(gje_invert(c, nmat, src, fin, known));
+    if (known) {   // keep the result only if the given order passed its check
+      int herr[8] = {0};
+      PROPAGATE(enqueue_gje_err(c, nmat, herr));
+      HIPCK(hipStreamSynchronize(c.s));
+      bool rejected = false;
+      for (int z = 0; z < nmat; ++z) rejected |= herr[4 * z + 1] != 0;
+      c.reuse_tries += nmat;
+      if (rejected) {
+        c.reuse_fails += nmat;
+        try_below = kReuseRetry;
+        PROPAGATE(gje_invert(c, nmat, src, fin, false));
+      }
+    }
+    for (int z = 0; z < nmat; ++z) c.have_order[z] = true;
     *ninv += nmat;
     if (tape != nullptr)
       for (int z = 0; z < nmat; ++z)
@@ -539,6 +595,7 @@ Status db_sqrt(Ctx& c, const double* X0, double* Xout, int max_iter, int* iters,
     }
     if (tape != nullptr) tape->mu.push_back(h[8]);
     const bool stop = db_stop(rel, rel_prev, scaled, tol);
+    rel_last = rel;
     if ((tape != nullptr && tape->force_iters > 0) ? it == tape->force_iters : stop) {
       *iters = it;
       return st;
@@ -767,6 +824,10 @@ Status forward_r64(Ctx& c, const double* A, int64_t lda, double* L, int64_t ldl,
   double* B = c.mat(3);
   double* B2 = c.mat(4);
   int* nonfinite = c.iflag();
+  // the taped forward replays roots bit for bit in the reverse sweep: it searches
+  c.reuse = rc == nullptr && o.pivot_search == 0;
+  c.have_order[0] = c.have_order[1] = false;
+  c.reuse_tries = c.reuse_fails = 0;
   HIPCK(hipMemsetAsync(nonfinite, 0, sizeof(int), c.s));
   HIPCK(launch_load_padded(A, lda, X, n, np, 1.0, nonfinite, c.s));
   int bad = 0;
@@ -839,6 +900,8 @@ Status forward_r64(Ctx& c, const double* A, int64_t lda, double* L, int64_t ldl,
   info.k = k;
   info.m = T.m[k];
   info.n_matvec = est.nmv;
+  info.n_inv_reordered = c.reuse_tries - c.reuse_fails;
+  info.n_order_rejected = c.reuse_fails;
   info.norm1_b = n1;
   info.norm1_b2 = n2;
   const double nd = n;
@@ -1170,10 +1233,56 @@ Status backward_r64(Ctx& c, const double* A, int64_t lda, const double* G, int64
 }
 
 // -------------------------------------------------------- call wrapper ---
+// Look-ahead resources of a call (a side stream and two events), pooled per device:
+// a call takes a set and gives it back, so concurrent calls never share one and a
+// process creates only as many sets as it ever ran calls at the same time.
+struct SideRes {
+  hipStream_t side = nullptr;
+  hipEvent_t upd = nullptr, pan = nullptr;
+};
+std::mutex g_side_mu;
+std::map<int, std::vector<SideRes>> g_side_pool;
+
+bool side_create(SideRes& r) {
+  if (hipStreamCreateWithFlags(&r.side, hipStreamNonBlocking) != hipSuccess) {
+    r = SideRes{};
+    return false;
+  }
+  if (hipEventCreateWithFlags(&r.upd, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&r.pan, hipEventDisableTiming) != hipSuccess) {
+    if (r.upd != nullptr) (void)hipEventDestroy(r.upd);
+    (void)hipStreamDestroy(r.side);
+    r = SideRes{};
+    return false;
+  }
+  return true;
+}
+
+// A set from the pool of device dev; a new one when the pool is empty and create.
+bool side_take(int dev, SideRes& r, bool create) {
+  {
+    std::lock_guard<std::mutex> lk(g_side_mu);
+    auto& pool = g_side_pool[dev];
+    if (!pool.empty()) {
+      r = pool.back();
+      pool.pop_back();
+      return true;
+    }
+  }
+  return create && side_create(r);
+}
+
+void side_give(int dev, const SideRes& r) {
+  std::lock_guard<std::mutex> lk(g_side_mu);
+  g_side_pool[dev].push_back(r);
+}
+
 struct Call {
   Ctx c;
   bool owned = false;
   Status st;
+  int dev = -1;
+  SideRes side;
   Call(int64_t n, void* ws, size_t ws_bytes, void* stream, const logm_opts* bwd = nullptr,
        size_t extra = 0) {
     c.s = reinterpret_cast<hipStream_t>(stream);
@@ -1198,22 +1307,19 @@ struct Call {
       c.base = static_cast<char*>(ws);
       c.bytes = ws_bytes;
     }
-    // look-ahead resources; without them the inversion runs on the main stream only
-    if (hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking) != hipSuccess) c.side = nullptr;
-    if (c.side != nullptr &&
-        (hipEventCreateWithFlags(&c.ev_upd, hipEventDisableTiming) != hipSuccess ||
-         hipEventCreateWithFlags(&c.ev_pan, hipEventDisableTiming) != hipSuccess)) {
-      (void)hipStreamDestroy(c.side);
-      c.side = nullptr;
+    // look-ahead resources, needed when an inversion has more than one outer step;
+    // without them the inversion runs on the main stream only
+    if (c.p.n_pad > kNBO && hipGetDevice(&dev) == hipSuccess && side_take(dev, side, true)) {
+      c.side = side.side;
+      c.ev_upd = side.upd;
+      c.ev_pan = side.pan;
     }
   }
   ~Call() {
     if (c.side != nullptr) {
       (void)hipStreamSynchronize(c.side);   // error paths can leave a panel in flight
-      (void)hipStreamDestroy(c.side);
+      side_give(dev, side);
     }
-    if (c.ev_upd != nullptr) (void)hipEventDestroy(c.ev_upd);
-    if (c.ev_pan != nullptr) (void)hipEventDestroy(c.ev_pan);
     if (owned) {
       (void)hipFreeAsync(c.base, c.s);
       (void)hipStreamSynchronize(c.s);
@@ -1228,8 +1334,8 @@ bool opts_ok(const logm_opts& o) {
   if (o.theta_source != 0 && o.theta_source != 1) return false;
   if (o.graph_fp32 != 0 && o.graph_fp32 != 1) return false;
   if (o.balance != 0 && o.balance != 1) return false;
-  for (int i = 0; i < 2; ++i)
-    if (o.reserved[i] != 0) return false;
+  if (o.pivot_search != 0 && o.pivot_search != 1) return false;
+  if (o.reserved != 0) return false;
   return true;
 }
 
@@ -1804,44 +1910,56 @@ int logm_autotune(int64_t n, void* ws, size_t ws_bytes, void* stream, int32_t* b
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIPCK(hipEventCreate(&e0));
     HIPCK(hipEventCreate(&e1));
-    const int cand[] = {96, 128, 160, 192, 224, 256};
-    int best = kLookaheadWgs;
-    float best_t = 0.0f;
-    for (int wgs : cand) {
+    const std::vector<int> cand[2] = {{96, 128, 160, 192, 224, 256},
+                                      {224, 256, 320, 384, 448, 512}};
+    for (int known = 0; known < 2 && st.code == LOGM_OK; ++known) {
+      int best = kLookaheadWgs[known];
+      float best_t = 0.0f;
+      // the given-order mode takes the order the searching inversions left
+      bool usable = true;
+      for (int wgs : cand[known]) {
+        {
+          std::lock_guard<std::mutex> lk(g_cap_mu);
+          g_cap[{np, known}] = wgs;
+        }
+        Status s1 = gje_invert(c, 2, src, fin, known != 0);   // warm-up
+        if (s1.code != LOGM_OK) st = s1;
+        if (known && st.code == LOGM_OK) {
+          int h[8] = {0};
+          PROPAGATE(enqueue_gje_err(c, 2, h));
+          HIPCK(hipStreamSynchronize(c.s));
+          if (h[1] != 0 || h[5] != 0) usable = false;   // order rejected: keep the default
+        }
+        if (!usable) break;
+        if (hipEventRecord(e0, c.s) != hipSuccess) st.code = LOGM_EHIP;
+        for (int r = 0; r < 2 && st.code == LOGM_OK; ++r) {
+          Status s2 = gje_invert(c, 2, src, fin, known != 0);
+          if (s2.code != LOGM_OK) st = s2;
+        }
+        float t = 0.0f;
+        if (st.code == LOGM_OK && (hipEventRecord(e1, c.s) != hipSuccess ||
+                                   hipEventSynchronize(e1) != hipSuccess ||
+                                   hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+          st.code = LOGM_EHIP;
+        if (st.code != LOGM_OK) break;
+        if (best_t == 0.0f || t < best_t) {
+          best_t = t;
+          best = wgs;
+        }
+      }
       {
         std::lock_guard<std::mutex> lk(g_cap_mu);
-        g_cap[np] = wgs;
+        if (st.code == LOGM_OK && usable)
+          g_cap[{np, known}] = best;
+        else
+          g_cap.erase({np, known});
       }
-      Status s1 = gje_invert(c, 2, src, fin);   // warm-up
-      if (s1.code != LOGM_OK) st = s1;
-      if (hipEventRecord(e0, c.s) != hipSuccess) st.code = LOGM_EHIP;
-      for (int r = 0; r < 2 && st.code == LOGM_OK; ++r) {
-        Status s2 = gje_invert(c, 2, src, fin);
-        if (s2.code != LOGM_OK) st = s2;
-      }
-      float t = 0.0f;
-      if (st.code == LOGM_OK && (hipEventRecord(e1, c.s) != hipSuccess ||
-                                 hipEventSynchronize(e1) != hipSuccess ||
-                                 hipEventElapsedTime(&t, e0, e1) != hipSuccess))
-        st.code = LOGM_EHIP;
-      if (st.code != LOGM_OK) break;
-      if (best_t == 0.0f || t < best_t) {
-        best_t = t;
-        best = wgs;
-      }
+      if (st.code == LOGM_OK) PROPAGATE(check_gje_err(c, 2));
+      best_wgs[known] = usable ? best : kLookaheadWgs[known];
+      if (best_ms != nullptr) best_ms[known] = usable ? best_t / 2.0 : 0.0;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    {
-      std::lock_guard<std::mutex> lk(g_cap_mu);
-      if (st.code == LOGM_OK)
-        g_cap[np] = best;
-      else
-        g_cap.erase(np);
-    }
-    if (st.code == LOGM_OK) PROPAGATE(check_gje_err(c, 2));
-    *best_wgs = best;
-    if (best_ms != nullptr) *best_ms = best_t / 2.0;
     return st;
   }();
   return st.code;

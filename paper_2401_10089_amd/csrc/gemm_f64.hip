@@ -285,29 +285,37 @@ struct PolyOp {
 // Rank-nbo Gauss-Jordan trailing update (see gje.hip for the derivation):
 //   out[i][c] = U[i][c-k0]                                    c in K
 //   out[i][c] = [i not in K] * Min[pi(i)][c] + sum_t U[i][t] Min[pi(k0+t)][c]   otherwise
-// where U (n_pad x nbo) is the fully processed panel.
+// where U (n_pad x nbo) is the fully processed panel; pi == nullptr is the identity.
+// With Pn set, the columns [pn_k0, pn_k0 + pn_ld) go to the next step's panel Pn
+// (leading dimension pn_ld) instead of Mout: the look-ahead update of an inversion
+// in a given row order writes that panel directly.
 struct GjeOuterOp {
   const double* U[2];
   const double* Min[2];
   const int* pi[2];
   double* Mout[2];
+  double* Pn[2];
   int64_t ld;
   int k0, nbo;
+  int pn_k0, pn_ld;
   const double* u;
   const double* mi;
   const int* p;
   double* mo;
+  double* pn;
   __device__ void select(int z) {
     const bool one = (z != 0);
     u = one ? U[1] : U[0];
     mi = one ? Min[1] : Min[0];
     p = one ? pi[1] : pi[0];
     mo = one ? Mout[1] : Mout[0];
+    pn = one ? Pn[1] : Pn[0];
   }
+  __device__ int row_of(int i) const { return p != nullptr ? p[i] : i; }
   __device__ bool copy_tile(int, int col0, int tn) const { return col0 >= k0 && col0 + tn <= k0 + nbo; }
   __device__ void copy(int i, int j) const { mo[(int64_t)i * ld + j] = u[(int64_t)i * nbo + (j - k0)]; }
   __device__ const double* a_row(int i) const { return u + (int64_t)i * nbo; }
-  __device__ const double* b_row(int t) const { return mi + (int64_t)p[k0 + t] * ld; }
+  __device__ const double* b_row(int t) const { return mi + (int64_t)row_of(k0 + t) * ld; }
   // branch-free: every load of the group is issued before the first store
   template <int NI>
   __device__ void store_group(const int* rows, const int* cols, double (*v)[NI], int M, int N) const {
@@ -316,7 +324,7 @@ struct GjeOuterOp {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = min(rows[r], M - 1);
-      src[r] = mi + (int64_t)p[i] * ld;
+      src[r] = mi + (int64_t)row_of(i) * ld;
       rowk[r] = rows[r] >= k0 && rows[r] < k0 + nbo;
     }
     bool colk[NI];
@@ -348,7 +356,13 @@ struct GjeOuterOp {
 #pragma unroll
       for (int ni = 0; ni < NI; ++ni) {
         const double out = colk[ni] ? uv[r][ni] : ((rowk[r] ? 0.0 : base[r][ni]) + v[r][ni]);
-        if (rows[r] < M && cols[ni] < N) mo[(int64_t)rows[r] * ld + cols[ni]] = out;
+        if (rows[r] < M && cols[ni] < N) {
+          const int cn = cols[ni] - pn_k0;
+          if (pn != nullptr && cn >= 0 && cn < pn_ld)
+            pn[(int64_t)rows[r] * pn_ld + cn] = out;
+          else
+            mo[(int64_t)rows[r] * ld + cols[ni]] = out;
+        }
       }
   }
 };
@@ -383,17 +397,21 @@ hipError_t launch_gemm_poly(int n, const PolyGemmArgs& a, bool fp32, hipStream_t
 }
 
 hipError_t launch_gje_outer_update(const GjeArgs& a, int c_lo, int c_hi, bool inside,
-                                   int max_wgs, hipStream_t s) {
+                                   int max_wgs, hipStream_t s, double* const* next_panel,
+                                   int next_nbo) {
   GjeOuterOp op{};
   for (int z = 0; z < a.nmat; ++z) {
     op.U[z] = a.m[z].P[a.pcur];
     op.Min[z] = a.m[z].Min;
     op.pi[z] = a.m[z].pi;
     op.Mout[z] = a.m[z].Mout;
+    op.Pn[z] = (next_panel != nullptr) ? next_panel[z] : nullptr;
   }
   op.ld = a.n_pad;
   op.k0 = a.k0;
   op.nbo = a.nbo;
+  op.pn_k0 = c_lo;
+  op.pn_ld = next_nbo;
   if (inside) {
     // the look-ahead columns are on the critical path: small tiles spread them over
     // every CU (c_lo is a multiple of 128, so also of 64)

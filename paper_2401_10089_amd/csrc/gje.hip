@@ -510,54 +510,139 @@ __device__ __forceinline__ void mm32x64(const double (*As)[LDA], const double (*
   }
 }
 
-// Inner Gauss-Jordan step on the panel, IU_ROWS rows per workgroup (see the file
-// comment): C U = Acol and G L = C are solved by 16-column block substitution with
-// explicit inverses of the 16 x 16 diagonal blocks only, then out = base - G R.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void inner_update_kernel(GjeArgs A) {
-  // LU and Di/Ts live during the solves, Rs during the output chunks: the regions
-  // alias so that two workgroups fit in one CU's LDS
-  __shared__ __attribute__((aligned(16))) double s_a[NB * LDA];
-  __shared__ __attribute__((aligned(16))) double s_b[8 * 16 * 17 + IU_ROWS * 17];
-  __shared__ double Cs[IU_ROWS][LDA];
-  double (*LU)[LDA] = reinterpret_cast<double (*)[LDA]>(s_a);          // L (strict lower) and U of the pivot block
-  double (*Rs)[LDA] = reinterpret_cast<double (*)[LDA]>(s_a);          // pivot rows of one column chunk
-  double (*Di)[16][17] = reinterpret_cast<double (*)[16][17]>(s_b);   // inverses of the diagonal blocks: 0-3 of U, 4-7 of L
-  double (*Ts)[17] = reinterpret_cast<double (*)[17]>(s_b + 8 * 16 * 17);
-  __shared__ int s_src[IU_ROWS];
-  __shared__ int s_q[NB];
-
-  const GjeMat& m = A.m[blockIdx.y];
-  const double* P = m.P[A.pcur];
-  double* Q = m.P[A.pcur ^ 1];
-  const int nbo = A.nbo;
-  const int r0 = A.r0;
-  const int c0 = A.c0;
+// Given row order: factors the 64 x 64 block at rows r0s.., columns c0s.. of src
+// (leading dimension ld) without a search and publishes it: tri_out (row-major,
+// unit L strictly below the diagonal, U on and above), *logdet_out = sum log|u_jj|
+// (fixed order), err[1] |= 1 when a multiplier exceeds tau in magnitude or a pivot
+// is zero; s_piv holds 128 doubles (pivots, their logs).  Right-looking in four
+// 16-column panels on the block in LDS (A, 64 x LDA):
+// wave 0 factors a panel with its rows in registers (lane = row, the pivot row
+// broadcast by cross-lane reads, no barrier per step), the 16 x 16 unit-lower
+// solve gives the U rows right of the panel, and the matrix cores take the Schur
+// update.  All 256 threads of the workgroup.
+__device__ __noinline__ void lu64_publish(const double* src, int ld, int r0s, int c0s, double tau,
+                             double* tri_out, double* logdet_out, int* err, double (*A)[LDA],
+                             double* s_piv) {
   const int tid = threadIdx.x;
-  const int row0 = blockIdx.x * IU_ROWS;
-  const bool inblock = row0 >= r0 && row0 < r0 + NB;
-
-  // source row of each output row: the selected row inside the block, the displaced
-  // block row at a vacated position, the row itself elsewhere
-  if (tid < IU_ROWS) s_src[tid] = inblock ? m.qsel[row0 - r0 + tid] : row0 + tid;
-  if (tid < NB) s_q[tid] = m.qsel[tid];
-  __syncthreads();
-  if (!inblock && tid < NB) {
-    const int nv = m.vac[0];
-    const int v = m.vac[1 + tid];
-    const int src = m.vac[65 + tid];
-    if (tid < nv && v >= row0 && v < row0 + IU_ROWS) s_src[v - row0] = src;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
+#pragma unroll
+  for (int k = 0; k < NB * NB / 256; ++k) {
+    const int e = tid + 256 * k;
+    A[e / NB][e % NB] = src[(int64_t)(r0s + e / NB) * ld + c0s + e % NB];
   }
+  __syncthreads();
+  bool bad = false;
+#pragma unroll
+  for (int kb = 0; kb < NB / 16; ++kb) {
+    const int cb = 16 * kb;
+    if (wave == 0) {   // panel: rows cb..63, columns cb..cb+15; lane = row
+      // the serial chain of the factorization: ahead of co-resident waves
+      __builtin_amdgcn_s_setprio(3);
+      double p[16];
+#pragma unroll
+      for (int t = 0; t < 16; ++t) p[t] = (lane >= cb) ? A[lane][cb + t] : 0.0;
+#pragma unroll
+      for (int jj = 0; jj < 16; ++jj) {
+        const int j = cb + jj;
+        const double piv = readlane_d(p[jj], j);
+        double u[16];
+#pragma unroll
+        for (int t = jj + 1; t < 16; ++t) u[t] = readlane_d(p[t], j);
+        const double rp = pivot_recip(piv);
+        bad |= (piv == 0.0);
+        if (lane > j) {
+          const double l = p[jj] * rp;
+          bad |= !(fabs(l) <= tau);
+          p[jj] = l;
+#pragma unroll
+          for (int t = jj + 1; t < 16; ++t) p[t] = fma(-l, u[t], p[t]);
+        }
+        if (lane == 0) s_piv[j] = piv;
+      }
+      if (lane >= cb) {
+#pragma unroll
+        for (int t = 0; t < 16; ++t) A[lane][cb + t] = p[t];
+      }
+      __builtin_amdgcn_s_setprio(0);
+    }
+    __syncthreads();
+    // log|u_jj| of this panel's pivots on a wave the next phase leaves idle
+    if (wave == 1 && lane < 16) s_piv[NB + cb + lane] = log(fabs(s_piv[cb + lane]));
+    if (kb + 1 < NB / 16) {
+      const int nr = NB - cb - 16;   // rows and columns right of / below the panel
+      // U rows of the panel right of it: solve L11 X = A12 (unit lower, 16 x 16),
+      // one column per thread
+      if (tid < nr) {
+        const int c = cb + 16 + tid;
+        double x[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          double acc = A[cb + r][c];
+#pragma unroll
+          for (int t = 0; t < r; ++t) acc = fma(-A[cb + r][cb + t], x[t], acc);
+          x[r] = acc;
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) A[cb + r][c] = x[r];
+      }
+      __syncthreads();
+      // Schur update A22 -= L21 U12 on 16 x 16 tiles, k = 16 (four matrix-core steps)
+      const int nt = nr / 16;
+      const int lr = lane & 15;
+      const int lk = lane >> 4;
+      for (int tile = wave; tile < nt * nt; tile += 4) {
+        const int r0t = cb + 16 + 16 * (tile / nt);
+        const int c0t = cb + 16 + 16 * (tile % nt);
+        f64x4 acc = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+          acc = mfma_f64_16x16x4(A[r0t + lr][cb + 4 * kk + lk], A[cb + 4 * kk + lk][c0t + lr], acc);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) A[r0t + 4 * r + lk][c0t + lr] -= acc[r];
+      }
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NB * NB / 256; ++k) {
+    const int e = tid + 256 * k;
+    tri_out[e] = A[e / NB][e % NB];
+  }
+  __syncthreads();
+  if (tid < 64) {
+    const double ls = wave_sum(s_piv[NB + tid]);
+    if (tid == 0) *logdet_out = ls;
+  }
+  if (__syncthreads_or(bad ? 1 : 0) && tid == 0) atomicOr(&err[1], 1);
+}
+
+// ---- pieces of an inner step on IU_ROWS rows (see the file comment) ----
+// LDS of one workgroup: the LU factors of the pivot block (later the pivot rows of
+// one column chunk), the inverses of the 16 x 16 diagonal blocks with a scratch
+// block, and the IU_ROWS x 64 right-hand side C.
+struct StepLds {
+  double a[NB * LDA];                        // LU (L strictly lower, U) / Rs
+  double b[8 * 16 * 17 + IU_ROWS * 17];      // Di: inverses, 0-3 of U, 4-7 of L; Ts
+  double c[IU_ROWS][LDA];                    // C
+};
+
+// Factors of the pivot block (row-major 64 x 64, device) into LDS; with inverses,
+// also the inverses of its 16 x 16 diagonal blocks (thread (blk, col) runs one
+// column of a 16 x 16 substitution).  Ends with a barrier.
+__device__ void step_factors(StepLds& L, const double* tri, bool inverses = true) {
+  const int tid = threadIdx.x;
+  double (*LU)[LDA] = reinterpret_cast<double (*)[LDA]>(L.a);
+  double (*Di)[16][17] = reinterpret_cast<double (*)[16][17]>(L.b);
   {
     double t[16];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) t[k] = m.tri[tid + 256 * k];
+    for (int k = 0; k < 16; ++k) t[k] = tri[tid + 256 * k];
 #pragma unroll
     for (int k = 0; k < 16; ++k) LU[(tid + 256 * k) / NB][(tid + 256 * k) % NB] = t[k];
   }
   __syncthreads();
-
-  // diagonal block inverses: thread (blk, col) runs one column of a 16 x 16 substitution
-  if (tid < 128) {
+  if (inverses && tid < 128) {
     const int blk = tid >> 4;
     const int c = tid & 15;
     const int b0 = (blk & 3) * 16;
@@ -585,32 +670,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void i
 #pragma unroll
     for (int r = 0; r < 16; ++r) Di[blk][r][c] = x[r];
   }
-  // right-hand side of C U = Acol: panel rows, or -E (identity rows) inside the block
-  {
-    double t[IU_ROWS * NB / 256];
-#pragma unroll
-    for (int k = 0; k < IU_ROWS * NB / 256; ++k) {
-      const int e = tid + 256 * k;
-      const int r = e / NB;
-      const int c = e % NB;
-      t[k] = inblock ? ((row0 - r0 + r == c) ? -1.0 : 0.0) : P[(int64_t)s_src[r] * nbo + c0 + c];
-    }
-#pragma unroll
-    for (int k = 0; k < IU_ROWS * NB / 256; ++k) {
-      const int e = tid + 256 * k;
-      Cs[e / NB][e % NB] = t[k];
-    }
-  }
   __syncthreads();
+}
 
-  // C U = Acol, blocks left to right: C_b = (Acol_b - C_{<b} U_{<b,b}) inv(U_bb).
-  // Every loop has a compile-time trip count (each thread owns IU_ROWS * 16 / 256
-  // elements per block), so the LDS loads are issued ahead of the FMA chains (the
-  // long sums unrolled by 8: fully unrolled they spill); the products with the
-  // diagonal-block inverses run over all 16 terms, the inverses holding exact zeros
-  // outside their triangle (the nonzero terms keep their order).
+// C U = C and G L = C in place on the IU_ROWS x 64 block C (LDS), blocks of 16 with
+// the diagonal-block inverses: C_b = (C_b - C_{<b} U_{<b,b}) inv(U_bb) left to right,
+// then G_b = (C_b - G_{>b} L_{>b,b}) inv(L_bb) right to left.  Every loop has a
+// compile-time trip count (each thread owns IU_ROWS * 16 / 256 elements per block),
+// so the LDS loads are issued ahead of the FMA chains (the long sums unrolled by 8:
+// fully unrolled they spill); the products with the diagonal-block inverses run
+// over all 16 terms, the inverses holding exact zeros outside their triangle.
+// check: returns true when |C| after the first solve (the multipliers of candidate
+// rows) exceeds tau anywhere.
+__device__ bool step_solve(StepLds& L, bool check, double tau) {
+  const int tid = threadIdx.x;
+  double (*LU)[LDA] = reinterpret_cast<double (*)[LDA]>(L.a);
+  double (*Di)[16][17] = reinterpret_cast<double (*)[16][17]>(L.b);
+  double (*Ts)[17] = reinterpret_cast<double (*)[17]>(L.b + 8 * 16 * 17);
+  double (*Cs)[LDA] = L.c;
   static_assert(IU_ROWS * 16 % 256 == 0, "whole elements per thread");
   constexpr int EPT = IU_ROWS * 16 / 256;
+  bool bad = false;
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
 #pragma unroll
@@ -633,10 +713,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void i
 #pragma unroll
       for (int t = 0; t < 16; ++t) acc = fma(Ts[r][t], Di[b][t][cl], acc);
       Cs[r][b * 16 + cl] = acc;
+      if (check) bad |= !(fabs(acc) <= tau);
     }
     __syncthreads();
   }
-  // G L = C, blocks right to left: G_b = (C_b - G_{>b} L_{>b,b}) inv(L_bb)
 #pragma unroll
   for (int b = 3; b >= 0; --b) {
 #pragma unroll
@@ -662,8 +742,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void i
     }
     __syncthreads();
   }
+  return bad;
+}
 
-  // ---- output chunks: -G in the inner block, base - G R elsewhere
+// Output of the step for IU_ROWS rows, column chunk by column chunk: -G in the
+// inner block c0, base - G R elsewhere.  rrow(j) is pivot row j (nbo doubles),
+// base_row(r) row r of this block's input (nullptr inside the pivot block: base 0),
+// out_row(r) where output row r goes.
+template <class RRow, class Base, class Out>
+__device__ void step_output(StepLds& L, int nbo, int c0, RRow rrow, Base base_row, Out out_row) {
+  const int tid = threadIdx.x;
+  double (*Rs)[LDA] = reinterpret_cast<double (*)[LDA]>(L.a);
+  double (*Cs)[LDA] = L.c;
   const int lane = tid & 63;
   const int w = tid >> 6;
   const int rb = w >> 1;
@@ -672,11 +762,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void i
   const int lk = lane >> 4;
   for (int cc = 0; cc < nbo; cc += NB) {
     if (cc == c0) {
-      for (int e = tid; e < IU_ROWS * NB; e += 256) {
-        const int r = e / NB;
-        const int c = e % NB;
-        Q[(int64_t)(row0 + r) * nbo + cc + c] = -Cs[r][c];
-      }
+      for (int e = tid; e < IU_ROWS * NB; e += 256) out_row(e / NB)[cc + e % NB] = -Cs[e / NB][e % NB];
       continue;
     }
     {
@@ -684,7 +770,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void i
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
         const int e = tid + 256 * k;
-        t[k] = P[(int64_t)s_q[e / NB] * nbo + cc + e % NB];
+        t[k] = rrow(e / NB)[cc + e % NB];
       }
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
@@ -698,7 +784,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void i
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int rr = rb * 16 + 4 * r + lk;
-        base[b][r] = inblock ? 0.0 : P[(int64_t)s_src[rr] * nbo + cc + (cb + b) * 16 + lr];
+        const double* br = base_row(rr);
+        base[b][r] = (br != nullptr) ? br[cc + (cb + b) * 16 + lr] : 0.0;
       }
     __syncthreads();
     f64x4 acc[2];
@@ -708,17 +795,120 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void i
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int rr = rb * 16 + 4 * r + lk;
-        const int c = cc + (cb + b) * 16 + lr;
-        Q[(int64_t)(row0 + rr) * nbo + c] = base[b][r] - acc[b][r];
+        out_row(rr)[cc + (cb + b) * 16 + lr] = base[b][r] - acc[b][r];
       }
     __syncthreads();
   }
 }
 
+// Right-hand side of C U = Acol for IU_ROWS rows: src_row(r)'s inner block, or -E
+// (identity rows, as C = -U^{-1} gives the rows of S^{-1}) inside the pivot block
+// (inblock: local row r is pivot row row_in_block + r).  Ends with a barrier.
+template <class Src>
+__device__ void step_rhs(StepLds& L, bool inblock, int row_in_block, int c0, Src src_row) {
+  const int tid = threadIdx.x;
+  double t[IU_ROWS * NB / 256];
+#pragma unroll
+  for (int k = 0; k < IU_ROWS * NB / 256; ++k) {
+    const int e = tid + 256 * k;
+    const int r = e / NB;
+    const int c = e % NB;
+    t[k] = inblock ? ((row_in_block + r == c) ? -1.0 : 0.0) : src_row(r)[c0 + c];
+  }
+#pragma unroll
+  for (int k = 0; k < IU_ROWS * NB / 256; ++k) {
+    const int e = tid + 256 * k;
+    L.c[e / NB][e % NB] = t[k];
+  }
+  __syncthreads();
+}
+
+// Inner Gauss-Jordan step on the panel, IU_ROWS rows per workgroup (see the file
+// comment): C U = Acol and G L = C are solved by 16-column block substitution with
+// explicit inverses of the 16 x 16 diagonal blocks only, then out = base - G R.
+// Search (KNOWN = false): rows are read through the step's row maps, the factors
+// are the tournament root's.  Given order (KNOWN = true): the pivot rows are the
+// positions r0..r0+63, whose factors were published before the launch (tri slot
+// c0 / 64 % 2); the multipliers of the rows below the block are checked against
+// tau, and the last of the two workgroups that produce the next block's pivot rows
+// factors that block (lu64_publish, the other slot) for the next launch.  Those two
+// workgroups take the first two indices, so that the factorization runs beside the
+// other workgroups' updates.
+template <bool KNOWN>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void inner_update_kernel(GjeArgs A) {
+  __shared__ __attribute__((aligned(16))) StepLds L;
+  __shared__ int s_src[IU_ROWS];
+  __shared__ int s_q[NB];
+  __shared__ int s_last;
+
+  const GjeMat& m = A.m[blockIdx.y];
+  const double* P = m.P[A.pcur];
+  double* Q = m.P[A.pcur ^ 1];
+  const int nbo = A.nbo;
+  const int r0 = A.r0;
+  const int c0 = A.c0;
+  const int tid = threadIdx.x;
+  const bool next = KNOWN && c0 + NB < nbo;   // a next pivot block to factor
+  const int nrb = A.n_pad / IU_ROWS;
+  const int row0 = (next ? (blockIdx.x + (r0 + NB) / IU_ROWS) % nrb : blockIdx.x) * IU_ROWS;
+  const bool inblock = row0 >= r0 && row0 < r0 + NB;
+  const bool below = row0 >= r0 + NB;
+  const double* tri = KNOWN ? m.tri + (int64_t)((c0 / NB) & 1) * NB * NB : m.tri;
+
+  if (KNOWN) {
+    if (tid < IU_ROWS) s_src[tid] = row0 + tid;
+    if (tid < NB) s_q[tid] = r0 + tid;
+  } else {
+    // source row of each output row: the selected row inside the block, the displaced
+    // block row at a vacated position, the row itself elsewhere
+    if (tid < IU_ROWS) s_src[tid] = inblock ? m.qsel[row0 - r0 + tid] : row0 + tid;
+    if (tid < NB) s_q[tid] = m.qsel[tid];
+    __syncthreads();
+    if (!inblock && tid < NB) {
+      const int nv = m.vac[0];
+      const int v = m.vac[1 + tid];
+      const int src = m.vac[65 + tid];
+      if (tid < nv && v >= row0 && v < row0 + IU_ROWS) s_src[v - row0] = src;
+    }
+  }
+  step_factors(L, tri);
+  step_rhs(L, inblock, row0 - r0, c0, [&](int r) { return P + (int64_t)s_src[r] * nbo; });
+  const bool bad = step_solve(L, KNOWN && below, A.tau);
+  if (KNOWN && __syncthreads_or(bad ? 1 : 0) && tid == 0) atomicOr(&m.err[1], 1);
+  step_output(
+      L, nbo, c0, [&](int j) { return P + (int64_t)s_q[j] * nbo; },
+      [&](int r) -> const double* { return inblock ? nullptr : P + (int64_t)s_src[r] * nbo; },
+      [&](int r) { return Q + (int64_t)(row0 + r) * nbo; });
+  if (next && row0 >= r0 + NB && row0 < r0 + 2 * NB) {
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) {
+      const int old = atomicAdd(&m.cnt[0], 1);
+      s_last = (old == NB / IU_ROWS - 1);
+      if (s_last) atomicExch(&m.cnt[0], 0);
+    }
+    __syncthreads();
+    if (s_last) {
+      __threadfence();
+      lu64_publish(Q, nbo, r0 + NB, c0 + NB, A.tau, m.tri + (int64_t)(((c0 / NB) + 1) & 1) * NB * NB,
+                   m.logdet + (r0 + NB) / NB, m.err, reinterpret_cast<double (*)[LDA]>(L.a), L.b);
+    }
+  }
+}
+
+// The first pivot block of a panel in a given row order (one workgroup per matrix):
+// its factors to tri slot 0.
+__global__ __launch_bounds__(256) void lu64_kernel(GjeArgs A) {
+  __shared__ double s_blk[NB][LDA];
+  __shared__ double s_piv[2 * NB];
+  const GjeMat& m = A.m[blockIdx.y];
+  lu64_publish(m.P[A.pcur], A.nbo, A.k0, 0, A.tau, m.tri, m.logdet + A.k0 / NB, m.err, s_blk, s_piv);
+}
+
 __global__ void begin_kernel(GjeArgs A, int nslots, int ncnt) {
   const GjeMat& m = A.m[blockIdx.y];
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < A.n_pad; p += gridDim.x * blockDim.x)
-    m.ptot[p] = p;
+    m.ptot[p] = A.known ? min(max(m.order[p], 0), A.n_pad - 1) : p;
   if (blockIdx.x == 0) {
     for (int t = threadIdx.x; t < nslots; t += blockDim.x) m.logdet[t] = 0.0;
     for (int t = threadIdx.x; t < ncnt; t += blockDim.x) m.cnt[t] = 0;
@@ -731,19 +921,25 @@ __global__ void panel_copy_kernel(GjeArgs A) {
   const int nbo = A.nbo;
   const int64_t total = (int64_t)A.n_pad * nbo;
   double* P = m.P[A.pcur];
+  // the first outer step of a given-order inversion reads the rows in that order
+  const bool gather = A.known && A.k0 == 0;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = e / nbo;
     const int c = (int)(e % nbo);
-    P[e] = m.Min[i * A.n_pad + A.k0 + c];
-    if (c == 0) m.pi[i] = (int)i;
+    const int src = gather ? min(max(m.order[i], 0), A.n_pad - 1) : (int)i;
+    P[e] = m.Min[(int64_t)src * A.n_pad + A.k0 + c];
+    if (c == 0 && m.pi != nullptr) m.pi[i] = src;
   }
 }
 
 __global__ void finish_kernel(GjeArgs A) {
   const GjeMat& m = A.m[blockIdx.y];
-  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < A.n_pad; p += gridDim.x * blockDim.x)
-    m.pinv[m.ptot[p]] = p;
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < A.n_pad; p += gridDim.x * blockDim.x) {
+    const int q = m.ptot[p];
+    m.pinv[q] = p;
+    if (m.order != nullptr) m.order[p] = q;
+  }
 }
 
 __global__ void unpermute_kernel(const double* M, const int* pinv, int64_t ld, double* dst,
@@ -776,7 +972,15 @@ hipError_t launch_gje_tournament(const GjeArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_gje_inner_update(const GjeArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(inner_update_kernel, dim3(a.n_pad / IU_ROWS, a.nmat), dim3(256), 0, s, a);
+  if (a.known)
+    hipLaunchKernelGGL(inner_update_kernel<true>, dim3(a.n_pad / IU_ROWS, a.nmat), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(inner_update_kernel<false>, dim3(a.n_pad / IU_ROWS, a.nmat), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_gje_lu64(const GjeArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(lu64_kernel, dim3(1, a.nmat), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -41,7 +41,8 @@ struct GjeMat {
   const double* Min;     // matrix at the start of the outer step (n_pad x n_pad, ld n_pad)
   double* Mout;          // matrix after the outer step
   double* P[2];          // ping-pong panels n_pad x nbo (ld = nbo)
-  double* tri;           // 64 x 64: LU factors of the current pivot block (pivot order)
+  double* tri;           // 64 x 64: LU factors of the current pivot block (pivot order);
+                         // a given order alternates two such slots by inner step
   int* pi;               // n_pad: gather map of the current outer step
   int* ptot;             // n_pad: accumulated row order (position -> original row)
   int* pinv;             // n_pad: inverse of ptot (filled by launch_gje_finish)
@@ -50,7 +51,10 @@ struct GjeMat {
   int* cand;             // tournament scratch
   int* cnt;              // tournament arrival counters (self-resetting)
   double* logdet;        // n_pad / 64 slots: log|det| of each pivot block
-  int* err;              // error flags: [0] bit 0 zero pivot met, bit 1 a bounded wait gave up
+  int* err;              // error flags: [0] bit 0 zero pivot met, bit 1 a bounded wait gave up;
+                         // [1] a multiplier of a given-order inversion exceeded tau
+  int* order;            // n_pad: row order of the previous inversion of this matrix
+                         // (position -> original row), kept by launch_gje_finish
 };
 
 struct GjeArgs {
@@ -62,25 +66,40 @@ struct GjeArgs {
   int pcur;              // which P[] holds the current panel
   int c0;                // inner block offset inside the panel (multiple of 64)
   int r0;                // first candidate position (k0 + c0)
+  int known;             // 1: pivot rows in the given order (m.order), no search
+  double tau;            // known order: largest multiplier magnitude accepted
 };
 
 // Tournament scratch sizes (ints) per matrix.
 inline int gje_cand_ints(int n_pad) { return 2 * (n_pad / 128 + 2) * 65; }
 inline int gje_cnt_ints(int n_pad) { return 2 * (n_pad / 128 + 2); }
 
-// Reset ptot to the identity, zero the error flags, logdet slots and counters.
+// Reset ptot to the identity (a.known: to m.order), zero the error flags, logdet
+// slots and counters.
 hipError_t launch_gje_begin(const GjeArgs& a, hipStream_t s);
-// P[pcur] = Min[:, k0:k0+nbo]; pi = identity.
+// P[pcur] = Min[:, k0:k0+nbo]; pi = identity.  With a.known the first outer step
+// (k0 = 0) gathers the rows in the given order instead: P[i] = Min[order[i]],
+// pi = order.
 hipError_t launch_gje_panel_copy(const GjeArgs& a, hipStream_t s);
 hipError_t launch_gje_tournament(const GjeArgs& a, hipStream_t s);
+// Inner step on the panel (P[pcur] -> P[pcur ^ 1]) with the tournament's pivot rows,
+// or (a.known) with the pivot rows r0..r0+63 in order, whose factors are in tri slot
+// c0 / 64 % 2; the launch then also factors the next block into the other slot.
+// err[1] is raised when a multiplier exceeds a.tau or a pivot is zero.
 hipError_t launch_gje_inner_update(const GjeArgs& a, hipStream_t s);
+// Given order: the factors of the panel's first pivot block (rows k0..k0+63 of
+// P[pcur]) into tri slot 0, with log|det| and the multiplier check.
+hipError_t launch_gje_lu64(const GjeArgs& a, hipStream_t s);
 // Outer update of the columns [c_lo, c_hi) (inside) or of all others (!inside);
 // c_lo is a multiple of 128, the ranges are rounded out to whole 128-column tiles.
 // max_wgs > 0 caps the workgroups per matrix (persistent tiles), leaving CUs to
-// work that runs beside it.
+// work that runs beside it.  A null m[z].pi reads Min without a gather.
+// next_panel[z] (inside only): the columns [c_lo, c_lo + next_nbo) are written to
+// that n_pad x next_nbo panel instead of Mout.
 hipError_t launch_gje_outer_update(const GjeArgs& a, int c_lo, int c_hi, bool inside,
-                                   int max_wgs, hipStream_t s);
-// pinv = ptot^{-1}.
+                                   int max_wgs, hipStream_t s, double* const* next_panel = nullptr,
+                                   int next_nbo = 0);
+// pinv = ptot^{-1}; order = ptot (the next inversion of the matrix may reuse it).
 hipError_t launch_gje_finish(const GjeArgs& a, hipStream_t s);
 // dst (n x n, ldd) = A^{-1}: dst[i][ptot[c]] = Mfinal[i][c].
 hipError_t launch_gje_unpermute(const double* Mfinal, const int* pinv, int64_t ld, double* dst,

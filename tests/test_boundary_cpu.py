@@ -88,7 +88,10 @@ def test_forward_argument_validation(lib):
     o.max_sqrt = 65
     assert fwd(lib, opts=o) == 1
     o = lm.default_opts()
-    o.reserved[0] = 1
+    o.reserved = 1
+    assert fwd(lib, opts=o) == 1
+    o = lm.default_opts()
+    o.pivot_search = 2                                 # 0 or 1 only
     assert fwd(lib, opts=o) == 1
     o = lm.default_opts()
     o.graph_fp32 = 2                                   # 0 or 1 only
@@ -100,10 +103,10 @@ def test_forward_argument_validation(lib):
 
 
 def test_component_argument_validation(lib):
-    best = ctypes.c_int32(0)
-    assert lib.logm_autotune(0, None, 0, None, ctypes.byref(best), None) == 1
+    best = (ctypes.c_int32 * 2)()
+    assert lib.logm_autotune(0, None, 0, None, best, None) == 1
     assert lib.logm_autotune(64, None, 0, None, None, None) == 1
-    assert lib.logm_autotune(64, FAKE, 100, None, ctypes.byref(best), None) == 3
+    assert lib.logm_autotune(64, FAKE, 100, None, best, None) == 3
     assert lib.logm_balance_f64(0, FAKE, 4, FAKE, 4, FAKE, None, None, 0, None) == 1
     assert lib.logm_balance_f64(4, FAKE, 4, FAKE, 3, FAKE, None, None, 0, None) == 1
     assert lib.logm_balance_f64(4, FAKE, 4, FAKE, 4, None, None, None, 0, None) == 1

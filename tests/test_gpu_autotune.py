@@ -27,9 +27,10 @@ def test_autotune_then_logm_matches_oracle(lm):
     import torch
 
     n = 300
-    cap, ms = lm.autotune(n)
-    assert cap in (96, 128, 160, 192, 224, 256)
-    assert ms > 0.0
+    caps, ms = lm.autotune(n)
+    assert caps[0] in (96, 128, 160, 192, 224, 256)
+    assert caps[1] in (224, 256, 320, 384, 448, 512)
+    assert ms[0] > 0.0 and ms[1] > 0.0
     A = disk_matrix(n, 9100)
     L, info = lm.logm(torch.from_numpy(A).to("cuda:0"))
     Lo, io = oracle.logm(A)
