@@ -129,6 +129,17 @@ int logm_workspace_size(int32_t dtype, int64_t n, const logm_opts* o, size_t* by
 int logm_forward(int32_t dtype, int64_t n, const void* A, int64_t lda, void* L, int64_t ldl,
                  const logm_opts* o, logm_info* info, void* ws, size_t ws_bytes, void* stream);
 
+/* L = log(A) like logm_forward for a real n x n matrix with 1 <= n <= 256, with no
+ * workspace argument and no device memory allocation: for callers that cannot
+ * allocate (code under stream capture, serving loops, harnesses that forbid
+ * hipMalloc).  The workspace is a fixed 16 MiB device array inside the library, one
+ * per device, held until the process ends; every call on a device shares it, so
+ * calls that overlap on one device race (issue them on one stream, or serialise
+ * them).  A, L, o, info and stream as for logm_forward (dtype LOGM_R64); n > 256
+ * gives LOGM_EINVAL.  Synchronises `stream` like logm_forward. */
+int logm_forward_noalloc(int64_t n, const double* A, int64_t lda, double* L, int64_t ldl,
+                         const logm_opts* o, logm_info* info, void* stream);
+
 /* ---- reverse mode ---- */
 
 /* Minimum workspace bytes for logm_backward: the forward workspace plus

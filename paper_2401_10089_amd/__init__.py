@@ -26,6 +26,8 @@ from ._binding import (  # noqa: F401
     logm_backward,
     logm_backward_taped,
     logm_forward_taped,
+    logm_noalloc,
+    NOALLOC_MAX_N,
     Tape,
     backward_workspace_size,
     normest,

@@ -34,6 +34,7 @@ EXPORTS = (
     "logm_strerror",
     "logm_workspace_size",
     "logm_forward",
+    "logm_forward_noalloc",
     "logm_backward_workspace_size",
     "logm_backward",
     "logm_forward_taped",
@@ -146,6 +147,8 @@ def load_library(path: str = LIB_PATH):
         "logm_workspace_size": (ctypes.c_int, [_i32, _i64, ctypes.POINTER(LogmOpts), ctypes.POINTER(_sz)]),
         "logm_forward": (ctypes.c_int, [_i32, _i64, _vp, _i64, _vp, _i64, ctypes.POINTER(LogmOpts),
                                         ctypes.POINTER(LogmInfo), _vp, _sz, _vp]),
+        "logm_forward_noalloc": (ctypes.c_int, [_i64, _vp, _i64, _vp, _i64, ctypes.POINTER(LogmOpts),
+                                                ctypes.POINTER(LogmInfo), _vp]),
         "logm_backward_workspace_size": (ctypes.c_int, [_i32, _i64, ctypes.POINTER(LogmOpts),
                                                         ctypes.POINTER(_sz)]),
         "logm_backward": (ctypes.c_int, [_i32, _i64, _vp, _i64, _vp, _i64, _vp, _i64, ctypes.POINTER(LogmOpts),
@@ -309,6 +312,27 @@ def logm(A, k_max: int = 5, max_sqrt: int = 50, db_max_iter: int = 30, theta_sou
                             ctypes.byref(o), ctypes.byref(info), _vp(ws.data_ptr()), ws.numel(),
                             _stream_ptr(A))
     _check(rc, "logm_forward", info.status_detail)
+    return L, info.as_dict()
+
+
+NOALLOC_MAX_N = 256
+
+
+def logm_noalloc(A, k_max: int = 5, max_sqrt: int = 50, db_max_iter: int = 30, theta_source: int = 0,
+                 out=None, pivot_search: bool = False):
+    """L = log(A) through logm_forward_noalloc: real A, n <= 256, no workspace (the
+    library's fixed device array) and no device allocation.  Returns (L, info dict)."""
+    torch = _torch()
+    A = _as_matrix(A)
+    n = A.shape[0]
+    L = out if out is not None else torch.empty((n, n), dtype=A.dtype, device=A.device)
+    o = default_opts()
+    o.k_max, o.max_sqrt, o.db_max_iter, o.theta_source = k_max, max_sqrt, db_max_iter, theta_source
+    o.pivot_search = 1 if pivot_search else 0
+    info = LogmInfo()
+    rc = lib().logm_forward_noalloc(n, _vp(A.data_ptr()), A.stride(0), _vp(L.data_ptr()), L.stride(0),
+                                    ctypes.byref(o), ctypes.byref(info), _stream_ptr(A))
+    _check(rc, "logm_forward_noalloc", info.status_detail)
     return L, info.as_dict()
 
 

@@ -12,7 +12,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "liblogm.so")
 
-SOURCES = ["gemm_f64.hip", "gje.hip", "elementwise.hip", "batched.hip", "driver.cpp"]
+SOURCES = ["gemm_f64.hip", "gje.hip", "elementwise.hip", "batched.hip", "noalloc.hip", "driver.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

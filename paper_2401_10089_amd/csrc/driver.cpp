@@ -1468,6 +1468,36 @@ int logm_forward(int32_t dtype, int64_t n, const void* A, int64_t lda, void* L, 
   return st.code;
 }
 
+int logm_forward_noalloc(int64_t n, const double* A, int64_t lda, double* L, int64_t ldl,
+                         const logm_opts* o, logm_info* info, void* stream) {
+  logm_opts opts;
+  logm_default_opts(&opts);
+  if (o != nullptr) opts = *o;
+  if (n < 1 || n > kNoallocMaxN || A == nullptr || L == nullptr || lda < n || ldl < n)
+    return LOGM_EINVAL;
+  if (!opts_ok(opts)) return LOGM_EINVAL;
+  logm_info local{};
+  logm_info& inf = (info != nullptr) ? *info : local;
+  std::memset(&inf, 0, sizeof(inf));
+  void* ws = nullptr;
+  const hipError_t e = noalloc_scratch(&ws);
+  if (e != hipSuccess) {
+    inf.status_detail = (int)e;
+    return LOGM_EHIP;
+  }
+  // the plan of the largest size fits the array (n_pad <= 256: one outer step, so
+  // no look-ahead stream either)
+  if (make_plan(n).total > kNoallocBytes) return LOGM_EWORKSPACE;
+  Call call(n, ws, kNoallocBytes, stream);
+  if (call.st.code != LOGM_OK) {
+    inf.status_detail = call.st.detail;
+    return call.st.code;
+  }
+  Status st = forward_r64(call.c, A, lda, L, ldl, opts, inf);
+  inf.status_detail = st.detail;
+  return st.code;
+}
+
 int logm_backward_workspace_size(int32_t dtype, int64_t n, const logm_opts* o, size_t* bytes) {
   logm_opts opts;
   logm_default_opts(&opts);

@@ -221,6 +221,15 @@ hipError_t launch_check_finite(const double* M, int64_t ld, int n, int* flag, hi
 hipError_t launch_scale_out(const double* src, int64_t ld, double* dst, int64_t ldd, int n,
                             double scale, int* nonfinite, hipStream_t s);
 
+// -------------------------------------------------------- fixed scratch --
+// Largest n and the scratch bytes of logm_forward_noalloc (a logm of n <= 256 needs
+// about 10 MB of workspace; the driver checks that its plan fits).
+constexpr int kNoallocMaxN = 256;
+constexpr size_t kNoallocBytes = (size_t)16 << 20;
+// Device address of the current device's scratch array (looked up on the first call
+// on each device, with that device current).
+hipError_t noalloc_scratch(void** ptr);
+
 // ---------------------------------------------------------------- batched --
 // Workspace bytes of the batched path: 13 buffers of the size class's largest
 // matrix per resident workgroup of the device, one region per class (n <= 64

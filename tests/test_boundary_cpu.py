@@ -102,6 +102,20 @@ def test_forward_argument_validation(lib):
     assert fwd(lib, ws=FAKE, ws_bytes=100) == 3        # workspace too small
 
 
+def test_noalloc_argument_validation(lib):
+    """The allocation-free entry point refuses bad sizes and pointers before any
+    device work (n above its fixed scratch's 256 included)."""
+    f = lib.logm_forward_noalloc
+    assert f(0, FAKE, 1, FAKE, 1, None, None, None) == 1
+    assert f(257, FAKE, 257, FAKE, 257, None, None, None) == 1
+    assert f(4, None, 4, FAKE, 4, None, None, None) == 1
+    assert f(4, FAKE, 4, None, 4, None, None, None) == 1
+    assert f(4, FAKE, 3, FAKE, 4, None, None, None) == 1
+    o = lm.default_opts()
+    o.k_max = 0
+    assert f(4, FAKE, 4, FAKE, 4, ctypes.byref(o), None, None) == 1
+
+
 def test_component_argument_validation(lib):
     best = (ctypes.c_int32 * 2)()
     assert lib.logm_autotune(0, None, 0, None, best, None) == 1
