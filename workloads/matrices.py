@@ -37,16 +37,18 @@ def disk_matrix(n: int, seed: int, rho: float = 0.8) -> np.ndarray:
 
 
 def rotscale_matrix(n: int, seed: int, r_lo: float = 1e-3, r_hi: float = 1e3,
-                    with_log: bool = True):
+                    with_log: bool = True, theta_max: float = 0.9):
     """Real A = V D V^{-1} with conjugate-pair spectrum; returns (A, log A exact).
 
-    For odd n the last eigenvalue is real and positive (log-uniform like r).
+    theta ~ U(-theta_max pi, theta_max pi) (0.9 in the benchmark workloads; values
+    near 1 put eigenvalues close to the negative real axis).  For odd n the last
+    eigenvalue is real and positive (log-uniform like r).
     """
     rng = np.random.default_rng(seed)
     V = np.eye(n) + 0.1 * rng.standard_normal((n, n)) / np.sqrt(n)
     npair = n // 2
     r = np.exp(rng.uniform(np.log(r_lo), np.log(r_hi), size=npair + (n % 2)))
-    theta = rng.uniform(-0.9 * np.pi, 0.9 * np.pi, size=npair)
+    theta = rng.uniform(-theta_max * np.pi, theta_max * np.pi, size=npair)
     a = r[:npair] * np.cos(theta)
     b = r[:npair] * np.sin(theta)
     D = np.zeros((n, n))
