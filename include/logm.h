@@ -83,7 +83,7 @@ typedef struct logm_opts {
   int32_t pivot_search; /* 0 (default): an inversion of the square-root iteration may
                            take the row order of the previous inversion of the same
                            iterate (X or Y) instead of searching for pivots; the result
-                           is kept only if every elimination multiplier is at most 2 in
+                           is kept only if every elimination multiplier is at most 4 in
                            magnitude, otherwise the inversion is redone with the search
                            (logm_forward only; the reverse mode always searches);
                            1: pivot search (tournament) for every inversion */

@@ -49,10 +49,12 @@ constexpr int kLookaheadWgs[2] = {LOGM_LOOKAHEAD_WGS, LOGM_LOOKAHEAD_WGS_REORDER
 // Pivot order reuse: an inversion in the previous one's row order is kept only if
 // every multiplier is at most kReuseTau in magnitude (threshold partial pivoting);
 // it is tried when the previous Denman-Beavers step changed the iterate by less
-// than kReuseTry relative (by less than kReuseRetry after a rejected attempt).
-constexpr double kReuseTau = 2.0;
-constexpr double kReuseTry = 1.0;
-constexpr double kReuseRetry = 0.5;
+// than kReuseTry relative (by less than kReuseRetry after a rejected attempt).  A
+// rejected attempt costs about a reused inversion, a kept one saves about a third
+// of a searching one, so the thresholds are set where attempts rarely fail.
+constexpr double kReuseTau = 4.0;
+constexpr double kReuseTry = 0.5;
+constexpr double kReuseRetry = 0.25;
 
 // The cap per padded size and mode (0: search, 1: given order) chosen by
 // logm_autotune (process-wide); the default otherwise.
