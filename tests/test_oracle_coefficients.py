@@ -332,3 +332,26 @@ def test_k4_table_is_the_fit_output():
         assert np.allclose(h[j], H[j], rtol=1e-12, atol=1e-15), j
         assert np.allclose(g[j], G[j], rtol=1e-12, atol=1e-15), j
     assert np.allclose(y, Y, rtol=1e-12, atol=1e-15)
+
+
+def test_k6_fit_layout_and_expansion():
+    """The k = 6 search script parametrises eq. five_mult_degopt with the paper's 46
+    free coefficients, and its series expansion agrees with evaluating the product
+    recurrence directly at scalar points (a polynomial of degree 64 is fixed by 65
+    values; 80 points are used)."""
+    from oracle import fit_k6
+
+    assert fit_k6.NPAR == 46
+    rng = np.random.default_rng(6)
+    p = rng.standard_normal(fit_k6.NPAR) * 0.5
+    b = fit_k6.expand(p)
+    h, g, y = fit_k6.unpack(p)
+    xs = np.linspace(-0.4, 0.4, 80)
+    for x in xs:
+        P = {1: 1.0, 2: x, 3: x * x}
+        for j in range(2, 7):
+            P[j + 2] = (sum(h[j][i - 2] * P[i] for i in range(2, j + 2))
+                        * sum(g[j][i - 2] * P[i] for i in range(2, j + 2)))
+        direct = x + sum(y[q - 1] * P[q] for q in range(3, 9))
+        series = np.polynomial.polynomial.polyval(x, b)
+        assert abs(direct - series) <= 1e-13 * max(1.0, abs(direct))
