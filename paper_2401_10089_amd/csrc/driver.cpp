@@ -242,7 +242,7 @@ Plan make_plan(int64_t n) {
   for (int i = 0; i < kMats; ++i) p.mat[i] = take(np * np * sizeof(double));
   for (int z = 0; z < 2; ++z) {
     for (int q = 0; q < 2; ++q)
-      for (int b = 0; b < 2; ++b) p.panel[z][q][b] = take(np * kNBO * sizeof(double));
+      for (int b = 0; b < 2; ++b) p.panel[z][q][b] = take(np * std::min<size_t>(np, kNBO) * sizeof(double));
     p.W[z] = take(2 * kNB * kNB * sizeof(double));   // two slots: a given order alternates
     p.logdet[z] = take(np / kNB * sizeof(double));
     for (int q = 0; q < 2; ++q) p.pi[z][q] = take(np * sizeof(int));

@@ -854,6 +854,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void i
   const bool inblock = row0 >= r0 && row0 < r0 + NB;
   const bool below = row0 >= r0 + NB;
   const double* tri = KNOWN ? m.tri + (int64_t)((c0 / NB) & 1) * NB * NB : m.tri;
+  // the panel chain is the critical path beside the trailing update's waves
+  __builtin_amdgcn_s_setprio(2);
 
   if (KNOWN) {
     if (tid < IU_ROWS) s_src[tid] = row0 + tid;
