@@ -748,7 +748,8 @@ __device__ bool step_solve(StepLds& L, bool check, double tau) {
 // Output of the step for IU_ROWS rows, column chunk by column chunk: -G in the
 // inner block c0, base - G R elsewhere.  rrow(j) is pivot row j (nbo doubles),
 // base_row(r) row r of this block's input (nullptr inside the pivot block: base 0),
-// out_row(r) where output row r goes.
+// out_row(r) where output row r goes.  The next chunk of pivot rows is loaded into
+// registers while the current one is multiplied.
 template <class RRow, class Base, class Out>
 __device__ void step_output(StepLds& L, int nbo, int c0, RRow rrow, Base base_row, Out out_row) {
   const int tid = threadIdx.x;
@@ -760,23 +761,24 @@ __device__ void step_output(StepLds& L, int nbo, int c0, RRow rrow, Base base_ro
   const int cb = (w & 1) * 2;
   const int lr = lane & 15;
   const int lk = lane >> 4;
-  for (int cc = 0; cc < nbo; cc += NB) {
-    if (cc == c0) {
-      for (int e = tid; e < IU_ROWS * NB; e += 256) out_row(e / NB)[cc + e % NB] = -Cs[e / NB][e % NB];
-      continue;
+  auto load_r = [&](int cc, double (&t)[16]) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int e = tid + 256 * k;
+      t[k] = rrow(e / NB)[cc + e % NB];
     }
-    {
-      double t[16];
+  };
+  int cc = (c0 == 0) ? NB : 0;   // first chunk outside the inner block
+  double t[16];
+  if (cc < nbo) load_r(cc, t);
+  for (int e = tid; e < IU_ROWS * NB; e += 256) out_row(e / NB)[c0 + e % NB] = -Cs[e / NB][e % NB];
+  while (cc < nbo) {
+    int nx = cc + NB;
+    if (nx == c0) nx += NB;
 #pragma unroll
-      for (int k = 0; k < 16; ++k) {
-        const int e = tid + 256 * k;
-        t[k] = rrow(e / NB)[cc + e % NB];
-      }
-#pragma unroll
-      for (int k = 0; k < 16; ++k) {
-        const int e = tid + 256 * k;
-        Rs[e / NB][e % NB] = t[k];
-      }
+    for (int k = 0; k < 16; ++k) {
+      const int e = tid + 256 * k;
+      Rs[e / NB][e % NB] = t[k];
     }
     double base[2][4];
 #pragma unroll
@@ -788,6 +790,7 @@ __device__ void step_output(StepLds& L, int nbo, int c0, RRow rrow, Base base_ro
         base[b][r] = (br != nullptr) ? br[cc + (cb + b) * 16 + lr] : 0.0;
       }
     __syncthreads();
+    if (nx < nbo) load_r(nx, t);
     f64x4 acc[2];
     mm32x64(Cs, Rs, acc);
 #pragma unroll
@@ -798,25 +801,31 @@ __device__ void step_output(StepLds& L, int nbo, int c0, RRow rrow, Base base_ro
         out_row(rr)[cc + (cb + b) * 16 + lr] = base[b][r] - acc[b][r];
       }
     __syncthreads();
+    cc = nx;
   }
 }
 
-// Right-hand side of C U = Acol for IU_ROWS rows: src_row(r)'s inner block, or -E
-// (identity rows, as C = -U^{-1} gives the rows of S^{-1}) inside the pivot block
-// (inblock: local row r is pivot row row_in_block + r).  Ends with a barrier.
+// Right-hand side of C U = Acol for IU_ROWS rows, in two halves so that its loads
+// can be issued before the factors are set up: rhs_load reads src_row(r)'s inner
+// block, or forms -E (identity rows, as C = -U^{-1} gives the rows of S^{-1}) inside
+// the pivot block (inblock: local row r is pivot row row_in_block + r); rhs_store
+// puts it into LDS and ends with a barrier.
+constexpr int RHS_PT = IU_ROWS * NB / 256;
 template <class Src>
-__device__ void step_rhs(StepLds& L, bool inblock, int row_in_block, int c0, Src src_row) {
+__device__ void rhs_load(bool inblock, int row_in_block, int c0, Src src_row, double (&t)[RHS_PT]) {
   const int tid = threadIdx.x;
-  double t[IU_ROWS * NB / 256];
 #pragma unroll
-  for (int k = 0; k < IU_ROWS * NB / 256; ++k) {
+  for (int k = 0; k < RHS_PT; ++k) {
     const int e = tid + 256 * k;
     const int r = e / NB;
     const int c = e % NB;
     t[k] = inblock ? ((row_in_block + r == c) ? -1.0 : 0.0) : src_row(r)[c0 + c];
   }
+}
+__device__ void rhs_store(StepLds& L, const double (&t)[RHS_PT]) {
+  const int tid = threadIdx.x;
 #pragma unroll
-  for (int k = 0; k < IU_ROWS * NB / 256; ++k) {
+  for (int k = 0; k < RHS_PT; ++k) {
     const int e = tid + 256 * k;
     L.c[e / NB][e % NB] = t[k];
   }
@@ -873,8 +882,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void i
       if (tid < nv && v >= row0 && v < row0 + IU_ROWS) s_src[v - row0] = src;
     }
   }
+  __syncthreads();   // the row maps above are complete
+  double rhs[RHS_PT];
+  rhs_load(inblock, row0 - r0, c0, [&](int r) { return P + (int64_t)s_src[r] * nbo; }, rhs);
   step_factors(L, tri);
-  step_rhs(L, inblock, row0 - r0, c0, [&](int r) { return P + (int64_t)s_src[r] * nbo; });
+  rhs_store(L, rhs);
   const bool bad = step_solve(L, KNOWN && below, A.tau);
   if (KNOWN && __syncthreads_or(bad ? 1 : 0) && tid == 0) atomicOr(&m.err[1], 1);
   step_output(
