@@ -49,12 +49,13 @@ constexpr int kLookaheadWgs[2] = {LOGM_LOOKAHEAD_WGS, LOGM_LOOKAHEAD_WGS_REORDER
 // Pivot order reuse: an inversion in the previous one's row order is kept only if
 // every multiplier is at most kReuseTau in magnitude (threshold partial pivoting);
 // it is tried when the previous Denman-Beavers step changed the iterate by less
-// than kReuseTry relative (by less than kReuseRetry after a rejected attempt).  A
-// rejected attempt costs about a reused inversion, a kept one saves about a third
-// of a searching one, so the thresholds are set where attempts rarely fail.
+// than kReuseTry relative, and after a rejection in the same root only below
+// kReuseRetry.  A rejected attempt stops at the first failed check (its remaining
+// kernels return at once), so it costs about a tenth of a searching inversion,
+// while a kept one saves about a third of one.
 constexpr double kReuseTau = 4.0;
-constexpr double kReuseTry = 0.5;
-constexpr double kReuseRetry = 0.25;
+constexpr double kReuseTry = 2.0;
+constexpr double kReuseRetry = 0.5;
 
 // The cap per padded size and mode (0: search, 1: given order) chosen by
 // logm_autotune (process-wide); the default otherwise.
@@ -208,6 +209,15 @@ struct Profiler {
       pool.push_back(p.b);
     }
     pending.clear();
+  }
+  // forget the launches recorded since mark (work that was skipped: a rejected
+  // given-order attempt returns early, so its launches do not do their flops)
+  void discard_from(size_t mark) {
+    for (size_t i = mark; i < pending.size(); ++i) {
+      pool.push_back(pending[i].a);
+      pool.push_back(pending[i].b);
+    }
+    if (mark < pending.size()) pending.resize(mark);
   }
 };
 Profiler g_prof;
@@ -546,6 +556,7 @@ Status db_sqrt(Ctx& c, const double* X0, double* Xout, int max_iter, int* iters,
     double* fin[2] = {nullptr, nullptr};
     const bool known = c.reuse && c.have_order[0] && (nmat == 1 || c.have_order[1]) &&
                        rel_last < try_below;
+    const size_t prof_mark = g_prof.pending.size();
     PROPAGATE(gje_invert(c, nmat, src, fin, known));
     if (known) {   // keep the result only if the given order passed its check
       int herr[8] = {0};
@@ -557,6 +568,7 @@ Status db_sqrt(Ctx& c, const double* X0, double* Xout, int max_iter, int* iters,
       if (rejected) {
         c.reuse_fails += nmat;
         try_below = kReuseRetry;
+        if (g_prof.on) g_prof.discard_from(prof_mark);
         PROPAGATE(gje_invert(c, nmat, src, fin, false));
       }
     }

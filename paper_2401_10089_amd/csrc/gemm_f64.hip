@@ -68,6 +68,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
 
   op.select(blockIdx.z);
   const int tid = threadIdx.x;
+  if constexpr (Op::kCanSkip) {   // a work item given up upstream: nothing to do
+    __shared__ int s_skip;
+    if (tid == 0) s_skip = op.skip() ? 1 : 0;
+    __syncthreads();
+    if (s_skip) return;
+  }
   const int wave = tid >> 6;
   const int lane = tid & 63;
   const int wm = wave >> 1;
@@ -199,6 +205,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
 
 // ------------------------------------------------------------------ ops ---
 struct PlainOp {
+  static constexpr bool kCanSkip = false;
   const double* A;
   int64_t lda;
   const double* B;
@@ -233,6 +240,7 @@ struct PlainOp {
 };
 
 struct PolyOp {
+  static constexpr bool kCanSkip = false;
   PolyGemmArgs a;
   __device__ void select(int) {}
   __device__ bool copy_tile(int, int, int) const { return false; }
@@ -290,6 +298,8 @@ struct PolyOp {
 // (leading dimension pn_ld) instead of Mout: the look-ahead update of an inversion
 // in a given row order writes that panel directly.
 struct GjeOuterOp {
+  static constexpr bool kCanSkip = true;
+  const int* abort[2];   // given row order: the multiplier-check flags (err[1]) of both matrices
   const double* U[2];
   const double* Min[2];
   const int* pi[2];
@@ -312,6 +322,15 @@ struct GjeOuterOp {
     pn = one ? Pn[1] : Pn[0];
   }
   __device__ int row_of(int i) const { return p != nullptr ? p[i] : i; }
+  // a rejected given-order attempt is redone with the search: its remaining updates
+  // are skipped
+  __device__ bool skip() const {
+    bool r = false;
+#pragma unroll
+    for (int z = 0; z < 2; ++z)
+      if (abort[z] != nullptr) r |= __hip_atomic_load(abort[z], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+    return r;
+  }
   __device__ bool copy_tile(int, int col0, int tn) const { return col0 >= k0 && col0 + tn <= k0 + nbo; }
   __device__ void copy(int i, int j) const { mo[(int64_t)i * ld + j] = u[(int64_t)i * nbo + (j - k0)]; }
   __device__ const double* a_row(int i) const { return u + (int64_t)i * nbo; }
@@ -406,6 +425,7 @@ hipError_t launch_gje_outer_update(const GjeArgs& a, int c_lo, int c_hi, bool in
     op.pi[z] = a.m[z].pi;
     op.Mout[z] = a.m[z].Mout;
     op.Pn[z] = (next_panel != nullptr) ? next_panel[z] : nullptr;
+    op.abort[z] = a.known ? a.m[z].err + 1 : nullptr;
   }
   op.ld = a.n_pad;
   op.k0 = a.k0;

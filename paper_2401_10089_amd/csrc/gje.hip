@@ -832,6 +832,20 @@ __device__ void rhs_store(StepLds& L, const double (&t)[RHS_PT]) {
   __syncthreads();
 }
 
+// Given row order: true once a multiplier check of either matrix has failed (the
+// attempt will be redone with the search, so its remaining steps are skipped).  Read
+// by one thread and shared, so that the whole workgroup takes the same branch.
+__device__ __forceinline__ bool given_aborted(const GjeArgs& A, int* s_flag) {
+  if (threadIdx.x == 0) {
+    int f = 0;
+    for (int z = 0; z < A.nmat; ++z)
+      f |= __hip_atomic_load(&A.m[z].err[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *s_flag = f;
+  }
+  __syncthreads();
+  return *s_flag != 0;
+}
+
 // Inner Gauss-Jordan step on the panel, IU_ROWS rows per workgroup (see the file
 // comment): C U = Acol and G L = C are solved by 16-column block substitution with
 // explicit inverses of the 16 x 16 diagonal blocks only, then out = base - G R.
@@ -863,6 +877,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void i
   const bool inblock = row0 >= r0 && row0 < r0 + NB;
   const bool below = row0 >= r0 + NB;
   const double* tri = KNOWN ? m.tri + (int64_t)((c0 / NB) & 1) * NB * NB : m.tri;
+  if (KNOWN && given_aborted(A, &s_last)) return;
   // the panel chain is the critical path beside the trailing update's waves
   __builtin_amdgcn_s_setprio(2);
 
@@ -915,6 +930,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void i
 __global__ __launch_bounds__(256) void lu64_kernel(GjeArgs A) {
   __shared__ double s_blk[NB][LDA];
   __shared__ double s_piv[2 * NB];
+  __shared__ int s_abort;
+  if (given_aborted(A, &s_abort)) return;
   const GjeMat& m = A.m[blockIdx.y];
   lu64_publish(m.P[A.pcur], A.nbo, A.k0, 0, A.tau, m.tri, m.logdet + A.k0 / NB, m.err, s_blk, s_piv);
 }
