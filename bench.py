@@ -27,8 +27,8 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE counter runs summarised in profiles/, each scaled by what the same
 # counter reads for a plain copy of known size (--copy-calibration).  Tied to the
 # kernel source it was measured on: any later edit of that file voids it.
-TRAFFIC = {"bytes_per_launch": 4.2000e+08,
-           "source_sha256": "daa05ac89d1af06a618a874c43b1566237af2a6a9a5bcb0888b9f17ec62abbce"}
+TRAFFIC = {"bytes_per_launch": 4.1652e+08,
+           "source_sha256": "5520fea9bf0e0381abab966dc08e8a5f6f043412574565e6fd56c76438c255ce"}
 TRAFFIC_SOURCE = os.path.join(ROOT, "paper_2401_10089_amd", "csrc", "gemm_f64.hip")
 COPY_CALIBRATION_DOUBLES = 1 << 27   # 1 GiB read + 1 GiB written
 
