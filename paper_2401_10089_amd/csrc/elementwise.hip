@@ -30,7 +30,12 @@ __device__ __forceinline__ void row_range(int n, int nblk, int& i0, int& i1) {
 // Row-block kernels below write the whole padded range and sum norms over the
 // valid block only.
 
-__global__ __launch_bounds__(TPB) void db_update_kernel(DbArgs a, int nblk) {
+// Four times the usual workgroup: one row block per workgroup is all the partial-sum
+// layout allows, and the column gathers through the inverses' row maps need more
+// waves in flight than one per SIMD.  Each column still has one thread, which sums
+// its rows in order.
+constexpr int DB_TPB = 4 * TPB;
+__global__ __launch_bounds__(DB_TPB) void db_update_kernel(DbArgs a, int nblk) {
   __shared__ double s_mu;
   const int n = a.n;
   const int np = (int)a.ld;
@@ -49,7 +54,7 @@ __global__ __launch_bounds__(TPB) void db_update_kernel(DbArgs a, int nblk) {
   row_range(np, nblk, i0, i1);
   double* p0 = a.part + (int64_t)blockIdx.x * n;
   double* p1 = a.part + (int64_t)(nblk + blockIdx.x) * n;
-  for (int c = threadIdx.x; c < np; c += TPB) {
+  for (int c = threadIdx.x; c < np; c += DB_TPB) {
     const int qx = a.px[c];
     const int qy = (a.py != nullptr) ? a.py[c] : -1;
     double sdiff = 0.0, snew = 0.0;
@@ -481,7 +486,7 @@ inline dim3 row_grid(int n, int rows) { return dim3((unsigned)std::min(8, (n + 2
 }  // namespace
 
 hipError_t launch_db_update(const DbArgs& a, int nblk, hipStream_t s) {
-  hipLaunchKernelGGL(db_update_kernel, dim3(nblk), dim3(TPB), 0, s, a, nblk);
+  hipLaunchKernelGGL(db_update_kernel, dim3(nblk), dim3(DB_TPB), 0, s, a, nblk);
   return hipGetLastError();
 }
 
