@@ -301,8 +301,9 @@ struct Status {
 struct Ctx {
   hipStream_t s = nullptr;
   hipStream_t side = nullptr;     // factors the next Gauss-Jordan panel (look-ahead)
-  hipEvent_t ev_upd = nullptr;    // next panel's columns updated (on s)
-  hipEvent_t ev_pan = nullptr;    // next panel factored (on side)
+  hipEvent_t ev_upd = nullptr;    // next panel's columns updated (on s at step 0, then on side)
+  hipEvent_t ev_pan = nullptr;    // last panel factored (on side)
+  hipEvent_t ev_gemm = nullptr;   // trailing update of the step done (on s)
   Plan p;
   char* base = nullptr;
   size_t bytes = 0;               // usable workspace (the plan and any reverse-mode region)
@@ -391,17 +392,19 @@ Status factor_panel(GjeArgs& a, hipStream_t s, bool panel_written = false) {
 }
 
 Status outer_update(Ctx& c, const GjeArgs& a, int c_lo, int c_hi, bool inside, int max_wgs = 0,
-                    double* const* next_panel = nullptr, int next_nbo = 0) {
+                    double* const* next_panel = nullptr, int next_nbo = 0,
+                    hipStream_t strm = nullptr) {
   Status st;
+  hipStream_t s = strm != nullptr ? strm : c.s;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (g_prof.on) {
     e0 = g_prof.get();
     e1 = g_prof.get();
-    if (e0) HIPCK(hipEventRecord(e0, c.s));
+    if (e0) HIPCK(hipEventRecord(e0, s));
   }
-  HIPCK(launch_gje_outer_update(a, c_lo, c_hi, inside, max_wgs, c.s, next_panel, next_nbo));
+  HIPCK(launch_gje_outer_update(a, c_lo, c_hi, inside, max_wgs, s, next_panel, next_nbo));
   if (g_prof.on && e0 && e1) {
-    HIPCK(hipEventRecord(e1, c.s));
+    HIPCK(hipEventRecord(e1, s));
     // algorithmic work: the columns outside the step's block get a rank-nbo update
     const double npd = a.n_pad;
     const int tn = (a.n_pad + 127) / 128;
@@ -431,8 +434,13 @@ Status outer_update(Ctx& c, const GjeArgs& a, int c_lo, int c_hi, bool inside, i
 //
 // Look-ahead: the outer update of step K first updates the columns of step K+1's
 // panel; the side stream then factors that panel while the rest of step K's update
-// runs on the main stream.  Panels and gather maps alternate between two buffers
-// by step parity, so the side stream never touches what the running update reads.
+// runs on the main stream.  From step 1 on, that look-ahead update runs on the side
+// stream right after the panel it needs (once the previous step's trailing update
+// is done), so the serial chain panel -> look-ahead -> panel crosses no stream; the
+// trailing update of step K starts on the main stream once the look-ahead update
+// has had the device to itself.  Panels and gather maps alternate between two
+// buffers by step parity, so the side stream never touches what the running update
+// reads.
 Status gje_invert(Ctx& c, int nmat, const double* const src[2], double* fin[2],
                   bool known = false) {
   Status st;
@@ -458,7 +466,6 @@ Status gje_invert(Ctx& c, int nmat, const double* const src[2], double* fin[2],
     if (K == 0 || !ahead) {
       PROPAGATE(factor_panel(a, c.s));
     } else {
-      HIPCK(hipStreamWaitEvent(c.s, c.ev_pan, 0));
       a.pcur = (a.nbo / kNB) & 1;   // where the side stream's panel ended
     }
     if (ahead && K + 1 < nsteps) {
@@ -473,15 +480,24 @@ Status gje_invert(Ctx& c, int nmat, const double* const src[2], double* fin[2],
       }
       // in a given order the look-ahead columns go straight into the next panel
       double* next_panel[2] = {b.m[0].P[0], nmat > 1 ? b.m[1].P[0] : nullptr};
-      PROPAGATE(outer_update(c, a, n_lo, n_hi, true, 0, known ? next_panel : nullptr, b.nbo));
-      HIPCK(hipEventRecord(c.ev_upd, c.s));
-      HIPCK(hipStreamWaitEvent(c.side, c.ev_upd, 0));
+      // step 0's panel was factored on the main stream, later ones on the side stream;
+      // the look-ahead update follows it there, after the previous trailing update
+      hipStream_t la = (K == 0) ? c.s : c.side;
+      if (K > 0) HIPCK(hipStreamWaitEvent(c.side, c.ev_gemm, 0));
+      PROPAGATE(outer_update(c, a, n_lo, n_hi, true, 0, known ? next_panel : nullptr, b.nbo, la));
+      HIPCK(hipEventRecord(c.ev_upd, la));
+      if (K == 0) HIPCK(hipStreamWaitEvent(c.side, c.ev_upd, 0));
       PROPAGATE(factor_panel(b, c.side, known));
-      HIPCK(hipEventRecord(c.ev_pan, c.side));
       // the rest of the update runs beside the next panel's factorization, which is
       // the critical path: cap its workgroups so that the panel kernels find free CUs
+      if (K > 0) HIPCK(hipStreamWaitEvent(c.s, c.ev_upd, 0));
       PROPAGATE(outer_update(c, a, n_lo, n_hi, false, lookahead_wgs(c.p.n_pad, a.known) / a.nmat));
+      HIPCK(hipEventRecord(c.ev_gemm, c.s));
     } else {
+      if (K > 0 && ahead) {   // the last panel, factored on the side stream
+        HIPCK(hipEventRecord(c.ev_pan, c.side));
+        HIPCK(hipStreamWaitEvent(c.s, c.ev_pan, 0));
+      }
       PROPAGATE(outer_update(c, a, 0, 0, false));   // every column, full tiles
     }
     for (int z = 0; z < nmat; ++z) cur[z] = a.m[z].Mout;
@@ -1252,7 +1268,7 @@ Status backward_r64(Ctx& c, const double* A, int64_t lda, const double* G, int64
 // process creates only as many sets as it ever ran calls at the same time.
 struct SideRes {
   hipStream_t side = nullptr;
-  hipEvent_t upd = nullptr, pan = nullptr;
+  hipEvent_t upd = nullptr, pan = nullptr, gemm = nullptr;
 };
 std::mutex g_side_mu;
 std::map<int, std::vector<SideRes>> g_side_pool;
@@ -1263,8 +1279,10 @@ bool side_create(SideRes& r) {
     return false;
   }
   if (hipEventCreateWithFlags(&r.upd, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&r.pan, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&r.pan, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&r.gemm, hipEventDisableTiming) != hipSuccess) {
     if (r.upd != nullptr) (void)hipEventDestroy(r.upd);
+    if (r.pan != nullptr) (void)hipEventDestroy(r.pan);
     (void)hipStreamDestroy(r.side);
     r = SideRes{};
     return false;
@@ -1327,6 +1345,7 @@ struct Call {
       c.side = side.side;
       c.ev_upd = side.upd;
       c.ev_pan = side.pan;
+      c.ev_gemm = side.gemm;
     }
   }
   ~Call() {
