@@ -391,18 +391,23 @@ Status factor_panel(GjeArgs& a, hipStream_t s, bool panel_written = false) {
   return st;
 }
 
+// Outer update launch.  With profiling on, the trailing updates (not the look-ahead
+// columns, which run on the serial chain where extra event records would cost time)
+// are bracketed by timing events; `done` is recorded right after the launch, ahead
+// of the closing timing event.
 Status outer_update(Ctx& c, const GjeArgs& a, int c_lo, int c_hi, bool inside, int max_wgs = 0,
                     double* const* next_panel = nullptr, int next_nbo = 0,
-                    hipStream_t strm = nullptr) {
+                    hipStream_t strm = nullptr, hipEvent_t done = nullptr) {
   Status st;
   hipStream_t s = strm != nullptr ? strm : c.s;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (g_prof.on) {
+  if (g_prof.on && !inside) {
     e0 = g_prof.get();
     e1 = g_prof.get();
     if (e0) HIPCK(hipEventRecord(e0, s));
   }
   HIPCK(launch_gje_outer_update(a, c_lo, c_hi, inside, max_wgs, s, next_panel, next_nbo));
+  if (done != nullptr) HIPCK(hipEventRecord(done, s));
   if (g_prof.on && e0 && e1) {
     HIPCK(hipEventRecord(e1, s));
     // algorithmic work: the columns outside the step's block get a rank-nbo update
@@ -491,8 +496,8 @@ Status gje_invert(Ctx& c, int nmat, const double* const src[2], double* fin[2],
       // the rest of the update runs beside the next panel's factorization, which is
       // the critical path: cap its workgroups so that the panel kernels find free CUs
       if (K > 0) HIPCK(hipStreamWaitEvent(c.s, c.ev_upd, 0));
-      PROPAGATE(outer_update(c, a, n_lo, n_hi, false, lookahead_wgs(c.p.n_pad, a.known) / a.nmat));
-      HIPCK(hipEventRecord(c.ev_gemm, c.s));
+      PROPAGATE(outer_update(c, a, n_lo, n_hi, false, lookahead_wgs(c.p.n_pad, a.known) / a.nmat,
+                             nullptr, 0, nullptr, c.ev_gemm));
     } else {
       if (K > 0 && ahead) {   // the last panel, factored on the side stream
         HIPCK(hipEventRecord(c.ev_pan, c.side));
