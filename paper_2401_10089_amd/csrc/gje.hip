@@ -947,21 +947,21 @@ __global__ void begin_kernel(GjeArgs A, int nslots, int ncnt) {
   }
 }
 
-__global__ void panel_copy_kernel(GjeArgs A) {
+// Four panel rows per workgroup, one wave per row, 16-byte loads of the contiguous
+// row segment (n_pad and k0 are multiples of 64).
+__global__ __launch_bounds__(256) void panel_copy_kernel(GjeArgs A) {
   const GjeMat& m = A.m[blockIdx.y];
   const int nbo = A.nbo;
-  const int64_t total = (int64_t)A.n_pad * nbo;
-  double* P = m.P[A.pcur];
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= A.n_pad) return;
   // the first outer step of a given-order inversion reads the rows in that order
   const bool gather = A.known && A.k0 == 0;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = e / nbo;
-    const int c = (int)(e % nbo);
-    const int src = gather ? min(max(m.order[i], 0), A.n_pad - 1) : (int)i;
-    P[e] = m.Min[(int64_t)src * A.n_pad + A.k0 + c];
-    if (c == 0 && m.pi != nullptr) m.pi[i] = src;
-  }
+  const int src = gather ? min(max(m.order[i], 0), A.n_pad - 1) : i;
+  const f64x2* from = reinterpret_cast<const f64x2*>(m.Min + (int64_t)src * A.n_pad + A.k0);
+  f64x2* to = reinterpret_cast<f64x2*>(m.P[A.pcur] + (int64_t)i * nbo);
+  for (int q = lane; q < nbo / 2; q += 64) to[q] = from[q];
+  if (lane == 0 && m.pi != nullptr) m.pi[i] = src;
 }
 
 __global__ void finish_kernel(GjeArgs A) {
@@ -989,9 +989,7 @@ hipError_t launch_gje_begin(const GjeArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_gje_panel_copy(const GjeArgs& a, hipStream_t s) {
-  const int64_t total = (int64_t)a.n_pad * a.nbo;
-  const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
-  hipLaunchKernelGGL(panel_copy_kernel, dim3(blocks, a.nmat), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(panel_copy_kernel, dim3((a.n_pad + 3) / 4, a.nmat), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
