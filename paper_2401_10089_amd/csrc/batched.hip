@@ -309,17 +309,29 @@ __device__ __forceinline__ bool wg_inverse(Shm<RA, CW>& sh, const double* M, dou
 template <int RA, int CW>
 __device__ int wg_apply(Shm<RA, CW>& sh, const double* B2, const double* B, int n, int q, int r,
                         bool adj, int src, int s1, int s2) {
+  constexpr int N = 64 * RA;
+  constexpr int NP = Shm<RA, CW>::NT / N;   // threads per output element (4)
   int cur = src, nxt = s1;
+  // output i = tid % N, its sum over k split in NP contiguous parts (part tid / N),
+  // the parts added in a fixed order
   auto step = [&](const double* M, bool t) {
+    const int i = tid() % N, part = tid() / N;
+    const int k0 = part * n / NP, k1 = (part + 1) * n / NP;
     double acc = 0.0;
-    if (tid() < n) {
+    if (i < n) {
       if (!t)
-        for (int k = 0; k < n; ++k) acc = fma(M[tid() * n + k], sh.vec[cur][k], acc);
+        for (int k = k0; k < k1; ++k) acc = fma(M[i * n + k], sh.vec[cur][k], acc);
       else
-        for (int k = 0; k < n; ++k) acc = fma(M[k * n + tid()], sh.vec[cur][k], acc);
+        for (int k = k0; k < k1; ++k) acc = fma(M[k * n + i], sh.vec[cur][k], acc);
     }
+    sh.red[tid()] = acc;
     __syncthreads();
-    if (tid() < n) sh.vec[nxt][tid()] = acc;
+    if (tid() < n) {
+      double y = sh.red[tid()];
+#pragma unroll
+      for (int pp = 1; pp < NP; ++pp) y += sh.red[pp * N + tid()];
+      sh.vec[nxt][tid()] = y;
+    }
     __syncthreads();
     cur = nxt;
     nxt = (nxt == s1) ? s2 : s1;
