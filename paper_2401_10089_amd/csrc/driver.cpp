@@ -565,6 +565,9 @@ Status db_sqrt(Ctx& c, const double* X0, double* Xout, int max_iter, int* iters,
   double rel_prev = INFINITY;
   const double tol = std::sqrt((double)n) * kU;
   double rel = INFINITY;
+  // a taped root (forward or replay) starts without a previous order, so that both
+  // make the same reuse decisions
+  if (tape != nullptr) c.have_order[0] = c.have_order[1] = false;
   // change of the iterate before the first iteration: X_0 is the previous root's
   // converged iterate, whose last inversion left its order in order[0]
   double rel_last = c.have_order[0] ? 0.0 : INFINITY;
@@ -859,8 +862,12 @@ Status forward_r64(Ctx& c, const double* A, int64_t lda, double* L, int64_t ldl,
   double* B = c.mat(3);
   double* B2 = c.mat(4);
   int* nonfinite = c.iflag();
-  // the taped forward replays roots bit for bit in the reverse sweep: it searches
-  c.reuse = rc == nullptr && o.pivot_search == 0;
+  // Row orders are reused above one outer block only: below, the tournament is a
+  // single node and the host synchronisation that reads a reused order's check costs
+  // more than it saves.  The reverse sweep may replay a taped root bit for bit: a
+  // taped root reuses orders only from its own inversions (db_sqrt), so that the
+  // replay takes the same steps.
+  c.reuse = o.pivot_search == 0 && c.p.n_pad > kNBO;
   c.have_order[0] = c.have_order[1] = false;
   c.reuse_tries = c.reuse_fails = 0;
   HIPCK(hipMemsetAsync(nonfinite, 0, sizeof(int), c.s));
@@ -962,7 +969,7 @@ constexpr uint32_t kTapeMagic = 0x4c4f474du;
 constexpr int kTapeMu = 4096;
 struct TapeHeader {
   uint32_t magic;
-  int32_t n, k_max, max_sqrt, db_max_iter, theta_source;
+  int32_t n, k_max, max_sqrt, db_max_iter, theta_source, pivot_search;
   int64_t cap, written;
   int64_t first[64];        // ring position of each root's first inverse
   int32_t mu_off[65];       // mu of root r: mu[mu_off[r] .. mu_off[r + 1]); -1: not kept
@@ -1019,6 +1026,7 @@ Status taped_forward(Ctx& c, const double* A, int64_t lda, double* L, int64_t ld
   h.max_sqrt = o.max_sqrt;
   h.db_max_iter = o.db_max_iter;
   h.theta_source = o.theta_source;
+  h.pivot_search = o.pivot_search;
   h.cap = rc.cap;
   h.written = rc.written;
   int off = 0;
@@ -1046,6 +1054,7 @@ Status taped_forward(Ctx& c, const double* A, int64_t lda, double* L, int64_t ld
 Status taped_backward(Ctx& c, const double* G, int64_t ldg, double* gradA, int64_t ldga,
                       const logm_opts& o, logm_info& info) {
   Status st;
+  c.reuse = o.pivot_search == 0 && c.p.n_pad > kNBO;   // a replayed root takes the forward's steps
   const int n = c.p.n;
   const int np = c.p.n_pad;
   const BwdLayout lay = bwd_layout(c, o);
@@ -1057,7 +1066,8 @@ Status taped_backward(Ctx& c, const double* G, int64_t ldg, double* gradA, int64
   HIPCK(hipMemcpyAsync(hbuf.data(), tape_header(c), sizeof(TapeHeader), hipMemcpyDeviceToHost, c.s));
   HIPCK(hipStreamSynchronize(c.s));
   if (h.magic != kTapeMagic || h.n != n || h.k_max != o.k_max || h.max_sqrt != o.max_sqrt ||
-      h.db_max_iter != o.db_max_iter || h.theta_source != o.theta_source || h.cap != cap) {
+      h.db_max_iter != o.db_max_iter || h.theta_source != o.theta_source ||
+      h.pivot_search != o.pivot_search || h.cap != cap) {
     st.code = LOGM_EINVAL;   // no matching taped forward pass in this workspace
     return st;
   }

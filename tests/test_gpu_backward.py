@@ -111,11 +111,10 @@ def test_autograd_matches_backward(lm):
     L.backward(torch.from_numpy(G).to(dev))
     gA, _ = gpu_backward(lm, A, G)
     assert np.array_equal(At.grad.cpu().numpy(), gA)
-    # the taped forward searches pivots in every inversion: bit for bit the plain
-    # forward with the search, and the default forward (previous orders reused) to
-    # rounding
+    # the taped forward reuses row orders only within a root (the reverse sweep may
+    # replay a root): the plain forward with or without reuse agrees to rounding
     L1, _ = lm.logm(torch.from_numpy(A).to(dev), pivot_search=True)
-    assert np.array_equal(L.detach().cpu().numpy(), L1.cpu().numpy())
+    assert relf(L.detach().cpu().numpy(), L1.cpu().numpy()) < 1e-12
     L2, _ = lm.logm(torch.from_numpy(A).to(dev))
     assert relf(L.detach().cpu().numpy(), L2.cpu().numpy()) < 1e-12
 
@@ -131,9 +130,10 @@ def test_backward_nonfinite_G(lm):
 
 
 def test_taped_pair_matches_self_contained_backward(lm):
-    """logm_forward_taped + logm_backward_taped give the same L and gradient as
-    logm_forward and logm_backward, bit for bit, also with a ring too short for the
-    whole tape (roots replayed) and for several G after one forward."""
+    """logm_forward_taped + logm_backward_taped give the gradient of the self-contained
+    logm_backward bit for bit (and L equal to logm_forward to rounding), also with a
+    ring too short for the whole tape (roots replayed) and for several G after one
+    forward."""
     import torch
 
     n = 96
@@ -142,11 +142,17 @@ def test_taped_pair_matches_self_contained_backward(lm):
     Gs = [rng.standard_normal((n, n)) for _ in range(2)]
     dev = torch.device("cuda:0")
     At = torch.from_numpy(A).to(dev)
-    L_ref, _ = lm.logm(At, pivot_search=True)   # the taped forward searches pivots
+    L_ref, _ = lm.logm(At)
+    L_first = None
     for tape_mats in (None, 0):
         tape = lm.Tape(n, dev, tape_mats=tape_mats)
         L, info = lm.logm_forward_taped(At, tape)
-        assert torch.equal(L, L_ref)
+        # the taped forward reuses orders within roots only: the plain forward to
+        # rounding, and every taped forward bit for bit
+        assert relf(L.cpu().numpy(), L_ref.cpu().numpy()) < 1e-12
+        if L_first is None:
+            L_first = L.clone()
+        assert torch.equal(L, L_first)
         for G in Gs + Gs[:1]:          # a G repeated after another: the tape stays valid
             gA, ib = lm.logm_backward_taped(torch.from_numpy(G).to(dev), tape)
             ref, _ = lm.logm_backward(At, torch.from_numpy(G).to(dev))

@@ -105,9 +105,9 @@ def test_complex_taped_pair(lm):
     Ad = torch.from_numpy(A).to(dev)
     tape = lm.Tape(n, dev, complex=True)
     L, info = lm.logm_forward_taped(Ad, tape)
-    L_plain, _ = lm.logm(Ad, pivot_search=True)   # the taped forward searches pivots
+    L_plain, _ = lm.logm(Ad)   # orders reused across roots too: equal to rounding
     assert L.dtype == torch.complex128
-    assert torch.equal(L, L_plain)
+    assert relf(L.cpu().numpy(), L_plain.cpu().numpy()) < 1e-12
     rng = np.random.default_rng(8601)
     for _ in range(2):
         G = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))

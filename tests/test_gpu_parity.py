@@ -291,13 +291,16 @@ def test_logm_rotscale1024():
 @pytest.mark.parametrize("n,seed", [(64, 11), (300, 12), (1024, 2001)])
 def test_logm_pivot_order_reuse_vs_search(n, seed):
     """The same logarithm with the previous row order reused where its multipliers
-    allow (default) and with the pivot search in every inversion: both against the
-    oracle, and the searching run reuses nothing."""
+    allow (default; above one 256-column outer block) and with the pivot search in
+    every inversion: both against the oracle, and the searching run reuses nothing."""
     A, Lx = rotscale_matrix(n, seed)
     L1, i1 = lm.logm(dev(A))
     L2, i2 = lm.logm(dev(A), pivot_search=True)
     assert i2["n_inv_reordered"] == 0 and i2["n_order_rejected"] == 0
-    assert i1["n_inv_reordered"] > 0
+    if n > 256:
+        assert i1["n_inv_reordered"] > 0
+    else:
+        assert i1["n_inv_reordered"] == 0 and i1["n_order_rejected"] == 0
     if n == 1024:
         # the first root's second iteration changes the iterate by about 1 relative:
         # the reused order is tried there, fails its multiplier check, and the rest of

@@ -138,5 +138,5 @@ def test_logm_eigenvalues_near_negative_axis(n, seed, theta_max, pivot_search):
         Lo, _ = oracle.logm(A, force={"s": info["s"], "k": info["k"], "db_iters": info["db_iters"]})
     assert relf(Lg, Lo) < 1e-12
     assert relf(Lg, Lx) < 1e-11
-    if not pivot_search:
+    if not pivot_search and n > 256:   # orders are reused above one outer block
         assert info["n_inv_reordered"] > 0
