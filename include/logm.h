@@ -80,12 +80,14 @@ typedef struct logm_opts {
                            applied).  logm_forward only: logm_backward differentiates
                            the unbalanced map (the same function) and logm_batched_f64
                            rejects it. */
-  int32_t pivot_search; /* 0 (default): an inversion of the square-root iteration may
-                           take the row order of the previous inversion of the same
-                           iterate (X or Y) instead of searching for pivots; the result
-                           is kept only if every elimination multiplier is at most 4 in
-                           magnitude, otherwise the inversion is redone with the search
-                           (logm_forward only; the reverse mode always searches);
+  int32_t pivot_search; /* 0 (default): for n above 256, an inversion of the
+                           square-root iteration may take the row order of the previous
+                           inversion of the same iterate (X or Y) instead of searching
+                           for pivots; the result is kept only if every elimination
+                           multiplier is at most 4 in magnitude, otherwise the inversion
+                           is redone with the search.  The reverse mode (taped forward and
+                           its replays) reuses orders only within one square root, and
+                           a backward call must use the taped forward's setting;
                            1: pivot search (tournament) for every inversion */
   int32_t reserved;     /* must be zero */
 } logm_opts;
