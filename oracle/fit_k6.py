@@ -1,48 +1,75 @@
-"""Attempted fit of a k = 6 degree-optimal scheme (test infrastructure; no table is
-shipped from it).
+"""Coefficients of the k = 6 degree-optimal scheme (test infrastructure).
 
 Table 2 lists k = 6 (six products, degree 64, order m_6 = 20+, Theta_6 = 3.72e-1) but
-the paper prints no coefficients.  This script searches the form of eq.
-five_mult_degopt with k = 6 under the paper's reduction h_{j,1} = g_{j,1} = 0:
+the paper prints no coefficients for it.  This script derives a scheme of the form
+of eq. five_mult_degopt with k = 6 under the paper's reduction h_{j,1} = g_{j,1} = 0:
 
     P_1 = I, P_2 = x, P_3 = x^2,
     P_{j+2} = (sum_{i=2}^{j+1} h_{j,i} P_i) (sum_{i=2}^{j+1} g_{j,i} P_i),  j = 2..6,
     S = sum_{q=1}^{8} y_q P_q,  y_1 = 0, y_2 = 1,
 
-46 free coefficients (the paper's count).  Each trial starts from seeded random
-coefficients and runs a Levenberg-Marquardt (regularised Gauss-Newton) fit of the
-power-series coefficients b_i of S to 1/i (eq. Taylor_log): the orders i <= 20 with a
-large weight, the tail i = 21..64 with weight rho^(i-20) for a continuation
-rho = 0.3 then 0.35 -- by Parseval, a least-squares fit of the error on the circle
-|z| = rho, the L2 stand-in for the min-max problem of eq. eq:minmax.  Minimum-norm
-Newton steps then make the orders i <= 20 exact, and Theta_6 of eq. theta_Eb is
-computed for m = 20.
+46 free coefficients (the paper's count), whose power-series coefficients b_i equal
+1/i for i <= 20 (eq. Taylor_log), the rest of the degree-64 expansion being the
+approximated "+" terms.
 
-Result: over about two hundred starts (five seeds) the best Theta_6 is 0.247, against the printed
-0.372 and Theta_5 = 0.246 (0.2448 recomputed from Table 1), so such a scheme would
-cost one more product for no fewer square roots; it is not shipped (k_max = 5).
-Relaxing the orders near 20 (weights theta^(i-1) / u on every coefficient instead of
-exact conditions) does not help in double precision: the weights span fifteen
-orders of magnitude.  The paper's optimum evidently lies in another basin than
-random starts of this size reach.
+Search (``--search``): seeded random starts, each fitted by Levenberg-Marquardt
+(regularised Gauss-Newton) on the residuals (b_i - 1/i) i, the orders i <= 34 with a
+large weight and the tail i = 35..64 with weight rho^(i-34) for a continuation
+rho = 0.3, 0.35, 0.4 -- by Parseval a least-squares fit of the error on the circle
+|z| = rho, an L2 stand-in for the min-max problem of eq. eq:minmax.  Matching the
+orders 21..34 closely, not only the exact ones, is what makes Theta large: the
+backward-error series of eq. Eb then starts near order 35.  Minimum-norm Newton
+steps then make the orders i <= 20 exact, and Theta_6 of eq. theta_Eb is computed
+for m = 20.  Over the matched-order counts tried (20 to 40), 34 gave the largest
+Theta_6 (about 0.25 at 20, 0.33 at 26, 0.36-0.38 at 28, 0.40 at 32, 0.42 at 34; the
+fits stop converging above 36).
 
-Run:  python oracle/fit_k6.py [seed] [trials]       (about 5 s per trial)
+Table (default run): from the stored best search result (START), minimum-norm Newton
+steps on the 19 order conditions in 50-digit arithmetic, then every coefficient
+rounded to double once.  Theta_6 recomputed for it is about 0.42, above the printed
+0.372, which the oracle therefore keeps (like Theta_4 for the k = 4 fit).  The
+oracle's table and the library's own copy are this output; the tests pin it
+independently (exact expansion, Theta_6, scalar and matrix accuracy, the rounding
+indicator of eq. stability_error).
+
+Run:  python oracle/fit_k6.py                    (about ten seconds)
+      python oracle/fit_k6.py --search [seed]    (re-derives START; minutes)
 """
 
 from __future__ import annotations
 
 import sys
 
+import mpmath
 import numpy as np
 
 from oracle.fit_k4 import backward_theta
 
 K = 6
-M = 20
+M = 20                                  # exact orders
+MFIT = 34                               # orders weighted heavily in the search
 DEG = 2 ** K
 JS = list(range(2, K + 1))             # products j = 2..K give P_{j+2}
 NPAR = sum(2 * j for j in JS) + K      # h_j, g_j (j entries each), y_3..y_{K+2}
 INV = np.array([0.0] + [1.0 / i for i in range(1, DEG + 1)])
+
+# Best search result (seed 113, its 59th start), orders <= 20 made exact in double.
+START = (0.611463599113279, 0.6551419906597338, 0.013861196489175607,
+         0.43379873165584487, -0.058280636237119425, -1.151167662087299,
+         -2.7011731906687975, 0.9579161512566763, -0.3677056624767909,
+         1.7847633734525987, 0.17128073055138868, 0.2652768597574684,
+         1.7277813849963357, -0.4441276436211222, -0.27886151152038846,
+         0.7921827346670384, -0.8791009403050623, -0.8924946006135868,
+         0.48718539792300064, -2.241449415243459, -4.499109177725456,
+         -0.5400909980310883, -0.4208206120415121, -0.6927324514905338,
+         0.3556328515079867, -2.806077840505822, -0.2128204398472927,
+         0.2893603187224304, -0.017337259950268448, 0.4468074294838243,
+         0.6492537800488953, -0.616834165712584, -0.0160163778142875,
+         -0.05761148329031118, -0.9109366807385031, 0.6823817999521171,
+         3.1443213766324853, -2.694064769789194, -0.18149430321291934,
+         0.4177685366744957, 0.49368029200358676, 0.6069552763877066,
+         -0.13664421237233967, 0.1587532123613366, -0.004824073438632691,
+         -0.03157239306164784)
 
 
 def unpack(p):
@@ -73,17 +100,17 @@ def expand(p):
     return S
 
 
-def residual(p, rho, wcond=1e5):
+def residual(p, rho, mfit=MFIT, wcond=1e5):
     b = expand(p)
-    r1 = (b[2:M + 1] - INV[2:M + 1]) * np.arange(2, M + 1) * wcond
-    k = np.arange(M + 1, DEG + 1)
-    r2 = (b[M + 1:] - INV[M + 1:]) * k * rho ** (k - M)
+    r1 = (b[2:mfit + 1] - INV[2:mfit + 1]) * np.arange(2, mfit + 1) * wcond
+    k = np.arange(mfit + 1, DEG + 1)
+    r2 = (b[mfit + 1:] - INV[mfit + 1:]) * k * rho ** (k - mfit)
     return np.concatenate([r1, r2])
 
 
-def levenberg_marquardt(p, rho, iters=300, lam=1e-3):
+def levenberg_marquardt(p, rho, mfit=MFIT, iters=250, lam=1e-3):
     p = p.copy()
-    f = residual(p, rho)
+    f = residual(p, rho, mfit)
     cost = f @ f
     for _ in range(iters):
         J = np.empty((len(f), len(p)))
@@ -91,13 +118,16 @@ def levenberg_marquardt(p, rho, iters=300, lam=1e-3):
             q = p.copy()
             dh = 1e-7 * max(1.0, abs(p[j]))
             q[j] += dh
-            J[:, j] = (residual(q, rho) - f) / dh
+            J[:, j] = (residual(q, rho, mfit) - f) / dh
         A = J.T @ J
         gvec = J.T @ f
         while True:
-            step = np.linalg.solve(A + lam * np.diag(np.diag(A) + 1e-12), -gvec)
+            try:
+                step = np.linalg.solve(A + lam * np.diag(np.diag(A) + 1e-12), -gvec)
+            except np.linalg.LinAlgError:
+                return p
             q = p + step
-            fq = residual(q, rho)
+            fq = residual(q, rho, mfit)
             cq = fq @ fq
             if np.isfinite(cq) and cq < cost:
                 p, f, cost = q, fq, cq
@@ -117,7 +147,7 @@ def order_error(p):
 
 
 def make_exact(p, iters=30):
-    """Minimum-norm Newton steps on the orders i <= 20 alone."""
+    """Minimum-norm Newton steps on the orders i <= 20 alone (double precision)."""
     p = p.copy()
     for _ in range(iters):
         b = expand(p)
@@ -134,18 +164,18 @@ def make_exact(p, iters=30):
     return p
 
 
-def search(seed=0, trials=20, rhos=(0.3, 0.35)):
+def search(seed=113, trials=60, mfit=MFIT, scale=0.8, rhos=(0.3, 0.35, 0.4)):
     """Best (Theta_6, coefficients) over seeded random starts."""
     rng = np.random.default_rng(seed)
     best = (0.0, None)
     for _ in range(trials):
-        p = rng.standard_normal(NPAR) * 0.7
+        p = rng.standard_normal(NPAR) * scale
         for rho in rhos:
-            p = levenberg_marquardt(p, rho)
+            p = levenberg_marquardt(p, rho, mfit)
         if order_error(p) > 1e-6:
             continue
         p = make_exact(p)
-        if order_error(p) > 1e-13 or np.max(np.abs(p)) > 20:
+        if order_error(p) > 1e-13 or np.max(np.abs(p)) > 30:
             continue
         theta = backward_theta(list(expand(p)), m=M, nterms=200)
         if theta > best[0]:
@@ -153,12 +183,77 @@ def search(seed=0, trials=20, rhos=(0.3, 0.35)):
     return best
 
 
+def _orders_mp(p):
+    """(b_i - 1/i) i for i = 2..20 in mpmath (series truncated at degree 20)."""
+    h, g, o = {}, {}, 0
+    for j in JS:
+        h[j] = p[o:o + j]
+        o += j
+        g[j] = p[o:o + j]
+        o += j
+    y = [mpmath.mpf(0), mpmath.mpf(1)] + list(p[o:o + K])
+    zero = [mpmath.mpf(0)] * (M + 1)
+    P = {2: list(zero), 3: list(zero)}
+    P[2][1] = mpmath.mpf(1)
+    P[3][2] = mpmath.mpf(1)
+    for j in JS:
+        L = [sum(h[j][i - 2] * P[i][d] for i in range(2, j + 2)) for d in range(M + 1)]
+        R = [sum(g[j][i - 2] * P[i][d] for i in range(2, j + 2)) for d in range(M + 1)]
+        P[j + 2] = [sum(L[a] * R[d - a] for a in range(d + 1)) for d in range(M + 1)]
+    S = list(zero)
+    S[1] = mpmath.mpf(1)
+    for q in range(3, K + 3):
+        S = [S[d] + y[q - 1] * P[q][d] for d in range(M + 1)]
+    return [(S[i] - mpmath.mpf(1) / i) * i for i in range(2, M + 1)]
+
+
+def newton_mp(p, dps=50, iters=8):
+    """Minimum-norm Newton steps on the 19 order conditions in mpmath."""
+    mpmath.mp.dps = dps
+    p = [mpmath.mpf(float(v)) for v in p]
+    for _ in range(iters):
+        f = mpmath.matrix(_orders_mp(p))
+        if mpmath.norm(f, mpmath.inf) < mpmath.mpf(10) ** (-dps + 8):
+            break
+        hstep = mpmath.mpf(10) ** (-dps // 2)
+        J = mpmath.matrix(len(f), len(p))
+        for j in range(len(p)):
+            q = list(p)
+            q[j] += hstep
+            fj = _orders_mp(q)
+            for i in range(len(f)):
+                J[i, j] = (fj[i] - f[i]) / hstep
+        step = J.T * mpmath.lu_solve(J * J.T, -f)
+        p = [p[j] + step[j] for j in range(len(p))]
+    return p
+
+
+def fit(start=None):
+    """The table: (h, g, y) with h[j], g[j] for j = 2..6 on P_2..P_{j+1} and y on
+    P_1..P_8, every coefficient rounded to double once."""
+    pm = newton_mp(START if start is None else start)
+    h, g, y = unpack([float(v) for v in pm])
+    return ({j: tuple(float(v) for v in h[j]) for j in JS},
+            {j: tuple(float(v) for v in g[j]) for j in JS},
+            tuple(float(v) for v in y))
+
+
 def main():
-    seed = int(sys.argv[1]) if len(sys.argv) > 1 else 0
-    trials = int(sys.argv[2]) if len(sys.argv) > 2 else 20
-    theta, p = search(seed, trials)
-    print(f"best Theta_6 over {trials} starts (seed {seed}): {theta:.4f} "
-          f"(Table 2: 0.372; Theta_5 printed 0.246)")
+    if "--search" in sys.argv:
+        rest = [a for a in sys.argv[1:] if a != "--search"]
+        seed = int(rest[0]) if rest else 113
+        theta, p = search(seed)
+        print(f"best Theta_6 (seed {seed}): {theta:.4f}")
+        print("START = (" + ", ".join(repr(float(v)) for v in p) + ")")
+        return
+    h, g, y = fit()
+    print("# k = 6: h_{j,i}, g_{j,i} for i = 2..j+1; y_1..y_8")
+    for j in JS:
+        print(f"H[{j}] = ({', '.join(repr(v) for v in h[j])})")
+        print(f"G[{j}] = ({', '.join(repr(v) for v in g[j])})")
+    print(f"Y = ({', '.join(repr(v) for v in y)})")
+    p = np.concatenate([np.concatenate([h[j], g[j]]) for j in JS] + [np.array(y[2:])])
+    print(f"Theta_6 = {backward_theta(list(expand(p)), m=M, nterms=200):.6f}")
 
 
 if __name__ == "__main__":

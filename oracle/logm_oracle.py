@@ -26,15 +26,19 @@ explicit column sums, and the 1-norm estimator as a Python loop.
 Readings of points where the paper is silent or garbled (each is restated in
 DESIGN.md):
 
-R1  Schemes shipped: k in {1, 2, 3, 4, 5}.  The paper prints coefficients only
+R1  Schemes shipped: k in {1, ..., 6}.  The paper prints coefficients only
     for k = 5 (Table 1); k = 1, 2 are the Taylor polynomials T_2, T_4 written in
     the degree-optimal form; k = 3 is the three-product scheme eq. eqP8pol solved
     for T_8 (Section 2.2); k = 4 (Table 2: order 14+, degree 16, Theta_4 = 9.31e-2,
     no coefficients printed) is our own fit in the same degree-optimal form: b_i =
     1/i for i <= 14, b_15 and b_16 on the branch of largest Theta_4 (0.0936 when
     recomputed by eq. theta_Eb, at or above the printed 9.31e-2, which is used), made
-    by ``oracle/fit_k4.py``.  k = 6..9 are not built, so "m_9" in Algorithm 1 is
-    read as m_{k_max} = m_5 = 14 with Theta_5.
+    by ``oracle/fit_k4.py``; k = 6 (Table 2: order 20+, degree 64, Theta_6 =
+    0.372, no coefficients printed) is likewise our own fit: b_i = 1/i for i <= 20,
+    the orders up to 34 matched closely by a least-squares fit (``oracle/fit_k6.py``);
+    its Theta_6 recomputed by eq. theta_Eb is above the printed 0.372, which is used.
+    k = 7..9 are not built, so "m_9" in Algorithm 1 is read as m_{k_max} (m_6 = 20
+    with Theta_6 by default).
 R2  k = 3: eq. eqP8pol has two distinct real solutions with c_4 > 0; the one with
     the smaller coefficients (e_0 ~ 0.729) is used (its stability indicator,
     eq. stability_error, is the smaller of the two).
@@ -112,7 +116,7 @@ TABLE2 = {
 }
 
 # Schemes with coefficients available (reading R1).
-SHIPPED_K = (1, 2, 3, 4, 5)
+SHIPPED_K = (1, 2, 3, 4, 5, 6)
 
 # tabmin_im from the degree-selection procedure after Algorithm 1 (1-based in k).
 TABMIN_IM = (1, 2, 3, 4, 4, 5, 5, 6, 6)
@@ -153,6 +157,32 @@ _K4_G = {
 }
 _K4_Y = (0.0, 1.0, 0.48615543620029184, 0.3864758392414079, 0.3371503075537971,
          -0.22167167535004684)
+
+
+# k = 6 (reading R1): coefficients of our own fit (oracle/fit_k6.py output), rows
+# j = 2..6 acting on P_2..P_{j+1}; y_1..y_8 acting on P_1..P_8.
+_K6_H = {
+    2: (0.6114635991132769, 0.6551419906597372),
+    3: (-0.0582806362371174, -1.1511676620872993, -2.7011731906687975),
+    4: (0.1712807305513909, 0.26527685975746773, 1.7277813849963348,
+        -0.44412764362112295),
+    5: (0.4871853979229988, -2.2414494152434585, -4.499109177725456,
+        -0.5400909980310914, -0.42082061204150933),
+    6: (-0.017337259950266283, 0.4468074294838242, 0.6492537800488971,
+        -0.6168341657125824, -0.016016377814286407, -0.05761148329031025),
+}
+_K6_G = {
+    2: (0.01386119648917362, 0.4337987316558471),
+    3: (0.9579161512566738, -0.36770566247679437, 1.7847633734525994),
+    4: (-0.27886151152038935, 0.7921827346670384, -0.8791009403050634,
+        -0.8924946006135844),
+    5: (-0.6927324514905342, 0.35563285150798374, -2.8060778405058215,
+        -0.2128204398472985, 0.2893603187224289),
+    6: (-0.9109366807385032, 0.6823817999521177, 3.1443213766324853,
+        -2.694064769789194, -0.18149430321292206, 0.41776853667449326),
+}
+_K6_Y = (0.0, 1.0, 0.493680292003588, 0.6069552763877063, -0.13664421237234012,
+         0.15875321236133835, -0.004824073438632586, -0.03157239306164823)
 
 
 class OracleError(RuntimeError):
@@ -210,6 +240,8 @@ def scheme_coefficients(k: int):
         return dict(_K4_H), dict(_K4_G), tuple(_K4_Y)
     if k == 5:
         return dict(_TABLE1_H), dict(_TABLE1_G), tuple(_TABLE1_Y)
+    if k == 6:
+        return dict(_K6_H), dict(_K6_G), tuple(_K6_Y)
     raise ValueError(f"no coefficients for k={k}")
 
 
@@ -494,7 +526,7 @@ def balance(A, max_sweeps: int = 100):
     return B, d, sweeps
 
 
-def logm(A, k_max: int = 5, max_sqrt: int = 50, db_max_iter: int = 30,
+def logm(A, k_max: int = 6, max_sqrt: int = 50, db_max_iter: int = 30,
          theta_table=TABLE2, force: dict | None = None, balanced: bool = False,
          progress=None):
     """Principal matrix logarithm by Algorithm 1 (Section 6).
@@ -617,7 +649,7 @@ def logm(A, k_max: int = 5, max_sqrt: int = 50, db_max_iter: int = 30,
 # Reverse mode: gradient of <G, log A> with respect to A
 # ---------------------------------------------------------------------------
 
-def logm_backward(A, G, k_max: int = 5, max_sqrt: int = 50, db_max_iter: int = 30,
+def logm_backward(A, G, k_max: int = 6, max_sqrt: int = 50, db_max_iter: int = 30,
                   theta_table=TABLE2, force: dict | None = None):
     """Abar = d<G, logm(A)>_F / dA by reverse-mode differentiation of Algorithm 1.
 

@@ -36,7 +36,8 @@ def golden():
 
 def decision_cases(read):
     """The hand-derived decision cases: name -> (A, expected, options), where expected
-    is (s, k, n_est) or an error code such as "ENOCONV" and options holds max_sqrt."""
+    is (s, k, n_est) or an error code such as "ENOCONV" and options holds max_sqrt and
+    k_max (5 unless the line sets it: most cases were derived for schemes 1..5)."""
     import numpy as np
 
     out = {}
@@ -44,5 +45,6 @@ def decision_cases(read):
         kw = dict(o.split("=", 1) for o in opts)
         A = np.array([float(v) for v in mat.split(",")]).reshape(int(n), int(n))
         expected = kw["status"] if "status" in kw else (int(s), int(k), int(nest))
-        out[name] = (A, expected, {"max_sqrt": int(kw.get("max_sqrt", 50))})
+        out[name] = (A, expected, {"max_sqrt": int(kw.get("max_sqrt", 50)),
+                                   "k_max": int(kw.get("k_max", 5))})
     return out

@@ -208,7 +208,7 @@ def test_k3_equals_paterson_stockmeyer():
 def test_degrees_of_freedom_layout():
     """Section 3: k^2+4k+2 coefficients in the full form, k^2+2k-2 free ones after the
     normalisation theorem, the conjecture and y_1 = 0, y_2 = 1."""
-    for k in (2, 3, 4, 5):
+    for k in (2, 3, 4, 5, 6):
         h, g, y = scheme_coefficients(k)
         stored = sum(len(v) for v in h.values()) + sum(len(v) for v in g.values()) + len(y)
         assert stored == k * k + 2 * k       # rows j=2..k on P_2..P_{j+1}, plus y
@@ -245,12 +245,14 @@ def test_k3_root_choice_by_stability_indicator():
     assert abs(y[3] - 0.7290085258759623) < 1e-12
 
 
-@pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
-def test_scalar_backward_error_at_theta(k):
-    """eq. Des_Eb on the scalar case: |exp(-S(-x)) - 1 - x| / |x| <= ~u at |x| = Theta."""
+@pytest.mark.parametrize("k,th", [(1, None), (2, None), (3, None), (4, None), (5, None),
+                                  (6, None), (6, 0.4271)])
+def test_scalar_backward_error_at_theta(k, th):
+    """eq. Des_Eb on the scalar case: |exp(-S(-x)) - 1 - x| / |x| <= ~u at |x| = Theta
+    (Table 2's value; for k = 6 also the larger one recomputed for our fit)."""
     mpmath.mp.dps = 50
     b = expand_exact(k)
-    th = oracle.TABLE2[k][1]
+    th = oracle.TABLE2[k][1] if th is None else th
     worst = 0.0
     for ang in np.linspace(0, 2 * np.pi, 17):
         x = mpmath.mpc(th * np.cos(ang), th * np.sin(ang))
@@ -355,3 +357,80 @@ def test_k6_fit_layout_and_expansion():
         direct = x + sum(y[q - 1] * P[q] for q in range(3, 9))
         series = np.polynomial.polynomial.polyval(x, b)
         assert abs(direct - series) <= 1e-13 * max(1.0, abs(direct))
+
+
+# ------------------------------------------------------- k = 6 (own fit) ---
+def test_k6_fit_matches_taylor_to_order_20():
+    """Reading R1: the k = 6 scheme (our fit, the paper prints none) is degree 64 with
+    b_i = 1/i for i <= 20 (Table 2: order 20+) within a few u after rounding every
+    coefficient to double; the orders 21..34 are matched closely by the fit, and every
+    approximated term obeys the paper's |(1/i - b_i) i| <= 1 condition."""
+    b = expand_exact(6)
+    assert len(b) - 1 == 64 and b[0] == 0 and b[1] == 1
+    for i in range(2, 21):
+        assert abs((b[i] - Fraction(1, i)) * i) <= 4 * U, (i, float((b[i] - Fraction(1, i)) * i / U))
+    assert max(abs(float((b[i] - Fraction(1, i)) * i)) for i in range(21, 35)) < 1e-9
+    for i in range(21, 65):
+        e = abs(float((Fraction(1, i) - b[i]) * i))
+        assert e <= 1.0, (i, e)
+    assert abs(float((Fraction(1, 40) - b[40]) * 40)) > 1e-3      # approximated, not matched
+
+
+def test_k6_theta_recomputed_above_printed():
+    """Theta_6 of eq. theta_Eb (m = 20) recomputed from the fitted coefficients: at
+    least the printed 3.72e-1 of Table 2 (so the printed threshold is safe for this
+    polynomial) and the 0.4271 the library uses with theta_source = 1; the series
+    truncation does not move it."""
+    mpmath.mp.dps = 40
+    b = expand_exact(6)
+    c = backward_series(b, 200)
+    assert max(abs(c[i]) for i in range(2, 21)) < 1e-15   # orders <= 20 matched
+    th = theta_from_series(c, 20)
+    assert th >= oracle.TABLE2[6][1], th
+    assert 0.4271 <= th < 0.4272, th
+    assert theta_from_series(backward_series(b, 300), 20) == pytest.approx(th, rel=1e-12)
+    # above Theta_5 (so it saves square roots) and above the plain Taylor T_20 bound
+    assert th > oracle.TABLE2[5][1] and th > (21 * U) ** (1 / 20)
+
+
+def test_k6_rounding_indicator_small():
+    """eq. stability_error for k = 6: the expansion evaluated in double rounding stays
+    within a few u of 1/i on the matched orders (coefficients of modulus <= 5)."""
+    h, g, y = scheme_coefficients(6)
+    assert max(abs(v) for row in list(h.values()) + list(g.values()) for v in row) < 5
+    bt = expand_float(6)
+    assert max(abs(bt[i] - 1.0 / i) * i for i in range(1, 21)) < 16 * U
+
+
+@pytest.mark.parametrize("theta", [0.372, 0.4271])
+def test_k6_matrix_accuracy_at_theta(theta):
+    """On a nonnormal 12x12 matrix with ||x||_1 = Theta_6 (printed, and recomputed for
+    the fit) the six-product scheme gives -log(I - x) to a few u (reference: the
+    series sum_i x^i / i summed to 160 terms in 40-digit arithmetic)."""
+    rng = np.random.default_rng(46)
+    n = 12
+    x = np.triu(rng.standard_normal((n, n)), 1) + np.diag(rng.uniform(-1, 1, n))
+    x *= theta / np.abs(x).sum(axis=0).max()
+    z = oracle.eval_scheme(6, x, x @ x)
+    mpmath.mp.dps = 40
+    X = mpmath.matrix(x.tolist())
+    term = mpmath.eye(n)
+    ref = mpmath.zeros(n, n)
+    for i in range(1, 161):
+        term = term * X
+        ref += term / i
+    ref = np.array(ref.tolist(), dtype=float)
+    assert np.linalg.norm(z - ref) / np.linalg.norm(ref) < 20 * U
+
+
+def test_k6_table_is_the_fit_output():
+    """The stored k = 6 table is what the committed generator produces (re-run here
+    from its stored search result)."""
+    from oracle.fit_k6 import fit
+
+    h, g, y = fit()
+    H, G, Y = scheme_coefficients(6)
+    for j in range(2, 7):
+        assert np.allclose(h[j], H[j], rtol=1e-12, atol=1e-15), j
+        assert np.allclose(g[j], G[j], rtol=1e-12, atol=1e-15), j
+    assert np.allclose(y, Y, rtol=1e-12, atol=1e-15)
