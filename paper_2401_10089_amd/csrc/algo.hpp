@@ -10,8 +10,15 @@
 
 namespace logm {
 
+// Largest scheme with coefficients (k = 1 .. kKMax).
+constexpr int kKMax = 6;
+// Theta_6 of eq. theta_Eb (m = 20) recomputed for the six-product coefficients,
+// which the paper does not print (they are our own fit of eq. five_mult_degopt).
+constexpr double kTheta6Fit = 0.4271;   // 0.42714 rounded down
+
 // Table 2 (k -> m_k, Theta_{m_k}); theta_source 1 replaces Theta_5 by 0.2448,
-// the value Table 1 yields when recomputed.
+// the value Table 1 yields when recomputed, and Theta_6 by the value recomputed
+// for the six-product coefficients (kTheta6Fit).
 struct ThetaTable {
   int m[10];
   double th[10];
@@ -26,20 +33,44 @@ __host__ __device__ inline ThetaTable theta_table(int source) {
     t.m[k] = m[k];
     t.th[k] = th[k];
   }
-  if (source == 1) t.th[5] = 0.2448;
+  if (source == 1) {
+    t.th[5] = 0.2448;
+    t.th[6] = kTheta6Fit;
+  }
   return t;
 }
 
-// Schemes available up to k_max, increasing (shipped: 1 to 5).
+// Coefficients of the schemes k = 1..kKMax of eq. five_mult_degopt packed in one
+// array, as the batched kernel takes them: scheme k holds h (rows j = 2..k, row j
+// with the j weights of P_2..P_{j+1}), then g in the same layout, then y_1..y_{k+2}.
+__host__ __device__ constexpr int scheme_coef_count(int k) { return k * k + 2 * k; }
+__host__ __device__ constexpr int scheme_coef_base(int k) {
+  int b = 0;
+  for (int q = 1; q < k; ++q) b += scheme_coef_count(q);
+  return b;
+}
+constexpr int kSchemeCoefTotal = scheme_coef_base(kKMax + 1);
+
+struct PackedScheme {
+  const double* c;   // scheme_coef_count(k) values from scheme_coef_base(k)
+  int k;
+  __host__ __device__ int rows() const { return k * (k + 1) / 2 - 1; }   // values in h
+  __host__ __device__ static int row(int j) { return j * (j - 1) / 2 - 1; }
+  __host__ __device__ double h(int j, int i) const { return c[row(j) + i - 2]; }
+  __host__ __device__ double g(int j, int i) const { return c[rows() + row(j) + i - 2]; }
+  __host__ __device__ double y(int q) const { return c[2 * rows() + q - 1]; }
+};
+
+// Schemes available up to k_max, increasing (shipped: 1 to kKMax).
 struct SchemeSet {
-  int k[5];
+  int k[kKMax];
   int n;
 };
 
 __host__ __device__ inline SchemeSet scheme_set(int k_max) {
   SchemeSet s;
   s.n = 0;
-  for (int k = 1; k <= 5; ++k)
+  for (int k = 1; k <= kKMax; ++k)
     if (k <= k_max) s.k[s.n++] = k;
   return s;
 }

@@ -34,7 +34,7 @@ typedef double d16 __attribute__((ext_vector_type(16)));
 
 constexpr int BN_MAX = 128;   // largest n
 constexpr int KC = 32;        // rows of a right factor staged per chunk
-constexpr int NBUF = 13;      // n x n buffers per workgroup
+constexpr int NBUF = 14;      // n x n buffers per workgroup
 
 __device__ __forceinline__ int tid() { return threadIdx.x; }
 
@@ -497,12 +497,6 @@ __device__ __forceinline__ int wg_db_sqrt(Shm<RA, CW>& sh, const double* X0, dou
   return (rel > 1e-6) ? LOGM_ENOCONV : LOGM_OK;
 }
 
-// ---- graph schemes (eq. five_mult_degopt; Table 1 for k = 5) --------------------
-struct DevScheme {
-  double h[4][5], g[4][5];   // row j - 2: coefficients on P_2 .. P_{j+1}
-  double y[7];               // weights of P_1 .. P_{k+2}
-};
-
 struct BatchArgs {
   int batch;
   const int* order;         // processing order: largest matrices first
@@ -518,7 +512,7 @@ struct BatchArgs {
   int split;                // class boundary: the n <= 64 class takes n <= split
   int n_max;                // largest size the workspace was sized for (<= BN_MAX)
   int k_max, max_sqrt, db_max_iter, theta_source;
-  DevScheme sch[5];         // schemes k = 1 .. 5
+  double coef[kSchemeCoefTotal];   // schemes k = 1 .. kKMax of eq. five_mult_degopt, packed
 };
 
 template <int RA, int CW>
@@ -606,10 +600,14 @@ __global__ __launch_bounds__(256 * RA, 4) void batched_logm_kernel(BatchArgs a) 
     if (code == LOGM_OK) {
       n2 = wg_norm1<N>(sh.red, B2, n);
       k = dev_select_degree(sh, B2, B, n, n1, n2, a.k_max, a.theta_source, &dec);
-      const DevScheme& S = a.sch[k - 1];
+      const PackedScheme S{a.coef + scheme_coef_base(k), k};
       const double scale = -ldexp(1.0, s);
-      // accumulators: L_j, R_j (j = 2..k) and Z in buffers 4-6, 8-12 and A2's
-      auto acc = [&](int t) -> double* { return (t < 3) ? buf(4 + t) : ((t < 8) ? buf(5 + t) : A2); };
+      // accumulators: L_j, R_j (j = 2..k) and Z in buffers 4-6, 8-13, A2's and X's
+      // (X is free once B and B2 are formed)
+      double* const spare[2] = {A2, X};
+      auto acc = [&](int t) -> double* {
+        return (t < 3) ? buf(4 + t) : ((t < 9) ? buf(5 + t) : spare[t - 9]);
+      };
       auto Lacc = [&](int j) { return acc(2 * (j - 2)); };
       auto Racc = [&](int j) { return acc(2 * (j - 2) + 1); };
       double* Z = acc(2 * (k - 1));
@@ -619,10 +617,10 @@ __global__ __launch_bounds__(256 * RA, 4) void batched_logm_kernel(BatchArgs a) 
         const double I = (e / n == e % n) ? 1.0 : 0.0;
         const double x = -B[e], x2 = B2[e];
         for (int j = 2; j <= k; ++j) {
-          Lacc(j)[e] = S.h[j - 2][0] * x + S.h[j - 2][1] * x2;
-          Racc(j)[e] = S.g[j - 2][0] * x + S.g[j - 2][1] * x2;
+          Lacc(j)[e] = S.h(j, 2) * x + S.h(j, 3) * x2;
+          Racc(j)[e] = S.g(j, 2) * x + S.g(j, 3) * x2;
         }
-        Z[e] = S.y[0] * I + S.y[1] * x + S.y[2] * x2;
+        Z[e] = S.y(1) * I + S.y(2) * x + S.y(3) * x2;
       }
       __syncthreads();
       for (int j = 2; j <= k; ++j) {   // P_{j+2} = L_j R_j, folded into the later sums
@@ -633,10 +631,10 @@ __global__ __launch_bounds__(256 * RA, 4) void batched_logm_kernel(BatchArgs a) 
         for (int e = tid(); e < n * n; e += nthreads()) {
           const double pv = P[e];
           for (int jp = j + 1; jp <= k; ++jp) {
-            Lacc(jp)[e] = fma(S.h[jp - 2][j], pv, Lacc(jp)[e]);
-            Racc(jp)[e] = fma(S.g[jp - 2][j], pv, Racc(jp)[e]);
+            Lacc(jp)[e] = fma(S.h(jp, j + 2), pv, Lacc(jp)[e]);
+            Racc(jp)[e] = fma(S.g(jp, j + 2), pv, Racc(jp)[e]);
           }
-          Z[e] = fma(S.y[j + 1], pv, Z[e]);
+          Z[e] = fma(S.y(j + 2), pv, Z[e]);
         }
         __syncthreads();
       }
@@ -761,8 +759,7 @@ bool fork_res(ForkRes& r, hipStream_t s) {
 hipError_t launch_batched_logm(int batch, int n_max, const int* dims, const int64_t* offsets,
                                const double* A, double* L, int* status, void* ws, size_t ws_bytes,
                                int64_t total_elems, int k_max, int max_sqrt, int db_max_iter,
-                               int theta_source, const double (*h)[4][5], const double (*g)[4][5],
-                               const double (*y)[7], int split, hipStream_t s) {
+                               int theta_source, const double* coef, int split, hipStream_t s) {
   const int nb_small = std::min(batch, class_blocks<1, 16>());
   const int nb_large = std::min(batch, class_blocks<2, 16>());
   const size_t small_bytes = class_region_bytes(batch, 64, class_blocks<1, 16>());
@@ -786,14 +783,7 @@ hipError_t launch_batched_logm(int batch, int n_max, const int* dims, const int6
   a.theta_source = theta_source;
   a.split = (n_max <= 64) ? 64 : std::min(std::max(split, 1), 64);
   a.n_max = n_max;
-  for (int i = 0; i < 5; ++i) {
-    for (int r = 0; r < 4; ++r)
-      for (int c = 0; c < 5; ++c) {
-        a.sch[i].h[r][c] = h[i][r][c];
-        a.sch[i].g[r][c] = g[i][r][c];
-      }
-    for (int c = 0; c < 7; ++c) a.sch[i].y[c] = y[i][c];
-  }
+  for (int i = 0; i < kSchemeCoefTotal; ++i) a.coef[i] = coef[i];
   hipLaunchKernelGGL(batched_reset_kernel, dim3(1), dim3(ORDER_THREADS), 0, s, counters, batch, dims,
                      order);
   BatchArgs as = a, al = a;

@@ -6,10 +6,11 @@
 //
 // Readings of points the paper leaves open (shared with the test oracle, which
 // implements them separately):
-//  * schemes k in {1,...,5}: k = 1, 2 are T_2, T_4; k = 3 solves eq. eqP8pol for
-//    T_8 (root with the smaller coefficients); k = 4 is a fit of the degree-optimal
-//    form matching T_14 (Table 2 prints Theta_4 and the order but no coefficients);
-//    k = 5 is Table 1.  "m_9" of Algorithm 1 is read as m_{k_max}.
+//  * schemes k in {1,...,6}: k = 1, 2 are T_2, T_4; k = 3 solves eq. eqP8pol for
+//    T_8 (root with the smaller coefficients); k = 4 and k = 6 are fits of the
+//    degree-optimal form matching T_14 and T_20 (Table 2 prints their Theta and
+//    orders but no coefficients); k = 5 is Table 1.  "m_9" of Algorithm 1 is read as
+//    m_{k_max}.
 //  * B^2 is formed once at s = 0 before the scaling loop.
 //  * Denman-Beavers stops when rel = ||X'-X||/||X'|| <= sqrt(n) u, or (scaling off,
 //    rel < 1e-6, rel > rel_prev/2); scaling is switched off once rel < 1e-2.
@@ -36,7 +37,10 @@ namespace {
 constexpr double kU = 1.1102230246251565e-16;  // 2^-53
 constexpr int kNB = 64;
 constexpr int kNBO = 256;
-constexpr int kMats = 11;
+// padded n x n matrices of the forward workspace: X, Y, A2, B, B2, four for the
+// inversions' ping-pong outputs and two more, which the graph polynomial's 2k - 1
+// accumulators share with X, Y, A2 and the ping-pong matrices
+constexpr int kMats = 13;
 #ifndef LOGM_LOOKAHEAD_WGS
 #define LOGM_LOOKAHEAD_WGS 224   // the autotuner's choice at n = 4096 with the two-wave GEMM
 #endif
@@ -156,23 +160,45 @@ Scheme make_scheme(int k) {
             -6.000256005636980e-01, 1.063393233943084e+00}};
     s.y = {0.0, 1.0, 5.065546620208965e-01, 3.832512052972577e-01, 1.088307723749078e+00,
            2.787461897212877e-01, 8.157421998489228e-01};
+  } else if (k == 6) {
+    // Degree 64 with b_i = 1/i for i <= 20 (Table 2: order 20+); the paper prints no
+    // coefficients for k = 6, these are a fit of the same degree-optimal form whose
+    // orders up to 34 are matched closely, so that Theta_6 recomputed for it
+    // (kTheta6Fit) is above the printed 0.372.
+    s.h = {{0.6114635991132769, 0.6551419906597372},
+           {-0.0582806362371174, -1.1511676620872993, -2.7011731906687975},
+           {0.1712807305513909, 0.26527685975746773, 1.7277813849963348, -0.44412764362112295},
+           {0.4871853979229988, -2.2414494152434585, -4.499109177725456, -0.5400909980310914,
+            -0.42082061204150933},
+           {-0.017337259950266283, 0.4468074294838242, 0.6492537800488971, -0.6168341657125824,
+            -0.016016377814286407, -0.05761148329031025}};
+    s.g = {{0.01386119648917362, 0.4337987316558471},
+           {0.9579161512566738, -0.36770566247679437, 1.7847633734525994},
+           {-0.27886151152038935, 0.7921827346670384, -0.8791009403050634, -0.8924946006135844},
+           {-0.6927324514905342, 0.35563285150798374, -2.8060778405058215, -0.2128204398472985,
+            0.2893603187224289},
+           {-0.9109366807385032, 0.6823817999521177, 3.1443213766324853, -2.694064769789194,
+            -0.18149430321292206, 0.41776853667449326}};
+    s.y = {0.0, 1.0, 0.493680292003588, 0.6069552763877063, -0.13664421237234012,
+           0.15875321236133835, -0.004824073438632586, -0.03157239306164823};
   }
   return s;
 }
 
 const Scheme& scheme(int k) {
   static const Scheme s1 = make_scheme(1), s2 = make_scheme(2), s3 = make_scheme(3),
-                      s4 = make_scheme(4), s5 = make_scheme(5);
+                      s4 = make_scheme(4), s5 = make_scheme(5), s6 = make_scheme(6);
   switch (k) {
     case 1: return s1;
     case 2: return s2;
     case 3: return s3;
     case 4: return s4;
-    default: return s5;
+    case 5: return s5;
+    default: return s6;
   }
 }
 
-bool shipped(int k) { return k >= 1 && k <= 5; }
+bool shipped(int k) { return k >= 1 && k <= kKMax; }
 
 // ------------------------------------------------------------ profiling ---
 struct Profiler {
@@ -747,7 +773,7 @@ Status poly(Ctx& c, int k, int s, const double* B, const double* B2, double* L, 
   const int n = c.p.n;
   const int np = c.p.n_pad;
   const double scale = -std::ldexp(1.0, s);
-  const int slots[9] = {0, 1, 2, 5, 6, 7, 8, 9, 10};
+  const int slots[2 * kKMax - 1] = {0, 1, 2, 5, 6, 7, 8, 9, 10, 11, 12};
   int* flag = c.iflag() + 1;
   HIPCK(hipMemsetAsync(flag, 0, sizeof(int), c.s));
   if (k == 1) {
@@ -959,7 +985,9 @@ Status forward_r64(Ctx& c, const double* A, int64_t lda, double* L, int64_t ldl,
 // one: a graph node P = L R gives Lh = R Ph and Rh = Ph L; an inverse M = X^{-1}
 // gives Xh = -M Mh M.  Root inputs are checkpointed by the forward pass; each root
 // is replayed with its recorded iteration count to tape its inverses.
-constexpr int kBwdFixed = 26;   // graph factors, products, adjoints and temporaries
+// graph factors L_j, R_j and adjoints (kKMax - 1 each), products P_4..P_{kKMax+1},
+// and seven adjoints and temporaries
+constexpr int kBwdFixed = 5 * (kKMax - 1) - 1 + 7;
 
 size_t bwd_mat_bytes(const Plan& p) { return align_up((size_t)p.n_pad * p.n_pad * sizeof(double), 256); }
 
@@ -1074,18 +1102,20 @@ Status taped_backward(Ctx& c, const double* G, int64_t ldg, double* gradA, int64
   info = h.info;             // the forward's decisions; the counters are this call's
   info.n_inv = info.n_gemm = info.n_matvec = info.n_est = 0;
   // fixed slots
-  auto LJ = [&](int j) { return M(fx + (j - 2)); };        // left factor of P_{j+2}
-  auto RJ = [&](int j) { return M(fx + 4 + (j - 2)); };    // right factor
-  auto PP = [&](int i) { return M(fx + 8 + (i - 4)); };    // P_4 .. P_6
-  auto LH = [&](int j) { return M(fx + 11 + (j - 2)); };
-  auto RH = [&](int j) { return M(fx + 15 + (j - 2)); };
-  double* Zh = M(fx + 19);
-  double* Ph = M(fx + 20);
-  double* B2h = M(fx + 21);
-  double* Xh = M(fx + 22);
-  double* Yh = M(fx + 23);
-  double* T1 = M(fx + 24);
-  double* T2 = M(fx + 25);
+  constexpr int nj = kKMax - 1;                              // products j = 2..kKMax
+  auto LJ = [&](int j) { return M(fx + (j - 2)); };          // left factor of P_{j+2}
+  auto RJ = [&](int j) { return M(fx + nj + (j - 2)); };     // right factor
+  auto PP = [&](int i) { return M(fx + 2 * nj + (i - 4)); }; // P_4 .. P_{kKMax+1}
+  auto LH = [&](int j) { return M(fx + 3 * nj - 1 + (j - 2)); };
+  auto RH = [&](int j) { return M(fx + 4 * nj - 1 + (j - 2)); };
+  double* Zh = M(fx + 5 * nj - 1);
+  double* Ph = M(fx + 5 * nj);
+  double* B2h = M(fx + 5 * nj + 1);
+  double* Xh = M(fx + 5 * nj + 2);
+  double* Yh = M(fx + 5 * nj + 3);
+  double* T1 = M(fx + 5 * nj + 4);
+  double* T2 = M(fx + 5 * nj + 5);
+  static_assert(5 * nj + 6 == kBwdFixed, "reverse-mode fixed slots");
   int ngemm = 0;
   auto gemm = [&](double alpha, const double* Aop, const double* Bop, double beta, double* C) {
     ++ngemm;
@@ -1376,7 +1406,7 @@ struct Call {
 };
 
 bool opts_ok(const logm_opts& o) {
-  if (o.k_max < 1 || o.k_max > 5) return false;
+  if (o.k_max < 1 || o.k_max > kKMax) return false;
   if (o.max_sqrt < 0 || o.max_sqrt > 64) return false;
   if (o.db_max_iter < 1 || o.db_max_iter > 1000) return false;
   if (o.theta_source != 0 && o.theta_source != 1) return false;
@@ -1391,19 +1421,23 @@ bool opts_ok(const logm_opts& o) {
 hipError_t batched_launch(int batch, int n_max, const int32_t* dims, const int64_t* offsets,
                           const double* A, double* L, int32_t* status, void* ws, size_t ws_bytes,
                           int64_t total_elems, const logm_opts& opts, int split, hipStream_t s) {
-  double h[5][4][5] = {}, g[5][4][5] = {}, y[5][7] = {};
-  for (int i = 0; i < 5; ++i) {
-    const Scheme& S = scheme(i + 1);
-    for (size_t r = 0; r < S.h.size(); ++r)
-      for (size_t c = 0; c < S.h[r].size(); ++c) {
-        h[i][r][c] = S.h[r][c];
-        g[i][r][c] = S.g[r][c];
-      }
-    for (size_t c = 0; c < S.y.size(); ++c) y[i][c] = S.y[c];
-  }
+  static const std::vector<double> coef = [] {
+    std::vector<double> c(kSchemeCoefTotal, 0.0);
+    for (int k = 1; k <= kKMax; ++k) {   // the layout of PackedScheme
+      const Scheme& S = scheme(k);
+      double* p = c.data() + scheme_coef_base(k);
+      int t = 0;
+      for (const auto& r : S.h)
+        for (double v : r) p[t++] = v;
+      for (const auto& r : S.g)
+        for (double v : r) p[t++] = v;
+      for (double v : S.y) p[t++] = v;
+    }
+    return c;
+  }();
   return launch_batched_logm(batch, n_max, dims, offsets, A, L, status, ws, ws_bytes, total_elems,
-                             opts.k_max, opts.max_sqrt, opts.db_max_iter, opts.theta_source, h, g,
-                             y, split, s);
+                             opts.k_max, opts.max_sqrt, opts.db_max_iter, opts.theta_source,
+                             coef.data(), split, s);
 }
 
 // Workspace of the complex batch: the real path's at twice the size, then the real
@@ -1433,7 +1467,7 @@ extern "C" {
 void logm_default_opts(logm_opts* o) {
   if (o == nullptr) return;
   std::memset(o, 0, sizeof(*o));
-  o->k_max = 5;
+  o->k_max = kKMax;
   o->max_sqrt = 50;
   o->db_max_iter = 30;
   o->theta_source = 0;

@@ -16,7 +16,9 @@ hipError_t launch_gemm_plain(int M, int N, int K, double alpha, const double* A,
 // Graph-node product P = Lf * Rf (n x n, leading dimension ld) whose result is
 // never stored: the epilogue adds coef[t] * P into accumulator acc[t] for every
 // t < nacc, and, when dst != nullptr, writes dst = scale * (base + ycoef * P)
-// restricted to the leading nvalid x nvalid block (leading dimension ldd).
+// restricted to the leading nvalid x nvalid block (leading dimension ldd).  Nine
+// accumulators cover the first product of the six-product scheme: the two factors
+// of each later product and the output sum.
 struct PolyGemmArgs {
   const double* Lf;
   const double* Rf;
@@ -155,15 +157,16 @@ hipError_t launch_gemv(const double* M, int64_t ld, int n, const double* x, doub
                        bool transposed, double* part, int nblk, hipStream_t s);
 
 // Polynomial accumulator initialisation: out[t] = c2[t] * P2 + c3[t] * P3 + c1[t] * I
-// on the valid n x n block, zero on the rest of the padded ld x ld matrix.
+// on the valid n x n block, zero on the rest of the padded ld x ld matrix (at most
+// 11 outputs: L_j, R_j for j = 2..6 and the output sum of the six-product scheme).
 struct LincombArgs {
   const double* P2;
   const double* P3;
   int nout;
-  double* out[9];
-  double c1[9];
-  double c2[9];
-  double c3[9];
+  double* out[11];
+  double c1[11];
+  double c2[11];
+  double c3[11];
   int n;
   int64_t ld;
 };
@@ -247,7 +250,6 @@ size_t batched_workspace_bytes(int batch, int n_max);
 hipError_t launch_batched_logm(int batch, int n_max, const int* dims, const int64_t* offsets,
                                const double* A, double* L, int* status, void* ws, size_t ws_bytes,
                                int64_t total_elems, int k_max, int max_sqrt, int db_max_iter,
-                               int theta_source, const double (*h)[4][5], const double (*g)[4][5],
-                               const double (*y)[7], int split, hipStream_t s);
+                               int theta_source, const double* coef, int split, hipStream_t s);
 
 }  // namespace logm

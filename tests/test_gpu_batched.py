@@ -53,7 +53,7 @@ ITER_TIES = []  # a converged root stopped one iteration apart (stopping rule at
 TIE = 1e-9     # relative move of the Theta values that a rounding tie may need
 
 
-def tie_explains(A, s, k, k_max=5):
+def tie_explains(A, s, k, k_max=6):
     """True if the oracle, with every Theta moved by a relative TIE up or down, takes
     the device's (s, k)."""
     for f in (1.0 - TIE, 1.0 + TIE):
@@ -67,7 +67,7 @@ def tie_explains(A, s, k, k_max=5):
     return False
 
 
-def check_against_oracle(Lg, st, A, tol=TOL, k_max=5):
+def check_against_oracle(Lg, st, A, tol=TOL, k_max=6):
     """Device result against the oracle.  A flip of (s, k) must be a rounding tie (see
     tie_explains); an iteration count may differ by one on a root that converged (the
     stopping rule compares changes at the rounding floor).  The oracle then replays
@@ -214,16 +214,16 @@ def test_batched_hand_derived_decisions(lm, golden):
 
     groups = {}
     for name, (A, expected, kw) in decision_cases(golden).items():
-        groups.setdefault(kw["max_sqrt"], []).append((name, A, expected))
-    for max_sqrt, cases in groups.items():
-        Ls, st = run_batch(lm, [A for _, A, _ in cases], max_sqrt=max_sqrt)
+        groups.setdefault((kw["max_sqrt"], kw["k_max"]), []).append((name, A, expected))
+    for (max_sqrt, k_max), cases in groups.items():
+        Ls, st = run_batch(lm, [A for _, A, _ in cases], max_sqrt=max_sqrt, k_max=k_max)
         for (name, A, expected), Lg, row in zip(cases, Ls, st):
             if isinstance(expected, str):
                 assert row[0] == 6 and expected == "ENOCONV", (name, row)   # LOGM_ENOCONV
                 continue
             assert row[0] == 0, (name, row)
             assert (int(row[1]), int(row[2])) == expected[:2], (name, row, expected)
-            Lo, _ = oracle.logm(A, max_sqrt=max_sqrt)
+            Lo, _ = oracle.logm(A, max_sqrt=max_sqrt, k_max=k_max)
             assert relf(Lg, Lo) < TOL, name
 
 

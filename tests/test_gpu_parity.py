@@ -160,7 +160,7 @@ def test_sqrt_spd():
 
 
 # ------------------------------------------------------------- polynomial -
-@pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6])
 @pytest.mark.parametrize("n,s", [(1, 0), (64, 0), (100, 3), (257, 1)])
 def test_poly_matches_oracle(k, n, s):
     rng = np.random.default_rng(100 * k + n)
@@ -202,7 +202,7 @@ def decisions(info):
     return info["s"], info["k"], list(info["db_iters"])
 
 
-def tie_explains(A, info, k_max=5, progress=None):
+def tie_explains(A, info, k_max=6, progress=None):
     """True if the oracle, with every Theta moved by a relative TIE up or down, takes
     the device's (s, k): the two sides straddled a threshold by rounding."""
     for f in (1.0 - TIE, 1.0 + TIE):
@@ -225,7 +225,7 @@ def check_counters(info, io, n):
         2 * nd ** 3 * (info["n_inv"] + info["n_gemm"]) + 2 * nd ** 2 * info["n_matvec"], rel=1e-12)
 
 
-def oracle_parity(A, Lg, info, tol=TOL_LOGM, k_max=5, case=None, progress=None):
+def oracle_parity(A, Lg, info, tol=TOL_LOGM, k_max=6, case=None, progress=None):
     """Compare a device result with the oracle (decisions, counters, values); on a
     flip check that it is a tie and compare with the oracle's replay of the device's
     decisions.  Returns ((s, k) equal, oracle info, relative Frobenius error)."""
@@ -255,7 +255,7 @@ def oracle_parity(A, Lg, info, tol=TOL_LOGM, k_max=5, case=None, progress=None):
 def compare_with_oracle(A, tol=TOL_LOGM, **kw):
     L, info = lm.logm(dev(A), **kw)
     Lg = host(L)
-    same, _, _ = oracle_parity(A, Lg, info, tol=tol, k_max=kw.get("k_max", 5))
+    same, _, _ = oracle_parity(A, Lg, info, tol=tol, k_max=kw.get("k_max", 6))
     return Lg, info, same
 
 
@@ -272,7 +272,7 @@ def test_logm_rotscale_vs_oracle_and_exact(n, seed):
     A, Lx = rotscale_matrix(n, seed)
     Lg, info, same = compare_with_oracle(A)
     assert relf(Lg, Lx) < 1e-11
-    assert info["k"] in (1, 2, 3, 4, 5)
+    assert info["k"] in (1, 2, 3, 4, 5, 6)
 
 
 def test_logm_rotscale1024():
@@ -391,10 +391,23 @@ def test_logm_smaller_kmax(kmax):
 @pytest.mark.parametrize("n,rho", [(64, 0.05), (200, 0.09), (333, 0.12)])
 def test_logm_selects_k4(n, rho):
     """||A - I|| just above Theta_4's neighbourhood: no root is taken and the four-product
-    scheme (our fit, reading R1) is selected on both sides."""
+    scheme (our fit, reading R1) is selected on both sides (schemes up to k = 5; with
+    k = 6 available the last case's estimates pass Theta_5 first)."""
+    A = disk_matrix(n, 31, rho)
+    Lg, info, same = compare_with_oracle(A, k_max=5)
+    assert same and info["s"] == 0 and info["k"] == 4
+
+
+@pytest.mark.parametrize("n,rho,s", [(64, 0.55, 0), (200, 0.6, 0), (200, 0.75, 1)])
+def test_logm_selects_k6(n, rho, s):
+    """The six-product scheme (our fit, reading R1) is selected on both sides where the
+    last root's powers lie between Theta_5 and Theta_6, and it saves a square root:
+    with schemes up to k = 5 the device takes s + 1 roots on the same matrix."""
     A = disk_matrix(n, 31, rho)
     Lg, info, same = compare_with_oracle(A)
-    assert same and info["s"] == 0 and info["k"] == 4
+    assert same and info["s"] == s and info["k"] == 6
+    _, info5 = lm.logm(dev(A), k_max=5)
+    assert info5["s"] == s + 1 and info5["k"] == 5
 
 
 def test_logm_closed_forms():
