@@ -313,16 +313,32 @@ __device__ int wg_apply(Shm<RA, CW>& sh, const double* B2, const double* B, int 
   constexpr int NP = Shm<RA, CW>::NT / N;   // threads per output element (4)
   int cur = src, nxt = s1;
   // output i = tid % N, its sum over k split in NP contiguous parts (part tid / N),
-  // the parts added in a fixed order
+  // the parts added in a fixed order; within a part the matrix loads are issued eight
+  // (then four) at a time ahead of their FMAs (the sum stays in increasing k)
   auto step = [&](const double* M, bool t) {
     const int i = tid() % N, part = tid() / N;
     const int k0 = part * n / NP, k1 = (part + 1) * n / NP;
+    const int64_t di = t ? 1 : n, dk = t ? n : 1;   // element (i, k) of op(M)
     double acc = 0.0;
     if (i < n) {
-      if (!t)
-        for (int k = k0; k < k1; ++k) acc = fma(M[i * n + k], sh.vec[cur][k], acc);
-      else
-        for (int k = k0; k < k1; ++k) acc = fma(M[k * n + i], sh.vec[cur][k], acc);
+      const double* Mi = M + i * di;
+      int k = k0;
+      for (; k + 8 <= k1; k += 8) {
+        double m[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) m[u] = Mi[(k + u) * dk];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc = fma(m[u], sh.vec[cur][k + u], acc);
+      }
+      if (k + 4 <= k1) {
+        double m[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) m[u] = Mi[(k + u) * dk];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc = fma(m[u], sh.vec[cur][k + u], acc);
+        k += 4;
+      }
+      for (; k < k1; ++k) acc = fma(Mi[k * dk], sh.vec[cur][k], acc);
     }
     sh.red[tid()] = acc;
     __syncthreads();
@@ -472,7 +488,30 @@ __device__ __forceinline__ int wg_db_sqrt(Shm<RA, CW>& sh, const double* X0, dou
     const int j = tid() % N, g = tid() / N;
     double d = 0.0, a = 0.0;
     if (j < n) {
-      for (int i = g; i < n; i += nthreads() / N) {
+      constexpr int G = Shm<RA, CW>::NT / N;   // rows apart of one thread's elements
+      int i = g;
+      for (; i + 3 * G < n; i += 4 * G) {        // four rows' loads ahead of their stores
+        double xr[4], yv[4], xv[4], yiv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int r = i + u * G, e = r * n + j;
+          xr[u] = Xr[e];
+          yv[u] = Y[e];
+          xv[u] = Xi[e];
+          yiv[u] = (it > 1) ? Yi[e] : ((r == j) ? 1.0 : 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = (i + u * G) * n + j;
+          const double xn = 0.5 * (mu * xr[u] + yiv[u] / mu);
+          const double yn = 0.5 * (mu * yv[u] + xv[u] / mu);
+          d += fabs(xn - xr[u]);
+          a += fabs(xn);
+          Xr[e] = xn;
+          Y[e] = yn;
+        }
+      }
+      for (; i < n; i += G) {
         const int e = i * n + j;
         const double yi = (it > 1) ? Yi[e] : ((i == j) ? 1.0 : 0.0);
         const double xn = 0.5 * (mu * Xr[e] + yi / mu);
