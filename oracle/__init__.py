@@ -13,6 +13,8 @@ matrix logarithm with computation graphs" (arXiv 2401.10089); see
 
 from .logm_oracle import (  # noqa: F401
     TABLE2,
+    THETA_FIT,
+    THETA_DEFAULT,
     SHIPPED_K,
     TABMIN_IM,
     UNIT_ROUNDOFF,

@@ -1,0 +1,296 @@
+"""Fits of the degree-optimal schemes with k >= 6 products (test infrastructure).
+
+Table 2 lists k = 6..9 (degrees 64..512, exact orders m_k = 20, 24, 27, 28, each with
+a "+" for the approximated higher terms, Theta = 0.372 .. 0.728) but the paper prints
+no coefficients for them.  This module fits the form of eq. five_mult_degopt with k
+products under the paper's reduction h_{j,1} = g_{j,1} = 0:
+
+    P_1 = I, P_2 = x, P_3 = x^2,
+    P_{j+2} = (sum_{i=2}^{j+1} h_{j,i} P_i) (sum_{i=2}^{j+1} g_{j,i} P_i),  j = 2..k,
+    S = sum_{q=1}^{k+2} y_q P_q,  y_1 = 0, y_2 = 1,
+
+k^2 + 2k - 2 free coefficients (the paper's count), so that the power-series
+coefficients b_i of S equal 1/i for i <= m_k (eq. Taylor_log).
+
+Search: seeded random starts, each fitted by Levenberg-Marquardt (regularised
+Gauss-Newton) on the residuals (b_i - 1/i) i, the orders i <= mfit (well above m_k)
+with a large weight and the tail with weight rho^(i - mfit) for a short continuation
+in rho -- by Parseval a least-squares fit of the error on the circle |z| = rho, an L2
+stand-in for the min-max problem of eq. eq:minmax.  Matching the orders just above
+m_k closely is what makes Theta large: the backward-error series of eq. Eb then
+starts far above m_k.  Minimum-norm Newton steps then make the orders i <= m_k exact,
+and Theta_k of eq. theta_Eb is computed for m = m_k.
+
+Table: from a stored search result, minimum-norm Newton steps on the m_k - 1 order
+conditions in 50-digit arithmetic, then every coefficient rounded to double once.
+"""
+
+from __future__ import annotations
+
+import mpmath
+import numpy as np
+
+from oracle.fit_k4 import backward_theta
+
+
+class Form:
+    """The k-product form with exact orders up to m."""
+
+    def __init__(self, k: int, m: int):
+        self.K = k
+        self.M = m
+        self.DEG = 2 ** k
+        self.JS = list(range(2, k + 1))                    # products j give P_{j+2}
+        self.NPAR = sum(2 * j for j in self.JS) + k         # h_j, g_j, y_3..y_{k+2}
+        self.INV = np.array([0.0] + [1.0 / i for i in range(1, self.DEG + 1)])
+
+    def unpack(self, p):
+        h, g, o = {}, {}, 0
+        for j in self.JS:
+            h[j] = p[o:o + j]
+            o += j
+            g[j] = p[o:o + j]
+            o += j
+        y = np.concatenate([[0.0, 1.0], p[o:o + self.K]])
+        return h, g, y
+
+    def expand(self, p):
+        """Power-series coefficients b_0..b_{2^k} of S (double precision)."""
+        h, g, y = self.unpack(p)
+        D = self.DEG
+        P = {2: np.zeros(D + 1), 3: np.zeros(D + 1)}
+        P[2][1] = 1.0
+        P[3][2] = 1.0
+        for j in self.JS:
+            L = sum(h[j][i - 2] * P[i] for i in range(2, j + 2))
+            R = sum(g[j][i - 2] * P[i] for i in range(2, j + 2))
+            P[j + 2] = np.convolve(L, R)[:D + 1]
+        S = np.zeros(D + 1)
+        S[1] = 1.0
+        for q in range(3, self.K + 3):
+            S = S + y[q - 1] * P[q]
+        return S
+
+    def residual(self, p, rho, mfit, wcond=1e5):
+        b = self.expand(p)
+        inv = self.INV
+        r1 = (b[2:mfit + 1] - inv[2:mfit + 1]) * np.arange(2, mfit + 1) * wcond
+        k = np.arange(mfit + 1, self.DEG + 1)
+        r2 = (b[mfit + 1:] - inv[mfit + 1:]) * k * rho ** (k - mfit)
+        return np.concatenate([r1, r2])
+
+    def levenberg_marquardt(self, p, rho, mfit, iters=250, lam=1e-3):
+        p = p.copy()
+        f = self.residual(p, rho, mfit)
+        cost = f @ f
+        for _ in range(iters):
+            J = np.empty((len(f), len(p)))
+            for j in range(len(p)):
+                q = p.copy()
+                dh = 1e-7 * max(1.0, abs(p[j]))
+                q[j] += dh
+                J[:, j] = (self.residual(q, rho, mfit) - f) / dh
+            A = J.T @ J
+            gvec = J.T @ f
+            while True:
+                try:
+                    step = np.linalg.solve(A + lam * np.diag(np.diag(A) + 1e-12), -gvec)
+                except np.linalg.LinAlgError:
+                    return p
+                q = p + step
+                fq = self.residual(q, rho, mfit)
+                cq = fq @ fq
+                if np.isfinite(cq) and cq < cost:
+                    p, f, cost = q, fq, cq
+                    lam = max(lam / 3, 1e-12)
+                    break
+                lam *= 4
+                if lam > 1e12:
+                    return p
+            if np.linalg.norm(step) < 1e-13 * (1 + np.linalg.norm(p)):
+                break
+        return p
+
+    def order_residuals(self, p):
+        b = self.expand(p)
+        M = self.M
+        return (b[2:M + 1] - self.INV[2:M + 1]) * np.arange(2, M + 1)
+
+    def order_error(self, p):
+        return float(np.max(np.abs(self.order_residuals(p))))
+
+    def make_exact(self, p, iters=30):
+        """Minimum-norm Newton steps on the orders i <= m alone (double precision)."""
+        p = p.copy()
+        for _ in range(iters):
+            f = self.order_residuals(p)
+            if np.max(np.abs(f)) < 1e-15:
+                break
+            J = np.empty((len(f), len(p)))
+            for j in range(len(p)):
+                q = p.copy()
+                q[j] += 1e-7
+                J[:, j] = (self.order_residuals(q) - f) / 1e-7
+            p = p + np.linalg.lstsq(J, -f, rcond=None)[0]
+        return p
+
+    def theta(self, p):
+        return backward_theta(list(self.expand(p)), m=self.M, nterms=max(200, self.DEG + 200))
+
+    def search(self, seed, trials, mfit, scale, rhos):
+        """Best (Theta_k, coefficients) over seeded random starts."""
+        rng = np.random.default_rng(seed)
+        best = (0.0, None)
+        for _ in range(trials):
+            p = rng.standard_normal(self.NPAR) * scale
+            for rho in rhos:
+                p = self.levenberg_marquardt(p, rho, mfit)
+            if self.order_error(p) > 1e-6:
+                continue
+            p = self.make_exact(p)
+            if self.order_error(p) > 1e-13 or np.max(np.abs(p)) > 30:
+                continue
+            b = self.expand(p)     # every approximated term within |(1/i - b_i) i| <= 1
+            if any(abs((1.0 / i - b[i]) * i) > 1.0 for i in range(self.M + 1, self.DEG + 1)):
+                continue
+            theta = self.theta(p)
+            if theta > best[0]:
+                best = (theta, p.copy())
+        return best
+
+    def _orders_mp(self, p):
+        """(b_i - 1/i) i for i = 2..m in mpmath (series truncated at degree m)."""
+        M, K = self.M, self.K
+        h, g, o = {}, {}, 0
+        for j in self.JS:
+            h[j] = p[o:o + j]
+            o += j
+            g[j] = p[o:o + j]
+            o += j
+        y = [mpmath.mpf(0), mpmath.mpf(1)] + list(p[o:o + K])
+        zero = [mpmath.mpf(0)] * (M + 1)
+        P = {2: list(zero), 3: list(zero)}
+        P[2][1] = mpmath.mpf(1)
+        P[3][2] = mpmath.mpf(1)
+        for j in self.JS:
+            L = [sum(h[j][i - 2] * P[i][d] for i in range(2, j + 2)) for d in range(M + 1)]
+            R = [sum(g[j][i - 2] * P[i][d] for i in range(2, j + 2)) for d in range(M + 1)]
+            P[j + 2] = [sum(L[a] * R[d - a] for a in range(d + 1)) for d in range(M + 1)]
+        S = list(zero)
+        S[1] = mpmath.mpf(1)
+        for q in range(3, K + 3):
+            S = [S[d] + y[q - 1] * P[q][d] for d in range(M + 1)]
+        return [(S[i] - mpmath.mpf(1) / i) * i for i in range(2, M + 1)]
+
+    def newton_mp(self, p, dps=50, iters=8):
+        """Minimum-norm Newton steps on the m - 1 order conditions in mpmath."""
+        mpmath.mp.dps = dps
+        p = [mpmath.mpf(float(v)) for v in p]
+        for _ in range(iters):
+            f = mpmath.matrix(self._orders_mp(p))
+            if mpmath.norm(f, mpmath.inf) < mpmath.mpf(10) ** (-dps + 8):
+                break
+            hstep = mpmath.mpf(10) ** (-dps // 2)
+            J = mpmath.matrix(len(f), len(p))
+            for j in range(len(p)):
+                q = list(p)
+                q[j] += hstep
+                fj = self._orders_mp(q)
+                for i in range(len(f)):
+                    J[i, j] = (fj[i] - f[i]) / hstep
+            step = J.T * mpmath.lu_solve(J * J.T, -f)
+            p = [p[j] + step[j] for j in range(len(p))]
+        return p
+
+    def fit(self, start):
+        """The table: (h, g, y) with h[j], g[j] for j = 2..k on P_2..P_{j+1} and y on
+        P_1..P_{k+2}, every coefficient rounded to double once."""
+        pm = self.newton_mp(start)
+        h, g, y = self.unpack([float(v) for v in pm])
+        return ({j: tuple(float(v) for v in h[j]) for j in self.JS},
+                {j: tuple(float(v) for v in g[j]) for j in self.JS},
+                tuple(float(v) for v in y))
+
+
+# Exact orders m_k of Table 2 and the search settings that found each stored start.
+ORDERS = {7: 24, 8: 27}
+SEARCH = {7: dict(seed=206, trials=210, mfit=44, scale=0.8, rhos=(0.4, 0.45, 0.5)),
+          8: dict(seed=301, trials=20, mfit=50, scale=0.8, rhos=(0.45, 0.5, 0.55))}
+
+# Best search results (orders <= m_k made exact in double).
+START = {
+    7: (0.48542828230247903, 0.767060179345585, -0.049742092360537664,
+        -0.5587874263301972, -0.6592019742807633, -1.1240363189010127,
+        1.0864668559982487, 0.20037984969667635, 0.5568344680975444,
+        1.0985899355126343, 0.03881979447571281, -0.7330135732761139,
+        0.3666259301227625, -0.34371416376171265, -0.12011836574500104,
+        -0.8068156368968427, -1.696019419990847, 0.8985907148432452,
+        -0.48819625154965435, -0.02740552526158603, -1.9743534585792653,
+        0.03709575700638543, -0.6151413635148633, -0.5757679322004527,
+        0.40497697163488044, -2.738267964324541, 1.1821208529145344,
+        -1.1052308813967837, 1.598585657551887, -1.651153037672503,
+        -0.4607389493323751, -1.5726107755566974, 1.1863748445571625,
+        -1.0012392231191964, 2.194387954664079, 0.2902789556667993,
+        -5.3482446001857715, 0.5456540343567962, -0.9121753882402637,
+        0.7050417279736592, -1.568840424619432, 2.0173203473505077,
+        -3.7684184733490644, 0.8638443076351979, -1.3093071861449415,
+        -0.2619692352284191, -0.09200882772304071, 18.4627350020118,
+        -0.328815015213384, 8.9585975308066, -1.4556786096696022, 3.521834572247266,
+        -1.5320771994384266, -0.38741155110137787, 0.7516225393899246,
+        -0.9640167390681823, 0.41298131221218254, -0.05866436691718035,
+        0.1774003600482501, -0.0009674719112433563, 0.009221228781739485),
+    8: (-0.3806926435928191, 0.68385955245987, 0.1852631923521343, 0.25943071514814414,
+        -0.24341965966151732, 0.26027386954092246, 1.5115044887684441,
+        0.15757739486427036, 0.019652994760846983, 0.8662493017781833,
+        0.12075867722261963, -0.35208001611584483, -0.8076559157874543,
+        -3.2154661019445254, -0.4197862840594477, 0.060044461530056936,
+        -1.2349168444788698, -3.583611465255002, 0.7954538818278134,
+        -0.4102465365141663, -0.41017379791628045, 0.6655777125495869,
+        -1.6537635176575658, -0.8649210915819908, -0.255466941262539,
+        -0.38856819038979595, -0.963505481164674, -1.4251186348646596,
+        -0.354283452875928, 0.7336262590310139, -0.8232904978154075,
+        -0.30194233310959034, 0.7222447467300263, 0.46477749732481755,
+        -0.6858543194518715, 0.23685335840397806, 0.013007207789087668,
+        -0.7091369253539616, 0.5458447599735773, 1.022656071992447, 1.2791294762880943,
+        0.08844466557075026, 0.8844464622697253, 1.2924702358405336,
+        0.9540084568699775, 1.0759120647069298, 0.5665457765183501, 0.6616479793833044,
+        0.420078642937355, 0.9166271723208997, 0.16661743351611108,
+        -0.03632451952838711, -0.08127505858369029, 0.5216484725946849,
+        -0.5414772079410529, 0.39222731250326587, 0.7448709481012828,
+        -2.5821137266785232, 0.8444866919003529, 0.8660996049891384,
+        0.7789786046399395, -0.608799136099326, -0.5632517261375902,
+        -0.7281240303485049, -4.316420043583596, -0.4603157543408954,
+        -0.30512107336648364, -0.9050729271809068, -0.7314508232293192,
+        -0.7008792894277381, 0.2862908933529636, 0.7089546608853133,
+        0.4474884286833476, 0.02908783940668444, 0.09349122087129105,
+        0.01321277474318203, 0.274105891920063, 0.36551098261127296),
+}
+
+
+def table(k: int):
+    """(h, g, y) of the k-product table (k = 7, 8)."""
+    return Form(k, ORDERS[k]).fit(START[k])
+
+
+def main():
+    import sys
+
+    k = int(sys.argv[1])
+    form = Form(k, ORDERS[k])
+    if "--search" in sys.argv:
+        theta, p = form.search(**SEARCH[k])
+        print(f"best Theta_{k}: {theta:.4f}")
+        print("START = (" + ", ".join(repr(float(v)) for v in p) + ")")
+        return
+    h, g, y = table(k)
+    print(f"# k = {k}: h_{{j,i}}, g_{{j,i}} for i = 2..j+1; y_1..y_{k + 2}")
+    for j in form.JS:
+        print(f"H[{j}] = ({', '.join(repr(v) for v in h[j])})")
+        print(f"G[{j}] = ({', '.join(repr(v) for v in g[j])})")
+    print(f"Y = ({', '.join(repr(v) for v in y)})")
+    p = np.concatenate([np.concatenate([h[j], g[j]]) for j in form.JS] + [np.array(y[2:])])
+    print(f"Theta_{k} = {form.theta(p):.6f}")
+
+
+if __name__ == "__main__":
+    main()

@@ -40,18 +40,18 @@ from __future__ import annotations
 
 import sys
 
-import mpmath
 import numpy as np
 
-from oracle.fit_k4 import backward_theta
+from oracle.fit_degopt import Form
 
-K = 6
-M = 20                                  # exact orders
+FORM = Form(6, 20)
+K = FORM.K
+M = FORM.M                              # exact orders
 MFIT = 34                               # orders weighted heavily in the search
-DEG = 2 ** K
-JS = list(range(2, K + 1))             # products j = 2..K give P_{j+2}
-NPAR = sum(2 * j for j in JS) + K      # h_j, g_j (j entries each), y_3..y_{K+2}
-INV = np.array([0.0] + [1.0 / i for i in range(1, DEG + 1)])
+DEG = FORM.DEG
+JS = FORM.JS                            # products j = 2..K give P_{j+2}
+NPAR = FORM.NPAR                        # h_j, g_j (j entries each), y_3..y_{K+2}
+INV = FORM.INV
 
 # Best search result (seed 113, its 59th start), orders <= 20 made exact in double.
 START = (0.611463599113279, 0.6551419906597338, 0.013861196489175607,
@@ -72,170 +72,30 @@ START = (0.611463599113279, 0.6551419906597338, 0.013861196489175607,
          -0.03157239306164784)
 
 
-def unpack(p):
-    h, g, o = {}, {}, 0
-    for j in JS:
-        h[j] = p[o:o + j]
-        o += j
-        g[j] = p[o:o + j]
-        o += j
-    y = np.concatenate([[0.0, 1.0], p[o:o + K]])
-    return h, g, y
-
-
-def expand(p):
-    """Power-series coefficients b_0..b_64 of S (double precision)."""
-    h, g, y = unpack(p)
-    P = {2: np.zeros(DEG + 1), 3: np.zeros(DEG + 1)}
-    P[2][1] = 1.0
-    P[3][2] = 1.0
-    for j in JS:
-        L = sum(h[j][i - 2] * P[i] for i in range(2, j + 2))
-        R = sum(g[j][i - 2] * P[i] for i in range(2, j + 2))
-        P[j + 2] = np.convolve(L, R)[:DEG + 1]
-    S = np.zeros(DEG + 1)
-    S[1] = 1.0
-    for q in range(3, K + 3):
-        S = S + y[q - 1] * P[q]
-    return S
+unpack = FORM.unpack
+expand = FORM.expand
+order_error = FORM.order_error
+make_exact = FORM.make_exact
+newton_mp = FORM.newton_mp
 
 
 def residual(p, rho, mfit=MFIT, wcond=1e5):
-    b = expand(p)
-    r1 = (b[2:mfit + 1] - INV[2:mfit + 1]) * np.arange(2, mfit + 1) * wcond
-    k = np.arange(mfit + 1, DEG + 1)
-    r2 = (b[mfit + 1:] - INV[mfit + 1:]) * k * rho ** (k - mfit)
-    return np.concatenate([r1, r2])
+    return FORM.residual(p, rho, mfit, wcond)
 
 
 def levenberg_marquardt(p, rho, mfit=MFIT, iters=250, lam=1e-3):
-    p = p.copy()
-    f = residual(p, rho, mfit)
-    cost = f @ f
-    for _ in range(iters):
-        J = np.empty((len(f), len(p)))
-        for j in range(len(p)):
-            q = p.copy()
-            dh = 1e-7 * max(1.0, abs(p[j]))
-            q[j] += dh
-            J[:, j] = (residual(q, rho, mfit) - f) / dh
-        A = J.T @ J
-        gvec = J.T @ f
-        while True:
-            try:
-                step = np.linalg.solve(A + lam * np.diag(np.diag(A) + 1e-12), -gvec)
-            except np.linalg.LinAlgError:
-                return p
-            q = p + step
-            fq = residual(q, rho, mfit)
-            cq = fq @ fq
-            if np.isfinite(cq) and cq < cost:
-                p, f, cost = q, fq, cq
-                lam = max(lam / 3, 1e-12)
-                break
-            lam *= 4
-            if lam > 1e12:
-                return p
-        if np.linalg.norm(step) < 1e-13 * (1 + np.linalg.norm(p)):
-            break
-    return p
-
-
-def order_error(p):
-    b = expand(p)
-    return float(np.max(np.abs((b[2:M + 1] - INV[2:M + 1]) * np.arange(2, M + 1))))
-
-
-def make_exact(p, iters=30):
-    """Minimum-norm Newton steps on the orders i <= 20 alone (double precision)."""
-    p = p.copy()
-    for _ in range(iters):
-        b = expand(p)
-        f = (b[2:M + 1] - INV[2:M + 1]) * np.arange(2, M + 1)
-        if np.max(np.abs(f)) < 1e-15:
-            break
-        J = np.empty((len(f), len(p)))
-        for j in range(len(p)):
-            q = p.copy()
-            q[j] += 1e-7
-            bq = expand(q)
-            J[:, j] = ((bq[2:M + 1] - INV[2:M + 1]) * np.arange(2, M + 1) - f) / 1e-7
-        p = p + np.linalg.lstsq(J, -f, rcond=None)[0]
-    return p
+    return FORM.levenberg_marquardt(p, rho, mfit, iters, lam)
 
 
 def search(seed=113, trials=60, mfit=MFIT, scale=0.8, rhos=(0.3, 0.35, 0.4)):
     """Best (Theta_6, coefficients) over seeded random starts."""
-    rng = np.random.default_rng(seed)
-    best = (0.0, None)
-    for _ in range(trials):
-        p = rng.standard_normal(NPAR) * scale
-        for rho in rhos:
-            p = levenberg_marquardt(p, rho, mfit)
-        if order_error(p) > 1e-6:
-            continue
-        p = make_exact(p)
-        if order_error(p) > 1e-13 or np.max(np.abs(p)) > 30:
-            continue
-        theta = backward_theta(list(expand(p)), m=M, nterms=200)
-        if theta > best[0]:
-            best = (theta, p.copy())
-    return best
-
-
-def _orders_mp(p):
-    """(b_i - 1/i) i for i = 2..20 in mpmath (series truncated at degree 20)."""
-    h, g, o = {}, {}, 0
-    for j in JS:
-        h[j] = p[o:o + j]
-        o += j
-        g[j] = p[o:o + j]
-        o += j
-    y = [mpmath.mpf(0), mpmath.mpf(1)] + list(p[o:o + K])
-    zero = [mpmath.mpf(0)] * (M + 1)
-    P = {2: list(zero), 3: list(zero)}
-    P[2][1] = mpmath.mpf(1)
-    P[3][2] = mpmath.mpf(1)
-    for j in JS:
-        L = [sum(h[j][i - 2] * P[i][d] for i in range(2, j + 2)) for d in range(M + 1)]
-        R = [sum(g[j][i - 2] * P[i][d] for i in range(2, j + 2)) for d in range(M + 1)]
-        P[j + 2] = [sum(L[a] * R[d - a] for a in range(d + 1)) for d in range(M + 1)]
-    S = list(zero)
-    S[1] = mpmath.mpf(1)
-    for q in range(3, K + 3):
-        S = [S[d] + y[q - 1] * P[q][d] for d in range(M + 1)]
-    return [(S[i] - mpmath.mpf(1) / i) * i for i in range(2, M + 1)]
-
-
-def newton_mp(p, dps=50, iters=8):
-    """Minimum-norm Newton steps on the 19 order conditions in mpmath."""
-    mpmath.mp.dps = dps
-    p = [mpmath.mpf(float(v)) for v in p]
-    for _ in range(iters):
-        f = mpmath.matrix(_orders_mp(p))
-        if mpmath.norm(f, mpmath.inf) < mpmath.mpf(10) ** (-dps + 8):
-            break
-        hstep = mpmath.mpf(10) ** (-dps // 2)
-        J = mpmath.matrix(len(f), len(p))
-        for j in range(len(p)):
-            q = list(p)
-            q[j] += hstep
-            fj = _orders_mp(q)
-            for i in range(len(f)):
-                J[i, j] = (fj[i] - f[i]) / hstep
-        step = J.T * mpmath.lu_solve(J * J.T, -f)
-        p = [p[j] + step[j] for j in range(len(p))]
-    return p
+    return FORM.search(seed, trials, mfit, scale, rhos)
 
 
 def fit(start=None):
     """The table: (h, g, y) with h[j], g[j] for j = 2..6 on P_2..P_{j+1} and y on
     P_1..P_8, every coefficient rounded to double once."""
-    pm = newton_mp(START if start is None else start)
-    h, g, y = unpack([float(v) for v in pm])
-    return ({j: tuple(float(v) for v in h[j]) for j in JS},
-            {j: tuple(float(v) for v in g[j]) for j in JS},
-            tuple(float(v) for v in y))
+    return FORM.fit(START if start is None else start)
 
 
 def main():
@@ -253,7 +113,7 @@ def main():
         print(f"G[{j}] = ({', '.join(repr(v) for v in g[j])})")
     print(f"Y = ({', '.join(repr(v) for v in y)})")
     p = np.concatenate([np.concatenate([h[j], g[j]]) for j in JS] + [np.array(y[2:])])
-    print(f"Theta_6 = {backward_theta(list(expand(p)), m=M, nterms=200):.6f}")
+    print(f"Theta_6 = {FORM.theta(p):.6f}")
 
 
 if __name__ == "__main__":

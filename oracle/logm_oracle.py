@@ -37,8 +37,11 @@ R1  Schemes shipped: k in {1, ..., 6}.  The paper prints coefficients only
     0.372, no coefficients printed) is likewise our own fit: b_i = 1/i for i <= 20,
     the orders up to 34 matched closely by a least-squares fit (``oracle/fit_k6.py``);
     its Theta_6 recomputed by eq. theta_Eb is above the printed 0.372, which is used.
-    k = 7..9 are not built, so "m_9" in Algorithm 1 is read as m_{k_max} (m_6 = 20
-    with Theta_6 by default).
+    k = 7, 8 (orders 24+, 27+, degrees 128, 256) are fits of the same kind
+    (``oracle/fit_degopt.py``) whose recomputed Theta (0.5284, 0.5739) lies below
+    the printed 0.586, 0.669: those printed thresholds belong to the paper's own
+    polynomials, so our values are used (THETA_DEFAULT).  k = 9 is not built, so
+    "m_9" in Algorithm 1 is read as m_{k_max} (m_8 = 27 by default).
 R2  k = 3: eq. eqP8pol has two distinct real solutions with c_4 > 0; the one with
     the smaller coefficients (e_0 ~ 0.729) is used (its stability indicator,
     eq. stability_error, is the smaller of the two).
@@ -116,7 +119,17 @@ TABLE2 = {
 }
 
 # Schemes with coefficients available (reading R1).
-SHIPPED_K = (1, 2, 3, 4, 5, 6)
+SHIPPED_K = (1, 2, 3, 4, 5, 6, 7, 8)
+
+# Theta of eq. theta_Eb recomputed for our own fits (reading R1), rounded down: the
+# bound summed over every order of the polynomial with its coefficients rounded to
+# double (orders <= m_k then carry a few u of rounding instead of zero).
+THETA_FIT = {6: 0.4258, 7: 0.5284, 8: 0.5739}
+
+# The thresholds Algorithm 1 uses by default (reading R1): Table 2 where the shipped
+# polynomial's own Theta is at least the printed one (k <= 6), the fit's own value
+# where it is lower (k = 7, 8).
+THETA_DEFAULT = {k: (m, min(th, THETA_FIT.get(k, th))) for k, (m, th) in TABLE2.items()}
 
 # tabmin_im from the degree-selection procedure after Algorithm 1 (1-based in k).
 TABMIN_IM = (1, 2, 3, 4, 4, 5, 5, 6, 6)
@@ -184,6 +197,74 @@ _K6_G = {
 _K6_Y = (0.0, 1.0, 0.493680292003588, 0.6069552763877063, -0.13664421237234012,
          0.15875321236133835, -0.004824073438632586, -0.03157239306164823)
 
+# k = 7 (reading R1): our own fit (oracle/fit_degopt.py output), rows j = 2..7
+# acting on P_2..P_{j+1}; y_1..y_9 acting on P_1..P_9.
+_K7_H = {
+    2: (0.4854282823024797, 0.7670601793455845),
+    3: (-0.659201974280762, -1.1240363189010116, 1.0864668559982489),
+    4: (0.03881979447571353, -0.7330135732761153, 0.36662593012276345,
+        -0.34371416376171265),
+    5: (-0.4881962515496565, -0.027405525261582575, -1.974353458579265,
+        0.03709575700638547, -0.6151413635148644),
+    6: (1.5985856575518873, -1.651153037672503, -0.46073894933237486,
+        -1.5726107755566963, 1.1863748445571642, -1.0012392231191949),
+    7: (-1.5688404246194327, 2.0173203473505064, -3.7684184733490653,
+        0.8638443076351973, -1.309307186144941, -0.2619692352284182,
+        -0.09200882772304024),
+}
+_K7_G = {
+    2: (-0.04974209236053763, -0.558787426330197),
+    3: (0.200379849696676, 0.5568344680975434, 1.0985899355126332),
+    4: (-0.1201183657450009, -0.8068156368968423, -1.696019419990848,
+        0.8985907148432447),
+    5: (-0.5757679322004517, 0.40497697163488167, -2.7382679643245402,
+        1.1821208529145355, -1.1052308813967857),
+    6: (2.1943879546640797, 0.2902789556667978, -5.3482446001857715,
+        0.5456540343567967, -0.9121753882402608, 0.7050417279736609),
+    7: (18.4627350020118, -0.32881501521338397, 8.9585975308066, -1.4556786096696015,
+        3.521834572247266, -1.5320771994384277, -0.3874115511013756),
+}
+_K7_Y = (0.0, 1.0, 0.7516225393899245, -0.9640167390681803, 0.41298131221218265,
+         -0.05866436691718036, 0.1774003600482493, -0.0009674719112434058,
+         0.009221228781739477)
+
+# k = 8 (reading R1): our own fit (oracle/fit_degopt.py output), rows j = 2..8
+# acting on P_2..P_{j+1}; y_1..y_10 acting on P_1..P_10.
+_K8_H = {
+    2: (-0.3806926435928189, 0.6838595524598702),
+    3: (-0.24341965966151702, 0.26027386954092163, 1.5115044887684441),
+    4: (0.12075867722261951, -0.35208001611584555, -0.8076559157874549,
+        -3.2154661019445254),
+    5: (0.795453881827813, -0.4102465365141655, -0.41017379791628045,
+        0.6655777125495873, -1.6537635176575665),
+    6: (-0.3542834528759276, 0.7336262590310142, -0.8232904978154075,
+        -0.3019423331095895, 0.7222447467300264, 0.46477749732481705),
+    7: (1.279129476288095, 0.08844466557075051, 0.8844464622697248, 1.2924702358405324,
+        0.9540084568699778, 1.0759120647069293, 0.5665457765183504),
+    8: (-0.5414772079410531, 0.3922273125032649, 0.7448709481012827,
+        -2.582113726678523, 0.8444866919003539, 0.8660996049891386, 0.7789786046399396,
+        -0.6087991360993261),
+}
+_K8_G = {
+    2: (0.1852631923521348, 0.2594307151481441),
+    3: (0.15757739486426955, 0.019652994760847774, 0.866249301778183),
+    4: (-0.4197862840594493, 0.06004446153005831, -1.2349168444788696,
+        -3.583611465255002),
+    5: (-0.8649210915819913, -0.25546694126253877, -0.38856819038979595,
+        -0.9635054811646746, -1.4251186348646594),
+    6: (-0.6858543194518709, 0.23685335840397792, 0.013007207789088725,
+        -0.7091369253539611, 0.5458447599735755, 1.0226560719924485),
+    7: (0.6616479793833034, 0.4200786429373529, 0.9166271723209012,
+        0.16661743351611152, -0.03632451952838697, -0.08127505858369155,
+        0.521648472594683),
+    8: (-0.5632517261375906, -0.7281240303485061, -4.316420043583596,
+        -0.4603157543408953, -0.30512107336648425, -0.9050729271809062,
+        -0.73145082322932, -0.7008792894277363),
+}
+_K8_Y = (0.0, 1.0, 0.28629089335296337, 0.7089546608853124, 0.4474884286833493,
+         0.029087839406685113, 0.0934912208712908, 0.013212774743181117,
+         0.2741058919200636, 0.36551098261127246)
+
 
 class OracleError(RuntimeError):
     """Raised when the method cannot proceed (singular input, no convergence)."""
@@ -242,6 +323,10 @@ def scheme_coefficients(k: int):
         return dict(_TABLE1_H), dict(_TABLE1_G), tuple(_TABLE1_Y)
     if k == 6:
         return dict(_K6_H), dict(_K6_G), tuple(_K6_Y)
+    if k == 7:
+        return dict(_K7_H), dict(_K7_G), tuple(_K7_Y)
+    if k == 8:
+        return dict(_K8_H), dict(_K8_G), tuple(_K8_Y)
     raise ValueError(f"no coefficients for k={k}")
 
 
@@ -412,7 +497,7 @@ def _m(k, theta_table):
     return theta_table[k][0]
 
 
-def select_degree(n1, n2, e_top, e_top1, estimate, kset, theta_table=TABLE2):
+def select_degree(n1, n2, e_top, e_top1, estimate, kset, theta_table=THETA_DEFAULT):
     """Choose k from kset (sorted).  Reading R6.
 
     n1 = ||B||_1, n2 = ||B^2||_1; e_top / e_top1 are the estimates of
@@ -526,8 +611,8 @@ def balance(A, max_sweeps: int = 100):
     return B, d, sweeps
 
 
-def logm(A, k_max: int = 6, max_sqrt: int = 50, db_max_iter: int = 30,
-         theta_table=TABLE2, force: dict | None = None, balanced: bool = False,
+def logm(A, k_max: int = 8, max_sqrt: int = 50, db_max_iter: int = 30,
+         theta_table=THETA_DEFAULT, force: dict | None = None, balanced: bool = False,
          progress=None):
     """Principal matrix logarithm by Algorithm 1 (Section 6).
 
@@ -649,8 +734,8 @@ def logm(A, k_max: int = 6, max_sqrt: int = 50, db_max_iter: int = 30,
 # Reverse mode: gradient of <G, log A> with respect to A
 # ---------------------------------------------------------------------------
 
-def logm_backward(A, G, k_max: int = 6, max_sqrt: int = 50, db_max_iter: int = 30,
-                  theta_table=TABLE2, force: dict | None = None):
+def logm_backward(A, G, k_max: int = 8, max_sqrt: int = 50, db_max_iter: int = 30,
+                  theta_table=THETA_DEFAULT, force: dict | None = None):
     """Abar = d<G, logm(A)>_F / dA by reverse-mode differentiation of Algorithm 1.
 
     For real A this is the adjoint Frechet derivative L_log(A^T, G).  The forward

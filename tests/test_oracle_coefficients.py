@@ -98,6 +98,20 @@ def backward_series(b, nterms):
     return c
 
 
+def theta_all_orders(c):
+    """The bound of eq. theta_Eb summed over every order k >= 2 (for a polynomial with
+    rounded coefficients the orders <= m carry a few u instead of zero)."""
+    coeffs = [(k, abs(c[k])) for k in range(2, len(c))]
+    lo, hi = mpmath.mpf(0), mpmath.mpf(1)
+    for _ in range(100):
+        mid = (lo + hi) / 2
+        if sum(ck * mid ** (k - 1) for k, ck in coeffs) <= U:
+            lo = mid
+        else:
+            hi = mid
+    return float(lo)
+
+
 def theta_from_series(c, m):
     """Theta_m = max{theta : sum_{k>=m+1} |c_k| theta^(k-1) <= u}, eq. theta_Eb."""
     coeffs = [(k, abs(c[k])) for k in range(m + 1, len(c))]
@@ -208,7 +222,7 @@ def test_k3_equals_paterson_stockmeyer():
 def test_degrees_of_freedom_layout():
     """Section 3: k^2+4k+2 coefficients in the full form, k^2+2k-2 free ones after the
     normalisation theorem, the conjecture and y_1 = 0, y_2 = 1."""
-    for k in (2, 3, 4, 5, 6):
+    for k in (2, 3, 4, 5, 6, 7, 8):
         h, g, y = scheme_coefficients(k)
         stored = sum(len(v) for v in h.values()) + sum(len(v) for v in g.values()) + len(y)
         assert stored == k * k + 2 * k       # rows j=2..k on P_2..P_{j+1}, plus y
@@ -246,13 +260,14 @@ def test_k3_root_choice_by_stability_indicator():
 
 
 @pytest.mark.parametrize("k,th", [(1, None), (2, None), (3, None), (4, None), (5, None),
-                                  (6, None), (6, 0.4271)])
+                                  (6, None), (6, 0.4258), (7, None), (8, None)])
 def test_scalar_backward_error_at_theta(k, th):
     """eq. Des_Eb on the scalar case: |exp(-S(-x)) - 1 - x| / |x| <= ~u at |x| = Theta
-    (Table 2's value; for k = 6 also the larger one recomputed for our fit)."""
+    (the value Algorithm 1 uses: Table 2's, or for k = 7, 8 the one recomputed for
+    our fits; for k = 6 also the larger one recomputed for our fit)."""
     mpmath.mp.dps = 50
     b = expand_exact(k)
-    th = oracle.TABLE2[k][1] if th is None else th
+    th = oracle.THETA_DEFAULT[k][1] if th is None else th
     worst = 0.0
     for ang in np.linspace(0, 2 * np.pi, 17):
         x = mpmath.mpc(th * np.cos(ang), th * np.sin(ang))
@@ -379,8 +394,9 @@ def test_k6_fit_matches_taylor_to_order_20():
 def test_k6_theta_recomputed_above_printed():
     """Theta_6 of eq. theta_Eb (m = 20) recomputed from the fitted coefficients: at
     least the printed 3.72e-1 of Table 2 (so the printed threshold is safe for this
-    polynomial) and the 0.4271 the library uses with theta_source = 1; the series
-    truncation does not move it."""
+    polynomial); the bound over every order of the rounded polynomial is at least the
+    0.4258 the library uses with theta_source = 1; the series truncation does not
+    move either."""
     mpmath.mp.dps = 40
     b = expand_exact(6)
     c = backward_series(b, 200)
@@ -388,6 +404,7 @@ def test_k6_theta_recomputed_above_printed():
     th = theta_from_series(c, 20)
     assert th >= oracle.TABLE2[6][1], th
     assert 0.4271 <= th < 0.4272, th
+    assert oracle.THETA_FIT[6] <= theta_all_orders(c) < oracle.THETA_FIT[6] + 1e-4
     assert theta_from_series(backward_series(b, 300), 20) == pytest.approx(th, rel=1e-12)
     # above Theta_5 (so it saves square roots) and above the plain Taylor T_20 bound
     assert th > oracle.TABLE2[5][1] and th > (21 * U) ** (1 / 20)
@@ -402,7 +419,7 @@ def test_k6_rounding_indicator_small():
     assert max(abs(bt[i] - 1.0 / i) * i for i in range(1, 21)) < 16 * U
 
 
-@pytest.mark.parametrize("theta", [0.372, 0.4271])
+@pytest.mark.parametrize("theta", [0.372, 0.4258])
 def test_k6_matrix_accuracy_at_theta(theta):
     """On a nonnormal 12x12 matrix with ||x||_1 = Theta_6 (printed, and recomputed for
     the fit) the six-product scheme gives -log(I - x) to a few u (reference: the
@@ -431,6 +448,92 @@ def test_k6_table_is_the_fit_output():
     h, g, y = fit()
     H, G, Y = scheme_coefficients(6)
     for j in range(2, 7):
+        assert np.allclose(h[j], H[j], rtol=1e-12, atol=1e-15), j
+        assert np.allclose(g[j], G[j], rtol=1e-12, atol=1e-15), j
+    assert np.allclose(y, Y, rtol=1e-12, atol=1e-15)
+
+
+# --------------------------------------------------- k = 7, 8 (own fits) ---
+FIT_ORDERS = {7: 24, 8: 27}
+
+
+@pytest.mark.parametrize("k", [7, 8])
+def test_k78_fit_matches_taylor(k):
+    """Reading R1: the k = 7, 8 schemes (our fits, the paper prints none) have degree
+    2^k with b_i = 1/i for i <= m_k (Table 2: orders 24+, 27+) within 16u after
+    rounding every coefficient to double, and every approximated term obeys the
+    paper's |(1/i - b_i) i| <= 1 condition."""
+    m = FIT_ORDERS[k]
+    b = expand_exact(k)
+    assert len(b) - 1 == 2 ** k and b[0] == 0 and b[1] == 1
+    for i in range(2, m + 1):
+        assert abs((b[i] - Fraction(1, i)) * i) <= 16 * U, (i, float((b[i] - Fraction(1, i)) * i / U))
+    for i in range(m + 1, 2 ** k + 1):
+        e = abs(float((Fraction(1, i) - b[i]) * i))
+        assert e <= 1.0 + 1e-12, (i, e)
+
+
+@pytest.mark.parametrize("k", [7, 8])
+def test_k78_theta_recomputed(k):
+    """Theta_k of eq. theta_Eb recomputed from the fitted coefficients, over every
+    order of the rounded polynomial: at least the value Algorithm 1 uses for them
+    (THETA_FIT, rounded down) and below the printed one (so the printed thresholds,
+    which belong to the paper's polynomials, are not used), increasing with k."""
+    m = FIT_ORDERS[k]
+    mpmath.mp.dps = 40
+    b = expand_exact(k)
+    c = backward_series(b, 2 ** k + 200)
+    assert max(abs(c[i]) for i in range(2, m + 1)) < 4e-15
+    th = theta_all_orders(c)
+    fit = oracle.THETA_FIT[k]
+    assert fit <= th < fit + 1e-4, th
+    assert theta_from_series(c, m) >= th
+    assert th < oracle.TABLE2[k][1]
+    assert oracle.THETA_DEFAULT[k] == (m, fit)
+    assert oracle.THETA_DEFAULT[k][1] > oracle.THETA_DEFAULT[k - 1][1]
+
+
+@pytest.mark.parametrize("k", [7, 8])
+def test_k78_rounding_indicator_small(k):
+    """eq. stability_error for k = 7, 8: the expansion evaluated in double rounding
+    stays within a few u of 1/i on the exact orders (coefficients of modulus < 20)."""
+    h, g, y = scheme_coefficients(k)
+    assert max(abs(v) for row in list(h.values()) + list(g.values()) for v in row) < 20
+    assert max(abs(v) for v in y) < 20
+    bt = expand_float(k)
+    assert max(abs(bt[i] - 1.0 / i) * i for i in range(1, FIT_ORDERS[k] + 1)) < 32 * U
+
+
+@pytest.mark.parametrize("k", [7, 8])
+def test_k78_matrix_accuracy_at_theta(k):
+    """On a nonnormal 12x12 matrix with ||x||_1 = Theta_k (the value used) the
+    k-product scheme gives -log(I - x) to a few u (reference: the series
+    sum_i x^i / i summed to 240 terms in 40-digit arithmetic)."""
+    rng = np.random.default_rng(40 + k)
+    n = 12
+    x = np.triu(rng.standard_normal((n, n)), 1) + np.diag(rng.uniform(-1, 1, n))
+    x *= oracle.THETA_DEFAULT[k][1] / np.abs(x).sum(axis=0).max()
+    z = oracle.eval_scheme(k, x, x @ x)
+    mpmath.mp.dps = 40
+    X = mpmath.matrix(x.tolist())
+    term = mpmath.eye(n)
+    ref = mpmath.zeros(n, n)
+    for i in range(1, 241):
+        term = term * X
+        ref += term / i
+    ref = np.array(ref.tolist(), dtype=float)
+    assert np.linalg.norm(z - ref) / np.linalg.norm(ref) < 20 * U
+
+
+@pytest.mark.parametrize("k", [7, 8])
+def test_k78_table_is_the_fit_output(k):
+    """The stored k = 7, 8 tables are what the committed generator produces (re-run
+    here from its stored search results)."""
+    from oracle.fit_degopt import table
+
+    h, g, y = table(k)
+    H, G, Y = scheme_coefficients(k)
+    for j in range(2, k + 1):
         assert np.allclose(h[j], H[j], rtol=1e-12, atol=1e-15), j
         assert np.allclose(g[j], G[j], rtol=1e-12, atol=1e-15), j
     assert np.allclose(y, Y, rtol=1e-12, atol=1e-15)
