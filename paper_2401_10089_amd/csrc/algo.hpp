@@ -11,14 +11,19 @@
 namespace logm {
 
 // Largest scheme with coefficients (k = 1 .. kKMax).
-constexpr int kKMax = 6;
-// Theta_6 of eq. theta_Eb (m = 20) recomputed for the six-product coefficients,
-// which the paper does not print (they are our own fit of eq. five_mult_degopt).
-constexpr double kTheta6Fit = 0.4271;   // 0.42714 rounded down
+constexpr int kKMax = 8;
+// Theta of eq. theta_Eb recomputed for our own fits of eq. five_mult_degopt (the
+// paper prints no coefficients for k = 6, 7, 8), summed over every order of the
+// polynomial with its coefficients rounded to double, rounded down.
+constexpr double kTheta6Fit = 0.4258;
+constexpr double kTheta7Fit = 0.5284;
+constexpr double kTheta8Fit = 0.5739;
 
-// Table 2 (k -> m_k, Theta_{m_k}); theta_source 1 replaces Theta_5 by 0.2448,
-// the value Table 1 yields when recomputed, and Theta_6 by the value recomputed
-// for the six-product coefficients (kTheta6Fit).
+// Table 2 (k -> m_k, Theta_{m_k}) as Algorithm 1 uses it: the printed Theta where
+// the shipped polynomial's own Theta is at least that (k <= 6), the fits' own below
+// it (k = 7, 8: the printed values belong to the paper's polynomials).  theta_source
+// 1 replaces Theta_5 by 0.2448, the value Table 1 yields when recomputed, and
+// Theta_6 by the value recomputed for our six-product fit.
 struct ThetaTable {
   int m[10];
   double th[10];
@@ -33,6 +38,8 @@ __host__ __device__ inline ThetaTable theta_table(int source) {
     t.m[k] = m[k];
     t.th[k] = th[k];
   }
+  t.th[7] = kTheta7Fit;
+  t.th[8] = kTheta8Fit;
   if (source == 1) {
     t.th[5] = 0.2448;
     t.th[6] = kTheta6Fit;

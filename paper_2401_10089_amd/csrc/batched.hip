@@ -34,7 +34,7 @@ typedef double d16 __attribute__((ext_vector_type(16)));
 
 constexpr int BN_MAX = 128;   // largest n
 constexpr int KC = 32;        // rows of a right factor staged per chunk
-constexpr int NBUF = 14;      // n x n buffers per workgroup
+constexpr int NBUF = 2 * kKMax + 2;   // n x n buffers per workgroup
 
 __device__ __forceinline__ int tid() { return threadIdx.x; }
 
@@ -641,11 +641,13 @@ __global__ __launch_bounds__(256 * RA, 4) void batched_logm_kernel(BatchArgs a) 
       k = dev_select_degree(sh, B2, B, n, n1, n2, a.k_max, a.theta_source, &dec);
       const PackedScheme S{a.coef + scheme_coef_base(k), k};
       const double scale = -ldexp(1.0, s);
-      // accumulators: L_j, R_j (j = 2..k) and Z in buffers 4-6, 8-13, A2's and X's
-      // (X is free once B and B2 are formed)
+      // accumulators: L_j, R_j (j = 2..k) and Z in buffers 4-6, 8..NBUF-1, A2's and
+      // X's (X is free once B and B2 are formed)
       double* const spare[2] = {A2, X};
+      constexpr int nhigh = NBUF - 8;
+      static_assert(3 + nhigh + 2 >= 2 * kKMax - 1, "graph accumulators");
       auto acc = [&](int t) -> double* {
-        return (t < 3) ? buf(4 + t) : ((t < 9) ? buf(5 + t) : spare[t - 9]);
+        return (t < 3) ? buf(4 + t) : ((t < 3 + nhigh) ? buf(5 + t) : spare[t - 3 - nhigh]);
       };
       auto Lacc = [&](int j) { return acc(2 * (j - 2)); };
       auto Racc = [&](int j) { return acc(2 * (j - 2) + 1); };

@@ -6,11 +6,11 @@
 //
 // Readings of points the paper leaves open (shared with the test oracle, which
 // implements them separately):
-//  * schemes k in {1,...,6}: k = 1, 2 are T_2, T_4; k = 3 solves eq. eqP8pol for
-//    T_8 (root with the smaller coefficients); k = 4 and k = 6 are fits of the
-//    degree-optimal form matching T_14 and T_20 (Table 2 prints their Theta and
-//    orders but no coefficients); k = 5 is Table 1.  "m_9" of Algorithm 1 is read as
-//    m_{k_max}.
+//  * schemes k in {1,...,8}: k = 1, 2 are T_2, T_4; k = 3 solves eq. eqP8pol for
+//    T_8 (root with the smaller coefficients); k = 4, 6, 7, 8 are fits of the
+//    degree-optimal form matching T_14, T_20, T_24, T_27 (Table 2 prints their Theta
+//    and orders but no coefficients); k = 5 is Table 1.  "m_9" of Algorithm 1 is read
+//    as m_{k_max}.
 //  * B^2 is formed once at s = 0 before the scaling loop.
 //  * Denman-Beavers stops when rel = ||X'-X||/||X'|| <= sqrt(n) u, or (scaling off,
 //    rel < 1e-6, rel > rel_prev/2); scaling is switched off once rel < 1e-2.
@@ -38,9 +38,9 @@ constexpr double kU = 1.1102230246251565e-16;  // 2^-53
 constexpr int kNB = 64;
 constexpr int kNBO = 256;
 // padded n x n matrices of the forward workspace: X, Y, A2, B, B2, four for the
-// inversions' ping-pong outputs and two more, which the graph polynomial's 2k - 1
-// accumulators share with X, Y, A2 and the ping-pong matrices
-constexpr int kMats = 13;
+// inversions' ping-pong outputs and more up to the 2 kKMax - 1 accumulators of the
+// graph polynomial, which share X, Y, A2 and the ping-pong matrices
+constexpr int kMats = 2 * kKMax + 1;
 #ifndef LOGM_LOOKAHEAD_WGS
 #define LOGM_LOOKAHEAD_WGS 224   // the autotuner's choice at n = 4096 with the two-wave GEMM
 #endif
@@ -181,21 +181,70 @@ Scheme make_scheme(int k) {
             -0.18149430321292206, 0.41776853667449326}};
     s.y = {0.0, 1.0, 0.493680292003588, 0.6069552763877063, -0.13664421237234012,
            0.15875321236133835, -0.004824073438632586, -0.03157239306164823};
+  } else if (k == 7) {
+    // Degree 128 with b_i = 1/i for i <= 24 (Table 2: order 24+); our own fit of the
+    // degree-optimal form (the paper prints no coefficients), orders up to 44 matched
+    // closely; its recomputed Theta (kTheta7Fit) is below the printed 0.586.
+    s.h = {{0.4854282823024797, 0.7670601793455845},
+           {-0.659201974280762, -1.1240363189010116, 1.0864668559982489},
+           {0.03881979447571353, -0.7330135732761153, 0.36662593012276345, -0.34371416376171265},
+           {-0.4881962515496565, -0.027405525261582575, -1.974353458579265,
+            0.03709575700638547, -0.6151413635148644},
+           {1.5985856575518873, -1.651153037672503, -0.46073894933237486, -1.5726107755566963,
+            1.1863748445571642, -1.0012392231191949},
+           {-1.5688404246194327, 2.0173203473505064, -3.7684184733490653, 0.8638443076351973,
+            -1.309307186144941, -0.2619692352284182, -0.09200882772304024}};
+    s.g = {{-0.04974209236053763, -0.558787426330197},
+           {0.200379849696676, 0.5568344680975434, 1.0985899355126332},
+           {-0.1201183657450009, -0.8068156368968423, -1.696019419990848, 0.8985907148432447},
+           {-0.5757679322004517, 0.40497697163488167, -2.7382679643245402, 1.1821208529145355,
+            -1.1052308813967857},
+           {2.1943879546640797, 0.2902789556667978, -5.3482446001857715, 0.5456540343567967,
+            -0.9121753882402608, 0.7050417279736609},
+           {18.4627350020118, -0.32881501521338397, 8.9585975308066, -1.4556786096696015,
+            3.521834572247266, -1.5320771994384277, -0.3874115511013756}};
+    s.y = {0.0, 1.0, 0.7516225393899245, -0.9640167390681803, 0.41298131221218265,
+           -0.05866436691718036, 0.1774003600482493, -0.0009674719112434058,
+           0.009221228781739477};
+  } else if (k == 8) {
+    // Degree 256 with b_i = 1/i for i <= 27 (Table 2: order 27+); our own fit as for
+    // k = 7, orders up to 50 matched closely; Theta kTheta8Fit, below the printed 0.669.
+    s.h = {{-0.3806926435928189, 0.6838595524598702},
+           {-0.24341965966151702, 0.26027386954092163, 1.5115044887684441},
+           {0.12075867722261951, -0.35208001611584555, -0.8076559157874549, -3.2154661019445254},
+           {0.795453881827813, -0.4102465365141655, -0.41017379791628045, 0.6655777125495873,
+            -1.6537635176575665},
+           {-0.3542834528759276, 0.7336262590310142, -0.8232904978154075, -0.3019423331095895,
+            0.7222447467300264, 0.46477749732481705},
+           {1.279129476288095, 0.08844466557075051, 0.8844464622697248, 1.2924702358405324,
+            0.9540084568699778, 1.0759120647069293, 0.5665457765183504},
+           {-0.5414772079410531, 0.3922273125032649, 0.7448709481012827, -2.582113726678523,
+            0.8444866919003539, 0.8660996049891386, 0.7789786046399396, -0.6087991360993261}};
+    s.g = {{0.1852631923521348, 0.2594307151481441},
+           {0.15757739486426955, 0.019652994760847774, 0.866249301778183},
+           {-0.4197862840594493, 0.06004446153005831, -1.2349168444788696, -3.583611465255002},
+           {-0.8649210915819913, -0.25546694126253877, -0.38856819038979595,
+            -0.9635054811646746, -1.4251186348646594},
+           {-0.6858543194518709, 0.23685335840397792, 0.013007207789088725,
+            -0.7091369253539611, 0.5458447599735755, 1.0226560719924485},
+           {0.6616479793833034, 0.4200786429373529, 0.9166271723209012, 0.16661743351611152,
+            -0.03632451952838697, -0.08127505858369155, 0.521648472594683},
+           {-0.5632517261375906, -0.7281240303485061, -4.316420043583596, -0.4603157543408953,
+            -0.30512107336648425, -0.9050729271809062, -0.73145082322932, -0.7008792894277363}};
+    s.y = {0.0, 1.0, 0.28629089335296337, 0.7089546608853124, 0.4474884286833493,
+           0.029087839406685113, 0.0934912208712908, 0.013212774743181117, 0.2741058919200636,
+           0.36551098261127246};
   }
   return s;
 }
 
 const Scheme& scheme(int k) {
-  static const Scheme s1 = make_scheme(1), s2 = make_scheme(2), s3 = make_scheme(3),
-                      s4 = make_scheme(4), s5 = make_scheme(5), s6 = make_scheme(6);
-  switch (k) {
-    case 1: return s1;
-    case 2: return s2;
-    case 3: return s3;
-    case 4: return s4;
-    case 5: return s5;
-    default: return s6;
-  }
+  static const std::vector<Scheme> all = [] {
+    std::vector<Scheme> v;
+    for (int q = 1; q <= kKMax; ++q) v.push_back(make_scheme(q));
+    return v;
+  }();
+  return all[std::min(std::max(k, 1), kKMax) - 1];
 }
 
 bool shipped(int k) { return k >= 1 && k <= kKMax; }
@@ -773,7 +822,8 @@ Status poly(Ctx& c, int k, int s, const double* B, const double* B2, double* L, 
   const int n = c.p.n;
   const int np = c.p.n_pad;
   const double scale = -std::ldexp(1.0, s);
-  const int slots[2 * kKMax - 1] = {0, 1, 2, 5, 6, 7, 8, 9, 10, 11, 12};
+  auto slot = [](int t) { return t < 3 ? t : t + 2; };   // skips B and B2 (mats 3, 4)
+  static_assert(2 * kKMax - 1 + 2 <= kMats, "graph accumulators");
   int* flag = c.iflag() + 1;
   HIPCK(hipMemsetAsync(flag, 0, sizeof(int), c.s));
   if (k == 1) {
@@ -781,19 +831,19 @@ Status poly(Ctx& c, int k, int s, const double* B, const double* B2, double* L, 
     la.P2 = B;
     la.P3 = B2;
     la.nout = 1;
-    la.out[0] = c.mat(slots[0]);
+    la.out[0] = c.mat(slot(0));
     la.c1[0] = S.y[0];
     la.c2[0] = -S.y[1];
     la.c3[0] = S.y[2];
     la.n = n;
     la.ld = np;
     HIPCK(launch_lincomb_init(la, c.s));
-    HIPCK(launch_scale_out(c.mat(slots[0]), np, L, ldl, n, scale, flag, c.s));
+    HIPCK(launch_scale_out(c.mat(slot(0)), np, L, ldl, n, scale, flag, c.s));
   } else {
     // accumulator t: L_j at 2(j-2), R_j at 2(j-2)+1, Z at 2(k-1)
-    auto Lacc = [&](int j) { return c.mat(slots[2 * (j - 2)]); };
-    auto Racc = [&](int j) { return c.mat(slots[2 * (j - 2) + 1]); };
-    double* Z = c.mat(slots[2 * (k - 1)]);
+    auto Lacc = [&](int j) { return c.mat(slot(2 * (j - 2))); };
+    auto Racc = [&](int j) { return c.mat(slot(2 * (j - 2) + 1)); };
+    double* Z = c.mat(slot(2 * (k - 1)));
     LincombArgs la{};
     la.P2 = B;
     la.P3 = B2;
@@ -1149,17 +1199,10 @@ Status taped_backward(Ctx& c, const double* G, int64_t ldg, double* gradA, int64
 
   // operand list of a linear combination of P_2 = -B, P_3 = B2 and stored P_i
   auto add_P = [&](LincombGen& g, int i, double coef) {
-    if (coef == 0.0) return;
-    if (i == 2) {
-      g.in[g.m] = B;
-      g.c[g.m++] = -coef;
-    } else if (i == 3) {
-      g.in[g.m] = B2;
-      g.c[g.m++] = coef;
-    } else {
-      g.in[g.m] = PP(i);
-      g.c[g.m++] = coef;
-    }
+    if (coef == 0.0) return true;
+    if (i == 2) return g.add(B, -coef);
+    if (i == 3) return g.add(B2, coef);
+    return g.add(PP(i), coef);
   };
   auto lincomb = [&](LincombGen g, double* out, double beta) {
     g.out = out;
@@ -1172,10 +1215,11 @@ Status taped_backward(Ctx& c, const double* G, int64_t ldg, double* gradA, int64
   // graph forward with its factors (eq. five_mult_degopt)
   for (int j = 2; j <= k; ++j) {
     LincombGen gl{}, gr{};
-    for (int i = 2; i <= j + 1; ++i) {
-      add_P(gl, i, S.h[j - 2][i - 2]);
-      add_P(gr, i, S.g[j - 2][i - 2]);
-    }
+    for (int i = 2; i <= j + 1; ++i)
+      if (!add_P(gl, i, S.h[j - 2][i - 2]) || !add_P(gr, i, S.g[j - 2][i - 2])) {
+        st.code = LOGM_EINVAL;
+        return st;
+      }
     HIPCK(lincomb(gl, LJ(j), 0.0));
     HIPCK(lincomb(gr, RJ(j), 0.0));
     if (j < k) HIPCK(gemm(1.0, LJ(j), RJ(j), 0.0, PP(j + 2)));
@@ -1186,15 +1230,10 @@ Status taped_backward(Ctx& c, const double* G, int64_t ldg, double* gradA, int64
   // Ph_i = y_i Zh + sum_{j' >= i-1} (h_{j',i} Lh_{j'} + g_{j',i} Rh_{j'})
   auto p_hat = [&](int i, double sign, double* out) {
     LincombGen g{};
-    g.in[g.m] = Zh;
-    g.c[g.m++] = sign * S.y[i - 1];
-    for (int jp = std::max(2, i - 1); jp <= k; ++jp) {
-      g.in[g.m] = LH(jp);
-      g.c[g.m++] = sign * S.h[jp - 2][i - 2];
-      g.in[g.m] = RH(jp);
-      g.c[g.m++] = sign * S.g[jp - 2][i - 2];
-    }
-    return lincomb(g, out, 0.0);
+    bool ok = g.add(Zh, sign * S.y[i - 1]);
+    for (int jp = std::max(2, i - 1); jp <= k; ++jp)
+      ok = ok && g.add(LH(jp), sign * S.h[jp - 2][i - 2]) && g.add(RH(jp), sign * S.g[jp - 2][i - 2]);
+    return ok ? lincomb(g, out, 0.0) : hipErrorInvalidValue;
   };
   for (int j = k; j >= 2; --j) {
     HIPCK(p_hat(j + 2, 1.0, Ph));

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "algo.hpp"
+
 namespace logm {
 
 // ----------------------------------------------------------------- GEMM ----
@@ -16,16 +18,17 @@ hipError_t launch_gemm_plain(int M, int N, int K, double alpha, const double* A,
 // Graph-node product P = Lf * Rf (n x n, leading dimension ld) whose result is
 // never stored: the epilogue adds coef[t] * P into accumulator acc[t] for every
 // t < nacc, and, when dst != nullptr, writes dst = scale * (base + ycoef * P)
-// restricted to the leading nvalid x nvalid block (leading dimension ldd).  Nine
-// accumulators cover the first product of the six-product scheme: the two factors
+// restricted to the leading nvalid x nvalid block (leading dimension ldd).  The
+// first product of the largest scheme feeds the most accumulators: the two factors
 // of each later product and the output sum.
 struct PolyGemmArgs {
+  static constexpr int kMaxAcc = 2 * (kKMax - 2) + 1;
   const double* Lf;
   const double* Rf;
   int64_t ld;
   int nacc;
-  double* acc[9];
-  double coef[9];
+  double* acc[kMaxAcc];
+  double coef[kMaxAcc];
   double* dst;
   int64_t ldd;
   const double* base;
@@ -158,15 +161,16 @@ hipError_t launch_gemv(const double* M, int64_t ld, int n, const double* x, doub
 
 // Polynomial accumulator initialisation: out[t] = c2[t] * P2 + c3[t] * P3 + c1[t] * I
 // on the valid n x n block, zero on the rest of the padded ld x ld matrix (at most
-// 11 outputs: L_j, R_j for j = 2..6 and the output sum of the six-product scheme).
+// 2 kKMax - 1 outputs: L_j, R_j for j = 2..kKMax and the output sum).
 struct LincombArgs {
+  static constexpr int kMax = 2 * kKMax - 1;
   const double* P2;
   const double* P3;
   int nout;
-  double* out[11];
-  double c1[11];
-  double c2[11];
-  double c3[11];
+  double* out[kMax];
+  double c1[kMax];
+  double c2[kMax];
+  double c3[kMax];
   int n;
   int64_t ld;
 };
@@ -175,7 +179,9 @@ hipError_t launch_lincomb_init(const LincombArgs& a, hipStream_t s);
 // out = beta out + sum_{t < m} c[t] in[t] over the valid n x n block (row stride ld);
 // out may alias an input.
 struct LincombGen {
-  static constexpr int kMax = 12;
+  // the reverse mode's largest sum: the output adjoint and both factor adjoints of
+  // every product of the largest scheme
+  static constexpr int kMax = 2 * kKMax - 1;
   const double* in[kMax];
   double c[kMax];
   int m;
@@ -183,6 +189,13 @@ struct LincombGen {
   double* out;
   int n;
   int64_t ld;
+  // appends coef * p; false (nothing appended) when the operand list is full
+  bool add(const double* p, double coef) {
+    if (m >= kMax) return false;
+    in[m] = p;
+    c[m++] = coef;
+    return true;
+  }
 };
 hipError_t launch_lincomb_gen(const LincombGen& a, hipStream_t s);
 

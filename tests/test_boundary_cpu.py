@@ -47,7 +47,7 @@ def test_version_and_strerror(lib):
 
 def test_default_opts(lib):
     o = lm.default_opts()
-    assert (o.k_max, o.max_sqrt, o.db_max_iter, o.theta_source) == (6, 50, 30, 0)
+    assert (o.k_max, o.max_sqrt, o.db_max_iter, o.theta_source) == (8, 50, 30, 0)
 
 
 def test_workspace_size(lib):
@@ -82,7 +82,7 @@ def test_forward_argument_validation(lib):
     assert lib.logm_workspace_size(1, 100, None, ctypes.byref(b_c)) == 0
     assert b_c.value > 2 * b_r.value
     o = lm.default_opts()
-    o.k_max = 7                                        # k = 7..9 not built
+    o.k_max = 9                                        # k = 9 not built
     assert fwd(lib, opts=o) == 1
     o = lm.default_opts()
     o.max_sqrt = 65
@@ -129,7 +129,7 @@ def test_component_argument_validation(lib):
     assert lib.logm_gemm_f64(4, 4, 4, 1.0, FAKE, 3, FAKE, 4, 0.0, FAKE, 4, None) == 1
     assert lib.logm_inverse_f64(4, None, 4, FAKE, 4, None, None, 0, None) == 1
     assert lib.logm_sqrt_f64(4, FAKE, 4, FAKE, 4, 0, None, None, 0, None) == 1
-    assert lib.logm_poly_f64(4, 7, 0, FAKE, 4, FAKE, 4, FAKE, 4, None, 0, None) == 1
+    assert lib.logm_poly_f64(4, 9, 0, FAKE, 4, FAKE, 4, FAKE, 4, None, 0, None) == 1
     assert lib.logm_poly_f64(4, 5, -1, FAKE, 4, FAKE, 4, FAKE, 4, None, 0, None) == 1
     est = ctypes.c_double(0)
     assert lib.logm_normest_f64(4, FAKE, 4, FAKE, 4, 0, 0, ctypes.byref(est), None, None, 0, None) == 1
@@ -158,7 +158,7 @@ def test_backward_argument_validation(lib):
     assert call(ldga=7) == 1
     assert call(dtype=1) == 3                          # complex: workspace of the 2n run
     o = lm.default_opts()
-    o.k_max = 7
+    o.k_max = 9
     assert call(opts=o) == 1
     assert call() == 3                                 # workspace too small
     # taped pair: the workspace is required (it carries the tape)
@@ -199,7 +199,7 @@ def test_batched_argument_validation(lib):
     o.balance = 1                                      # no balancing on this path
     assert call(opts=o) == 1
     o = lm.default_opts()
-    o.k_max = 7
+    o.k_max = 9
     assert call(opts=o) == 1
     assert call(ws_bytes=100) == 3
 
@@ -266,20 +266,22 @@ def test_library_table1_matches_paper(golden):
 
 def test_library_table2_matches_paper(golden):
     t = golden("table2_theta.txt")
-    for k in (1, 2, 3, 4, 5, 6):
+    for k in (1, 2, 3, 4, 5, 6, 7, 8):
         m, _, theta = t[str(k)]
         _, _, _, mk, thk = lm.scheme(k)
-        assert (mk, thk) == (int(m), float(theta))
+        # k = 7, 8: the fits' own Theta, below the printed values (reading R1)
+        assert (mk, thk) == (int(m), oracle.THETA_DEFAULT[k][1])
+        assert thk == (float(theta) if k <= 6 else oracle.THETA_FIT[k])
     assert lm.scheme(5, theta_source=1)[4] == 0.2448
     # Theta_6 recomputed for the library's own six-product fit (rounded down)
-    assert lm.scheme(6, theta_source=1)[4] == 0.4271
+    assert lm.scheme(6, theta_source=1)[4] == oracle.THETA_FIT[6]
 
 
-@pytest.mark.parametrize("k", [1, 2, 3, 4, 6])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 6, 7, 8])
 def test_library_taylor_schemes_expand_to_taylor(k):
-    """The library's own k = 1, 2, 3, 4, 6 coefficients expand to T_{m_k} (exact
-    rationals; k = 4 matches orders up to m_4 = 14 of its degree 16, k = 6 orders up
-    to m_6 = 20 of its degree 64)."""
+    """The library's own k = 1, 2, 3, 4, 6, 7, 8 coefficients expand to T_{m_k}
+    (exact rationals; k = 4 matches orders up to m_4 = 14 of its degree 16, k = 6, 7,
+    8 orders up to 20, 24, 27 of their degrees 64, 128, 256)."""
     from fractions import Fraction
     h, g, y, m, _ = lm.scheme(k)
     P = [None, [Fraction(1)], [Fraction(0), Fraction(1)], [Fraction(0), Fraction(0), Fraction(1)]]
@@ -308,7 +310,7 @@ def test_library_taylor_schemes_expand_to_taylor(k):
     for q in range(1, k + 3):
         z = add(z, [Fraction(y[q - 1]) * c for c in P[q]])
     for i in range(1, m + 1):
-        assert abs(float((z[i] - Fraction(1, i)) * i)) <= (8 if k in (4, 6) else 4) * 2.0 ** -53
+        assert abs(float((z[i] - Fraction(1, i)) * i)) <= (16 if k >= 4 else 4) * 2.0 ** -53
 
 
 def test_library_k3_agrees_with_oracle():

@@ -53,11 +53,11 @@ ITER_TIES = []  # a converged root stopped one iteration apart (stopping rule at
 TIE = 1e-9     # relative move of the Theta values that a rounding tie may need
 
 
-def tie_explains(A, s, k, k_max=6):
+def tie_explains(A, s, k, k_max=8):
     """True if the oracle, with every Theta moved by a relative TIE up or down, takes
     the device's (s, k)."""
     for f in (1.0 - TIE, 1.0 + TIE):
-        table = {j: (m, th * f) for j, (m, th) in oracle.TABLE2.items()}
+        table = {j: (m, th * f) for j, (m, th) in oracle.THETA_DEFAULT.items()}
         try:
             _, io = oracle.logm(A, k_max=k_max, theta_table=table)
         except oracle.OracleError:
@@ -67,7 +67,7 @@ def tie_explains(A, s, k, k_max=6):
     return False
 
 
-def check_against_oracle(Lg, st, A, tol=TOL, k_max=6):
+def check_against_oracle(Lg, st, A, tol=TOL, k_max=8):
     """Device result against the oracle.  A flip of (s, k) must be a rounding tie (see
     tie_explains); an iteration count may differ by one on a root that converged (the
     stopping rule compares changes at the rounding floor).  The oracle then replays

@@ -160,12 +160,12 @@ def test_sqrt_spd():
 
 
 # ------------------------------------------------------------- polynomial -
-@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6, 7, 8])
 @pytest.mark.parametrize("n,s", [(1, 0), (64, 0), (100, 3), (257, 1)])
 def test_poly_matches_oracle(k, n, s):
     rng = np.random.default_rng(100 * k + n)
     B = rng.standard_normal((n, n))
-    B *= oracle.TABLE2[k][1] / max(np.linalg.norm(B, 1), 1e-300)
+    B *= oracle.THETA_DEFAULT[k][1] / max(np.linalg.norm(B, 1), 1e-300)
     B2 = B @ B
     L = lm.poly(dev(B), dev(B2), k, s)
     ref = -(2.0 ** s) * oracle.eval_scheme(k, -B, B2)
@@ -202,11 +202,11 @@ def decisions(info):
     return info["s"], info["k"], list(info["db_iters"])
 
 
-def tie_explains(A, info, k_max=6, progress=None):
+def tie_explains(A, info, k_max=8, progress=None):
     """True if the oracle, with every Theta moved by a relative TIE up or down, takes
     the device's (s, k): the two sides straddled a threshold by rounding."""
     for f in (1.0 - TIE, 1.0 + TIE):
-        table = {k: (m, th * f) for k, (m, th) in oracle.TABLE2.items()}
+        table = {k: (m, th * f) for k, (m, th) in oracle.THETA_DEFAULT.items()}
         try:
             _, io = oracle.logm(A, k_max=k_max, theta_table=table, progress=progress)
         except oracle.OracleError:
@@ -225,7 +225,7 @@ def check_counters(info, io, n):
         2 * nd ** 3 * (info["n_inv"] + info["n_gemm"]) + 2 * nd ** 2 * info["n_matvec"], rel=1e-12)
 
 
-def oracle_parity(A, Lg, info, tol=TOL_LOGM, k_max=6, case=None, progress=None):
+def oracle_parity(A, Lg, info, tol=TOL_LOGM, k_max=8, case=None, progress=None):
     """Compare a device result with the oracle (decisions, counters, values); on a
     flip check that it is a tie and compare with the oracle's replay of the device's
     decisions.  Returns ((s, k) equal, oracle info, relative Frobenius error)."""
@@ -255,7 +255,7 @@ def oracle_parity(A, Lg, info, tol=TOL_LOGM, k_max=6, case=None, progress=None):
 def compare_with_oracle(A, tol=TOL_LOGM, **kw):
     L, info = lm.logm(dev(A), **kw)
     Lg = host(L)
-    same, _, _ = oracle_parity(A, Lg, info, tol=tol, k_max=kw.get("k_max", 6))
+    same, _, _ = oracle_parity(A, Lg, info, tol=tol, k_max=kw.get("k_max", 8))
     return Lg, info, same
 
 
@@ -272,7 +272,7 @@ def test_logm_rotscale_vs_oracle_and_exact(n, seed):
     A, Lx = rotscale_matrix(n, seed)
     Lg, info, same = compare_with_oracle(A)
     assert relf(Lg, Lx) < 1e-11
-    assert info["k"] in (1, 2, 3, 4, 5, 6)
+    assert info["k"] in (1, 2, 3, 4, 5, 6, 7, 8)
 
 
 def test_logm_rotscale1024():
@@ -401,13 +401,25 @@ def test_logm_selects_k4(n, rho):
 @pytest.mark.parametrize("n,rho,s", [(64, 0.55, 0), (200, 0.6, 0), (200, 0.75, 1)])
 def test_logm_selects_k6(n, rho, s):
     """The six-product scheme (our fit, reading R1) is selected on both sides where the
-    last root's powers lie between Theta_5 and Theta_6, and it saves a square root:
-    with schemes up to k = 5 the device takes s + 1 roots on the same matrix."""
+    last root's powers lie between Theta_5 and Theta_6 (schemes up to k = 6), and it
+    saves a square root: with schemes up to k = 5 the device takes s + 1 roots."""
     A = disk_matrix(n, 31, rho)
-    Lg, info, same = compare_with_oracle(A)
+    Lg, info, same = compare_with_oracle(A, k_max=6)
     assert same and info["s"] == s and info["k"] == 6
     _, info5 = lm.logm(dev(A), k_max=5)
     assert info5["s"] == s + 1 and info5["k"] == 5
+
+
+@pytest.mark.parametrize("n,rho,s,k", [(64, 0.6, 0, 7), (64, 0.85, 0, 8), (200, 0.95, 0, 8),
+                                       (64, 1.15, 1, 7)])
+def test_logm_selects_k78(n, rho, s, k):
+    """The seven- and eight-product schemes (our fits, reading R1) are selected on both
+    sides at the default k_max = 8, each saving a square root against k_max = 6."""
+    A = disk_matrix(n, 31, rho)
+    Lg, info, same = compare_with_oracle(A)
+    assert same and info["s"] == s and info["k"] == k
+    _, info6 = lm.logm(dev(A), k_max=6)
+    assert info6["s"] == s + 1
 
 
 def test_logm_closed_forms():
