@@ -37,11 +37,11 @@ R1  Schemes shipped: k in {1, ..., 6}.  The paper prints coefficients only
     0.372, no coefficients printed) is likewise our own fit: b_i = 1/i for i <= 20,
     the orders up to 34 matched closely by a least-squares fit (``oracle/fit_k6.py``);
     its Theta_6 recomputed by eq. theta_Eb is above the printed 0.372, which is used.
-    k = 7, 8 (orders 24+, 27+, degrees 128, 256) are fits of the same kind
-    (``oracle/fit_degopt.py``) whose recomputed Theta (0.5284, 0.5739) lies below
-    the printed 0.586, 0.669: those printed thresholds belong to the paper's own
-    polynomials, so our values are used (THETA_DEFAULT).  k = 9 is not built, so
-    "m_9" in Algorithm 1 is read as m_{k_max} (m_8 = 27 by default).
+    k = 7, 8, 9 (orders 24+, 27+, 28+, degrees 128, 256, 512) are fits of the same
+    kind (``oracle/fit_degopt.py``) whose recomputed Theta (0.5284, 0.5739, 0.6184)
+    lies below the printed 0.586, 0.669, 0.728: those printed thresholds belong to
+    the paper's own polynomials, so our values are used (THETA_DEFAULT).  "m_9" in
+    Algorithm 1 is m_{k_max} (m_9 = 28 by default).
 R2  k = 3: eq. eqP8pol has two distinct real solutions with c_4 > 0; the one with
     the smaller coefficients (e_0 ~ 0.729) is used (its stability indicator,
     eq. stability_error, is the smaller of the two).
@@ -119,16 +119,16 @@ TABLE2 = {
 }
 
 # Schemes with coefficients available (reading R1).
-SHIPPED_K = (1, 2, 3, 4, 5, 6, 7, 8)
+SHIPPED_K = (1, 2, 3, 4, 5, 6, 7, 8, 9)
 
 # Theta of eq. theta_Eb recomputed for our own fits (reading R1), rounded down: the
 # bound summed over every order of the polynomial with its coefficients rounded to
 # double (orders <= m_k then carry a few u of rounding instead of zero).
-THETA_FIT = {6: 0.4258, 7: 0.5284, 8: 0.5739}
+THETA_FIT = {6: 0.4258, 7: 0.5284, 8: 0.5739, 9: 0.6184}
 
 # The thresholds Algorithm 1 uses by default (reading R1): Table 2 where the shipped
 # polynomial's own Theta is at least the printed one (k <= 6), the fit's own value
-# where it is lower (k = 7, 8).
+# where it is lower (k = 7, 8, 9).
 THETA_DEFAULT = {k: (m, min(th, THETA_FIT.get(k, th))) for k, (m, th) in TABLE2.items()}
 
 # tabmin_im from the degree-selection procedure after Algorithm 1 (1-based in k).
@@ -266,6 +266,51 @@ _K8_Y = (0.0, 1.0, 0.28629089335296337, 0.7089546608853124, 0.4474884286833493,
          0.2741058919200636, 0.36551098261127246)
 
 
+# k = 9 (reading R1): our own fit (oracle/fit_degopt.py output), rows j = 2..9
+# acting on P_2..P_{j+1}; y_1..y_11 acting on P_1..P_11.
+_K9_H = {
+    2: (1.0293774690516044, 0.0986497474609164),
+    3: (-0.5025042723076767, 0.5247128109060221, 1.3865109222218124),
+    4: (1.5801523405120685, 0.5646891581535393, -0.041325802357301704,
+        -0.3181291215699591),
+    5: (0.46209850104803757, -0.6629103717511978, 1.5561748125820298,
+        0.5629951027959472, -1.0915484419859594),
+    6: (0.4983592601693249, -0.2865322572654024, -0.14866362635306954,
+        -0.4255005462181858, 0.27097034269416354, 0.09517721322238752),
+    7: (0.2441865389518984, -0.8907619366173689, 0.2832614080467771,
+        -0.5559115256073457, -0.22953284648300407, 0.02320319717888621,
+        -0.24704400855650602),
+    8: (8.29440508611953, -3.4903312459043043, -1.6739773663378854, 0.3656203278354649,
+        0.2281889962148337, -0.3875771031594003, -0.9235864912211463,
+        0.36381161913462207),
+    9: (-0.02383477369623385, -0.2334157473932367, 0.0060532310712255715,
+        0.08365603505252057, -0.024950636985573166, -0.0036919692258725505,
+        -0.010245765351184849, -0.0019803019925272282, 0.11580064478486322),
+}
+_K9_G = {
+    2: (-0.567926898743273, 0.9073746556714914),
+    3: (-0.18886887732395102, -0.6489732205132462, -0.01670139192094852),
+    4: (-0.5158107828670548, -0.27688983990935284, -1.462952039008439,
+        0.3854266008750241),
+    5: (0.5445610154707972, -0.7204530569156263, -0.40179558991675046,
+        -0.42051866881404976, 0.6271217994353363),
+    6: (-0.5541098274524069, 0.09702125360365794, -0.08287621570475852,
+        -0.16955875954201557, 0.46719686290523976, 0.36754198740626737),
+    7: (-1.4980737562547197, -1.2274871512689252, 0.399255478050324,
+        -1.7543170697122306, 1.1298530554757429, -0.12801528218311853,
+        0.6443899429833408),
+    8: (0.2450621271754964, 0.08708301653068268, -0.0035785272532655845,
+        0.03200164112608482, -0.022585412765151733, -0.007473019081323353,
+        0.030364792548688332, -0.0017623317258204177),
+    9: (4.74937027235682, 2.9028386343156614, 2.158061838336138, -0.30945895027312137,
+        -1.264362424768732, -0.32355351009185146, 0.25539635982766695,
+        -0.5671996072436606, -0.08269636486032923),
+}
+_K9_Y = (0.0, 1.0, -0.08543192809800926, 0.4879886358942328, 0.25079822847146865,
+         -0.3419332478263414, -0.005176138267992704, 0.1537019870763135,
+         -0.026203437037517104, 0.28033063495128707, -0.28768165250742594)
+
+
 class OracleError(RuntimeError):
     """Raised when the method cannot proceed (singular input, no convergence)."""
 
@@ -327,6 +372,8 @@ def scheme_coefficients(k: int):
         return dict(_K7_H), dict(_K7_G), tuple(_K7_Y)
     if k == 8:
         return dict(_K8_H), dict(_K8_G), tuple(_K8_Y)
+    if k == 9:
+        return dict(_K9_H), dict(_K9_G), tuple(_K9_Y)
     raise ValueError(f"no coefficients for k={k}")
 
 
@@ -611,7 +658,7 @@ def balance(A, max_sweeps: int = 100):
     return B, d, sweeps
 
 
-def logm(A, k_max: int = 8, max_sqrt: int = 50, db_max_iter: int = 30,
+def logm(A, k_max: int = 9, max_sqrt: int = 50, db_max_iter: int = 30,
          theta_table=THETA_DEFAULT, force: dict | None = None, balanced: bool = False,
          progress=None):
     """Principal matrix logarithm by Algorithm 1 (Section 6).
@@ -734,7 +781,7 @@ def logm(A, k_max: int = 8, max_sqrt: int = 50, db_max_iter: int = 30,
 # Reverse mode: gradient of <G, log A> with respect to A
 # ---------------------------------------------------------------------------
 
-def logm_backward(A, G, k_max: int = 8, max_sqrt: int = 50, db_max_iter: int = 30,
+def logm_backward(A, G, k_max: int = 9, max_sqrt: int = 50, db_max_iter: int = 30,
                   theta_table=THETA_DEFAULT, force: dict | None = None):
     """Abar = d<G, logm(A)>_F / dA by reverse-mode differentiation of Algorithm 1.
 

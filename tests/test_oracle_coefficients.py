@@ -8,12 +8,14 @@ indicator of eq. stability_error.
 """
 
 from fractions import Fraction
+import functools
 
 import mpmath
 import numpy as np
 import pytest
 
 import oracle
+from exact_poly import expand_rows
 from oracle import scheme_coefficients
 
 U = 2.0 ** -53
@@ -37,21 +39,12 @@ def poly_add(a, b):
     return [x + z for x, z in zip(a, b)]
 
 
+@functools.lru_cache(maxsize=None)
 def expand_exact(k):
-    """Monomial coefficients b_0..b_{2^k} of the scheme, exact in the doubles."""
+    """Monomial coefficients b_0..b_{2^k} of the scheme, exact in the doubles (exact
+    dyadic integer arithmetic; the same rationals as Fraction arithmetic)."""
     h, g, y = scheme_coefficients(k)
-    P = [None, [Fraction(1)], [Fraction(0), Fraction(1)], [Fraction(0), Fraction(0), Fraction(1)]]
-    for j in range(2, k + 1):
-        left = [Fraction(0)]
-        right = [Fraction(0)]
-        for i in range(2, j + 2):
-            left = poly_add(left, [Fraction(h[j][i - 2]) * c for c in P[i]])
-            right = poly_add(right, [Fraction(g[j][i - 2]) * c for c in P[i]])
-        P.append(poly_mul(left, right))
-    z = [Fraction(0)]
-    for q in range(1, k + 3):
-        z = poly_add(z, [Fraction(y[q - 1]) * c for c in P[q]])
-    return z
+    return expand_rows(k, h, g, y)
 
 
 def expand_float(k, coeffs=None):
@@ -222,7 +215,7 @@ def test_k3_equals_paterson_stockmeyer():
 def test_degrees_of_freedom_layout():
     """Section 3: k^2+4k+2 coefficients in the full form, k^2+2k-2 free ones after the
     normalisation theorem, the conjecture and y_1 = 0, y_2 = 1."""
-    for k in (2, 3, 4, 5, 6, 7, 8):
+    for k in (2, 3, 4, 5, 6, 7, 8, 9):
         h, g, y = scheme_coefficients(k)
         stored = sum(len(v) for v in h.values()) + sum(len(v) for v in g.values()) + len(y)
         assert stored == k * k + 2 * k       # rows j=2..k on P_2..P_{j+1}, plus y
@@ -260,10 +253,10 @@ def test_k3_root_choice_by_stability_indicator():
 
 
 @pytest.mark.parametrize("k,th", [(1, None), (2, None), (3, None), (4, None), (5, None),
-                                  (6, None), (6, 0.4258), (7, None), (8, None)])
+                                  (6, None), (6, 0.4258), (7, None), (8, None), (9, None)])
 def test_scalar_backward_error_at_theta(k, th):
     """eq. Des_Eb on the scalar case: |exp(-S(-x)) - 1 - x| / |x| <= ~u at |x| = Theta
-    (the value Algorithm 1 uses: Table 2's, or for k = 7, 8 the one recomputed for
+    (the value Algorithm 1 uses: Table 2's, or for k = 7, 8, 9 the one recomputed for
     our fits; for k = 6 also the larger one recomputed for our fit)."""
     mpmath.mp.dps = 50
     b = expand_exact(k)
@@ -453,14 +446,14 @@ def test_k6_table_is_the_fit_output():
     assert np.allclose(y, Y, rtol=1e-12, atol=1e-15)
 
 
-# --------------------------------------------------- k = 7, 8 (own fits) ---
-FIT_ORDERS = {7: 24, 8: 27}
+# ------------------------------------------------ k = 7, 8, 9 (own fits) ---
+FIT_ORDERS = {7: 24, 8: 27, 9: 28}
 
 
-@pytest.mark.parametrize("k", [7, 8])
-def test_k78_fit_matches_taylor(k):
-    """Reading R1: the k = 7, 8 schemes (our fits, the paper prints none) have degree
-    2^k with b_i = 1/i for i <= m_k (Table 2: orders 24+, 27+) within 16u after
+@pytest.mark.parametrize("k", [7, 8, 9])
+def test_k789_fit_matches_taylor(k):
+    """Reading R1: the k = 7, 8, 9 schemes (our fits, the paper prints none) have degree
+    2^k with b_i = 1/i for i <= m_k (Table 2: orders 24+, 27+, 28+) within 16u after
     rounding every coefficient to double, and every approximated term obeys the
     paper's |(1/i - b_i) i| <= 1 condition."""
     m = FIT_ORDERS[k]
@@ -473,8 +466,8 @@ def test_k78_fit_matches_taylor(k):
         assert e <= 1.0 + 1e-12, (i, e)
 
 
-@pytest.mark.parametrize("k", [7, 8])
-def test_k78_theta_recomputed(k):
+@pytest.mark.parametrize("k", [7, 8, 9])
+def test_k789_theta_recomputed(k):
     """Theta_k of eq. theta_Eb recomputed from the fitted coefficients, over every
     order of the rounded polynomial: at least the value Algorithm 1 uses for them
     (THETA_FIT, rounded down) and below the printed one (so the printed thresholds,
@@ -493,9 +486,9 @@ def test_k78_theta_recomputed(k):
     assert oracle.THETA_DEFAULT[k][1] > oracle.THETA_DEFAULT[k - 1][1]
 
 
-@pytest.mark.parametrize("k", [7, 8])
-def test_k78_rounding_indicator_small(k):
-    """eq. stability_error for k = 7, 8: the expansion evaluated in double rounding
+@pytest.mark.parametrize("k", [7, 8, 9])
+def test_k789_rounding_indicator_small(k):
+    """eq. stability_error for k = 7, 8, 9: the expansion evaluated in double rounding
     stays within a few u of 1/i on the exact orders (coefficients of modulus < 20)."""
     h, g, y = scheme_coefficients(k)
     assert max(abs(v) for row in list(h.values()) + list(g.values()) for v in row) < 20
@@ -504,8 +497,8 @@ def test_k78_rounding_indicator_small(k):
     assert max(abs(bt[i] - 1.0 / i) * i for i in range(1, FIT_ORDERS[k] + 1)) < 32 * U
 
 
-@pytest.mark.parametrize("k", [7, 8])
-def test_k78_matrix_accuracy_at_theta(k):
+@pytest.mark.parametrize("k", [7, 8, 9])
+def test_k789_matrix_accuracy_at_theta(k):
     """On a nonnormal 12x12 matrix with ||x||_1 = Theta_k (the value used) the
     k-product scheme gives -log(I - x) to a few u (reference: the series
     sum_i x^i / i summed to 240 terms in 40-digit arithmetic)."""
@@ -525,9 +518,9 @@ def test_k78_matrix_accuracy_at_theta(k):
     assert np.linalg.norm(z - ref) / np.linalg.norm(ref) < 20 * U
 
 
-@pytest.mark.parametrize("k", [7, 8])
-def test_k78_table_is_the_fit_output(k):
-    """The stored k = 7, 8 tables are what the committed generator produces (re-run
+@pytest.mark.parametrize("k", [7, 8, 9])
+def test_k789_table_is_the_fit_output(k):
+    """The stored k = 7, 8, 9 tables are what the committed generator produces (re-run
     here from its stored search results)."""
     from oracle.fit_degopt import table
 
