@@ -13,9 +13,9 @@
  *     degree-selection procedure after Algorithm 1),
  *   - log(I+B) ~ -S(-B) (eqs. Taylor_log, logipASTM) evaluated as the
  *     degree-optimal computation graph of eq. five_mult_degopt (schemes with
- *     k = 1 to 8 matrix products; k = 5 uses Table 1, k = 4, 6, 7, 8 fits of the
- *     same form with b_i = 1/i for i <= 14, 20, 24, 27, since Table 2 gives their
- *     orders and Theta but no coefficients),
+ *     k = 1 to 9 matrix products; k = 5 uses Table 1, k = 4, 6, 7, 8, 9 fits of
+ *     the same form with b_i = 1/i for i <= 14, 20, 24, 27, 28, since Table 2 gives
+ *     their orders and Theta but no coefficients),
  *   - the squaring phase L = 2^s L.
  * Balancing (the pre- and post-processing steps of Algorithm 1) is optional
  * (logm_opts.balance, forward entry points only) and off by default.
@@ -62,12 +62,12 @@ typedef enum { LOGM_R64 = 0, LOGM_C128 = 1 } logm_dtype;
 
 /* Options of Algorithm 1 (Section 6). */
 typedef struct logm_opts {
-  int32_t k_max;        /* largest scheme (matrix products) allowed: 1 to 8 (default 8) */
+  int32_t k_max;        /* largest scheme (matrix products) allowed: 1 to 9 (default 9) */
   int32_t max_sqrt;     /* maximum number of square roots, "maxiter" (default 50, at most 64) */
   int32_t db_max_iter;  /* maximum Denman-Beavers iterations per root (default 30) */
   int32_t theta_source; /* 0: Theta values of Table 2 as printed (default), except
-                           k = 7, 8, whose fits' own Theta (0.5284, 0.5739) are
-                           below the printed ones and replace them;
+                           k = 7, 8, 9, whose fits' own Theta (0.5284, 0.5739,
+                           0.6184) are below the printed ones and replace them;
                            1: also Theta_5 = 0.2448 recomputed from Table 1 and
                            Theta_6 = 0.4258 recomputed for the six-product fit
                            (above the printed 0.372) */
@@ -149,7 +149,7 @@ int logm_forward_noalloc(int64_t n, const double* A, int64_t lda, double* L, int
 /* ---- reverse mode ---- */
 
 /* Minimum workspace bytes for logm_backward: the forward workspace plus
- * (o->max_sqrt + 2 * o->db_max_iter + 41) padded n x n matrices (checkpointed root
+ * (o->max_sqrt + 2 * o->db_max_iter + 46) padded n x n matrices (checkpointed root
  * inputs, the graph factors and adjoints, and a ring of taped inverses that holds
  * one root).  Any workspace beyond the minimum lengthens the ring by one inverse per
  * n_pad * n_pad * 8 bytes (n_pad = n rounded up to a multiple of 64, rounded up to
@@ -282,7 +282,7 @@ int logm_sqrt_f64(int64_t n, const double* A, int64_t lda, double* X, int64_t ld
                   int32_t db_max_iter, int32_t* iters, void* ws, size_t ws_bytes, void* stream);
 
 /* L = -2^s S_k(-B) with P_3 = B2 = B*B supplied (eq. five_mult_degopt with the
- * saved product of eq. AI2); 1 <= k <= 8, 0 <= s <= 64. */
+ * saved product of eq. AI2); 1 <= k <= 9, 0 <= s <= 64. */
 int logm_poly_f64(int64_t n, int32_t k, int32_t s, const double* B, int64_t ldb, const double* B2,
                   int64_t ldb2, double* L, int64_t ldl, void* ws, size_t ws_bytes, void* stream);
 
@@ -318,7 +318,7 @@ int logm_autotune(int64_t n, void* ws, size_t ws_bytes, void* stream, int32_t* b
 /* Host-side tables: the coefficients of scheme k (h and g rows j = 2..k on
  * P_2..P_{j+1}, concatenated; y on P_1..P_{k+2}), its order m_k and Theta_{m_k}.
  * Any output pointer may be NULL.  *nh receives the number of h (= g) values
- * (k (k + 1) / 2 - 1, at most 35); y receives k + 2 values. */
+ * (k (k + 1) / 2 - 1, at most 44); y receives k + 2 values. */
 int logm_scheme(int32_t k, int32_t theta_source, double* h, double* g, double* y, int32_t* nh,
                 int32_t* m, double* theta);
 

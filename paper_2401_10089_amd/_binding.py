@@ -289,7 +289,7 @@ def _workspace(n: int, device, workspace=None, dtype: int = LOGM_R64):
     return torch.empty(need, dtype=torch.uint8, device=device)
 
 
-def logm(A, k_max: int = 8, max_sqrt: int = 50, db_max_iter: int = 30, theta_source: int = 0,
+def logm(A, k_max: int = 9, max_sqrt: int = 50, db_max_iter: int = 30, theta_source: int = 0,
          out=None, workspace=None, graph_fp32: bool = False, balance: bool = False,
          pivot_search: bool = False):
     """L = log(A) on the GPU (Algorithm 1), A float64 or complex128.  Returns (L, info
@@ -318,7 +318,7 @@ def logm(A, k_max: int = 8, max_sqrt: int = 50, db_max_iter: int = 30, theta_sou
 NOALLOC_MAX_N = 256
 
 
-def logm_noalloc(A, k_max: int = 8, max_sqrt: int = 50, db_max_iter: int = 30, theta_source: int = 0,
+def logm_noalloc(A, k_max: int = 9, max_sqrt: int = 50, db_max_iter: int = 30, theta_source: int = 0,
                  out=None, pivot_search: bool = False):
     """L = log(A) through logm_forward_noalloc: real A, n <= 256, no workspace (the
     library's fixed device array) and no device allocation.  Returns (L, info dict)."""
@@ -351,7 +351,7 @@ def _bwd_mat_bytes(n: int) -> int:
     return (n_pad * n_pad * 8 + 255) // 256 * 256
 
 
-def logm_backward(A, G, k_max: int = 8, max_sqrt: int = 50, db_max_iter: int = 30,
+def logm_backward(A, G, k_max: int = 9, max_sqrt: int = 50, db_max_iter: int = 30,
                   theta_source: int = 0, out=None, workspace=None, tape_mats: int | None = None):
     """gradA = d<G, log A>/dA on the GPU (reverse mode of Algorithm 1).  Returns
     (gradA, info dict of the forward pass run inside the call).  Complex A, G give
@@ -390,7 +390,7 @@ class Tape:
     logm_backward_taped; holds the root checkpoints and taped inverses on the GPU.
     complex=True tapes a complex128 pass (run on the 2n x 2n real representation)."""
 
-    def __init__(self, n: int, device, tape_mats: int | None = None, k_max: int = 8, max_sqrt: int = 50,
+    def __init__(self, n: int, device, tape_mats: int | None = None, k_max: int = 9, max_sqrt: int = 50,
                  db_max_iter: int = 30, theta_source: int = 0, complex: bool = False):
         torch = _torch()
         self.n = n
@@ -513,7 +513,7 @@ class BatchPlan:
         return [flat[o:o + d * d].reshape(d, d) for o, d in zip(self.offsets_host, self.dims_host)]
 
 
-def logm_batched(A_flat, plan: "BatchPlan", L_flat=None, k_max: int = 8, max_sqrt: int = 50,
+def logm_batched(A_flat, plan: "BatchPlan", L_flat=None, k_max: int = 9, max_sqrt: int = 50,
                  db_max_iter: int = 30, theta_source: int = 0):
     """L_i = log(A_i) for a packed batch (one persistent launch, decisions on the
     device).  Returns (L_flat, status tensor [batch, 4]: code, s, k, DB iterations);
@@ -537,7 +537,7 @@ def logm_batched(A_flat, plan: "BatchPlan", L_flat=None, k_max: int = 8, max_sqr
     return L_flat, plan.status.view(-1, 4)
 
 
-def autotune_batched(A_flat, plan: "BatchPlan", k_max: int = 8, max_sqrt: int = 50,
+def autotune_batched(A_flat, plan: "BatchPlan", k_max: int = 9, max_sqrt: int = 50,
                      db_max_iter: int = 30, theta_source: int = 0):
     """Choose the batched class boundary by timing the caller's real batch (see
     logm_batched_autotune); returns (split, ms of the best run).  The choice holds for

@@ -11,17 +11,18 @@
 namespace logm {
 
 // Largest scheme with coefficients (k = 1 .. kKMax).
-constexpr int kKMax = 8;
+constexpr int kKMax = 9;
 // Theta of eq. theta_Eb recomputed for our own fits of eq. five_mult_degopt (the
-// paper prints no coefficients for k = 6, 7, 8), summed over every order of the
+// paper prints no coefficients for k = 6..9), summed over every order of the
 // polynomial with its coefficients rounded to double, rounded down.
 constexpr double kTheta6Fit = 0.4258;
 constexpr double kTheta7Fit = 0.5284;
 constexpr double kTheta8Fit = 0.5739;
+constexpr double kTheta9Fit = 0.6184;
 
 // Table 2 (k -> m_k, Theta_{m_k}) as Algorithm 1 uses it: the printed Theta where
 // the shipped polynomial's own Theta is at least that (k <= 6), the fits' own below
-// it (k = 7, 8: the printed values belong to the paper's polynomials).  theta_source
+// it (k = 7, 8, 9: the printed values belong to the paper's polynomials).  theta_source
 // 1 replaces Theta_5 by 0.2448, the value Table 1 yields when recomputed, and
 // Theta_6 by the value recomputed for our six-product fit.
 struct ThetaTable {
@@ -40,6 +41,7 @@ __host__ __device__ inline ThetaTable theta_table(int source) {
   }
   t.th[7] = kTheta7Fit;
   t.th[8] = kTheta8Fit;
+  t.th[9] = kTheta9Fit;
   if (source == 1) {
     t.th[5] = 0.2448;
     t.th[6] = kTheta6Fit;

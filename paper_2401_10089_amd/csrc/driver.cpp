@@ -6,11 +6,11 @@
 //
 // Readings of points the paper leaves open (shared with the test oracle, which
 // implements them separately):
-//  * schemes k in {1,...,8}: k = 1, 2 are T_2, T_4; k = 3 solves eq. eqP8pol for
-//    T_8 (root with the smaller coefficients); k = 4, 6, 7, 8 are fits of the
-//    degree-optimal form matching T_14, T_20, T_24, T_27 (Table 2 prints their Theta
-//    and orders but no coefficients); k = 5 is Table 1.  "m_9" of Algorithm 1 is read
-//    as m_{k_max}.
+//  * schemes k in {1,...,9}: k = 1, 2 are T_2, T_4; k = 3 solves eq. eqP8pol for
+//    T_8 (root with the smaller coefficients); k = 4, 6, 7, 8, 9 are fits of the
+//    degree-optimal form matching T_14, T_20, T_24, T_27, T_28 (Table 2 prints their
+//    Theta and orders but no coefficients); k = 5 is Table 1.  "m_9" of Algorithm 1
+//    is m_{k_max}.
 //  * B^2 is formed once at s = 0 before the scaling loop.
 //  * Denman-Beavers stops when rel = ||X'-X||/||X'|| <= sqrt(n) u, or (scaling off,
 //    rel < 1e-6, rel > rel_prev/2); scaling is switched off once rel < 1e-2.
@@ -234,6 +234,42 @@ Scheme make_scheme(int k) {
     s.y = {0.0, 1.0, 0.28629089335296337, 0.7089546608853124, 0.4474884286833493,
            0.029087839406685113, 0.0934912208712908, 0.013212774743181117, 0.2741058919200636,
            0.36551098261127246};
+  } else if (k == 9) {
+    // Degree 512 with b_i = 1/i for i <= 28 (Table 2: order 28+); our own fit as for
+    // k = 7, 8, orders up to 60 matched closely; Theta kTheta9Fit, below the printed
+    // 0.728.
+    s.h = {{1.0293774690516044, 0.0986497474609164},
+           {-0.5025042723076767, 0.5247128109060221, 1.3865109222218124},
+           {1.5801523405120685, 0.5646891581535393, -0.041325802357301704, -0.3181291215699591},
+           {0.46209850104803757, -0.6629103717511978, 1.5561748125820298, 0.5629951027959472,
+            -1.0915484419859594},
+           {0.4983592601693249, -0.2865322572654024, -0.14866362635306954, -0.4255005462181858,
+            0.27097034269416354, 0.09517721322238752},
+           {0.2441865389518984, -0.8907619366173689, 0.2832614080467771, -0.5559115256073457,
+            -0.22953284648300407, 0.02320319717888621, -0.24704400855650602},
+           {8.29440508611953, -3.4903312459043043, -1.6739773663378854, 0.3656203278354649,
+            0.2281889962148337, -0.3875771031594003, -0.9235864912211463, 0.36381161913462207},
+           {-0.02383477369623385, -0.2334157473932367, 0.0060532310712255715,
+            0.08365603505252057, -0.024950636985573166, -0.0036919692258725505,
+            -0.010245765351184849, -0.0019803019925272282, 0.11580064478486322}};
+    s.g = {{-0.567926898743273, 0.9073746556714914},
+           {-0.18886887732395102, -0.6489732205132462, -0.01670139192094852},
+           {-0.5158107828670548, -0.27688983990935284, -1.462952039008439, 0.3854266008750241},
+           {0.5445610154707972, -0.7204530569156263, -0.40179558991675046,
+            -0.42051866881404976, 0.6271217994353363},
+           {-0.5541098274524069, 0.09702125360365794, -0.08287621570475852,
+            -0.16955875954201557, 0.46719686290523976, 0.36754198740626737},
+           {-1.4980737562547197, -1.2274871512689252, 0.399255478050324, -1.7543170697122306,
+            1.1298530554757429, -0.12801528218311853, 0.6443899429833408},
+           {0.2450621271754964, 0.08708301653068268, -0.0035785272532655845,
+            0.03200164112608482, -0.022585412765151733, -0.007473019081323353,
+            0.030364792548688332, -0.0017623317258204177},
+           {4.74937027235682, 2.9028386343156614, 2.158061838336138, -0.30945895027312137,
+            -1.264362424768732, -0.32355351009185146, 0.25539635982766695, -0.5671996072436606,
+            -0.08269636486032923}};
+    s.y = {0.0, 1.0, -0.08543192809800926, 0.4879886358942328, 0.25079822847146865,
+           -0.3419332478263414, -0.005176138267992704, 0.1537019870763135,
+           -0.026203437037517104, 0.28033063495128707, -0.28768165250742594};
   }
   return s;
 }

@@ -47,7 +47,7 @@ def test_version_and_strerror(lib):
 
 def test_default_opts(lib):
     o = lm.default_opts()
-    assert (o.k_max, o.max_sqrt, o.db_max_iter, o.theta_source) == (8, 50, 30, 0)
+    assert (o.k_max, o.max_sqrt, o.db_max_iter, o.theta_source) == (9, 50, 30, 0)
 
 
 def test_workspace_size(lib):
@@ -82,7 +82,7 @@ def test_forward_argument_validation(lib):
     assert lib.logm_workspace_size(1, 100, None, ctypes.byref(b_c)) == 0
     assert b_c.value > 2 * b_r.value
     o = lm.default_opts()
-    o.k_max = 9                                        # k = 9 not built
+    o.k_max = 10                                       # Table 2 ends at k = 9
     assert fwd(lib, opts=o) == 1
     o = lm.default_opts()
     o.max_sqrt = 65
@@ -129,7 +129,7 @@ def test_component_argument_validation(lib):
     assert lib.logm_gemm_f64(4, 4, 4, 1.0, FAKE, 3, FAKE, 4, 0.0, FAKE, 4, None) == 1
     assert lib.logm_inverse_f64(4, None, 4, FAKE, 4, None, None, 0, None) == 1
     assert lib.logm_sqrt_f64(4, FAKE, 4, FAKE, 4, 0, None, None, 0, None) == 1
-    assert lib.logm_poly_f64(4, 9, 0, FAKE, 4, FAKE, 4, FAKE, 4, None, 0, None) == 1
+    assert lib.logm_poly_f64(4, 10, 0, FAKE, 4, FAKE, 4, FAKE, 4, None, 0, None) == 1
     assert lib.logm_poly_f64(4, 5, -1, FAKE, 4, FAKE, 4, FAKE, 4, None, 0, None) == 1
     est = ctypes.c_double(0)
     assert lib.logm_normest_f64(4, FAKE, 4, FAKE, 4, 0, 0, ctypes.byref(est), None, None, 0, None) == 1
@@ -158,7 +158,7 @@ def test_backward_argument_validation(lib):
     assert call(ldga=7) == 1
     assert call(dtype=1) == 3                          # complex: workspace of the 2n run
     o = lm.default_opts()
-    o.k_max = 9
+    o.k_max = 10
     assert call(opts=o) == 1
     assert call() == 3                                 # workspace too small
     # taped pair: the workspace is required (it carries the tape)
@@ -199,7 +199,7 @@ def test_batched_argument_validation(lib):
     o.balance = 1                                      # no balancing on this path
     assert call(opts=o) == 1
     o = lm.default_opts()
-    o.k_max = 9
+    o.k_max = 10
     assert call(opts=o) == 1
     assert call(ws_bytes=100) == 3
 
@@ -266,10 +266,10 @@ def test_library_table1_matches_paper(golden):
 
 def test_library_table2_matches_paper(golden):
     t = golden("table2_theta.txt")
-    for k in (1, 2, 3, 4, 5, 6, 7, 8):
+    for k in (1, 2, 3, 4, 5, 6, 7, 8, 9):
         m, _, theta = t[str(k)]
         _, _, _, mk, thk = lm.scheme(k)
-        # k = 7, 8: the fits' own Theta, below the printed values (reading R1)
+        # k = 7, 8, 9: the fits' own Theta, below the printed values (reading R1)
         assert (mk, thk) == (int(m), oracle.THETA_DEFAULT[k][1])
         assert thk == (float(theta) if k <= 6 else oracle.THETA_FIT[k])
     assert lm.scheme(5, theta_source=1)[4] == 0.2448
@@ -277,38 +277,21 @@ def test_library_table2_matches_paper(golden):
     assert lm.scheme(6, theta_source=1)[4] == oracle.THETA_FIT[6]
 
 
-@pytest.mark.parametrize("k", [1, 2, 3, 4, 6, 7, 8])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 6, 7, 8, 9])
 def test_library_taylor_schemes_expand_to_taylor(k):
-    """The library's own k = 1, 2, 3, 4, 6, 7, 8 coefficients expand to T_{m_k}
-    (exact rationals; k = 4 matches orders up to m_4 = 14 of its degree 16, k = 6, 7,
-    8 orders up to 20, 24, 27 of their degrees 64, 128, 256)."""
+    """The library's own k = 1, 2, 3, 4, 6..9 coefficients expand to T_{m_k} (exact
+    rationals; k = 4 matches orders up to m_4 = 14 of its degree 16, k = 6..9 orders
+    up to 20, 24, 27, 28 of their degrees 64..512)."""
     from fractions import Fraction
+
+    from exact_poly import expand_rows
+
     h, g, y, m, _ = lm.scheme(k)
-    P = [None, [Fraction(1)], [Fraction(0), Fraction(1)], [Fraction(0), Fraction(0), Fraction(1)]]
-
-    def add(a, b):
-        n = max(len(a), len(b))
-        return [(a[i] if i < len(a) else 0) + (b[i] if i < len(b) else 0) for i in range(n)]
-
-    def mul(a, b):
-        out = [Fraction(0)] * (len(a) + len(b) - 1)
-        for i, x in enumerate(a):
-            for j, z in enumerate(b):
-                out[i + j] += x * z
-        return out
-
-    pos = 0
+    rows_h, rows_g, pos = {}, {}, 0
     for j in range(2, k + 1):
-        L = [Fraction(0)]
-        R = [Fraction(0)]
-        for i in range(2, j + 2):
-            L = add(L, [Fraction(h[pos]) * c for c in P[i]])
-            R = add(R, [Fraction(g[pos]) * c for c in P[i]])
-            pos += 1
-        P.append(mul(L, R))
-    z = [Fraction(0)]
-    for q in range(1, k + 3):
-        z = add(z, [Fraction(y[q - 1]) * c for c in P[q]])
+        rows_h[j], rows_g[j] = h[pos:pos + j], g[pos:pos + j]
+        pos += j
+    z = expand_rows(k, rows_h, rows_g, y)
     for i in range(1, m + 1):
         assert abs(float((z[i] - Fraction(1, i)) * i)) <= (16 if k >= 4 else 4) * 2.0 ** -53
 

@@ -53,7 +53,7 @@ ITER_TIES = []  # a converged root stopped one iteration apart (stopping rule at
 TIE = 1e-9     # relative move of the Theta values that a rounding tie may need
 
 
-def tie_explains(A, s, k, k_max=8):
+def tie_explains(A, s, k, k_max=9):
     """True if the oracle, with every Theta moved by a relative TIE up or down, takes
     the device's (s, k)."""
     for f in (1.0 - TIE, 1.0 + TIE):
@@ -67,7 +67,7 @@ def tie_explains(A, s, k, k_max=8):
     return False
 
 
-def check_against_oracle(Lg, st, A, tol=TOL, k_max=8):
+def check_against_oracle(Lg, st, A, tol=TOL, k_max=9):
     """Device result against the oracle.  A flip of (s, k) must be a rounding tie (see
     tie_explains); an iteration count may differ by one on a root that converged (the
     stopping rule compares changes at the rounding floor).  The oracle then replays

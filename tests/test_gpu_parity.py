@@ -160,7 +160,7 @@ def test_sqrt_spd():
 
 
 # ------------------------------------------------------------- polynomial -
-@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6, 7, 8, 9])
 @pytest.mark.parametrize("n,s", [(1, 0), (64, 0), (100, 3), (257, 1)])
 def test_poly_matches_oracle(k, n, s):
     rng = np.random.default_rng(100 * k + n)
@@ -202,7 +202,7 @@ def decisions(info):
     return info["s"], info["k"], list(info["db_iters"])
 
 
-def tie_explains(A, info, k_max=8, progress=None):
+def tie_explains(A, info, k_max=9, progress=None):
     """True if the oracle, with every Theta moved by a relative TIE up or down, takes
     the device's (s, k): the two sides straddled a threshold by rounding."""
     for f in (1.0 - TIE, 1.0 + TIE):
@@ -225,7 +225,7 @@ def check_counters(info, io, n):
         2 * nd ** 3 * (info["n_inv"] + info["n_gemm"]) + 2 * nd ** 2 * info["n_matvec"], rel=1e-12)
 
 
-def oracle_parity(A, Lg, info, tol=TOL_LOGM, k_max=8, case=None, progress=None):
+def oracle_parity(A, Lg, info, tol=TOL_LOGM, k_max=9, case=None, progress=None):
     """Compare a device result with the oracle (decisions, counters, values); on a
     flip check that it is a tie and compare with the oracle's replay of the device's
     decisions.  Returns ((s, k) equal, oracle info, relative Frobenius error)."""
@@ -255,7 +255,7 @@ def oracle_parity(A, Lg, info, tol=TOL_LOGM, k_max=8, case=None, progress=None):
 def compare_with_oracle(A, tol=TOL_LOGM, **kw):
     L, info = lm.logm(dev(A), **kw)
     Lg = host(L)
-    same, _, _ = oracle_parity(A, Lg, info, tol=tol, k_max=kw.get("k_max", 8))
+    same, _, _ = oracle_parity(A, Lg, info, tol=tol, k_max=kw.get("k_max", 9))
     return Lg, info, same
 
 
@@ -272,7 +272,7 @@ def test_logm_rotscale_vs_oracle_and_exact(n, seed):
     A, Lx = rotscale_matrix(n, seed)
     Lg, info, same = compare_with_oracle(A)
     assert relf(Lg, Lx) < 1e-11
-    assert info["k"] in (1, 2, 3, 4, 5, 6, 7, 8)
+    assert info["k"] in oracle.SHIPPED_K
 
 
 def test_logm_rotscale1024():
@@ -280,7 +280,7 @@ def test_logm_rotscale1024():
     Lg, info, same = compare_with_oracle(A)
     assert same
     assert relf(Lg, Lx) < 1e-11
-    assert info["s"] >= 5
+    assert info["s"] >= 4      # several roots (4 with schemes up to k = 9)
     # most inversions ran in the previous inversion's row order; on this matrix one
     # attempt in the first root is rejected by the multiplier check and redone
     print("reordered inversions:", info["n_inv_reordered"], "rejected:", info["n_order_rejected"])
@@ -414,12 +414,23 @@ def test_logm_selects_k6(n, rho, s):
                                        (64, 1.15, 1, 7)])
 def test_logm_selects_k78(n, rho, s, k):
     """The seven- and eight-product schemes (our fits, reading R1) are selected on both
-    sides at the default k_max = 8, each saving a square root against k_max = 6."""
+    sides with schemes up to k = 8, each saving a square root against k_max = 6."""
     A = disk_matrix(n, 31, rho)
-    Lg, info, same = compare_with_oracle(A)
+    Lg, info, same = compare_with_oracle(A, k_max=8)
     assert same and info["s"] == s and info["k"] == k
     _, info6 = lm.logm(dev(A), k_max=6)
     assert info6["s"] == s + 1
+
+
+@pytest.mark.parametrize("n,rho", [(64, 0.95), (200, 1.0), (200, 1.05)])
+def test_logm_selects_k9(n, rho):
+    """The nine-product scheme (our fit, reading R1) is selected on both sides at the
+    default k_max = 9 with no root, where schemes up to k = 8 need one."""
+    A = disk_matrix(n, 31, rho)
+    Lg, info, same = compare_with_oracle(A)
+    assert same and info["s"] == 0 and info["k"] == 9
+    _, info8 = lm.logm(dev(A), k_max=8)
+    assert info8["s"] == 1
 
 
 def test_logm_closed_forms():
