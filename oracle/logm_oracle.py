@@ -64,13 +64,17 @@ R6  Degree selection: min_in is the *smallest* index whose Theta passes (the
     against the threshold being tested (Theta_j, or Theta_next for the "j+1"
     shortcut).
 R7  Balancing (steps 1 and 14) is off: log(T^{-1} A T) = T^{-1} log(A) T exactly.
-R13 Balancing (steps 1 and 14, the paper calls MATLAB's balance): the
-    Parlett-Reinsch diagonal similarity with radix 2, reached by Gauss-Seidel
-    sweeps over the indices; index i takes the power of two f that brings its
-    column and row 2-norms within a factor 2 of each other, and keeps it only if
-    c + r falls below 0.95 of its old value; sweeps stop when no index changes
-    (at most 100).  The permutation step of balance, which only isolates
-    eigenvalues of reducible matrices, is not applied.  Off by default.
+R13 Balancing (steps 1 and 14, the paper calls MATLAB's balance): first the
+    permutation step, which isolates eigenvalues of reducible matrices: while some
+    index of the active range [lo, hi] has a row with no nonzero off the diagonal
+    among the active columns, the largest such index is swapped with hi and hi
+    drops by one; then, while some index has such a column (among the active
+    rows), the smallest is swapped with lo and lo rises by one.  Then the
+    Parlett-Reinsch diagonal similarity with radix 2 on the active range, reached
+    by Gauss-Seidel sweeps over its indices; index i takes the power of two f that
+    brings its column and row 2-norms (over the active range) within a factor 2 of
+    each other, and keeps it only if c + r falls below 0.95 of its old value; sweeps
+    stop when no index changes (at most 100).  Off by default.
 R12 Reverse mode: the decisions (s, k, iterations per root) and the scaling
     factors mu are constants of the differentiated map.
 R14 maxiter: Algorithm 1's loop takes at most maxiter (``max_sqrt``) roots and
@@ -627,19 +631,49 @@ def select_degree(n1, n2, e_top, e_top1, estimate, kset, theta_table=THETA_DEFAU
 # Algorithm 1
 # ---------------------------------------------------------------------------
 
-def balance(A, max_sweeps: int = 100):
-    """Diagonal similarity B = T^{-1} A T, T = diag(d) with powers of two (reading
-    R13).  Returns (B, d, sweeps).  Every operation on B is an exact scaling by a
-    power of two, so log(A) = T log(B) T^{-1} holds up to the rounding of log(B)."""
+def balance(A, max_sweeps: int = 100, permute: bool = True):
+    """Similarity B = T^{-1} P^T A P T with P a permutation and T = diag(d) of powers
+    of two (reading R13).  Returns (B, d, sweeps, perm) with (P^T A P)[i, j] =
+    A[perm[i], perm[j]].  Every operation on B is a row/column exchange or an exact
+    scaling by a power of two, so log(A) = P T log(B) T^{-1} P^T holds up to the
+    rounding of log(B).  permute=False skips the permutation step."""
     B = np.array(A, dtype=np.float64, copy=True)
     n = B.shape[0]
     d = np.ones(n)
+    perm = list(range(n))
+    lo, hi = 0, n - 1
+
+    def swap(i, j):
+        if i != j:
+            B[[i, j], :] = B[[j, i], :]
+            B[:, [i, j]] = B[:, [j, i]]
+            perm[i], perm[j] = perm[j], perm[i]
+
+    def isolated_row(j):
+        return all(B[j, c] == 0.0 for c in range(lo, hi + 1) if c != j)
+
+    def isolated_col(j):
+        return all(B[r, j] == 0.0 for r in range(lo, hi + 1) if r != j)
+
+    if permute:
+        while hi > lo:
+            rows = [j for j in range(lo, hi + 1) if isolated_row(j)]
+            if not rows:
+                break
+            swap(max(rows), hi)
+            hi -= 1
+        while hi > lo:
+            cols = [j for j in range(lo, hi + 1) if isolated_col(j)]
+            if not cols:
+                break
+            swap(min(cols), lo)
+            lo += 1
     sweeps = 0
     for sweeps in range(1, max_sweeps + 1):
         changed = False
-        for i in range(n):
-            c = math.sqrt(float(np.sum(B[:, i] * B[:, i])))
-            r = math.sqrt(float(np.sum(B[i, :] * B[i, :])))
+        for i in range(lo, hi + 1):
+            c = math.sqrt(float(np.sum(B[lo:hi + 1, i] * B[lo:hi + 1, i])))
+            r = math.sqrt(float(np.sum(B[i, lo:hi + 1] * B[i, lo:hi + 1])))
             if c == 0.0 or r == 0.0 or not (math.isfinite(c) and math.isfinite(r)):
                 continue
             before = c + r
@@ -655,7 +689,7 @@ def balance(A, max_sweeps: int = 100):
                 changed = True
         if not changed:
             break
-    return B, d, sweeps
+    return B, d, sweeps, perm
 
 
 def logm(A, k_max: int = 9, max_sqrt: int = 50, db_max_iter: int = 30,
@@ -676,10 +710,12 @@ def logm(A, k_max: int = 9, max_sqrt: int = 50, db_max_iter: int = 30,
             raise ValueError("balancing is implemented for real input")
         if A.ndim == 2 and not np.all(np.isfinite(A)):
             raise OracleError("ENONFINITE", "input has non-finite entries")
-        Bal, d, sweeps = balance(A)
+        Bal, d, sweeps, perm = balance(A)
         L, info = logm(Bal, k_max, max_sqrt, db_max_iter, theta_table, force, progress=progress)
         info["balance_sweeps"] = sweeps
-        return L * d[:, None] / d[None, :], info
+        out = np.empty_like(L)
+        out[np.ix_(perm, perm)] = L * d[:, None] / d[None, :]    # P T log(B) T^{-1} P^T
+        return out, info
     if A.ndim != 2 or A.shape[0] != A.shape[1] or A.shape[0] < 1:
         raise ValueError("A must be a non-empty square matrix")
     if not np.all(np.isfinite(A)):
