@@ -78,12 +78,13 @@ typedef struct logm_opts {
                            inverses and the norm estimates.  Result error about u_32 ||B||
                            relative instead of u_64. */
   int32_t balance;      /* 0: no preprocessing (default); 1: steps 1 and 14 of
-                           Algorithm 1, run on T^{-1} A T and return T L T^{-1}, T the
-                           power-of-two diagonal of Parlett-Reinsch balancing (the
-                           paper calls MATLAB's balance; its permutation step is not
-                           applied).  logm_forward only: logm_backward differentiates
-                           the unbalanced map (the same function) and logm_batched_f64
-                           rejects it. */
+                           Algorithm 1, run on B = T^{-1} P^T A P T and return
+                           P T log(B) T^{-1} P^T, P the permutation isolating
+                           eigenvalues of a reducible A and T the power-of-two
+                           diagonal of Parlett-Reinsch balancing (the paper calls
+                           MATLAB's balance; see logm_balance_f64).  logm_forward
+                           only: logm_backward differentiates the unbalanced map (the
+                           same function) and logm_batched_f64 rejects it. */
   int32_t pivot_search; /* 0 (default): for n above 256, an inversion of the
                            square-root iteration may take the row order of the previous
                            inversion of the same iterate (X or Y) instead of searching
@@ -292,13 +293,18 @@ int logm_normest_f64(int64_t n, const double* B2, int64_t ldb2, const double* B,
                      int32_t q, int32_t r, double* est, int32_t* nmatvec, void* ws,
                      size_t ws_bytes, void* stream);
 
-/* B = T^{-1} A T (n x n, row-major, lda, ldb >= n; B may equal A when lda == ldb)
- * with T = diag(d) of powers of two: the balancing of steps 1 and 14 of Algorithm 1
- * (Gauss-Seidel sweeps of the Parlett-Reinsch rule with 2-norms, at most 100).  d
- * (device, n doubles) receives T's diagonal, *sweeps (host, may be NULL) the sweeps
- * used.  Every update is an exact scaling, so B is exactly the similarity. */
+/* B = T^{-1} P^T A P T (n x n, row-major, lda, ldb >= n; B may equal A when
+ * lda == ldb): the balancing of steps 1 and 14 of Algorithm 1.  With perm (device, n
+ * ints) not NULL, first the permutation step isolating eigenvalues of reducible
+ * matrices (indices whose row, then column, has no nonzero off the diagonal in the
+ * active range go to the bottom, then the top); perm[i] receives the index of A at
+ * position i, (P^T A P)[i][j] = A[perm[i]][perm[j]].  NULL skips that step (P = I).
+ * Then T = diag(d) of powers of two over the active range (Gauss-Seidel sweeps of the
+ * Parlett-Reinsch rule with 2-norms, at most 100).  d (device, n doubles) receives
+ * T's diagonal, *sweeps (host, may be NULL) the sweeps used.  Every update is an
+ * exchange or an exact scaling, so B is exactly the similarity. */
 int logm_balance_f64(int64_t n, const double* A, int64_t lda, double* B, int64_t ldb, double* d,
-                     int32_t* sweeps, void* ws, size_t ws_bytes, void* stream);
+                     int32_t* perm, int32_t* sweeps, void* ws, size_t ws_bytes, void* stream);
 
 /* Launch-shape autotuner: for matrices padded like n, times the inversion of two
  * synthetic n x n matrices (the shape of a Denman-Beavers iteration) with each

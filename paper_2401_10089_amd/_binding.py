@@ -173,8 +173,8 @@ def load_library(path: str = LIB_PATH):
         "logm_poly_f64": (ctypes.c_int, [_i64, _i32, _i32, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _sz, _vp]),
         "logm_normest_f64": (ctypes.c_int, [_i64, _vp, _i64, _vp, _i64, _i32, _i32, ctypes.POINTER(_f64),
                                             ctypes.POINTER(_i32), _vp, _sz, _vp]),
-        "logm_balance_f64": (ctypes.c_int, [_i64, _vp, _i64, _vp, _i64, _vp, ctypes.POINTER(_i32), _vp, _sz,
-                                            _vp]),
+        "logm_balance_f64": (ctypes.c_int, [_i64, _vp, _i64, _vp, _i64, _vp, _vp, ctypes.POINTER(_i32), _vp,
+                                            _sz, _vp]),
         "logm_autotune": (ctypes.c_int, [_i64, _vp, _sz, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_f64)]),
         "logm_scheme": (ctypes.c_int, [_i32, _i32, ctypes.POINTER(_f64), ctypes.POINTER(_f64),
                                        ctypes.POINTER(_f64), ctypes.POINTER(_i32), ctypes.POINTER(_i32),
@@ -598,20 +598,22 @@ def inverse(A, workspace=None):
     return Ai, ld.value
 
 
-def balance(A, workspace=None):
-    """(T^{-1} A T, diag(T), sweeps): the balancing of steps 1 and 14 on the GPU."""
+def balance(A, workspace=None, permute: bool = True):
+    """(T^{-1} P^T A P T, diag(T), sweeps, perm): the balancing of steps 1 and 14 on the
+    GPU, perm[i] the index of A at position i (None without the permutation step)."""
     torch = _torch()
     A = _as_matrix(A)
     n = A.shape[0]
     B = torch.empty_like(A)
     d = torch.empty(n, dtype=torch.float64, device=A.device)
+    perm = torch.empty(n, dtype=torch.int32, device=A.device) if permute else None
     sw = _i32(0)
     ws = _workspace(n, A.device, workspace)
     rc = lib().logm_balance_f64(n, _vp(A.data_ptr()), A.stride(0), _vp(B.data_ptr()), B.stride(0),
-                                _vp(d.data_ptr()), ctypes.byref(sw), _vp(ws.data_ptr()), ws.numel(),
-                                _stream_ptr(A))
+                                _vp(d.data_ptr()), _vp(perm.data_ptr()) if permute else None,
+                                ctypes.byref(sw), _vp(ws.data_ptr()), ws.numel(), _stream_ptr(A))
     _check(rc, "logm_balance_f64")
-    return B, d, sw.value
+    return B, d, sw.value, perm
 
 
 def autotune(n: int, device=None, workspace=None):

@@ -381,7 +381,9 @@ Plan make_plan(int64_t n) {
   p.vec = take(4 * np * sizeof(double));
   p.scal = take(16 * sizeof(double));
   p.iflag = take(16 * sizeof(int));
-  p.bal = take(np * sizeof(double) + 16 * sizeof(int));   // balancing diagonal, sweeps
+  // balancing: diagonal (np doubles), sweeps (16 ints), permutation (np ints) and the
+  // row and column counts of the permutation step (2 np ints)
+  p.bal = take(np * sizeof(double) + 16 * sizeof(int) + 3 * np * sizeof(int));
   p.total = off;
   return p;
 }
@@ -991,7 +993,9 @@ Status forward_r64(Ctx& c, const double* A, int64_t lda, double* L, int64_t ldl,
     return st;
   }
   double* bal_d = c.at<double>(c.p.bal);
-  if (o.balance) HIPCK(launch_balance(X, np, n, bal_d, 100, nullptr, c.s));   // step 1
+  int* bal_perm = c.at<int>(c.p.bal + (size_t)np * sizeof(double) + 16 * sizeof(int));
+  if (o.balance)   // step 1
+    HIPCK(launch_balance(X, np, n, bal_d, 100, nullptr, bal_perm, bal_perm + np, c.s));
   Estimator est{c, B2, B};
   EstCall ecall{est, Status{}};
   double n1, n2;
@@ -1048,7 +1052,10 @@ Status forward_r64(Ctx& c, const double* A, int64_t lda, double* L, int64_t ldl,
   if (!ok) return ecall.st;
   if (L != nullptr) {
     PROPAGATE(poly(c, k, s, B, B2, L, ldl, &info.n_gemm, o.graph_fp32 != 0));
-    if (o.balance) HIPCK(launch_unbalance(L, ldl, n, bal_d, c.s));   // step 14
+    if (o.balance) {   // step 14: L = P T log(B) T^{-1} P^T, through a free matrix
+      HIPCK(launch_scale_out(L, ldl, c.mat(0), np, n, 1.0, nullptr, c.s));
+      HIPCK(launch_unbalance_perm(c.mat(0), np, L, ldl, n, bal_d, bal_perm, c.s));
+    }
   }
   info.s = s;
   info.k = k;
@@ -2059,7 +2066,7 @@ int logm_normest_f64(int64_t n, const double* B2, int64_t ldb2, const double* B,
 }
 
 int logm_balance_f64(int64_t n, const double* A, int64_t lda, double* B, int64_t ldb, double* d,
-                     int32_t* sweeps, void* ws, size_t ws_bytes, void* stream) {
+                     int32_t* perm, int32_t* sweeps, void* ws, size_t ws_bytes, void* stream) {
   if (n < 1 || n > (int64_t)1 << 20 || A == nullptr || B == nullptr || d == nullptr || lda < n ||
       ldb < n || (A == B && lda != ldb))
     return LOGM_EINVAL;
@@ -2072,7 +2079,9 @@ int logm_balance_f64(int64_t n, const double* A, int64_t lda, double* B, int64_t
       HIPCK(hipMemcpy2DAsync(B, (size_t)ldb * sizeof(double), A, (size_t)lda * sizeof(double),
                              (size_t)n * sizeof(double), (size_t)n, hipMemcpyDeviceToDevice, c.s));
     int* sw = c.at<int>(c.p.bal + (size_t)c.p.n_pad * sizeof(double));
-    HIPCK(launch_balance(B, ldb, (int)n, d, 100, sw, c.s));
+    int* cnt = c.at<int>(c.p.bal + (size_t)c.p.n_pad * sizeof(double) + 16 * sizeof(int) +
+                         (size_t)c.p.n_pad * sizeof(int));
+    HIPCK(launch_balance(B, ldb, (int)n, d, 100, sw, perm, cnt, c.s));
     int h = 0;
     PROPAGATE(sync_read(c, &h, sw, sizeof(int)));
     if (sweeps != nullptr) *sweeps = h;

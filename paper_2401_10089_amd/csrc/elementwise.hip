@@ -310,25 +310,110 @@ __global__ __launch_bounds__(256) void transpose_kernel(const double* src, int64
 }
 
 // Balancing (steps 1 and 14 of Algorithm 1), in place on the n x n block (row stride
-// ld): B = T^{-1} A T with T = diag(d), d_i powers of two, by Gauss-Seidel sweeps
-// over the indices in one workgroup.  Index i takes the power of two f that brings
-// the 2-norms of its column (c) and row (r) within a factor 2 of each other, and
-// keeps it only if c + r drops below 0.95 of its old value; an index with a zero or
-// overflowing norm is skipped; sweeps stop when no index changes (at most
-// max_sweeps).  Every update is an exact power-of-two scaling.
+// ld), in one workgroup.  With perm != null, first the permutation step: while some
+// index of the active range [lo, hi] has a row with no nonzero off the diagonal among
+// the active columns, the largest such index is exchanged with hi (rows and columns)
+// and hi drops by one; then, while some index has such a column among the active
+// rows, the smallest is exchanged with lo and lo rises by one.  Counts of the active
+// off-diagonal nonzeros of every row and column (cnt, 2n ints) are formed once and
+// updated per isolated index, so the step costs O(n^2) in all.  perm[i] receives the
+// original index at position i.  Then B = T^{-1} B T with T = diag(d), d_i powers of
+// two, by Gauss-Seidel sweeps over the active indices: index i takes the power of two
+// f that brings the 2-norms of its column (c) and row (r) over the active range within
+// a factor 2 of each other, and keeps it only if c + r drops below 0.95 of its old
+// value; an index with a zero or overflowing norm is skipped; sweeps stop when no
+// index changes (at most max_sweeps).  Every update is an exchange or an exact
+// power-of-two scaling.
 constexpr int BAL_T = 1024;
+__device__ void bal_exchange(double* M, int64_t ld, int n, int a, int b, int* perm, int* rc,
+                             int* cc) {
+  const int t = threadIdx.x;
+  if (a != b) {
+    for (int k = t; k < n; k += BAL_T) {
+      const double x = M[(int64_t)a * ld + k];
+      M[(int64_t)a * ld + k] = M[(int64_t)b * ld + k];
+      M[(int64_t)b * ld + k] = x;
+    }
+    __syncthreads();
+    for (int k = t; k < n; k += BAL_T) {
+      const double x = M[(int64_t)k * ld + a];
+      M[(int64_t)k * ld + a] = M[(int64_t)k * ld + b];
+      M[(int64_t)k * ld + b] = x;
+    }
+    if (t == 0) {
+      int v = perm[a]; perm[a] = perm[b]; perm[b] = v;
+      v = rc[a]; rc[a] = rc[b]; rc[b] = v;
+      v = cc[a]; cc[a] = cc[b]; cc[b] = v;
+    }
+  }
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(BAL_T) void balance_kernel(double* M, int64_t ld, int n, double* d,
-                                                        int max_sweeps, int* sweeps_out) {
+                                                        int max_sweeps, int* sweeps_out, int* perm,
+                                                        int* cnt) {
   __shared__ double red[2][BAL_T / 64];
+  __shared__ int s_pick;
   const int t = threadIdx.x;
   for (int i = t; i < n; i += BAL_T) d[i] = 1.0;
+  int lo = 0, hi = n - 1;
+  if (perm != nullptr) {
+    int* rc = cnt;       // active off-diagonal nonzeros of row i
+    int* cc = cnt + n;   // ... and of column i
+    for (int i = t; i < n; i += BAL_T) {
+      perm[i] = i;
+      int r = 0, c = 0;
+      for (int k = 0; k < n; ++k)
+        if (k != i) {
+          r += (M[(int64_t)i * ld + k] != 0.0);
+          c += (M[(int64_t)k * ld + i] != 0.0);
+        }
+      rc[i] = r;
+      cc[i] = c;
+    }
+    __syncthreads();
+    while (hi > lo) {    // isolated rows to the bottom, the largest index first
+      if (t == 0) s_pick = -1;
+      __syncthreads();
+      int best = -1;
+      for (int j = lo + t; j <= hi; j += BAL_T)
+        if (rc[j] == 0) best = j;
+      if (best >= 0) atomicMax(&s_pick, best);
+      __syncthreads();
+      const int j = s_pick;
+      if (j < 0) break;  // uniform
+      // column j leaves the active range: rows with a nonzero there lose one
+      for (int r = lo + t; r <= hi; r += BAL_T)
+        if (r != j && M[(int64_t)r * ld + j] != 0.0) rc[r] -= 1;
+      __syncthreads();
+      bal_exchange(M, ld, n, j, hi, perm, rc, cc);
+      --hi;
+    }
+    while (hi > lo) {    // isolated columns to the top, the smallest index first
+      if (t == 0) s_pick = n;
+      __syncthreads();
+      int best = n;
+      for (int j = hi - t; j >= lo; j -= BAL_T)
+        if (cc[j] == 0) best = j;
+      if (best < n) atomicMin(&s_pick, best);
+      __syncthreads();
+      const int j = s_pick;
+      if (j >= n) break;  // uniform
+      // row j leaves the active range: columns with a nonzero there lose one
+      for (int c = lo + t; c <= hi; c += BAL_T)
+        if (c != j && M[(int64_t)j * ld + c] != 0.0) cc[c] -= 1;
+      __syncthreads();
+      bal_exchange(M, ld, n, j, lo, perm, rc, cc);
+      ++lo;
+    }
+  }
   int sweeps = 0;
   for (int sw = 1; sw <= max_sweeps; ++sw) {
     sweeps = sw;
     bool changed = false;
-    for (int i = 0; i < n; ++i) {
+    for (int i = lo; i <= hi; ++i) {
       double cs = 0.0, rs = 0.0;
-      for (int k = t; k < n; k += BAL_T) {
+      for (int k = lo + t; k <= hi; k += BAL_T) {
         const double a = M[(int64_t)k * ld + i];
         const double b = M[(int64_t)i * ld + k];
         cs = fma(a, a, cs);
@@ -376,12 +461,15 @@ __global__ __launch_bounds__(BAL_T) void balance_kernel(double* M, int64_t ld, i
   if (t == 0 && sweeps_out != nullptr) *sweeps_out = sweeps;
 }
 
-// L <- T L T^{-1}: L[i][j] *= d[i] / d[j] (exact, powers of two).
-__global__ void unbalance_kernel(double* L, int64_t ld, int n, const double* d) {
+// L[perm[i]][perm[j]] = LB[i][j] d[i] / d[j]: L = P T LB T^{-1} P^T (exact, powers
+// of two and an exchange of entries).
+__global__ void unbalance_perm_kernel(const double* LB, int64_t ldb, double* L, int64_t ldl, int n,
+                                      const double* d, const int* perm) {
   const int i = blockIdx.y;
   const double di = d[i];
+  const int64_t pi = perm[i];
   for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x)
-    L[(int64_t)i * ld + j] *= di / d[j];
+    L[pi * ldl + perm[j]] = LB[(int64_t)i * ldb + j] * (di / d[j]);
 }
 
 // Complex input through its real representation: P (2n x 2n, row stride ldp) =
@@ -537,13 +625,17 @@ hipError_t launch_transpose(const double* src, int64_t lds, double* dst, int64_t
 }
 
 hipError_t launch_balance(double* M, int64_t ld, int n, double* d, int max_sweeps, int* sweeps,
-                          hipStream_t s) {
-  hipLaunchKernelGGL(balance_kernel, dim3(1), dim3(BAL_T), 0, s, M, ld, n, d, max_sweeps, sweeps);
+                          int* perm, int* cnt, hipStream_t s) {
+  if (perm != nullptr && cnt == nullptr) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(balance_kernel, dim3(1), dim3(BAL_T), 0, s, M, ld, n, d, max_sweeps, sweeps,
+                     perm, cnt);
   return hipGetLastError();
 }
 
-hipError_t launch_unbalance(double* L, int64_t ld, int n, const double* d, hipStream_t s) {
-  hipLaunchKernelGGL(unbalance_kernel, row_grid(n, n), dim3(256), 0, s, L, ld, n, d);
+hipError_t launch_unbalance_perm(const double* LB, int64_t ldb, double* L, int64_t ldl, int n,
+                                 const double* d, const int* perm, hipStream_t s) {
+  hipLaunchKernelGGL(unbalance_perm_kernel, row_grid(n, n), dim3(256), 0, s, LB, ldb, L, ldl, n, d,
+                     perm);
   return hipGetLastError();
 }
 

@@ -199,12 +199,15 @@ struct LincombGen {
 };
 hipError_t launch_lincomb_gen(const LincombGen& a, hipStream_t s);
 
-// Balancing in place on the n x n block (row stride ld): M <- T^{-1} M T, d = diag(T)
-// (n doubles, powers of two), *sweeps = sweeps used (device int, may be null).
+// Balancing in place on the n x n block (row stride ld): M <- T^{-1} P^T M P T,
+// d = diag(T) (n doubles, powers of two), perm (n ints, may be null: no permutation
+// step) the original index at each position, cnt 2n ints of scratch (needed with
+// perm), *sweeps = sweeps used (device int, may be null).
 hipError_t launch_balance(double* M, int64_t ld, int n, double* d, int max_sweeps, int* sweeps,
-                          hipStream_t s);
-// L <- T L T^{-1} for d = diag(T).
-hipError_t launch_unbalance(double* L, int64_t ld, int n, const double* d, hipStream_t s);
+                          int* perm, int* cnt, hipStream_t s);
+// L = P T LB T^{-1} P^T (LB and L distinct).
+hipError_t launch_unbalance_perm(const double* LB, int64_t ldb, double* L, int64_t ldl, int n,
+                                 const double* d, const int* perm, hipStream_t s);
 
 // P (2n x 2n) = [[Re A, -Im A], [Im A, Re A]] for complex A (interleaved, lda in
 // complex elements); L (complex) = the left block column of R (2n x 2n).

@@ -121,10 +121,10 @@ def test_component_argument_validation(lib):
     assert lib.logm_autotune(0, None, 0, None, best, None) == 1
     assert lib.logm_autotune(64, None, 0, None, None, None) == 1
     assert lib.logm_autotune(64, FAKE, 100, None, best, None) == 3
-    assert lib.logm_balance_f64(0, FAKE, 4, FAKE, 4, FAKE, None, None, 0, None) == 1
-    assert lib.logm_balance_f64(4, FAKE, 4, FAKE, 3, FAKE, None, None, 0, None) == 1
-    assert lib.logm_balance_f64(4, FAKE, 4, FAKE, 4, None, None, None, 0, None) == 1
-    assert lib.logm_balance_f64(4, FAKE, 4, FAKE, 5, FAKE, None, None, 0, None) == 1   # in place needs lda == ldb
+    assert lib.logm_balance_f64(0, FAKE, 4, FAKE, 4, FAKE, None, None, None, 0, None) == 1
+    assert lib.logm_balance_f64(4, FAKE, 4, FAKE, 3, FAKE, None, None, None, 0, None) == 1
+    assert lib.logm_balance_f64(4, FAKE, 4, FAKE, 4, None, None, None, None, 0, None) == 1
+    assert lib.logm_balance_f64(4, FAKE, 4, FAKE, 5, FAKE, None, None, None, 0, None) == 1   # in place needs lda == ldb
     assert lib.logm_gemm_f64(0, 4, 4, 1.0, FAKE, 4, FAKE, 4, 0.0, FAKE, 4, None) == 1
     assert lib.logm_gemm_f64(4, 4, 4, 1.0, FAKE, 3, FAKE, 4, 0.0, FAKE, 4, None) == 1
     assert lib.logm_inverse_f64(4, None, 4, FAKE, 4, None, None, 0, None) == 1

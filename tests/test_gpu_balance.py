@@ -1,6 +1,7 @@
-"""Balancing on the GPU (steps 1 and 14 of Algorithm 1): the power-of-two similarity
-must be bit-identical to the oracle's (same decisions, exact scalings), and logm
-with balancing must match the oracle's balanced logm and the closed form."""
+"""Balancing on the GPU (steps 1 and 14 of Algorithm 1): the permuted power-of-two
+similarity must be bit-identical to the oracle's (same exchanges, same decisions,
+exact scalings), and logm with balancing must match the oracle's balanced logm and
+the closed form."""
 
 from __future__ import annotations
 
@@ -42,9 +43,9 @@ def test_balance_bit_identical_to_oracle(lm, n):
     import torch
 
     A, _, _ = scaled_spd(n, 6000 + n)
-    B, d, sweeps = lm.balance(torch.from_numpy(A).to("cuda:0"))
-    Bo, do, so = oracle.balance(A)
-    assert sweeps == so
+    B, d, sweeps, perm = lm.balance(torch.from_numpy(A).to("cuda:0"))
+    Bo, do, so, po = oracle.balance(A)
+    assert sweeps == so and perm.cpu().tolist() == po == list(range(n))
     assert np.array_equal(d.cpu().numpy(), do)
     assert np.array_equal(B.cpu().numpy(), Bo)
 
@@ -58,9 +59,10 @@ def test_balanced_logm_vs_oracle_and_closed_form(lm, n):
     L = L.cpu().numpy()
     Lo, io = oracle.logm(A, balanced=True)
     if (info["s"], info["k"], info["db_iters"]) != (io["s"], io["k"], io["db_iters"]):
-        Bo, do, _ = oracle.balance(A)
+        Bo, do, _, po = oracle.balance(A)
         Lb, _ = oracle.logm(Bo, force={"s": info["s"], "k": info["k"], "db_iters": info["db_iters"]})
-        Lo = Lb * do[:, None] / do[None, :]
+        Lo = np.empty_like(Lb)
+        Lo[np.ix_(po, po)] = Lb * do[:, None] / do[None, :]
     assert relf(L, Lo) < 1e-12
     w, V = np.linalg.eigh(M)
     exact = D[:, None] * ((V * np.log(w)) @ V.T) / D[None, :]
@@ -77,3 +79,73 @@ def test_balance_on_balanced_input_changes_nothing(lm):
     L1, i1 = lm.logm(At, balance=True)
     L0, i0 = lm.logm(At)
     assert relf(L1.cpu().numpy(), L0.cpu().numpy()) < 1e-13
+
+
+def hidden_block_triangular(n1, nm, n2, seed):
+    """P0 [[T1, X, Y], [0, M, Z], [0, 0, T2]] P0^T with T1, T2 upper triangular and M
+    dense with wide power-of-two row/column scaling (as in the oracle's pins)."""
+    rng = np.random.default_rng(seed)
+    n = n1 + nm + n2
+    T = np.zeros((n, n))
+    T[:n1, :n1] = np.triu(rng.uniform(1, 2, (n1, n1)))
+    D = 2.0 ** rng.integers(-12, 13, size=nm)
+    M = rng.standard_normal((nm, nm)) / nm + 1.5 * np.eye(nm)
+    T[n1:n1 + nm, n1:n1 + nm] = D[:, None] * M / D[None, :]
+    T[n1 + nm:, n1 + nm:] = np.triu(rng.uniform(1, 2, (n2, n2)))
+    T[:n1, n1:] = rng.standard_normal((n1, n - n1))
+    T[n1:n1 + nm, n1 + nm:] = rng.standard_normal((nm, n2))
+    p0 = rng.permutation(n)
+    A = np.empty_like(T)
+    A[np.ix_(p0, p0)] = T
+    return A
+
+
+@pytest.mark.parametrize("shape", [(3, 10, 4), (20, 70, 40), (5, 300, 9), (0, 1, 0)])
+def test_permutation_step_bit_identical_to_oracle(lm, shape):
+    """The permutation step on hidden block-triangular matrices (and a 1 x 1): the same
+    exchanges, scalings and sweeps as the oracle, bit for bit."""
+    import torch
+
+    A = hidden_block_triangular(*shape, 6300 + sum(shape))
+    B, d, sweeps, perm = lm.balance(torch.from_numpy(A).to("cuda:0"))
+    Bo, do, so, po = oracle.balance(A)
+    assert perm.cpu().tolist() == po and sweeps == so
+    assert np.array_equal(d.cpu().numpy(), do)
+    assert np.array_equal(B.cpu().numpy(), Bo)
+
+
+@pytest.mark.parametrize("n", [9, 200])
+def test_permutation_step_triangular(lm, n):
+    """Upper triangular input is left as it is; lower triangular input is reversed
+    into upper triangular form (every index isolated, no scaling)."""
+    import torch
+
+    U = np.triu(np.random.default_rng(n).uniform(1, 2, (n, n)))
+    for A, order in ((U, list(range(n))), (U.T.copy(), list(range(n - 1, -1, -1)))):
+        B, d, _, perm = lm.balance(torch.from_numpy(A).to("cuda:0"))
+        assert perm.cpu().tolist() == order
+        assert np.all(d.cpu().numpy() == 1.0)
+        assert np.array_equal(B.cpu().numpy(), A[np.ix_(order, order)])
+
+
+@pytest.mark.parametrize("shape", [(3, 10, 4), (20, 70, 40)])
+def test_balanced_logm_with_permutation_vs_oracle(lm, shape):
+    """logm with balancing on a hidden block-triangular matrix: against the oracle's
+    balanced logm (replayed on the device's decisions if they differ) and by its
+    residual exp(L) - A."""
+    import scipy.linalg as sl
+    import torch
+
+    A = hidden_block_triangular(*shape, 6400 + sum(shape))
+    L, info = lm.logm(torch.from_numpy(A).to("cuda:0"), balance=True)
+    L = L.cpu().numpy()
+    Lo, io = oracle.logm(A, balanced=True)
+    if (info["s"], info["k"], info["db_iters"]) != (io["s"], io["k"], io["db_iters"]):
+        Bo, do, _, po = oracle.balance(A)
+        Lb, _ = oracle.logm(Bo, force={"s": info["s"], "k": info["k"], "db_iters": info["db_iters"]})
+        Lo = np.empty_like(Lb)
+        Lo[np.ix_(po, po)] = Lb * do[:, None] / do[None, :]
+    assert relf(L, Lo) < 1e-12
+    # residual of the balanced result; condition numbers reach 1e13 here, and the
+    # oracle's unbalanced logarithm leaves 8e-9 on the larger case
+    assert relf(sl.expm(L), A) < 1e-11
