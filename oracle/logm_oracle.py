@@ -23,10 +23,10 @@ Every step is written plainly: matrix products with ``@``, inverses and
 log-determinants with ``numpy.linalg`` (LAPACK LU with partial pivoting), norms as
 explicit column sums, and the 1-norm estimator as a Python loop.
 
-Readings of points where the paper is silent or garbled (each is restated in
-DESIGN.md):
+Readings of points where the paper is silent or garbled (the library takes the
+same readings):
 
-R1  Schemes shipped: k in {1, ..., 6}.  The paper prints coefficients only
+R1  Schemes shipped: k in {1, ..., 9}.  The paper prints coefficients only
     for k = 5 (Table 1); k = 1, 2 are the Taylor polynomials T_2, T_4 written in
     the degree-optimal form; k = 3 is the three-product scheme eq. eqP8pol solved
     for T_8 (Section 2.2); k = 4 (Table 2: order 14+, degree 16, Theta_4 = 9.31e-2,
