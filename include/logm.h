@@ -67,7 +67,7 @@ typedef struct logm_opts {
   int32_t db_max_iter;  /* maximum Denman-Beavers iterations per root (default 30) */
   int32_t theta_source; /* 0: Theta values of Table 2 as printed (default), except
                            k = 7, 8, 9, whose fits' own Theta (0.5284, 0.5739,
-                           0.6184) are below the printed ones and replace them;
+                           0.6371) are below the printed ones and replace them;
                            1: also Theta_5 = 0.2448 recomputed from Table 1 and
                            Theta_6 = 0.4258 recomputed for the six-product fit
                            (above the printed 0.372) */

@@ -18,7 +18,7 @@ constexpr int kKMax = 9;
 constexpr double kTheta6Fit = 0.4258;
 constexpr double kTheta7Fit = 0.5284;
 constexpr double kTheta8Fit = 0.5739;
-constexpr double kTheta9Fit = 0.6184;
+constexpr double kTheta9Fit = 0.6371;
 
 // Table 2 (k -> m_k, Theta_{m_k}) as Algorithm 1 uses it: the printed Theta where
 // the shipped polynomial's own Theta is at least that (k <= 6), the fits' own below

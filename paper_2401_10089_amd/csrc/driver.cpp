@@ -236,40 +236,40 @@ Scheme make_scheme(int k) {
            0.36551098261127246};
   } else if (k == 9) {
     // Degree 512 with b_i = 1/i for i <= 28 (Table 2: order 28+); our own fit as for
-    // k = 7, 8, orders up to 60 matched closely; Theta kTheta9Fit, below the printed
-    // 0.728.
-    s.h = {{1.0293774690516044, 0.0986497474609164},
-           {-0.5025042723076767, 0.5247128109060221, 1.3865109222218124},
-           {1.5801523405120685, 0.5646891581535393, -0.041325802357301704, -0.3181291215699591},
-           {0.46209850104803757, -0.6629103717511978, 1.5561748125820298, 0.5629951027959472,
-            -1.0915484419859594},
-           {0.4983592601693249, -0.2865322572654024, -0.14866362635306954, -0.4255005462181858,
-            0.27097034269416354, 0.09517721322238752},
-           {0.2441865389518984, -0.8907619366173689, 0.2832614080467771, -0.5559115256073457,
-            -0.22953284648300407, 0.02320319717888621, -0.24704400855650602},
-           {8.29440508611953, -3.4903312459043043, -1.6739773663378854, 0.3656203278354649,
-            0.2281889962148337, -0.3875771031594003, -0.9235864912211463, 0.36381161913462207},
-           {-0.02383477369623385, -0.2334157473932367, 0.0060532310712255715,
-            0.08365603505252057, -0.024950636985573166, -0.0036919692258725505,
-            -0.010245765351184849, -0.0019803019925272282, 0.11580064478486322}};
-    s.g = {{-0.567926898743273, 0.9073746556714914},
-           {-0.18886887732395102, -0.6489732205132462, -0.01670139192094852},
-           {-0.5158107828670548, -0.27688983990935284, -1.462952039008439, 0.3854266008750241},
-           {0.5445610154707972, -0.7204530569156263, -0.40179558991675046,
-            -0.42051866881404976, 0.6271217994353363},
-           {-0.5541098274524069, 0.09702125360365794, -0.08287621570475852,
-            -0.16955875954201557, 0.46719686290523976, 0.36754198740626737},
-           {-1.4980737562547197, -1.2274871512689252, 0.399255478050324, -1.7543170697122306,
-            1.1298530554757429, -0.12801528218311853, 0.6443899429833408},
-           {0.2450621271754964, 0.08708301653068268, -0.0035785272532655845,
-            0.03200164112608482, -0.022585412765151733, -0.007473019081323353,
-            0.030364792548688332, -0.0017623317258204177},
-           {4.74937027235682, 2.9028386343156614, 2.158061838336138, -0.30945895027312137,
-            -1.264362424768732, -0.32355351009185146, 0.25539635982766695, -0.5671996072436606,
-            -0.08269636486032923}};
-    s.y = {0.0, 1.0, -0.08543192809800926, 0.4879886358942328, 0.25079822847146865,
-           -0.3419332478263414, -0.005176138267992704, 0.1537019870763135,
-           -0.026203437037517104, 0.28033063495128707, -0.28768165250742594};
+    // k = 7, 8, orders up to 60 matched closely, then refitted with orders up to 36;
+    // Theta kTheta9Fit, below the printed 0.728.
+    s.h = {{1.0293774654954253, 0.09864974578713993},
+           {-0.5025042764604413, 0.5247128099270713, 1.3865109154694404},
+           {1.5801523428015003, 0.564689160015981, -0.04132577877448772, -0.3181290938151138},
+           {0.46209852408664714, -0.6629103859826887, 1.5561749902802438, 0.5629952560758475,
+            -1.0915484372066382},
+           {0.49835926172479694, -0.28653227506899215, -0.148663647760357,
+            -0.42550057814451747, 0.27097034359597927, 0.09517721269484208},
+           {0.24418646603749197, -0.8907621306859403, 0.28326127166966864, -0.5559114148662169,
+            -0.22953287019543578, 0.023203182812738577, -0.2470439903453851},
+           {8.29440509121812, -3.49033133732231, -1.6739771964808716, 0.36562032918558984,
+            0.22818900730057426, -0.3875770985856795, -0.9235865066293164, 0.36381161102378407},
+           {-0.023834769495566645, -0.23341574404939838, 0.006053224523533507,
+            0.08365603572231681, -0.024950637694602044, -0.0036919690827584783,
+            -0.01024576501956019, -0.001980301964390939, 0.11580064591432652}};
+    s.g = {{-0.5679268981697152, 0.9073746556319018},
+           {-0.1888688828972382, -0.6489732179223974, -0.016701395738854},
+           {-0.5158107858819706, -0.27688984222151425, -1.462952032150161, 0.385426605929796},
+           {0.5445610155271876, -0.7204530771525424, -0.4017954226885495, -0.4205187159574827,
+            0.6271217991968194},
+           {-0.5541098492291089, 0.09702120404998095, -0.08287626673046147,
+            -0.16955862359803975, 0.4671968591746414, 0.36754199111062913},
+           {-1.4980736532582153, -1.2274870924136219, 0.3992554882177873, -1.7543169131231182,
+            1.1298530970998097, -0.1280152496457704, 0.6443899208593218},
+           {0.24506212259898344, 0.08708303301205642, -0.0035785214337910307,
+            0.03200164096912623, -0.022585413781135003, -0.007473020549877621,
+            0.030364793737184485, -0.001762330511638815},
+           {4.749370015173131, 2.9028387103212885, 2.158061318333538, -0.3094590148962265,
+            -1.2643625227754285, -0.3235535119771448, 0.2553964395723641, -0.5671995772820415,
+            -0.08269651711221634}};
+    s.y = {0.0, 1.0, -0.0854319232638356, 0.4879886274950546, 0.25079821700464683,
+           -0.34193325088945475, -0.005176141201285309, 0.1537019859530235,
+           -0.026203438469472096, 0.2803306387830884, -0.2876816519579588};
   }
   return s;
 }
